@@ -1,0 +1,75 @@
+/* Oracle internals.  TEST INFRASTRUCTURE (see oracle.h). */
+#ifndef DG_ORACLE_INTERNAL_H
+#define DG_ORACLE_INTERNAL_H
+
+#include "oracle.h"
+
+double orc_phi(int dim, const int *e, const double *xi);
+double orc_dphi(int dim, const int *e, const double *xi, int axis);
+double orc_ref_mass(int dim, const int *e);
+double orc_pressure(int dim, double gamma, const double *u);
+
+/* A leaf block: tree index, level (roots are level 1) and its integer
+ * position inside the tree at that level. */
+typedef struct {
+    int tree, level, idx[3];
+} orc_key;
+
+/* One piece of a guard cell: the part of the guard cell covered by one
+ * source cell.  Boxes are in global integer units (see forest.c). */
+typedef struct {
+    int leaf;        /* source leaf */
+    int cell;        /* source cell inside that leaf */
+    long lo[3], hi[3]; /* overlap box, unwrapped to the guard cell's frame */
+    long src_lo[3];  /* source cell lower corner in the same frame */
+    long src_size;   /* source cell edge */
+} orc_piece;
+
+typedef struct {
+    int kind;        /* 0 copy (same level), 1 projection, 2 outflow mirror */
+    int npiece;
+    orc_piece *piece;
+} orc_guard_plan;
+
+/* Neighbour relation across one face of a leaf, found geometrically. */
+typedef struct {
+    int boundary;    /* 1: domain boundary with outflow condition */
+    int nn;          /* number of face neighbours (1, or 2^(d-1) when finer) */
+    int nb[4];
+    int level_diff;  /* neighbour level - own level: -1, 0, +1 */
+} orc_face_nbr;
+
+struct orc_forest {
+    int dim, p, N, nb, nv, q;
+    int roots[3];
+    double lo[3], hi[3];
+    int bc[3];
+    int max_level;
+    double gamma;
+    int hanging;
+    long unit;        /* global units per root edge = N * 2^(max_level-1) */
+    int nleaves;
+    orc_key *leaf;
+    int *exps;        /* nb x 3 */
+    orc_face_nbr *fn; /* nleaves x 2d */
+    orc_guard_plan *gp; /* nleaves x 2d x N^(d-1) */
+    /* adaptation plan */
+    int new_n;
+    orc_key *new_leaf;
+};
+
+/* geometry helpers shared by the oracle's own files */
+void orc_leaf_box(const orc_forest *f, const orc_key *k, long *lo, long *size);
+long orc_domain_units(const orc_forest *f, int axis);
+void orc_build_topology(orc_forest *f);
+void orc_free_topology(orc_forest *f);
+int orc_ncell(const orc_forest *f);
+int orc_nface_cells(const orc_forest *f);
+void orc_cell_ijk(const orc_forest *f, int cell, int *ijk);
+int orc_cell_index(const orc_forest *f, const int *ijk);
+void orc_sort_leaves(const orc_forest *f, orc_key *leaves, int n);
+/* find the leaf of the current forest containing global point x (unwrapped
+ * coordinates are wrapped on periodic axes); -1 if outside the domain */
+int orc_find_leaf(const orc_forest *f, const orc_key *leaves, int n, const double *x);
+
+#endif

@@ -1,0 +1,705 @@
+/*
+ * Oracle - DG solver pieces: initial-condition projection, guard-cell fill
+ * (Sec. 3.5, Eq. 15-17), residual of the Galerkin weak form (Sec. 2,
+ * Eq. 3-5), SSP-RK3 (Sec. 2), CFL time step (Sec. 4.3), conserved totals,
+ * positivity limiter (named in Sec. 5.3.2), block indicator and errors.
+ * TEST INFRASTRUCTURE (see oracle.h).
+ *
+ * Everything is plain loops in FP64, in physical units, one cell at a time.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+#include "oracle_internal.h"
+
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* physical length of one global unit along an axis */
+static double unit_len(const orc_forest *f, int a)
+{
+    return (f->hi[a] - f->lo[a]) / (double)orc_domain_units(f, a);
+}
+
+static long sidx(const orc_forest *f, long leaf, int v, int m, int cell)
+{
+    return ((leaf * f->nv + v) * f->nb + m) * (long)orc_ncell(f) + cell;
+}
+
+static long gidx(const orc_forest *f, long leaf, int face, int v, int m, int t)
+{
+    return (((leaf * 2 * f->dim + face) * f->nv + v) * f->nb + m) * (long)orc_nface_cells(f) + t;
+}
+
+/* evaluate the cell polynomial with coefficients coef[v*stride_v + m*stride_m]
+ * at reference point xi */
+static void eval_poly(const orc_forest *f, const double *coef, long stride_v, long stride_m,
+                      const double *xi, double *u)
+{
+    for (int v = 0; v < f->nv; ++v) {
+        double s = 0.0;
+        for (int m = 0; m < f->nb; ++m) s += coef[v * stride_v + m * stride_m] * orc_phi(f->dim, f->exps + 3 * m, xi);
+        u[v] = s;
+    }
+}
+
+/* the same with the basis values at the point given (ph[m] = phi_m) */
+static void eval_with(const orc_forest *f, const double *coef, long stride_v, long stride_m,
+                      const double *ph, double *u)
+{
+    for (int v = 0; v < f->nv; ++v) {
+        double s = 0.0;
+        for (int m = 0; m < f->nb; ++m) s += coef[v * stride_v + m * stride_m] * ph[m];
+        u[v] = s;
+    }
+}
+
+/* Tensor Gauss points of an nq-per-axis rule over [-1,1]^dim. */
+static int tensor_points(int dim, int q, const double *gx, const double *gw, double (*xi)[3], double *w)
+{
+    int n = 1;
+    for (int a = 0; a < dim; ++a) n *= q;
+    for (int i = 0; i < n; ++i) {
+        int rem = i;
+        w[i] = 1.0;
+        xi[i][0] = xi[i][1] = xi[i][2] = 0.0;
+        for (int a = 0; a < dim; ++a) {
+            xi[i][a] = gx[rem % q];
+            w[i] *= gw[rem % q];
+            rem /= q;
+        }
+    }
+    return n;
+}
+
+/* L2 projection (Eq. 11-14 written for one overlap piece): accumulate into
+ * acc[v*nb+l] the contribution (1/M_dst,l) int_{overlap} phi^dst_l u^src dV
+ * for a source cell (lower corner src_lo, edge src_size) and a destination
+ * cell (dst_lo, dst_size).  src points at coefficient (v=0,m=0) with modes
+ * src_stride apart and variables nb*src_stride apart.  Gauss rule with p+1
+ * points per axis on the overlap box (exact: degree <= 2p per axis). */
+void orc_project_overlap(const orc_forest *f, const double *src, long src_stride,
+                         const long *src_lo, long src_size, const long *dst_lo, long dst_size,
+                         const long *olo, const long *ohi, double *acc)
+{
+    int q = f->p + 1;
+    double gx[8], gw[8];
+    orc_gauss_legendre(q, gx, gw);
+    double xi[512][3], w[512];
+    int nq = tensor_points(f->dim, q, gx, gw, xi, w);
+    double frac = 1.0; /* |overlap| / |dst| */
+    for (int a = 0; a < f->dim; ++a) frac *= (double)(ohi[a] - olo[a]) / (double)dst_size;
+    for (int iq = 0; iq < nq; ++iq) {
+        double xs[3] = {0, 0, 0}, xd[3] = {0, 0, 0};
+        for (int a = 0; a < f->dim; ++a) {
+            double x = olo[a] + 0.5 * (xi[iq][a] + 1.0) * (double)(ohi[a] - olo[a]);
+            xs[a] = 2.0 * (x - src_lo[a]) / (double)src_size - 1.0;
+            xd[a] = 2.0 * (x - dst_lo[a]) / (double)dst_size - 1.0;
+        }
+        double u[5];
+        eval_poly(f, src, (long)f->nb * src_stride, src_stride, xs, u);
+        for (int l = 0; l < f->nb; ++l) {
+            double ph = orc_phi(f->dim, f->exps + 3 * l, xd);
+            double c = frac * w[iq] * ph / orc_ref_mass(f->dim, f->exps + 3 * l);
+            for (int v = 0; v < f->nv; ++v) acc[v * f->nb + l] += c * u[v];
+        }
+    }
+}
+
+/* ---------------------------------------------------------------- initial conditions */
+
+static void prim_to_cons(int dim, double gamma, double rho, const double *vel, double p, double *u)
+{
+    double ke = 0.0;
+    u[0] = rho;
+    for (int a = 0; a < dim; ++a) {
+        u[1 + a] = rho * vel[a];
+        ke += vel[a] * vel[a];
+    }
+    u[dim + 1] = p / (gamma - 1.0) + 0.5 * rho * ke;
+}
+
+static double wrap_half(double d, double period)
+{
+    if (period <= 0.0) return d;
+    while (d >= 0.5 * period) d -= period;
+    while (d < -0.5 * period) d += period;
+    return d;
+}
+
+/* Analytic states used as initial conditions and exact solutions.
+ *  VORTEX  params: eps, xc, yc, u_inf, v_inf, period_x, period_y
+ *          isentropic vortex with mean (rho,u,v,p) = (1,u_inf,v_inf,1),
+ *          translated by (u_inf,v_inf) t; 3-D: extruded along z, w = 0.
+ *  SEDOV   params: p_ambient, p_centre, cx, cy, cz
+ *          rho = 1, u = 0; p = p_centre inside the 2^d cells of the finest
+ *          level that share the centre vertex, p_ambient elsewhere.
+ *  UNIFORM params: rho, u, v, w, p
+ *  XWAVE   params: amplitude, u, period_x
+ *          rho = 1 + A sin(2 pi (x - u t)/Lx), velocity (u,0,0), p = 1:
+ *          an exact entropy wave. */
+static void analytic_state(const orc_forest *f, int kind, const double *prm, double t,
+                           const double *x, double *u)
+{
+    const double pi = 3.14159265358979323846;
+    double g = f->gamma;
+    double vel[3] = {0, 0, 0};
+    if (kind == ORC_IC_VORTEX) {
+        double eps = prm[0];
+        double dx = wrap_half(x[0] - prm[1] - prm[3] * t, prm[5]);
+        double dy = wrap_half(x[1] - prm[2] - prm[4] * t, prm[6]);
+        double r2 = dx * dx + dy * dy;
+        double e1 = exp(0.5 * (1.0 - r2));
+        vel[0] = prm[3] - eps / (2.0 * pi) * e1 * dy;
+        vel[1] = prm[4] + eps / (2.0 * pi) * e1 * dx;
+        double T = 1.0 - (g - 1.0) * eps * eps / (8.0 * g * pi * pi) * exp(1.0 - r2);
+        double rho = pow(T, 1.0 / (g - 1.0));
+        double p = pow(rho, g);
+        prim_to_cons(f->dim, g, rho, vel, p, u);
+    } else if (kind == ORC_IC_SEDOV) {
+        int inside = 1;
+        for (int a = 0; a < f->dim; ++a) {
+            double hmin = unit_len(f, a); /* one global unit = finest cell edge */
+            if (fabs(x[a] - prm[2 + a]) >= hmin) inside = 0;
+        }
+        prim_to_cons(f->dim, g, 1.0, vel, inside ? prm[1] : prm[0], u);
+    } else if (kind == ORC_IC_UNIFORM) {
+        for (int a = 0; a < f->dim; ++a) vel[a] = prm[1 + a];
+        prim_to_cons(f->dim, g, prm[0], vel, prm[4], u);
+    } else { /* XWAVE */
+        double rho = 1.0 + prm[0] * sin(2.0 * pi * (x[0] - prm[1] * t) / prm[2]);
+        vel[0] = prm[1];
+        prim_to_cons(f->dim, g, rho, vel, 1.0, u);
+    }
+}
+
+/* physical coordinates of reference point xi in cell c of leaf i */
+static void cell_point(const orc_forest *f, int i, int c, const double *xi, double *x)
+{
+    long lo[3], size;
+    orc_leaf_box(f, &f->leaf[i], lo, &size);
+    long h = size / f->N;
+    int ijk[3];
+    orc_cell_ijk(f, c, ijk);
+    for (int a = 0; a < 3; ++a) x[a] = 0.0;
+    for (int a = 0; a < f->dim; ++a) {
+        double gl = lo[a] + ijk[a] * h + 0.5 * (xi[a] + 1.0) * h;
+        x[a] = f->lo[a] + gl * unit_len(f, a);
+    }
+}
+
+/* L2 projection of an analytic state with p+3 Gauss points per axis:
+ * K_l = (1/M_l) int phi_l U0 dV. */
+void orc_project_ic(const orc_forest *f, int kind, const double *params, double t, double *u)
+{
+    int q = f->p + 3, nc = orc_ncell(f);
+    double gx[8], gw[8];
+    orc_gauss_legendre(q, gx, gw);
+    double (*xi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *w = malloc(sizeof(double) * 512);
+    int nq = tensor_points(f->dim, q, gx, gw, xi, w);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < f->nleaves; ++i)
+        for (int c = 0; c < nc; ++c) {
+            double acc[5 * 20];
+            memset(acc, 0, sizeof(acc));
+            for (int iq = 0; iq < nq; ++iq) {
+                double x[3], s[5];
+                cell_point(f, i, c, xi[iq], x);
+                analytic_state(f, kind, params, t, x, s);
+                for (int l = 0; l < f->nb; ++l) {
+                    double ph = orc_phi(f->dim, f->exps + 3 * l, xi[iq]);
+                    for (int v = 0; v < f->nv; ++v) acc[v * f->nb + l] += w[iq] * ph * s[v];
+                }
+            }
+            /* |J| cancels between the mass matrix and the quadrature */
+            for (int v = 0; v < f->nv; ++v)
+                for (int l = 0; l < f->nb; ++l)
+                    u[sidx(f, i, v, l, c)] = acc[v * f->nb + l] / orc_ref_mass(f->dim, f->exps + 3 * l);
+        }
+    free(xi);
+    free(w);
+}
+
+/* ---------------------------------------------------------------- guard fill */
+
+/* index of the own cell at face (axis, side) and tangential index t */
+static int face_cell(const orc_forest *f, int axis, int side, int t)
+{
+    int ijk[3] = {0, 0, 0}, n = 0;
+    ijk[axis] = side > 0 ? f->N - 1 : 0;
+    for (int b = 0; b < f->dim; ++b) {
+        if (b == axis) continue;
+        ijk[b] = (n == 0) ? t % f->N : t / f->N;
+        ++n;
+    }
+    return orc_cell_index(f, ijk);
+}
+
+/* Sec. 3.5: each guard cell receives, from the stage input that is never
+ * modified during the stage, the copy of the same-level neighbour cell
+ * (Eq. 15), the split of the coarser neighbour cell (Eq. 16) or the combine
+ * of the finer neighbour cells (Eq. 17), all with the identity rotation.
+ * Outflow domain faces (Sec. 5.3.1) take the mirror image of the own cell,
+ * K_m (-1)^{m_axis}, so that both face traces coincide. */
+void orc_fill_guards(const orc_forest *f, const double *u, double *g)
+{
+    int nf = 2 * f->dim, nfc = orc_nface_cells(f), nc = orc_ncell(f);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < f->nleaves; ++i)
+        for (int face = 0; face < nf; ++face) {
+            int axis = face / 2, side = (face % 2) ? 1 : -1;
+            for (int t = 0; t < nfc; ++t) {
+                const orc_guard_plan *gp = &f->gp[((long)i * nf + face) * nfc + t];
+                if (gp->kind == 2) {
+                    int c = face_cell(f, axis, side, t);
+                    for (int v = 0; v < f->nv; ++v)
+                        for (int m = 0; m < f->nb; ++m) {
+                            double sgn = (f->exps[3 * m + axis] % 2) ? -1.0 : 1.0;
+                            g[gidx(f, i, face, v, m, t)] = sgn * u[sidx(f, i, v, m, c)];
+                        }
+                } else if (gp->kind == 0) {
+                    const orc_piece *pc = &gp->piece[0];
+                    for (int v = 0; v < f->nv; ++v)
+                        for (int m = 0; m < f->nb; ++m)
+                            g[gidx(f, i, face, v, m, t)] = u[sidx(f, pc->leaf, v, m, pc->cell)];
+                } else {
+                    /* the guard cell box in the same (unwrapped) frame */
+                    long lo[3], size;
+                    orc_leaf_box(f, &f->leaf[i], lo, &size);
+                    long h = size / f->N;
+                    int c = face_cell(f, axis, side, t);
+                    int ijk[3];
+                    orc_cell_ijk(f, c, ijk);
+                    long glo[3] = {0, 0, 0};
+                    for (int a = 0; a < f->dim; ++a) glo[a] = lo[a] + ijk[a] * h;
+                    glo[axis] += side * h;
+                    double acc[5 * 20];
+                    memset(acc, 0, sizeof(acc));
+                    for (int k = 0; k < gp->npiece; ++k) {
+                        const orc_piece *pc = &gp->piece[k];
+                        orc_project_overlap(f, u + sidx(f, pc->leaf, 0, 0, pc->cell), nc, pc->src_lo,
+                                            pc->src_size, glo, h, pc->lo, pc->hi, acc);
+                    }
+                    for (int v = 0; v < f->nv; ++v)
+                        for (int m = 0; m < f->nb; ++m) g[gidx(f, i, face, v, m, t)] = acc[v * f->nb + m];
+                }
+            }
+        }
+}
+
+/* ---------------------------------------------------------------- residual */
+
+/* R = M^{-1} [ int_cell F . grad(phi) dV - int_{boundary} Fhat phi dS ]
+ * (Eq. 3-4, source G = 0) for every cell of every leaf.  The neighbour
+ * state across a face is the adjacent cell inside the block, or the guard
+ * cell at the block boundary (Sec. 3.3).  With the conservative hanging
+ * mode, a coarse cell facing finer neighbours integrates instead over the
+ * fine sub-faces, using the fine cells' own traces (mortar). */
+void orc_residual(const orc_forest *f, const double *u, const double *g, double *r)
+{
+    int d = f->dim, nf = 2 * d, nfc = orc_nface_cells(f), nc = orc_ncell(f), q = f->q;
+    double gx[8], gw[8];
+    orc_gauss_legendre(q, gx, gw);
+    double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *vw = malloc(sizeof(double) * 512);
+    int nq = tensor_points(d, q, gx, gw, vxi, vw);
+    double (*fxi)[3] = malloc(sizeof(double) * 3 * 64);
+    double *fw = malloc(sizeof(double) * 64);
+    int nfq = tensor_points(d - 1, q, gx, gw, fxi, fw);
+    /* basis values at the volume points and at the face points seen from
+     * both sides of every face */
+    int nb = f->nb;
+    double *vphi = malloc(sizeof(double) * nq * nb);
+    double *vdphi = malloc(sizeof(double) * nq * d * nb);
+    double *fown = malloc(sizeof(double) * nf * nfq * nb);
+    double *fnbr = malloc(sizeof(double) * nf * nfq * nb);
+    for (int iq = 0; iq < nq; ++iq)
+        for (int m = 0; m < nb; ++m) {
+            vphi[iq * nb + m] = orc_phi(d, f->exps + 3 * m, vxi[iq]);
+            for (int a = 0; a < d; ++a) vdphi[(iq * d + a) * nb + m] = orc_dphi(d, f->exps + 3 * m, vxi[iq], a);
+        }
+    for (int face = 0; face < nf; ++face) {
+        int axis = face / 2, side = (face % 2) ? 1 : -1;
+        for (int iq = 0; iq < nfq; ++iq) {
+            double xo[3] = {0, 0, 0}, xn[3] = {0, 0, 0};
+            int n = 0;
+            for (int b = 0; b < d; ++b) {
+                if (b == axis) continue;
+                xo[b] = xn[b] = fxi[iq][n++];
+            }
+            xo[axis] = side;
+            xn[axis] = -side;
+            for (int m = 0; m < nb; ++m) {
+                fown[(face * nfq + iq) * nb + m] = orc_phi(d, f->exps + 3 * m, xo);
+                fnbr[(face * nfq + iq) * nb + m] = orc_phi(d, f->exps + 3 * m, xn);
+            }
+        }
+    }
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < f->nleaves; ++i) {
+        long lo[3], size;
+        orc_leaf_box(f, &f->leaf[i], lo, &size);
+        long hu = size / f->N;
+        double h[3] = {1, 1, 1};
+        for (int a = 0; a < d; ++a) h[a] = hu * unit_len(f, a);
+        double J = 1.0;
+        for (int a = 0; a < d; ++a) J *= 0.5 * h[a];
+        for (int c = 0; c < nc; ++c) {
+            int ijk[3];
+            orc_cell_ijk(f, c, ijk);
+            const double *K = u + sidx(f, i, 0, 0, c);
+            double acc[5 * 20];
+            memset(acc, 0, sizeof(acc));
+            /* volume integral */
+            for (int iq = 0; iq < nq; ++iq) {
+                double uq[5];
+                eval_with(f, K, (long)f->nb * nc, nc, vphi + iq * nb, uq);
+                for (int a = 0; a < d; ++a) {
+                    double fl[5];
+                    orc_euler_flux(d, f->gamma, uq, a, fl);
+                    for (int m = 0; m < f->nb; ++m) {
+                        double dp = vdphi[(iq * d + a) * nb + m] * 2.0 / h[a];
+                        for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] += vw[iq] * J * fl[v] * dp;
+                    }
+                }
+            }
+            /* surface integrals */
+            for (int face = 0; face < nf; ++face) {
+                int axis = face / 2, side = (face % 2) ? 1 : -1;
+                double Jf = 1.0;
+                for (int b = 0; b < d; ++b)
+                    if (b != axis) Jf *= 0.5 * h[b];
+                int nijk[3] = {ijk[0], ijk[1], ijk[2]};
+                nijk[axis] += side;
+                int interior = nijk[axis] >= 0 && nijk[axis] < f->N;
+                const orc_face_nbr *fn = &f->fn[i * nf + face];
+                /* tangential index of this cell on the block face */
+                int t = 0, mul = 1;
+                for (int b = 0; b < d; ++b) {
+                    if (b == axis) continue;
+                    t += ijk[b] * mul;
+                    mul *= f->N;
+                }
+                if (!interior && !fn->boundary && fn->level_diff == 1 && f->hanging == ORC_HANG_CONSERVATIVE) {
+                    /* mortar over the fine cells that touch this face */
+                    const orc_guard_plan *gp = &f->gp[((long)i * nf + face) * nfc + t];
+                    long plane = (side > 0) ? lo[axis] + (ijk[axis] + 1) * hu : lo[axis] + ijk[axis] * hu;
+                    long clo[3] = {0, 0, 0};
+                    for (int a = 0; a < d; ++a) clo[a] = lo[a] + ijk[a] * hu;
+                    for (int k = 0; k < gp->npiece; ++k) {
+                        const orc_piece *pc = &gp->piece[k];
+                        long touch = (side > 0) ? pc->src_lo[axis] : pc->src_lo[axis] + pc->src_size;
+                        if (touch != plane) continue;
+                        double Jff = 1.0;
+                        for (int b = 0; b < d; ++b)
+                            if (b != axis) Jff *= 0.5 * pc->src_size * unit_len(f, b);
+                        const double *Kf = u + sidx(f, pc->leaf, 0, 0, pc->cell);
+                        for (int iq = 0; iq < nfq; ++iq) {
+                            double xo[3] = {0, 0, 0}, xf[3] = {0, 0, 0};
+                            int n = 0;
+                            for (int b = 0; b < d; ++b) {
+                                if (b == axis) continue;
+                                double gxp = pc->src_lo[b] + 0.5 * (fxi[iq][n] + 1.0) * pc->src_size;
+                                xf[b] = fxi[iq][n];
+                                xo[b] = 2.0 * (gxp - clo[b]) / (double)hu - 1.0;
+                                ++n;
+                            }
+                            xo[axis] = side;
+                            xf[axis] = -side;
+                            double um[5], up[5], fh[5];
+                            eval_poly(f, K, (long)f->nb * nc, nc, xo, um);
+                            eval_poly(f, Kf, (long)f->nb * nc, nc, xf, up);
+                            orc_rusanov(d, f->gamma, um, up, axis, side, fh);
+                            for (int m = 0; m < f->nb; ++m) {
+                                double ph = orc_phi(d, f->exps + 3 * m, xo);
+                                for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] -= fw[iq] * Jff * fh[v] * ph;
+                            }
+                        }
+                    }
+                    continue;
+                }
+                const double *Kn;
+                long nsv, nsm;
+                if (interior) {
+                    Kn = u + sidx(f, i, 0, 0, orc_cell_index(f, nijk));
+                    nsv = (long)f->nb * nc;
+                    nsm = nc;
+                } else {
+                    Kn = g + gidx(f, i, face, 0, 0, t);
+                    nsv = (long)f->nb * nfc;
+                    nsm = nfc;
+                }
+                for (int iq = 0; iq < nfq; ++iq) {
+                    const double *po = fown + (face * nfq + iq) * nb;
+                    double um[5], up[5], fh[5];
+                    eval_with(f, K, (long)f->nb * nc, nc, po, um);
+                    eval_with(f, Kn, nsv, nsm, fnbr + (face * nfq + iq) * nb, up);
+                    orc_rusanov(d, f->gamma, um, up, axis, side, fh);
+                    for (int m = 0; m < f->nb; ++m) {
+                        double ph = po[m];
+                        for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] -= fw[iq] * Jf * fh[v] * ph;
+                    }
+                }
+            }
+            for (int v = 0; v < f->nv; ++v)
+                for (int m = 0; m < f->nb; ++m)
+                    r[sidx(f, i, v, m, c)] = acc[v * f->nb + m] / (J * orc_ref_mass(d, f->exps + 3 * m));
+        }
+    }
+    free(vxi);
+    free(vw);
+    free(fxi);
+    free(fw);
+    free(vphi);
+    free(vdphi);
+    free(fown);
+    free(fnbr);
+}
+
+/* ---------------------------------------------------------------- time stepping */
+
+/* Shu-Osher SSP-RK3 (Sec. 2, third order per Sec. 5.1):
+ *   U1   = Un + dt R(Un)
+ *   U2   = 3/4 Un + 1/4 (U1 + dt R(U1))
+ *   Un+1 = 1/3 Un + 2/3 (U2 + dt R(U2))
+ * stage s computes a_s Un + b_s (Us + dt R(Us)). */
+void orc_rk_combine(long n, int stage, double dt, const double *un, const double *us,
+                    const double *r, double *unext)
+{
+    double a = (stage == 0) ? 0.0 : (stage == 1 ? 0.75 : 1.0 / 3.0);
+    double b = (stage == 0) ? 1.0 : (stage == 1 ? 0.25 : 2.0 / 3.0);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < n; ++k) unext[k] = a * un[k] + b * (us[k] + dt * r[k]);
+}
+
+/* Largest sum over axes of (|mean u_a| + mean c) / h_a over all cells,
+ * from the cell means (mode 0). */
+double orc_max_rate(const orc_forest *f, const double *u)
+{
+    int d = f->dim, nc = orc_ncell(f);
+    double mx = 0.0;
+    for (int i = 0; i < f->nleaves; ++i) {
+        long lo[3], size;
+        orc_leaf_box(f, &f->leaf[i], lo, &size);
+        for (int c = 0; c < nc; ++c) {
+            double s[5];
+            for (int v = 0; v < f->nv; ++v) s[v] = u[sidx(f, i, v, 0, c)];
+            double cs = sqrt(f->gamma * orc_pressure(d, f->gamma, s) / s[0]);
+            double rate = 0.0;
+            for (int a = 0; a < d; ++a) rate += (fabs(s[1 + a] / s[0]) + cs) / ((size / f->N) * unit_len(f, a));
+            if (rate > mx) mx = rate;
+        }
+    }
+    return mx;
+}
+
+/* Sec. 4.3 step 2(a): critical time increment over all blocks,
+ * dt = CFL / max_cells sum_a (|u_a| + c) / h_a. */
+double orc_dt(const orc_forest *f, const double *u, double cfl) { return cfl / orc_max_rate(f, u); }
+
+/* T_v = sum over cells of |cell| * mean_v, leaf by leaf, cell by cell. */
+void orc_totals(const orc_forest *f, const double *u, double *totals)
+{
+    int nc = orc_ncell(f);
+    for (int v = 0; v < f->nv; ++v) totals[v] = 0.0;
+    for (int i = 0; i < f->nleaves; ++i) {
+        long lo[3], size;
+        orc_leaf_box(f, &f->leaf[i], lo, &size);
+        double vol = 1.0;
+        for (int a = 0; a < f->dim; ++a) vol *= (size / f->N) * unit_len(f, a);
+        for (int c = 0; c < nc; ++c)
+            for (int v = 0; v < f->nv; ++v) totals[v] += vol * u[sidx(f, i, v, 0, c)];
+    }
+}
+
+/* Positivity-preserving scaling limiter of Zhang and Shu (the paper's
+ * references for the positivity limiter), written from the published
+ * method.  For each cell, with eps = min(1e-13, mean rho, p(mean)) and the
+ * point set S = volume Gauss points and face Gauss points of all faces:
+ *   1. theta1 = min(1, (rho_mean - eps)/(rho_mean - min_S rho)); the
+ *      non-mean density modes are scaled by theta1;
+ *   2. for every point of S with p < eps, t solves p(Ubar + t(U - Ubar)) = eps
+ *      (the root in [0,1) of a quadratic after multiplying by rho);
+ *      theta2 = min t (1 where p >= eps); all non-mean modes are scaled by
+ *      theta2.  Cell means are unchanged. */
+void orc_limit_positivity(const orc_forest *f, double *u)
+{
+    int d = f->dim, nc = orc_ncell(f), q = f->q, nv = f->nv;
+    double gx[8], gw[8];
+    orc_gauss_legendre(q, gx, gw);
+    double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *vw = malloc(sizeof(double) * 512);
+    int nq = tensor_points(d, q, gx, gw, vxi, vw);
+    double (*fxi)[3] = malloc(sizeof(double) * 3 * 64);
+    double *fw = malloc(sizeof(double) * 64);
+    int nfq = tensor_points(d - 1, q, gx, gw, fxi, fw);
+    int npts = nq + 2 * d * nfq;
+    double (*pts)[3] = malloc(sizeof(double) * 3 * npts);
+    for (int k = 0; k < nq; ++k) memcpy(pts[k], vxi[k], sizeof(double) * 3);
+    int np = nq;
+    for (int face = 0; face < 2 * d; ++face) {
+        int axis = face / 2, side = (face % 2) ? 1 : -1;
+        for (int k = 0; k < nfq; ++k) {
+            int n = 0;
+            pts[np][0] = pts[np][1] = pts[np][2] = 0.0;
+            for (int b = 0; b < d; ++b)
+                pts[np][b] = (b == axis) ? side : fxi[k][n++];
+            ++np;
+        }
+    }
+    double g = f->gamma;
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < f->nleaves; ++i)
+        for (int c = 0; c < nc; ++c) {
+            double *K = u + sidx(f, i, 0, 0, c);
+            long sv = (long)f->nb * nc, sm = nc;
+            double mean[5];
+            for (int v = 0; v < nv; ++v) mean[v] = K[v * sv];
+            double pbar = orc_pressure(d, g, mean);
+            double eps = 1e-13;
+            if (mean[0] < eps) eps = mean[0];
+            if (pbar < eps) eps = pbar;
+            /* density */
+            double rmin = mean[0];
+            for (int k = 0; k < npts; ++k) {
+                double uq[5];
+                eval_poly(f, K, sv, sm, pts[k], uq);
+                if (uq[0] < rmin) rmin = uq[0];
+            }
+            double th1 = 1.0;
+            if (rmin < mean[0]) {
+                th1 = (mean[0] - eps) / (mean[0] - rmin);
+                if (th1 > 1.0) th1 = 1.0;
+            }
+            if (th1 < 1.0)
+                for (int m = 1; m < f->nb; ++m) K[m * sm] *= th1;
+            /* pressure */
+            double th2 = 1.0;
+            for (int k = 0; k < npts; ++k) {
+                double uq[5];
+                eval_poly(f, K, sv, sm, pts[k], uq);
+                if (orc_pressure(d, g, uq) >= eps) continue;
+                double dr = uq[0] - mean[0], dE = uq[d + 1] - mean[d + 1];
+                double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
+                for (int a = 0; a < d; ++a) {
+                    double dm = uq[1 + a] - mean[1 + a];
+                    dm2 += dm * dm;
+                    mdm += mean[1 + a] * dm;
+                    m2 += mean[1 + a] * mean[1 + a];
+                }
+                double A = dr * dE - 0.5 * dm2;
+                double B = mean[0] * dE + mean[d + 1] * dr - mdm - eps * dr / (g - 1.0);
+                double C = mean[0] * mean[d + 1] - 0.5 * m2 - eps * mean[0] / (g - 1.0);
+                double t = 0.0;
+                if (C > 0.0) {
+                    double disc = B * B - 4.0 * A * C;
+                    if (disc < 0.0) disc = 0.0;
+                    double den = -B + sqrt(disc);
+                    t = (den > 0.0) ? 2.0 * C / den : 0.0;
+                    if (t > 1.0) t = 1.0;
+                    if (t < 0.0) t = 0.0;
+                }
+                if (t < th2) th2 = t;
+            }
+            if (th2 < 1.0)
+                for (int v = 0; v < nv; ++v)
+                    for (int m = 1; m < f->nb; ++m) K[v * sv + m * sm] *= th2;
+        }
+    free(vxi);
+    free(vw);
+    free(fxi);
+    free(fw);
+    free(pts);
+}
+
+/* Block indicator: ratio of the largest to the smallest density cell mean
+ * over the block's cells and its face guard cells. */
+void orc_indicator(const orc_forest *f, const double *u, double *eta)
+{
+    int nc = orc_ncell(f), nfc = orc_nface_cells(f);
+    double *g = malloc(sizeof(double) * orc_guard_len(f));
+    orc_fill_guards(f, u, g);
+    for (int i = 0; i < f->nleaves; ++i) {
+        double mx = -1e300, mn = 1e300;
+        for (int c = 0; c < nc; ++c) {
+            double r = u[sidx(f, i, 0, 0, c)];
+            if (r > mx) mx = r;
+            if (r < mn) mn = r;
+        }
+        for (int face = 0; face < 2 * f->dim; ++face)
+            for (int t = 0; t < nfc; ++t) {
+                double r = g[gidx(f, i, face, 0, 0, t)];
+                if (r > mx) mx = r;
+                if (r < mn) mn = r;
+            }
+        eta[i] = mx / mn;
+    }
+    free(g);
+}
+
+double orc_step(const orc_forest *f, double cfl, double dt_fixed, int limiter, double *u)
+{
+    long n = orc_state_len(f);
+    double dt = dt_fixed > 0.0 ? dt_fixed : orc_dt(f, u, cfl);
+    double *un = malloc(sizeof(double) * n);
+    double *us = malloc(sizeof(double) * n);
+    double *r = malloc(sizeof(double) * n);
+    double *g = malloc(sizeof(double) * orc_guard_len(f));
+    memcpy(un, u, sizeof(double) * n);
+    memcpy(us, u, sizeof(double) * n);
+    for (int s = 0; s < 3; ++s) {
+        orc_fill_guards(f, us, g);
+        orc_residual(f, us, g, r);
+        orc_rk_combine(n, s, dt, un, us, r, u);
+        if (limiter) orc_limit_positivity(f, u);
+        memcpy(us, u, sizeof(double) * n);
+    }
+    free(un);
+    free(us);
+    free(r);
+    free(g);
+    return dt;
+}
+
+void orc_errors(const orc_forest *f, const double *u, int kind, const double *params, double t,
+                double *l1, double *l2)
+{
+    int q = f->p + 3, nc = orc_ncell(f);
+    double gx[8], gw[8];
+    orc_gauss_legendre(q, gx, gw);
+    double (*xi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *w = malloc(sizeof(double) * 512);
+    int nq = tensor_points(f->dim, q, gx, gw, xi, w);
+    for (int v = 0; v < f->nv; ++v) l1[v] = l2[v] = 0.0;
+    for (int i = 0; i < f->nleaves; ++i) {
+        long lo[3], size;
+        orc_leaf_box(f, &f->leaf[i], lo, &size);
+        double J = 1.0;
+        for (int a = 0; a < f->dim; ++a) J *= 0.5 * (size / f->N) * unit_len(f, a);
+        for (int c = 0; c < nc; ++c)
+            for (int iq = 0; iq < nq; ++iq) {
+                double x[3], ex[5], uh[5];
+                cell_point(f, i, c, xi[iq], x);
+                analytic_state(f, kind, params, t, x, ex);
+                eval_poly(f, u + sidx(f, i, 0, 0, c), (long)f->nb * nc, nc, xi[iq], uh);
+                for (int v = 0; v < f->nv; ++v) {
+                    double e = uh[v] - ex[v];
+                    l1[v] += w[iq] * J * fabs(e);
+                    l2[v] += w[iq] * J * e * e;
+                }
+            }
+    }
+    for (int v = 0; v < f->nv; ++v) l2[v] = sqrt(l2[v]);
+    free(xi);
+    free(w);
+}
