@@ -1,0 +1,170 @@
+/*
+ * dgamr - block-based AMR explicit discontinuous Galerkin residual for the
+ * compressible Euler equations on one MI355X (gfx950) GPU.
+ *
+ * Method: Liu et al., "An unstructured block-based adaptive mesh refinement
+ * approach for explicit discontinuous Galerkin method".  A forest of
+ * equal-size quad/hex blocks (Sec. 3.1), N^d cells per block with one layer
+ * of guard cells (Sec. 3.3), guard cells filled by copy / split / combine
+ * (Sec. 3.5, Eq. 15-17, operators of Sec. 3.4, Eq. 11-14), the Galerkin weak
+ * form M dK/dt = R (Sec. 2, Eq. 3-4) with the Lax-Friedrichs (Rusanov)
+ * numerical flux (Eq. 5) and SSP Runge-Kutta time marching (Sec. 2), all per
+ * the procedure of Sec. 4.3.
+ *
+ * Conventions
+ *  - Every call returns 0 (DGAMR_OK) or a negative DGAMR_E* code; the text
+ *    of the last error of the calling thread is dgamr_last_error().  No C++
+ *    exception crosses this interface.
+ *  - Ownership: the library owns the forest topology, the neighbour and
+ *    guard-fill tables and the basis tables (host and device copies).  The
+ *    caller owns every state, guard, residual and work buffer: device memory
+ *    passed as plain pointers, sized by dgamr_state_bytes().  Device calls
+ *    are asynchronous on the caller's stream; host calls are synchronous.
+ *    A forest handle must not be used by two threads at once.
+ *  - Layouts (all FP64 unless stated):
+ *      state    U[leaf][var][mode][cell]      cell = i + N*(j + N*k), x fastest
+ *      guard    G[leaf][face][var][mode][t]   face = 2*axis + (side > 0);
+ *               t indexes the N^(d-1) cells of the face, the lower of the
+ *               remaining axes fastest
+ *      residual R like U, FP64; FP32 when the forest precision is
+ *               DGAMR_FP32_MFMA
+ *      vars     (rho, rho u, rho v[, rho w], E), E = total energy per volume
+ *      modes    total-degree Legendre products P_mx P_my [P_mz], |m| <= p,
+ *               graded by |m|; inside one degree m_x descending, then m_y
+ *               descending.  Mode 0 is the cell mean.
+ *      leaves   trees row-major (x fastest), then Morton order inside a
+ *               tree; key = (tree, level, i, j, k), roots at level 1.
+ */
+#ifndef DGAMR_H
+#define DGAMR_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    DGAMR_OK = 0,
+    DGAMR_EINVAL = -1,       /* bad argument or descriptor */
+    DGAMR_EUNSUPPORTED = -2, /* valid but not built (e.g. degree or size limits) */
+    DGAMR_EBALANCE = -3,     /* topology violates 2:1 face balance */
+    DGAMR_EHIP = -4,         /* a HIP runtime call failed */
+    DGAMR_ENONPHYSICAL = -5, /* non-finite or non-positive density/pressure found */
+    DGAMR_ESTATE = -6        /* call out of order (e.g. apply before set) */
+};
+
+enum { DGAMR_BC_PERIODIC = 0, DGAMR_BC_OUTFLOW = 1 };
+enum { DGAMR_FP64 = 0, DGAMR_FP32_MFMA = 1 };
+enum { DGAMR_HANG_PAPER = 0, DGAMR_HANG_CONSERVATIVE = 1 };
+enum { DGAMR_LIMITER_NONE = 0, DGAMR_LIMITER_POSITIVITY = 1 };
+enum { DGAMR_IC_VORTEX = 0, DGAMR_IC_SEDOV = 1, DGAMR_IC_UNIFORM = 2, DGAMR_IC_XWAVE = 3 };
+
+typedef struct {
+    int dim;          /* 2 or 3 */
+    int degree;       /* polynomial degree p, 0..3 */
+    int n_cell;       /* N cells per block side: even, 2..16 (2-D) or 2..8 (3-D) */
+    int roots[3];     /* root blocks per axis (unused axes: 1) */
+    double lo[3];     /* domain box */
+    double hi[3];
+    int bc[3];        /* DGAMR_BC_* per axis */
+    int max_level;    /* >= 1; roots are level 1 */
+    double gamma;     /* ideal-gas ratio (Eq. 23) */
+    int precision;    /* DGAMR_FP64 or DGAMR_FP32_MFMA (residual contractions) */
+    int hanging;      /* DGAMR_HANG_PAPER (guard-cell fluxes, Sec. 3.5) or
+                         DGAMR_HANG_CONSERVATIVE (coarse side lifts the fine-side flux) */
+    int limiter;      /* DGAMR_LIMITER_* applied after each stage by dgamr_step */
+} dgamr_forest_desc;
+
+typedef struct dgamr_forest dgamr_forest;
+
+/* Sec. 3.1: a forest of root blocks at level 1 with periodic or outflow
+ * links (Sec. 5.1, 5.3.1).  Builds the host topology, the device neighbour
+ * tables and uploads them to the current device.  EINVAL on a bad
+ * descriptor, EUNSUPPORTED outside the built limits. */
+int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out);
+int dgamr_destroy_forest(dgamr_forest *f);
+
+/* Host queries.  keys: n_leaves x 5 int32 (tree, level, i, j, k). */
+int dgamr_num_leaves(const dgamr_forest *f, int64_t *n);
+int dgamr_leaf_keys(const dgamr_forest *f, int32_t *keys);
+/* Bytes of one state array, of the guard buffer, of the residual buffer and
+ * of the work buffer dgamr_step and the reductions need. */
+int dgamr_state_bytes(const dgamr_forest *f, size_t *u_bytes, size_t *guard_bytes,
+                      size_t *residual_bytes, size_t *work_bytes);
+
+/* Sec. 4.3 step 3, Sec. 3.1, Sec. 3.4: plan refinement from host flags
+ * (n_leaves int8: +1 refine, -1 coarsen, 0 keep).  Rules: flags count
+ * only inside [1, max_level]; refinement is closed under 2:1 face balance
+ * (refinement wins); a family of 2^d sibling leaves coarsens only if all
+ * are flagged -1, none refines, and no outside face neighbour ends finer
+ * than the family.  Writes the new leaf count.  Host only; the forest is
+ * unchanged until dgamr_apply_refinement. */
+int dgamr_set_refinement(dgamr_forest *f, const int8_t *flags, int64_t *n_new);
+/* Eq. 11-14: switch to the planned forest and write u_new (new layout,
+ * caller-allocated) from u_old (old layout) by L2 inheritance: refined
+ * children get the split of their parent cells, coarsened parents the
+ * combine of their children, other leaves are copied.  Synchronises the
+ * stream.  ESTATE if no plan is pending. */
+int dgamr_apply_refinement(dgamr_forest *f, const double *u_old, double *u_new, hipStream_t stream);
+
+/* Sec. 3.5, Eq. 15-17: fill every guard cell from the stage input u
+ * (read-only): copy (same level), split of the coarser neighbour cell,
+ * combine of the finer neighbour cells; outflow faces mirror the own cell. */
+int dgamr_fill_guardcells(dgamr_forest *f, const double *u, double *guard, hipStream_t stream);
+
+/* Sec. 2, Eq. 3-5: R = M^-1 [ volume flux integral - surface integral of the
+ * Rusanov flux ], neighbour traces from the block interior or the guard
+ * buffer.  r is FP64, or FP32 for DGAMR_FP32_MFMA forests. */
+int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, void *r,
+                      hipStream_t stream);
+
+/* Sec. 2 (SSP-RK3): u_next = a_s u_n + b_s (u_s + dt r), with
+ * (a,b) = (0,1), (3/4,1/4), (1/3,2/3) for stage 0,1,2.  dt is read from
+ * device memory.  u_next may alias u_s. */
+int dgamr_rk_stage(dgamr_forest *f, int stage, const double *dt_dev, const double *u_n,
+                   const double *u_s, const void *r, double *u_next, hipStream_t stream);
+
+/* Sec. 4.3 step 2(a): dt = cfl / max over cells of sum_a (|u_a| + c)/h_a
+ * from the cell means, written to device memory. */
+int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, void *work,
+                     hipStream_t stream);
+
+/* Sec. 4.3 step 2: one SSP-RK3 time step, in place on u: dt from the CFL
+ * condition (cfl > 0) or taken from dt_dev (cfl <= 0), then per stage the
+ * guard fill, the residual and the stage update (and the positivity limiter
+ * when the forest asks for it).  Asynchronous; captures into a HIP graph. */
+int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev,
+               hipStream_t stream);
+
+/* Conserved totals T_v = sum over cells |cell| * mean_v (FP64), written to
+ * totals_dev[n_var]; a fixed-order reduction. */
+int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev, void *work,
+                           hipStream_t stream);
+
+/* Positivity-preserving scaling limiter (Zhang-Shu, named in Sec. 5.3.2)
+ * applied in place. */
+int dgamr_limit_positivity(dgamr_forest *f, double *u, hipStream_t stream);
+
+/* Block indicator: max/min density cell mean over the block's cells and
+ * face-guard cells, per leaf (FP64, device). */
+int dgamr_indicator(dgamr_forest *f, const double *u, double *eta_dev, void *work,
+                    hipStream_t stream);
+
+/* L2 projection of an analytic state (DGAMR_IC_*, parameters as the test
+ * workloads define them) with p+3 Gauss points per axis. */
+int dgamr_project_ic(dgamr_forest *f, int kind, const double *params /* 8 */, double t,
+                     double *u, hipStream_t stream);
+
+/* Non-physical state check: sets *bad (host) to the number of cells with a
+ * non-finite value or a non-positive mean density or pressure.  Synchronous. */
+int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work, hipStream_t stream);
+
+const char *dgamr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

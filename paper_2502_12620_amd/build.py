@@ -1,0 +1,62 @@
+"""Build the HIP library libdgamr.so for gfx950 (in-tree, hipcc)."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libdgamr.so")
+OBJDIR = os.path.join(HERE, "_build")
+
+HIP_SOURCES = ["dgamr_api.hip"]
+CXX_SOURCES = ["forest.cpp"]
+# degree-templated kernels: one translation unit per (dim, degree)
+INSTANCES = [(d, p) for d in (2, 3) for p in (0, 1, 2, 3)]
+
+HIPFLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fconstexpr-steps=200000000",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unknown-pragmas",
+    "-I" + os.path.join(HERE, "..", "include"),
+]
+
+
+def _run(cmd):
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        sys.stderr.write(r.stdout + r.stderr)
+        raise RuntimeError("build failed: " + " ".join(cmd[:3]) + " ...")
+    return r.stderr
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = []
+    for s in HIP_SOURCES:
+        o = os.path.join(OBJDIR, s + ".o")
+        jobs.append(["hipcc", *HIPFLAGS, "-c", os.path.join(CSRC, s), "-o", o])
+    for d, p in INSTANCES:
+        o = os.path.join(OBJDIR, f"inst_{d}_{p}.o")
+        jobs.append(["hipcc", *HIPFLAGS, f"-DDG_D={d}", f"-DDG_P={p}", "-c", os.path.join(CSRC, "inst.hip"), "-o", o])
+    for s in CXX_SOURCES:
+        o = os.path.join(OBJDIR, s + ".o")
+        jobs.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
+                     "-I/opt/rocm/include", "-c", os.path.join(CSRC, s), "-o", o])
+    # longest first: the 3-D high-degree units dominate
+    jobs.sort(key=lambda j: ("DG_D=3" in " ".join(j), "DG_P=3" in " ".join(j)), reverse=True)
+    with ThreadPoolExecutor(max_workers=min(int(os.environ.get("MAX_JOBS", "8")), len(jobs))) as ex:
+        logs = list(ex.map(_run, jobs))
+    if verbose:
+        for l in logs:
+            sys.stderr.write(l)
+    objs = [j[-1] for j in jobs]
+    _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs])
+    os.replace(LIB + ".tmp", LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose=True))

@@ -1,0 +1,514 @@
+// C-ABI of the block-AMR DG library: forest handles, buffer sizes,
+// refinement, and the launches of the HIP kernels.  See include/dgamr.h.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "forest.hpp"
+#include "kernels_small.hpp"
+#include "launch.hpp"
+
+using dgamr::FaceLink;
+using dgamr::Forest;
+using dgamr::Inherit;
+using dgamr::LeafGeo;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg)
+{
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                          \
+    do {                                                                                       \
+        hipError_t e_ = (expr);                                                                \
+        if (e_ != hipSuccess) return fail(DGAMR_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
+    } while (0)
+
+} // namespace
+
+struct dgamr_forest {
+    Forest topo;
+    int device = 0;
+    LeafGeo *d_geo = nullptr;
+    FaceLink *d_links = nullptr;
+    int *d_hang = nullptr;   // (leaf*2d + face) of every coarse or fine link
+    int n_hang = 0;
+    int cap = 0;             // leaves the device tables can hold
+    int hang_cap = 0;
+    explicit dgamr_forest(const dgamr_forest_desc &d) : topo(d) {}
+};
+
+namespace {
+
+int ncell_of(const dgamr_forest *f)
+{
+    int n = f->topo.desc().n_cell;
+    return f->topo.dim() == 2 ? n * n : n * n * n;
+}
+int nfc_of(const dgamr_forest *f)
+{
+    int n = f->topo.desc().n_cell;
+    return f->topo.dim() == 2 ? n : n * n;
+}
+int nb_of(const dgamr_forest *f) { return dgk::num_modes(f->topo.dim(), f->topo.desc().degree); }
+int nv_of(const dgamr_forest *f) { return f->topo.dim() + 2; }
+size_t state_elems(const dgamr_forest *f) { return size_t(f->topo.n()) * nv_of(f) * nb_of(f) * ncell_of(f); }
+size_t guard_elems(const dgamr_forest *f)
+{
+    return size_t(f->topo.n()) * 2 * f->topo.dim() * nv_of(f) * nb_of(f) * nfc_of(f);
+}
+// work layout: [U1 | U2 | guard | residual | leaf maxima | leaf partials | scalars]
+struct Work {
+    double *u1, *u2, *guard, *res, *leafmax, *part, *scal;
+};
+Work carve(const dgamr_forest *f, void *work)
+{
+    Work w;
+    size_t s = state_elems(f), gsz = guard_elems(f), n = f->topo.n();
+    double *p = static_cast<double *>(work);
+    w.u1 = p;
+    w.u2 = w.u1 + s;
+    w.guard = w.u2 + s;
+    w.res = w.guard + gsz;
+    w.leafmax = w.res + s;
+    w.part = w.leafmax + n;
+    w.scal = w.part + n * 8;
+    return w;
+}
+size_t work_elems(const dgamr_forest *f)
+{
+    size_t s = state_elems(f), gsz = guard_elems(f), n = f->topo.n();
+    return 3 * s + gsz + n + n * 8 + 64;
+}
+
+int upload(dgamr_forest *f)
+{
+    int n = f->topo.n(), nf = 2 * f->topo.dim();
+    HIP_TRY(hipSetDevice(f->device));
+    if (n > f->cap) {
+        if (f->d_geo) HIP_TRY(hipFree(f->d_geo));
+        if (f->d_links) HIP_TRY(hipFree(f->d_links));
+        int cap = n + n / 2 + 16;
+        HIP_TRY(hipMalloc(&f->d_geo, sizeof(LeafGeo) * cap));
+        HIP_TRY(hipMalloc(&f->d_links, sizeof(FaceLink) * size_t(cap) * nf));
+        f->cap = cap;
+    }
+    std::vector<LeafGeo> geo = f->topo.geometry();
+    HIP_TRY(hipMemcpy(f->d_geo, geo.data(), sizeof(LeafGeo) * n, hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy(f->d_links, f->topo.links().data(), sizeof(FaceLink) * size_t(n) * nf, hipMemcpyHostToDevice));
+    std::vector<int> hang;
+    for (int i = 0; i < n * nf; ++i) {
+        int ty = f->topo.links()[i].type;
+        if (ty == dgamr::LINK_COARSE || ty == dgamr::LINK_FINE) hang.push_back(i);
+    }
+    f->n_hang = int(hang.size());
+    if (f->n_hang > f->hang_cap) {
+        if (f->d_hang) HIP_TRY(hipFree(f->d_hang));
+        f->hang_cap = f->n_hang + 64;
+        HIP_TRY(hipMalloc(&f->d_hang, sizeof(int) * f->hang_cap));
+    }
+    if (f->n_hang) HIP_TRY(hipMemcpy(f->d_hang, hang.data(), sizeof(int) * f->n_hang, hipMemcpyHostToDevice));
+    return DGAMR_OK;
+}
+
+// ---------------------------------------------------------------- dispatch
+template <class Fn>
+int dispatch(int d, int p, Fn &&fn)
+{
+    switch (d * 10 + p) {
+    case 20: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{});
+    case 21: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
+    case 22: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
+    case 23: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
+    case 30: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{});
+    case 31: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 1>{});
+    case 32: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
+    case 33: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{});
+    default: return fail(DGAMR_EUNSUPPORTED, "unsupported (dim, degree)");
+    }
+}
+
+int launch_fill(dgamr_forest *f, const double *u, double *guard, bool hanging_only, hipStream_t s)
+{
+    int nf = 2 * f->topo.dim();
+    dgk::FillArgs a{u, guard, f->d_links, hanging_only ? f->d_hang : nullptr,
+                    hanging_only ? f->n_hang : f->topo.n() * nf, f->topo.desc().n_cell};
+    if (a.nfaces == 0) return DGAMR_OK;
+    return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
+        HIP_TRY((dgk::launch_fill<D, P>(a, nfc_of(f), s)));
+        return DGAMR_OK;
+    });
+}
+
+int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t s)
+{
+    a.nleaves = f->topo.n();
+    a.N = f->topo.desc().n_cell;
+    a.gamma = f->topo.desc().gamma;
+    a.geo = f->d_geo;
+    a.links = f->d_links;
+    a.conservative = f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE;
+    if (a.nleaves == 0) return DGAMR_OK;
+    if (f->topo.desc().precision == DGAMR_FP32_MFMA) return fail(DGAMR_EUNSUPPORTED, "FP32-MFMA residual not built");
+    return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
+        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, s)));
+        return DGAMR_OK;
+    });
+}
+
+int launch_limit(dgamr_forest *f, double *u, hipStream_t s)
+{
+    long total = long(f->topo.n()) * ncell_of(f);
+    if (total == 0) return DGAMR_OK;
+    return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
+        HIP_TRY((dgk::launch_limit<D, P>(u, f->topo.desc().n_cell, total, f->topo.desc().gamma, s)));
+        return DGAMR_OK;
+    });
+}
+
+int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, const Work &w, hipStream_t s)
+{
+    int n = f->topo.n();
+    if (n == 0) return fail(DGAMR_EINVAL, "empty forest");
+    int ncell = ncell_of(f), block = 1;
+    while (block < ncell && block < 256) block <<= 1; // power of two for the tree reduction
+    if (f->topo.dim() == 2)
+        hipLaunchKernelGGL(dgk::k_rate<2>, dim3(n), dim3(block), 0, s, u, f->d_geo, f->topo.desc().n_cell, nb_of(f),
+                           f->topo.desc().gamma, w.leafmax);
+    else
+        hipLaunchKernelGGL(dgk::k_rate<3>, dim3(n), dim3(block), 0, s, u, f->d_geo, f->topo.desc().n_cell, nb_of(f),
+                           f->topo.desc().gamma, w.leafmax);
+    HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(dgk::k_dt_final, dim3(1), dim3(1024), 0, s, w.leafmax, n, cfl, dt_dev);
+    HIP_TRY(hipGetLastError());
+    return DGAMR_OK;
+}
+
+int check_ptr(const void *p, const char *name)
+{
+    if (!p) return fail(DGAMR_EINVAL, std::string(name) + " is null");
+    return DGAMR_OK;
+}
+
+#define CHECK(x)                      \
+    do {                              \
+        int rc_ = (x);                \
+        if (rc_ != DGAMR_OK) return rc_; \
+    } while (0)
+
+#define GUARD_API(...)                                                      \
+    try {                                                                   \
+        __VA_ARGS__                                                         \
+    } catch (const std::exception &e) {                                     \
+        return fail(DGAMR_EINVAL, std::string("internal error: ") + e.what()); \
+    } catch (...) {                                                         \
+        return fail(DGAMR_EINVAL, "internal error");                        \
+    }
+
+} // namespace
+
+extern "C" {
+
+const char *dgamr_last_error(void) { return g_err.c_str(); }
+
+int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out)
+{
+    GUARD_API({
+        CHECK(check_ptr(desc, "desc"));
+        CHECK(check_ptr(out, "out"));
+        *out = nullptr;
+        std::string err;
+        int rc = Forest::validate(*desc, err);
+        if (rc != DGAMR_OK) return fail(rc, err);
+        auto *f = new dgamr_forest(*desc);
+        HIP_TRY(hipGetDevice(&f->device));
+        rc = f->topo.build_links(err);
+        if (rc != DGAMR_OK) {
+            delete f;
+            return fail(rc, err);
+        }
+        rc = upload(f);
+        if (rc != DGAMR_OK) {
+            delete f;
+            return rc;
+        }
+        *out = f;
+        return DGAMR_OK;
+    })
+}
+
+int dgamr_destroy_forest(dgamr_forest *f)
+{
+    if (!f) return DGAMR_OK;
+    (void)hipFree(f->d_geo);
+    (void)hipFree(f->d_links);
+    (void)hipFree(f->d_hang);
+    delete f;
+    return DGAMR_OK;
+}
+
+int dgamr_num_leaves(const dgamr_forest *f, int64_t *n)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(n, "n"));
+    *n = f->topo.n();
+    return DGAMR_OK;
+}
+
+int dgamr_leaf_keys(const dgamr_forest *f, int32_t *keys)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(keys, "keys"));
+    for (int i = 0; i < f->topo.n(); ++i) {
+        const auto &k = f->topo.leaves()[i];
+        keys[5 * i + 0] = k.tree;
+        keys[5 * i + 1] = k.level;
+        keys[5 * i + 2] = k.idx[0];
+        keys[5 * i + 3] = k.idx[1];
+        keys[5 * i + 4] = k.idx[2];
+    }
+    return DGAMR_OK;
+}
+
+int dgamr_state_bytes(const dgamr_forest *f, size_t *u_bytes, size_t *guard_bytes, size_t *residual_bytes,
+                      size_t *work_bytes)
+{
+    CHECK(check_ptr(f, "forest"));
+    if (u_bytes) *u_bytes = state_elems(f) * sizeof(double);
+    if (guard_bytes) *guard_bytes = guard_elems(f) * sizeof(double);
+    if (residual_bytes)
+        *residual_bytes = state_elems(f) * (f->topo.desc().precision == DGAMR_FP32_MFMA ? sizeof(float) : sizeof(double));
+    if (work_bytes) *work_bytes = work_elems(f) * sizeof(double);
+    return DGAMR_OK;
+}
+
+int dgamr_set_refinement(dgamr_forest *f, const int8_t *flags, int64_t *n_new)
+{
+    GUARD_API({
+        CHECK(check_ptr(f, "forest"));
+        CHECK(check_ptr(flags, "flags"));
+        std::string err;
+        int rc = f->topo.plan(flags, err);
+        if (rc != DGAMR_OK) return fail(rc, err);
+        if (n_new) *n_new = f->topo.planned_n();
+        return DGAMR_OK;
+    })
+}
+
+int dgamr_apply_refinement(dgamr_forest *f, const double *u_old, double *u_new, hipStream_t stream)
+{
+    GUARD_API({
+        CHECK(check_ptr(f, "forest"));
+        if (!f->topo.has_plan()) return fail(DGAMR_ESTATE, "no refinement plan pending");
+        CHECK(check_ptr(u_old, "u_old"));
+        CHECK(check_ptr(u_new, "u_new"));
+        std::string err;
+        std::vector<Inherit> inh;
+        int rc = f->topo.commit(inh, err);
+        if (rc != DGAMR_OK) return fail(rc, err);
+        int n = f->topo.n();
+        Inherit *d_inh = nullptr;
+        HIP_TRY(hipMalloc(reinterpret_cast<void **>(&d_inh), sizeof(Inherit) * n));
+        HIP_TRY(hipMemcpyAsync(d_inh, inh.data(), sizeof(Inherit) * n, hipMemcpyHostToDevice, stream));
+        long total = long(n) * ncell_of(f);
+        rc = dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
+            HIP_TRY((dgk::launch_inherit<D, P>(u_old, u_new, d_inh, f->topo.desc().n_cell, total, stream)));
+            return DGAMR_OK;
+        });
+        HIP_TRY(hipStreamSynchronize(stream));
+        HIP_TRY(hipFree(d_inh));
+        if (rc != DGAMR_OK) return rc;
+        return upload(f);
+    })
+}
+
+int dgamr_fill_guardcells(dgamr_forest *f, const double *u, double *guard, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(guard, "guard"));
+    return launch_fill(f, u, guard, false, stream);
+}
+
+int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, void *r, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(guard, "guard"));
+    CHECK(check_ptr(r, "r"));
+    dgk::StageArgs a{};
+    a.us = u;
+    a.guard = guard;
+    bool r32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
+    a.out64 = r32 ? nullptr : static_cast<double *>(r);
+    a.out32 = r32 ? static_cast<float *>(r) : nullptr;
+    return launch_stage(f, a, dgk::GUARD_BUFFER, r32 ? dgk::OUT_RES32 : dgk::OUT_RES64, stream);
+}
+
+int dgamr_rk_stage(dgamr_forest *f, int stage, const double *dt_dev, const double *u_n, const double *u_s,
+                   const void *r, double *u_next, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    if (stage < 0 || stage > 2) return fail(DGAMR_EINVAL, "stage must be 0, 1 or 2");
+    CHECK(check_ptr(dt_dev, "dt_dev"));
+    CHECK(check_ptr(u_s, "u_s"));
+    CHECK(check_ptr(r, "r"));
+    CHECK(check_ptr(u_next, "u_next"));
+    if (stage > 0) CHECK(check_ptr(u_n, "u_n"));
+    static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
+    dgk::RkArgs a{u_n, u_s, r, u_next, dt_dev, A[stage], B[stage], long(state_elems(f)),
+                  f->topo.desc().precision == DGAMR_FP32_MFMA ? 1 : 0};
+    if (a.n == 0) return DGAMR_OK;
+    long blocks = (a.n + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(dgk::k_rk, dim3(unsigned(blocks)), dim3(256), 0, stream, a);
+    HIP_TRY(hipGetLastError());
+    return DGAMR_OK;
+}
+
+int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, void *work, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(dt_dev, "dt_dev"));
+    CHECK(check_ptr(work, "work"));
+    if (!(cfl > 0.0)) return fail(DGAMR_EINVAL, "cfl must be positive");
+    return launch_dt(f, cfl, u, dt_dev, carve(f, work), stream);
+}
+
+int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(work, "work"));
+    CHECK(check_ptr(dt_dev, "dt_dev"));
+    Work w = carve(f, work);
+    if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
+    const bool lim = f->topo.desc().limiter == DGAMR_LIMITER_POSITIVITY;
+    static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
+    const double *us = u;
+    double *outs[3] = {w.u1, w.u2, u};
+    for (int s = 0; s < 3; ++s) {
+        CHECK(launch_fill(f, us, w.guard, true, stream));
+        dgk::StageArgs a{};
+        a.us = us;
+        a.un = u;
+        a.guard = w.guard;
+        a.out64 = outs[s];
+        a.dt = dt_dev;
+        a.rk_a = A[s];
+        a.rk_b = B[s];
+        CHECK(launch_stage(f, a, dgk::GUARD_INLINE, dgk::OUT_RK, stream));
+        if (lim) CHECK(launch_limit(f, outs[s], stream));
+        us = outs[s];
+    }
+    return DGAMR_OK;
+}
+
+int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev, void *work, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(totals_dev, "totals_dev"));
+    CHECK(check_ptr(work, "work"));
+    Work w = carve(f, work);
+    int n = f->topo.n(), block = ncell_of(f) < 256 ? ncell_of(f) : 256;
+    if (n == 0) return fail(DGAMR_EINVAL, "empty forest");
+    int bp = 1;
+    while (bp < block) bp <<= 1; // power of two for the tree reduction
+    if (f->topo.dim() == 2) {
+        hipLaunchKernelGGL(dgk::k_totals_leaf<2>, dim3(n), dim3(bp), 0, stream, u, f->d_geo, f->topo.desc().n_cell,
+                           nb_of(f), w.part);
+        hipLaunchKernelGGL(dgk::k_totals_final<4>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
+    } else {
+        hipLaunchKernelGGL(dgk::k_totals_leaf<3>, dim3(n), dim3(bp), 0, stream, u, f->d_geo, f->topo.desc().n_cell,
+                           nb_of(f), w.part);
+        hipLaunchKernelGGL(dgk::k_totals_final<5>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
+    }
+    HIP_TRY(hipGetLastError());
+    return DGAMR_OK;
+}
+
+int dgamr_limit_positivity(dgamr_forest *f, double *u, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    return launch_limit(f, u, stream);
+}
+
+int dgamr_indicator(dgamr_forest *f, const double *u, double *eta_dev, void *work, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(eta_dev, "eta_dev"));
+    CHECK(check_ptr(work, "work"));
+    Work w = carve(f, work);
+    CHECK(launch_fill(f, u, w.guard, false, stream));
+    int n = f->topo.n();
+    if (n == 0) return DGAMR_OK;
+    if (f->topo.dim() == 2)
+        hipLaunchKernelGGL(dgk::k_indicator_leaf<2>, dim3(n), dim3(256), 0, stream, u, w.guard, f->topo.desc().n_cell,
+                           nb_of(f), eta_dev);
+    else
+        hipLaunchKernelGGL(dgk::k_indicator_leaf<3>, dim3(n), dim3(256), 0, stream, u, w.guard, f->topo.desc().n_cell,
+                           nb_of(f), eta_dev);
+    HIP_TRY(hipGetLastError());
+    return DGAMR_OK;
+}
+
+int dgamr_project_ic(dgamr_forest *f, int kind, const double *params, double t, double *u, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(params, "params"));
+    CHECK(check_ptr(u, "u"));
+    if (kind < DGAMR_IC_VORTEX || kind > DGAMR_IC_XWAVE) return fail(DGAMR_EINVAL, "unknown initial condition");
+    dgk::IcParams prm;
+    std::memcpy(prm.p, params, sizeof(prm.p));
+    const auto &d = f->topo.desc();
+    double hmin[3];
+    for (int a = 0; a < 3; ++a)
+        hmin[a] = (d.hi[a] - d.lo[a]) / (double(d.roots[a]) * d.n_cell * double(1 << (d.max_level - 1)));
+    long total = long(f->topo.n()) * ncell_of(f);
+    if (total == 0) return DGAMR_OK;
+    return dispatch(f->topo.dim(), d.degree, [&](auto D, auto P) -> int {
+        HIP_TRY((dgk::launch_project_ic<D, P>(u, f->d_geo, d.n_cell, total, kind, prm, t, d.gamma, hmin, stream)));
+        return DGAMR_OK;
+    });
+}
+
+int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(bad, "bad"));
+    CHECK(check_ptr(work, "work"));
+    Work w = carve(f, work);
+    auto *cnt = reinterpret_cast<unsigned long long *>(w.scal);
+    HIP_TRY(hipMemsetAsync(cnt, 0, sizeof(unsigned long long), stream));
+    long total = long(f->topo.n()) * ncell_of(f);
+    if (total > 0) {
+        dim3 grid(unsigned((total + 255) / 256)), block(256);
+        if (f->topo.dim() == 2)
+            hipLaunchKernelGGL(dgk::k_check<2>, grid, block, 0, stream, u, f->topo.desc().n_cell, nb_of(f), total,
+                               f->topo.desc().gamma, cnt);
+        else
+            hipLaunchKernelGGL(dgk::k_check<3>, grid, block, 0, stream, u, f->topo.desc().n_cell, nb_of(f), total,
+                               f->topo.desc().gamma, cnt);
+        HIP_TRY(hipGetLastError());
+    }
+    unsigned long long h = 0;
+    HIP_TRY(hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    *bad = int64_t(h);
+    return h ? fail(DGAMR_ENONPHYSICAL, "non-physical state: " + std::to_string(h) + " cells") : DGAMR_OK;
+}
+
+} // extern "C"

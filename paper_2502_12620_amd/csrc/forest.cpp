@@ -1,0 +1,335 @@
+// Host-side forest topology; see forest.hpp.
+#include "forest.hpp"
+
+#include <algorithm>
+#include <numeric>
+
+namespace dgamr {
+
+namespace {
+constexpr int kMaxLevel = 12; // idx < 2048 per axis: 11 bits each in the packed key
+}
+
+Forest::Forest(const dgamr_forest_desc &d) : desc_(d)
+{
+    for (int a = desc_.dim; a < 3; ++a) {
+        desc_.roots[a] = 1;
+        desc_.bc[a] = DGAMR_BC_PERIODIC;
+        desc_.lo[a] = 0.0;
+        desc_.hi[a] = 1.0;
+    }
+    int ntree = desc_.roots[0] * desc_.roots[1] * desc_.roots[2];
+    leaves_.resize(ntree);
+    for (int t = 0; t < ntree; ++t) leaves_[t].tree = t;
+    reindex();
+}
+
+int Forest::validate(const dgamr_forest_desc &d, std::string &err)
+{
+    if (d.dim != 2 && d.dim != 3) { err = "dim must be 2 or 3"; return DGAMR_EINVAL; }
+    if (d.degree < 0 || d.degree > 3) { err = "degree must be 0..3"; return DGAMR_EUNSUPPORTED; }
+    if (d.n_cell < 2 || d.n_cell % 2) { err = "n_cell must be even and >= 2"; return DGAMR_EINVAL; }
+    int nmax = d.dim == 2 ? 16 : 8;
+    if (d.n_cell > nmax) { err = "n_cell above the built limit (16 in 2-D, 8 in 3-D)"; return DGAMR_EUNSUPPORTED; }
+    if (d.max_level < 1 || d.max_level > kMaxLevel) { err = "max_level must be 1..12"; return DGAMR_EINVAL; }
+    long ntree = 1;
+    for (int a = 0; a < d.dim; ++a) {
+        if (d.roots[a] < 1) { err = "roots must be >= 1"; return DGAMR_EINVAL; }
+        if (!(d.hi[a] > d.lo[a])) { err = "hi must exceed lo"; return DGAMR_EINVAL; }
+        if (d.bc[a] != DGAMR_BC_PERIODIC && d.bc[a] != DGAMR_BC_OUTFLOW) { err = "bad bc"; return DGAMR_EINVAL; }
+        ntree *= d.roots[a];
+    }
+    if (ntree >= (1L << 24)) { err = "too many roots"; return DGAMR_EUNSUPPORTED; }
+    if (!(d.gamma > 1.0)) { err = "gamma must exceed 1"; return DGAMR_EINVAL; }
+    if (d.precision != DGAMR_FP64 && d.precision != DGAMR_FP32_MFMA) { err = "bad precision"; return DGAMR_EINVAL; }
+    if (d.hanging != DGAMR_HANG_PAPER && d.hanging != DGAMR_HANG_CONSERVATIVE) { err = "bad hanging mode"; return DGAMR_EINVAL; }
+    if (d.limiter != DGAMR_LIMITER_NONE && d.limiter != DGAMR_LIMITER_POSITIVITY) { err = "bad limiter"; return DGAMR_EINVAL; }
+    return DGAMR_OK;
+}
+
+uint64_t Forest::pack(int tree, int level, const int *idx) const
+{
+    return (uint64_t(tree) << 40) | (uint64_t(level) << 33) | (uint64_t(idx[2]) << 22) |
+           (uint64_t(idx[1]) << 11) | uint64_t(idx[0]);
+}
+
+int Forest::find(int tree, int level, const int *idx) const
+{
+    if (level < 1) return -1;
+    auto it = index_.find(pack(tree, level, idx));
+    return it == index_.end() ? -1 : it->second;
+}
+
+void Forest::reindex()
+{
+    index_.clear();
+    index_.reserve(leaves_.size() * 2);
+    for (int i = 0; i < n(); ++i) index_[pack(leaves_[i].tree, leaves_[i].level, leaves_[i].idx)] = i;
+}
+
+// root adjacent to `tree` across (axis, side), wrapping periodic axes;
+// false at an outflow boundary
+bool Forest::neighbour_root(int tree, int axis, int side, int &out) const
+{
+    int r[3] = {tree % desc_.roots[0], (tree / desc_.roots[0]) % desc_.roots[1],
+                tree / (desc_.roots[0] * desc_.roots[1])};
+    r[axis] += side;
+    if (r[axis] < 0 || r[axis] >= desc_.roots[axis]) {
+        if (desc_.bc[axis] != DGAMR_BC_PERIODIC) return false;
+        r[axis] = (r[axis] + desc_.roots[axis]) % desc_.roots[axis];
+    }
+    out = r[0] + desc_.roots[0] * (r[1] + desc_.roots[1] * r[2]);
+    return true;
+}
+
+uint64_t Forest::morton(const Key &k) const
+{
+    int shift = desc_.max_level - k.level;
+    uint64_t code = 0;
+    for (int b = 0; b < kMaxLevel; ++b)
+        for (int a = 0; a < desc_.dim; ++a)
+            code |= uint64_t(((k.idx[a] << shift) >> b) & 1) << (desc_.dim * b + a);
+    return code;
+}
+
+void Forest::sort_keys(std::vector<Key> &v) const
+{
+    std::stable_sort(v.begin(), v.end(), [this](const Key &x, const Key &y) {
+        if (x.tree != y.tree) return x.tree < y.tree;
+        return morton(x) < morton(y);
+    });
+}
+
+int Forest::build_links(std::string &err)
+{
+    const int d = desc_.dim, nf = 2 * d;
+    links_.assign(size_t(n()) * nf, FaceLink{});
+    for (int i = 0; i < n(); ++i) {
+        const Key &k = leaves_[i];
+        const int span = 1 << (k.level - 1);
+        for (int face = 0; face < nf; ++face) {
+            const int a = face / 2, s = (face % 2) ? 1 : -1;
+            FaceLink &L = links_[size_t(i) * nf + face];
+            for (int q = 0; q < 4; ++q) L.nbr[q] = -1;
+            int tang[2] = {0, 0}, nt = 0;
+            for (int b = 0; b < d; ++b)
+                if (b != a) tang[nt++] = b;
+            int nidx[3] = {k.idx[0], k.idx[1], k.idx[2]};
+            int ntree = k.tree;
+            nidx[a] += s;
+            if (nidx[a] < 0 || nidx[a] >= span) {
+                if (!neighbour_root(k.tree, a, s, ntree)) {
+                    L.type = LINK_BOUNDARY;
+                    continue;
+                }
+                nidx[a] = s > 0 ? 0 : span - 1;
+            }
+            int j = find(ntree, k.level, nidx);
+            if (j >= 0) {
+                L.type = LINK_SAME;
+                L.nbr[0] = j;
+                continue;
+            }
+            int pidx[3] = {nidx[0] >> 1, nidx[1] >> 1, nidx[2] >> 1};
+            j = find(ntree, k.level - 1, pidx);
+            if (j >= 0) {
+                L.type = LINK_COARSE;
+                L.nbr[0] = j;
+                for (int q = 0; q < nt; ++q) L.off[q] = k.idx[tang[q]] & 1;
+                continue;
+            }
+            bool ok = k.level < desc_.max_level;
+            for (int c = 0; ok && c < (1 << (d - 1)); ++c) {
+                int cidx[3] = {2 * nidx[0], 2 * nidx[1], 2 * nidx[2]};
+                cidx[a] += (s > 0) ? 0 : 1;
+                for (int q = 0; q < nt; ++q) cidx[tang[q]] += (c >> q) & 1;
+                int jj = find(ntree, k.level + 1, cidx);
+                if (jj < 0) ok = false;
+                L.nbr[c] = jj;
+            }
+            if (!ok) {
+                err = "forest violates 2:1 face balance";
+                return DGAMR_EBALANCE;
+            }
+            L.type = LINK_FINE;
+        }
+    }
+    return DGAMR_OK;
+}
+
+std::vector<LeafGeo> Forest::geometry() const
+{
+    std::vector<LeafGeo> g(n());
+    for (int i = 0; i < n(); ++i) {
+        const Key &k = leaves_[i];
+        int r[3] = {k.tree % desc_.roots[0], (k.tree / desc_.roots[0]) % desc_.roots[1],
+                    k.tree / (desc_.roots[0] * desc_.roots[1])};
+        LeafGeo &G = g[i];
+        G.vol = 1.0;
+        for (int a = 0; a < 3; ++a) {
+            double root = (desc_.hi[a] - desc_.lo[a]) / desc_.roots[a];
+            double edge = root / double(1 << (k.level - 1));
+            G.lo[a] = desc_.lo[a] + r[a] * root + k.idx[a] * edge;
+            G.h[a] = edge / desc_.n_cell;
+            G.scale[a] = 2.0 / G.h[a];
+            if (a < desc_.dim) G.vol *= G.h[a];
+        }
+        G.level = k.level;
+        G.pad = 0;
+    }
+    return g;
+}
+
+int Forest::plan(const int8_t *flags, std::string &err)
+{
+    const int d = desc_.dim, nf = 2 * d, nchild = 1 << d, nl = n();
+    std::vector<int> r(nl, 0);
+    for (int i = 0; i < nl; ++i) r[i] = (flags[i] > 0 && leaves_[i].level < desc_.max_level) ? 1 : 0;
+    auto face_nbrs = [&](int i, int face, int *out) {
+        const FaceLink &L = links_[size_t(i) * nf + face];
+        if (L.type == LINK_BOUNDARY) return 0;
+        if (L.type == LINK_FINE) {
+            for (int c = 0; c < (1 << (d - 1)); ++c) out[c] = L.nbr[c];
+            return 1 << (d - 1);
+        }
+        out[0] = L.nbr[0];
+        return 1;
+    };
+    // refinement closed under 2:1 face balance (worklist)
+    std::vector<int> work;
+    for (int i = 0; i < nl; ++i)
+        if (r[i]) work.push_back(i);
+    while (!work.empty()) {
+        int i = work.back();
+        work.pop_back();
+        for (int face = 0; face < nf; ++face) {
+            int nb[4];
+            int m = face_nbrs(i, face, nb);
+            for (int q = 0; q < m; ++q) {
+                int j = nb[q];
+                if (!r[j] && leaves_[i].level + r[i] > leaves_[j].level + 1) {
+                    r[j] = 1;
+                    work.push_back(j);
+                }
+            }
+        }
+    }
+    // coarsening families keyed by their parent
+    std::unordered_map<uint64_t, std::vector<int>> fam;
+    for (int i = 0; i < nl; ++i) {
+        const Key &k = leaves_[i];
+        if (k.level <= 1 || flags[i] >= 0 || r[i]) continue;
+        int pidx[3] = {k.idx[0] >> 1, k.idx[1] >> 1, k.idx[2] >> 1};
+        fam[pack(k.tree, k.level - 1, pidx)].push_back(i);
+    }
+    std::vector<int> grp(nl, -1);
+    std::vector<uint64_t> gkey;
+    for (auto &kv : fam) {
+        if (int(kv.second.size()) != nchild) continue; // some sibling is not a flagged leaf
+        int g = int(gkey.size());
+        gkey.push_back(kv.first);
+        for (int i : kv.second) grp[i] = g;
+    }
+    for (bool changed = true; changed;) {
+        changed = false;
+        for (int i = 0; i < nl; ++i) {
+            if (grp[i] < 0) continue;
+            bool bad = false;
+            for (int face = 0; face < nf && !bad; ++face) {
+                int nb[4];
+                int m = face_nbrs(i, face, nb);
+                for (int q = 0; q < m; ++q) {
+                    int j = nb[q];
+                    if (grp[j] == grp[i]) continue;
+                    int lj = leaves_[j].level + r[j] - (grp[j] >= 0 ? 1 : 0);
+                    if (lj > leaves_[i].level) bad = true;
+                }
+            }
+            if (bad) {
+                int g = grp[i];
+                for (int j = 0; j < nl; ++j)
+                    if (grp[j] == g) grp[j] = -1;
+                changed = true;
+            }
+        }
+    }
+    // new leaves with their inheritance sources
+    planned_.clear();
+    planned_inh_.clear();
+    std::vector<char> done(gkey.size(), 0);
+    for (int i = 0; i < nl; ++i) {
+        const Key &k = leaves_[i];
+        if (r[i]) {
+            for (int c = 0; c < nchild; ++c) {
+                Key ch;
+                ch.tree = k.tree;
+                ch.level = k.level + 1;
+                for (int a = 0; a < 3; ++a) ch.idx[a] = a < d ? 2 * k.idx[a] + ((c >> a) & 1) : 0;
+                Inherit in{};
+                in.type = INH_SPLIT;
+                in.src[0] = i;
+                in.child = c;
+                planned_.push_back(ch);
+                planned_inh_.push_back(in);
+            }
+        } else if (grp[i] >= 0) {
+            if (done[grp[i]]) continue;
+            done[grp[i]] = 1;
+            Key pa;
+            pa.tree = k.tree;
+            pa.level = k.level - 1;
+            for (int a = 0; a < 3; ++a) pa.idx[a] = k.idx[a] >> 1;
+            Inherit in{};
+            in.type = INH_COMBINE;
+            for (int c = 0; c < nchild; ++c) {
+                int cidx[3] = {0, 0, 0};
+                for (int a = 0; a < d; ++a) cidx[a] = 2 * pa.idx[a] + ((c >> a) & 1);
+                in.src[c] = find(k.tree, k.level, cidx);
+            }
+            planned_.push_back(pa);
+            planned_inh_.push_back(in);
+        } else {
+            Inherit in{};
+            in.type = INH_COPY;
+            in.src[0] = i;
+            planned_.push_back(k);
+            planned_inh_.push_back(in);
+        }
+    }
+    // sort keys and inheritance together
+    std::vector<int> perm(planned_.size());
+    std::iota(perm.begin(), perm.end(), 0);
+    std::stable_sort(perm.begin(), perm.end(), [this](int x, int y) {
+        const Key &a = planned_[x], &b = planned_[y];
+        if (a.tree != b.tree) return a.tree < b.tree;
+        return morton(a) < morton(b);
+    });
+    std::vector<Key> ks(perm.size());
+    std::vector<Inherit> is(perm.size());
+    for (size_t q = 0; q < perm.size(); ++q) {
+        ks[q] = planned_[perm[q]];
+        is[q] = planned_inh_[perm[q]];
+    }
+    planned_.swap(ks);
+    planned_inh_.swap(is);
+    has_plan_ = true;
+    (void)err;
+    return DGAMR_OK;
+}
+
+int Forest::commit(std::vector<Inherit> &inh, std::string &err)
+{
+    if (!has_plan_) {
+        err = "no refinement plan pending";
+        return DGAMR_ESTATE;
+    }
+    leaves_.swap(planned_);
+    inh.swap(planned_inh_);
+    planned_.clear();
+    planned_inh_.clear();
+    has_plan_ = false;
+    reindex();
+    return build_links(err);
+}
+
+} // namespace dgamr

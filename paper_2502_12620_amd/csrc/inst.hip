@@ -1,0 +1,72 @@
+// One (dim, degree) instantiation of the degree-templated kernels and their
+// launchers; compiled once per pair with -DDG_D=<dim> -DDG_P=<degree>.
+#include "kernels.hpp"
+#include "kernels_aux.hpp"
+#include "launch.hpp"
+
+#ifndef DG_D
+#error "DG_D must be defined"
+#endif
+#ifndef DG_P
+#error "DG_P must be defined"
+#endif
+
+namespace dgk {
+
+template <int D, int P>
+hipError_t launch_stage(const StageArgs &a, int gm, int om, hipStream_t s)
+{
+    const int ncell = D == 2 ? a.N * a.N : a.N * a.N * a.N;
+    const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * ncell;
+    const dim3 grid(a.nleaves), block(ncell);
+    if (gm == GUARD_BUFFER && om == OUT_RES64)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64>), grid, block, lds, s, a);
+    else if (gm == GUARD_BUFFER && om == OUT_RES32)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32>), grid, block, lds, s, a);
+    else if (gm == GUARD_INLINE && om == OUT_RK)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK>), grid, block, lds, s, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int D, int P>
+hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s)
+{
+    const long threads = long(a.nfaces) * nfc;
+    hipLaunchKernelGGL((k_fill<D, P>), dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int D, int P>
+hipError_t launch_limit(double *u, int N, long total, double gamma, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_limit<D, P>), dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, u, N, total, gamma);
+    return hipGetLastError();
+}
+
+template <int D, int P>
+hipError_t launch_project_ic(double *u, const LeafGeo *geo, int N, long total, int kind, const IcParams &prm,
+                             double t, double gamma, const double *hmin, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_project_ic<D, P>), dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, u, geo, N, total,
+                       kind, prm, t, gamma, hmin[0], hmin[1], hmin[2]);
+    return hipGetLastError();
+}
+
+template <int D, int P>
+hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, int N, long total, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_inherit<D, P>), dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, uold, unew, inh, N,
+                       total);
+    return hipGetLastError();
+}
+
+template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, hipStream_t);
+template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t);
+template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStream_t);
+template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,
+                                                   double, const double *, hipStream_t);
+template hipError_t launch_inherit<DG_D, DG_P>(const double *, double *, const Inherit *, int, long, hipStream_t);
+
+} // namespace dgk

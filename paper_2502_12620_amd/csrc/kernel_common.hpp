@@ -1,0 +1,132 @@
+// Device helpers and kernel argument blocks shared by the HIP kernels.
+//
+// Layout in HBM (block-major SoA): U[leaf][var][mode][cell], cell index x
+// fastest, so the N^d threads of one workgroup (one leaf, one thread per
+// cell) read every (var, mode) plane as one contiguous, coalesced run.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "dg_tables.hpp"
+#include "forest.hpp"
+
+namespace dgk {
+
+using dgamr::FaceLink;
+using dgamr::Inherit;
+using dgamr::LeafGeo;
+
+constexpr int kXcds = 8; // MI355X: 8 XCDs, workgroups dispatched round-robin
+
+// Workgroup index -> leaf such that each XCD owns one contiguous range of
+// leaves (neighbouring leaves in Morton order share that XCD's L2).
+__device__ __forceinline__ int xcd_leaf(int bid, int n)
+{
+    int q = n / kXcds, r = n % kXcds;
+    int x = bid % kXcds, slot = bid / kXcds;
+    return x * q + (x < r ? x : r) + slot;
+}
+
+__device__ __forceinline__ void cell_ijk(int cell, int N, int D, int *ijk)
+{
+    ijk[0] = cell % N;
+    ijk[1] = (cell / N) % N;
+    ijk[2] = D == 3 ? cell / (N * N) : 0;
+}
+
+// tangential index t of a cell on the face normal to axis a (the lower of
+// the remaining axes fastest)
+__device__ __forceinline__ int face_t(const int *ijk, int a, int N, int D)
+{
+    if (D == 2) return a == 0 ? ijk[1] : ijk[0];
+    return a == 0 ? ijk[1] + N * ijk[2] : (a == 1 ? ijk[0] + N * ijk[2] : ijk[0] + N * ijk[1]);
+}
+
+// cell index of (normal index n along a, tangential index t)
+__device__ __forceinline__ int face_cell(int a, int n, int t, int N, int D)
+{
+    int t0 = t % N, t1 = t / N;
+    int i, j, k;
+    if (a == 0) { i = n; j = t0; k = t1; }
+    else if (a == 1) { i = t0; j = n; k = t1; }
+    else { i = t0; j = t1; k = n; }
+    return i + N * (j + N * k);
+}
+
+// Euler flux along axis A (Eq. 2 and its 3-D analogue; EOS Eq. 23).
+template <int D, int A>
+__device__ __forceinline__ void euler_flux(const double *U, double ua, double p, double *F)
+{
+    F[0] = U[1 + A];
+#pragma unroll
+    for (int b = 0; b < D; ++b) F[1 + b] = U[1 + b] * ua;
+    F[1 + A] += p;
+    F[D + 1] = ua * (U[D + 1] + p);
+}
+
+template <int D>
+__device__ __forceinline__ double pressure(const double *U, double gm1)
+{
+    double ke = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b];
+    return gm1 * (U[D + 1] - 0.5 * ke / U[0]);
+}
+
+// Eq. 5, dissipative sign, flux in the +e_A direction between the left
+// state UL and the right state UR; alpha = max(|u_A| + c) of both sides.
+template <int D, int A>
+__device__ __forceinline__ void rusanov(const double *UL, const double *UR, double gamma, double *Phi)
+{
+    constexpr int NV = D + 2;
+    const double gm1 = gamma - 1.0;
+    double rl = 1.0 / UL[0], rr = 1.0 / UR[0];
+    double pl = pressure<D>(UL, gm1), pr = pressure<D>(UR, gm1);
+    double ul = UL[1 + A] * rl, ur = UR[1 + A] * rr;
+    double cl = sqrt(gamma * pl * rl), cr = sqrt(gamma * pr * rr);
+    double al = fabs(ul) + cl, ar = fabs(ur) + cr;
+    double alpha = al > ar ? al : ar;
+    double FL[NV], FR[NV];
+    euler_flux<D, A>(UL, ul, pl, FL);
+    euler_flux<D, A>(UR, ur, pr, FR);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) Phi[v] = 0.5 * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
+}
+
+// ------------------------------------------------------------------ argument blocks
+enum GuardMode : int {
+    GUARD_BUFFER = 0, // every block face from the guard buffer
+    GUARD_INLINE = 1  // same-level and outflow faces straight from the
+                      // neighbour's state; hanging faces from the guard buffer
+};
+enum OutMode : int { OUT_RES64 = 0, OUT_RES32 = 1, OUT_RK = 2 };
+
+struct StageArgs {
+    const double *us;     // stage input (read-only during the stage)
+    const double *un;     // RK base state (OUT_RK)
+    const double *guard;  // guard buffer
+    double *out64;        // residual (OUT_RES64) or next state (OUT_RK)
+    float *out32;         // residual (OUT_RES32)
+    const LeafGeo *geo;
+    const FaceLink *links;
+    const double *dt;     // device dt (OUT_RK)
+    double rk_a, rk_b;
+    double gamma;
+    int nleaves, N;
+    int conservative;     // mortar on hanging coarse faces
+};
+
+struct FillArgs {
+    const double *u;
+    double *guard;
+    const FaceLink *links;
+    const int *faces;  // optional list of (leaf*2d + face) to fill; null = all
+    int nfaces;        // number of faces to fill
+    int N;
+};
+
+struct IcParams {
+    double p[8];
+};
+
+} // namespace dgk

@@ -1,0 +1,467 @@
+// HIP kernels of the DG stage for gfx950: guard-cell fill (Sec. 3.5,
+// Eq. 15-17) and the residual of the Galerkin weak form (Sec. 2, Eq. 3-5),
+// optionally fused with the SSP-RK3 stage update.
+//
+// One workgroup per leaf, one thread per cell.  The thread keeps its cell's
+// coefficients K[var][mode] and residual R[var][mode] in registers; the
+// basis tables are compile-time constants, so after full unrolling every
+// table entry is an immediate and structural zeros disappear.  The flux of
+// each face inside the block is computed once: the + trace of every cell
+// goes through LDS to its + neighbour, which computes the Rusanov flux and
+// sends it back through LDS.
+#pragma once
+
+#include "kernel_common.hpp"
+
+namespace dgk {
+
+// Number of face points exchanged through LDS at once: all of them in 2-D,
+// one at a time in 3-D (keeps the register budget to one cell's state and
+// residual).
+template <int D, int P>
+constexpr int face_chunk() { return D == 2 ? Tab<D, P>::NF : 1; }
+
+// Full unrolling over the quadrature points makes every table entry an
+// immediate; for 3-D degree 3 (64 volume points, 20 modes) the unrolled
+// code is too large, so its point loops stay loops over tables in memory.
+template <int D, int P>
+constexpr bool unroll_points() { return !(D == 3 && P == 3); }
+
+// even / odd parts (in the normal mode index) of the trace of K at face
+// point f of axis a: the trace at xi_a = +1 is e + o, at xi_a = -1 it is e - o.
+template <int D, int P>
+__device__ __forceinline__ void trace_eo(const double *K, int a, int f, double &e, double &o)
+{
+    e = 0.0;
+    o = 0.0;
+#pragma unroll
+    for (int m = 0; m < Tab<D, P>::NB; ++m) {
+        const double c = kTab<D, P>.phi_f[a][f][m];
+        if (c != 0.0) {
+            if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(c, K[m], e);
+            else o = fma(c, K[m], o);
+        }
+    }
+}
+
+// the same for coefficients streamed from memory (coef[m*sm])
+template <int D, int P>
+__device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, long sm, int a, int f, double &e,
+                                             double &o)
+{
+    e = 0.0;
+    o = 0.0;
+#pragma unroll
+    for (int m = 0; m < Tab<D, P>::NB; ++m) {
+        const double c = kTab<D, P>.phi_f[a][f][m];
+        if (c != 0.0) {
+            const double k = coef[m * sm];
+            if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(c, k, e);
+            else o = fma(c, k, o);
+        }
+    }
+}
+
+// Conservative hanging-face flux: the coarse cell integrates the Rusanov
+// flux over the 2^(d-1) fine sub-faces at the fine Gauss points, with the
+// fine cells' own traces, and lifts it with its own basis evaluated at the
+// mapped points (tangential xi = (xi_fine + sigma)/2).
+template <int D, int P, int A>
+__device__ void mortar_lift(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB],
+                            double (&R)[D + 2][Tab<D, P>::NB], int side, const FaceLink &L, int t, double scale)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB, Q = P + 1, NF = Tab<D, P>::NF;
+    constexpr int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2; // tangential axes, lower first
+    const int N = g.N, ncell = D == 2 ? N * N : N * N * N;
+    const long sv = long(NB) * ncell;
+    const int t0 = t % N, t1 = t / N;
+    const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
+    const int fleaf = L.nbr[h0 + 2 * h1];
+    const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
+    const int fn = side > 0 ? 0 : N - 1;
+    const double sub = D == 2 ? 0.5 : 0.25; // fine face Jacobian / coarse face Jacobian
+    // runs only on hanging faces: kept as loops (table values computed on
+    // the fly) to keep the code small
+#pragma unroll 1
+    for (int S = 0; S < (1 << (D - 1)); ++S) {
+        const int s0 = S & 1, s1 = (S >> 1) & 1;
+        const int fcell = face_cell(A, fn, (ft0 + s0) + N * (ft1 + s1), N, D);
+        const double *fk = g.us + long(fleaf) * NV * sv + fcell;
+#pragma unroll 1
+        for (int F = 0; F < NF; ++F) {
+            const int q0 = F % Q, q1 = F / Q;
+            const double x0 = 0.5 * (gl_x(Q, q0) + (s0 ? 1.0 : -1.0));
+            const double x1 = 0.5 * (gl_x(Q, q1) + (s1 ? 1.0 : -1.0));
+            const double w = gl_w(Q, q0) * (D == 3 ? gl_w(Q, q1) : 1.0);
+            double Uf[NV], Uc[NV], Phi[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                double e, o;
+                trace_eo_mem<D, P>(fk + v * sv, ncell, A, F, e, o);
+                Uf[v] = side > 0 ? e - o : e + o; // the fine cell touches the face with its -side side
+                double ec = 0.0, oc = 0.0;
+#pragma unroll
+                for (int m = 0; m < NB; ++m) {
+                    const double c = leg(kTab<D, P>.e[m][TA], x0) * (D == 3 ? leg(kTab<D, P>.e[m][TBX], x1) : 1.0);
+                    if (c != 0.0) {
+                        if (kTab<D, P>.e[m][A] % 2 == 0) ec = fma(c, K[v][m], ec);
+                        else oc = fma(c, K[v][m], oc);
+                    }
+                }
+                Uc[v] = side > 0 ? ec + oc : ec - oc;
+            }
+            if (side > 0) rusanov<D, A>(Uc, Uf, g.gamma, Phi);
+            else rusanov<D, A>(Uf, Uc, g.gamma, Phi);
+            // +face: -int Phi phi ; -face: +int Phi phi with phi(-1) = (-1)^{m_A} phi(+1)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) {
+                const double f = scale * sub * w * Phi[v];
+#pragma unroll
+                for (int m = 0; m < NB; ++m) {
+                    const double c = leg(kTab<D, P>.e[m][TA], x0) * (D == 3 ? leg(kTab<D, P>.e[m][TBX], x1) : 1.0) *
+                                     kTab<D, P>.inv_mass[m];
+                    if (c != 0.0) {
+                        const double sg = side > 0 ? -1.0 : ((kTab<D, P>.e[m][A] % 2) ? -1.0 : 1.0);
+                        R[v][m] = fma(sg * c, f, R[v][m]);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Trace, at face point F of block face (A, side), of the polynomial on the
+// far side of the face for the cell with tangential index t: the guard
+// cell, the same-level neighbour cell (inline mode) or, at an outflow
+// boundary, the mirror image, whose trace is the own trace.
+template <int D, int P, int A, int GM>
+__device__ __forceinline__ void far_trace(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB], int leaf,
+                                          int side, int t, const FaceLink &L, int F, double *T)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
+    const int face = 2 * A + (side > 0);
+    // the far polynomial touches the face with its -side side
+    if (GM == GUARD_INLINE && L.type == dgamr::LINK_SAME) {
+        const int c = face_cell(A, side > 0 ? 0 : N - 1, t, N, D);
+        const double *nk = g.us + long(L.nbr[0]) * NV * NB * ncell + c;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double e, o;
+            trace_eo_mem<D, P>(nk + long(v) * NB * ncell, ncell, A, F, e, o);
+            T[v] = side > 0 ? e - o : e + o;
+        }
+    } else if (GM == GUARD_INLINE && L.type == dgamr::LINK_BOUNDARY) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double e, o;
+            trace_eo<D, P>(K[v], A, F, e, o);
+            T[v] = side > 0 ? e + o : e - o;
+        }
+    } else {
+        const double *gk = g.guard + ((long(leaf) * 2 * D + face) * NV * NB) * nfc + t;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double e, o;
+            trace_eo_mem<D, P>(gk + long(v) * NB * nfc, nfc, A, F, e, o);
+            T[v] = side > 0 ? e - o : e + o;
+        }
+    }
+}
+
+template <int D, int P, int GM, int OM>
+__global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
+    constexpr int FCH = face_chunk<D, P>();
+    extern __shared__ double lds[];
+
+    const int N = g.N, ncell = D == 2 ? N * N : N * N * N;
+    const int leaf = xcd_leaf(blockIdx.x, g.nleaves);
+    const int cell = threadIdx.x;
+    int ijk[3];
+    cell_ijk(cell, N, D, ijk);
+    const double scale[3] = {g.geo[leaf].scale[0], g.geo[leaf].scale[1], g.geo[leaf].scale[2]};
+    const long sv = long(NB) * ncell;
+    const long base = long(leaf) * NV * sv + cell;
+
+    double K[NV][NB], R[NV][NB];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            K[v][m] = g.us[base + v * sv + m * ncell];
+            R[v][m] = 0.0;
+        }
+
+    // ---- volume integral: sum_q w_q F_a(U_q) (2/h_a) dphi_m/dxi_a / M_m
+    const double gm1 = g.gamma - 1.0;
+    auto vol_point = [&](auto qv) {
+        const int q = qv;
+        double U[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                const double c = kTab<D, P>.phi_v[q][m];
+                if (c != 0.0) s = fma(c, K[v][m], s);
+            }
+            U[v] = s;
+        }
+        const double rinv = 1.0 / U[0];
+        const double p = pressure<D>(U, gm1);
+        static_for<0, D>([&](auto Ai) {
+            constexpr int A = Ai;
+            double F[NV];
+            euler_flux<D, A>(U, U[1 + A] * rinv, p, F);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) F[v] *= scale[A];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                const double c = kTab<D, P>.dproj[A][q][m];
+                if (c != 0.0) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) R[v][m] = fma(c, F[v], R[v][m]);
+                }
+            }
+        });
+    };
+    if constexpr (unroll_points<D, P>()) {
+        static_for<0, NQ>(vol_point);
+    } else {
+#pragma unroll 1
+        for (int q = 0; q < NQ; ++q) vol_point(q);
+    }
+
+    // ---- surface integrals, one axis at a time
+    static_for<0, D>([&](auto Ai) {
+        constexpr int A = Ai;
+        const int stride = A == 0 ? 1 : (A == 1 ? N : N * N);
+        const int ia = ijk[A];
+        const int t = face_t(ijk, A, N, D);
+        const double sc = scale[A];
+        const FaceLink Lm = g.links[leaf * 2 * D + 2 * A];
+        const FaceLink Lp = g.links[leaf * 2 * D + 2 * A + 1];
+        const bool mort_m = g.conservative && ia == 0 && Lm.type == dgamr::LINK_FINE;
+        const bool mort_p = g.conservative && ia == N - 1 && Lp.type == dgamr::LINK_FINE;
+        if (mort_m) mortar_lift<D, P, A>(g, K, R, -1, Lm, t, sc);
+        if (mort_p) mortar_lift<D, P, A>(g, K, R, +1, Lp, t, sc);
+        auto face_chunk_body = [&](auto cv) {
+            const int f0 = int(cv) * FCH;
+            // own + traces of this chunk -> LDS
+            __syncthreads();
+#pragma unroll
+            for (int fi = 0; fi < FCH; ++fi)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double e, o;
+                    trace_eo<D, P>(K[v], A, f0 + fi, e, o);
+                    lds[(v * FCH + fi) * ncell + cell] = e + o;
+                }
+            __syncthreads();
+            // flux on the - face: left state = the left neighbour's + trace
+            double Fm[FCH][NV];
+#pragma unroll
+            for (int fi = 0; fi < FCH; ++fi) {
+                double TL[NV], TR[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    double e, o;
+                    trace_eo<D, P>(K[v], A, f0 + fi, e, o);
+                    TR[v] = e - o;
+                }
+                if (ia > 0) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * ncell + cell - stride];
+                } else if (!mort_m) {
+                    far_trace<D, P, A, GM>(g, K, leaf, -1, t, Lm, f0 + fi, TL);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) TL[v] = TR[v];
+                }
+                rusanov<D, A>(TL, TR, g.gamma, Fm[fi]);
+            }
+            __syncthreads();
+#pragma unroll
+            for (int fi = 0; fi < FCH; ++fi)
+#pragma unroll
+                for (int v = 0; v < NV; ++v) lds[(v * FCH + fi) * ncell + cell] = Fm[fi][v];
+            __syncthreads();
+#pragma unroll
+            for (int fi = 0; fi < FCH; ++fi) {
+                const int F = f0 + fi;
+                double Fp[NV];
+                if (ia < N - 1) {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Fp[v] = lds[(v * FCH + fi) * ncell + cell + stride];
+                } else if (!mort_p) {
+                    double TL[NV], TR[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        double e, o;
+                        trace_eo<D, P>(K[v], A, F, e, o);
+                        TL[v] = e + o;
+                    }
+                    far_trace<D, P, A, GM>(g, K, leaf, +1, t, Lp, F, TR);
+                    rusanov<D, A>(TL, TR, g.gamma, Fp);
+                } else {
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Fp[v] = 0.0;
+                }
+                // lift: R_m += s_a w phi_m(+1)/M_m ((-1)^{m_A} Phi_- - Phi_+)
+                const double wm = mort_m ? 0.0 : sc, wp = mort_p ? 0.0 : sc;
+#pragma unroll
+                for (int v = 0; v < NV; ++v) {
+                    const double dm = wm * Fm[fi][v], dp = wp * Fp[v];
+                    const double even = dm - dp, odd = -(dm + dp);
+#pragma unroll
+                    for (int m = 0; m < NB; ++m) {
+                        const double c = kTab<D, P>.lift_f[A][F][m];
+                        if (c != 0.0) R[v][m] = fma(c, (kTab<D, P>.e[m][A] % 2 == 0) ? even : odd, R[v][m]);
+                    }
+                }
+            }
+        };
+        if constexpr (unroll_points<D, P>()) {
+            static_for<0, NF / FCH>(face_chunk_body);
+        } else {
+#pragma unroll 1
+            for (int ci = 0; ci < NF / FCH; ++ci) face_chunk_body(ci);
+        }
+    });
+
+    // ---- output
+    if constexpr (OM == OUT_RES64) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = R[v][m];
+    } else if constexpr (OM == OUT_RES32) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) g.out32[base + v * sv + m * ncell] = float(R[v][m]);
+    } else {
+        const double dt = *g.dt, a = g.rk_a, b = g.rk_b;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                const long idx = base + v * sv + m * ncell;
+                const double un = a != 0.0 ? g.un[idx] : 0.0;
+                g.out64[idx] = a * un + b * (K[v][m] + dt * R[v][m]);
+            }
+    }
+}
+
+// ------------------------------------------------------------------ guard fill
+// One thread per guard cell (leaf, face, t): Eq. 15 copy, Eq. 16 split of the
+// coarser neighbour cell, Eq. 17 combine of the 2^d finer cells, outflow
+// mirror K_m (-1)^{m_axis}.
+template <int D, int P, int CH>
+__device__ __forceinline__ void apply_split(const double *ks, double *out, int nfc, int v)
+{
+    constexpr int NB = Tab<D, P>::NB;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const double c = kTab<D, P>.split[CH][m][n];
+            if (c != 0.0) s = fma(c, ks[n], s);
+        }
+        out[(v * NB + m) * nfc] = s;
+    }
+}
+
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_fill(FillArgs g)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
+    const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= long(g.nfaces) * nfc) return;
+    const int fi = int(gid / nfc), t = int(gid % nfc);
+    const int lf = g.faces ? g.faces[fi] : fi;
+    const int leaf = lf / (2 * D), face = lf % (2 * D);
+    const int a = face / 2, side = (face & 1) ? 1 : -1;
+    const FaceLink L = g.links[lf];
+    double *out = g.guard + (long(lf) * NV * NB) * nfc + t;
+    const long sv = long(NB) * ncell;
+    const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2;
+    if (L.type == dgamr::LINK_SAME) {
+        const int c = face_cell(a, side > 0 ? 0 : N - 1, t, N, D);
+        const double *src = g.u + long(L.nbr[0]) * NV * sv + c;
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) out[(v * NB + m) * nfc] = src[v * sv + m * ncell];
+    } else if (L.type == dgamr::LINK_BOUNDARY) {
+        const int c = face_cell(a, side > 0 ? N - 1 : 0, t, N, D);
+        const double *src = g.u + long(leaf) * NV * sv + c;
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) {
+                const double k = src[v * sv + m * ncell];
+                const int ex = kTab<D, P>.e[m][0] * (a == 0) + kTab<D, P>.e[m][1] * (a == 1) +
+                               kTab<D, P>.e[m][2] * (a == 2);
+                out[(v * NB + m) * nfc] = (ex % 2) ? -k : k;
+            }
+    } else if (L.type == dgamr::LINK_COARSE) {
+        // the guard cell (fine size) lies in one coarse cell; along a it is
+        // the half nearest to this leaf
+        const int t0 = t % N, t1 = t / N;
+        const int c0 = (L.off[0] * N + t0) / 2, c1 = D == 3 ? (L.off[1] * N + t1) / 2 : 0;
+        const int b0 = t0 & 1, b1 = D == 3 ? (t1 & 1) : 0;
+        const int c = face_cell(a, side > 0 ? 0 : N - 1, c0 + N * c1, N, D);
+        const int child = ((side > 0 ? 0 : 1) << a) | (b0 << ta) | (D == 3 ? (b1 << tb) : 0);
+        const double *src = g.u + long(L.nbr[0]) * NV * sv + c;
+        for (int v = 0; v < NV; ++v) {
+            double ks[NB];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) ks[n] = src[v * sv + n * ncell];
+            switch (child) {
+            case 0: apply_split<D, P, 0>(ks, out, nfc, v); break;
+            case 1: apply_split<D, P, 1>(ks, out, nfc, v); break;
+            case 2: apply_split<D, P, 2>(ks, out, nfc, v); break;
+            case 3: apply_split<D, P, 3>(ks, out, nfc, v); break;
+            case 4: if constexpr (D == 3) apply_split<D, P, 4>(ks, out, nfc, v); break;
+            case 5: if constexpr (D == 3) apply_split<D, P, 5>(ks, out, nfc, v); break;
+            case 6: if constexpr (D == 3) apply_split<D, P, 6>(ks, out, nfc, v); break;
+            default: if constexpr (D == 3) apply_split<D, P, 7>(ks, out, nfc, v); break;
+            }
+        }
+    } else { // LINK_FINE: 2^d fine cells, 2 along a and 2^(d-1) tangential
+        const int t0 = t % N, t1 = t / N;
+        const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
+        const int fleaf = L.nbr[h0 + 2 * h1];
+        const int f0 = (2 * t0) % N, f1 = D == 3 ? (2 * t1) % N : 0;
+        const double *base = g.u + long(fleaf) * NV * sv;
+        for (int v = 0; v < NV; ++v) {
+            double acc[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) acc[m] = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < (1 << D); ++ch) {
+                const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
+                const int na = bits[a], n0 = bits[ta], n1 = D == 3 ? bits[tb] : 0;
+                const int nidx = side > 0 ? na : N - 2 + na;
+                const int c = face_cell(a, nidx, (f0 + n0) + N * (f1 + n1), N, D);
+                double ks[NB];
+#pragma unroll
+                for (int n = 0; n < NB; ++n) ks[n] = base[v * sv + n * ncell + c];
+#pragma unroll
+                for (int m = 0; m < NB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) {
+                        const double cc = kTab<D, P>.comb[ch][m][n];
+                        if (cc != 0.0) acc[m] = fma(cc, ks[n], acc[m]);
+                    }
+            }
+#pragma unroll
+            for (int m = 0; m < NB; ++m) out[(v * NB + m) * nfc] = acc[m];
+        }
+    }
+}
+
+} // namespace dgk

@@ -1,0 +1,330 @@
+// Auxiliary HIP kernels: positivity limiter, block indicator, analytic
+// initial-condition projection and L2 inheritance on refinement.
+#pragma once
+
+#include "kernels.hpp"  // apply_split
+
+namespace dgk {
+
+// ------------------------------------------------------------------ positivity limiter
+// Zhang-Shu scaling limiter (named in Sec. 5.3.2), per cell, on the point
+// set S = volume Gauss points + face Gauss points of all faces,
+// eps = min(1e-13, mean rho, p(mean)):
+//   theta1 = min(1, (rho_mean - eps)/(rho_mean - min_S rho)) scales the
+//   non-mean density modes; then theta2 = min over S of the root t in
+//   [0,1) of p(Ubar + t(U - Ubar)) = eps (1 where p >= eps) scales all
+//   non-mean modes.  The cell mean is never changed.
+template <int D, int P>
+struct LimiterPoints {
+    static constexpr int NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF, NB = Tab<D, P>::NB;
+    static constexpr int NPT = NQ + 2 * D * NF;
+    double phi[NPT][NB] = {};
+    constexpr LimiterPoints()
+    {
+            for (int q = 0; q < NQ; ++q)
+            for (int m = 0; m < NB; ++m) phi[q][m] = kTab<D, P>.phi_v[q][m];
+        int n = NQ;
+        for (int face = 0; face < 2 * D; ++face) {
+            int a = face / 2;
+            double sg = (face & 1) ? 1.0 : -1.0;
+            for (int f = 0; f < NF; ++f, ++n)
+                for (int m = 0; m < NB; ++m)
+                    phi[n][m] = kTab<D, P>.phi_f[a][f][m] * ((kTab<D, P>.e[m][a] % 2 && sg < 0) ? -1.0 : 1.0);
+        }
+    }
+};
+template <int D, int P>
+inline constexpr LimiterPoints<D, P> kLimPts{};
+
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_limit(double *u, int N, long ncell_total, double gamma)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    constexpr int NPT = LimiterPoints<D, P>::NPT;
+    const int ncell = D == 2 ? N * N : N * N * N;
+    long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= ncell_total) return;
+    long leaf = gid / ncell;
+    int c = int(gid % ncell);
+    const long sv = long(NB) * ncell, base = leaf * NV * sv + c;
+    double K[NV][NB];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NB; ++m) K[v][m] = u[base + v * sv + m * ncell];
+    const double gm1 = gamma - 1.0;
+    double mean[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mean[v] = K[v][0];
+    double pbar = pressure<D>(mean, gm1);
+    double eps = 1e-13;
+    eps = mean[0] < eps ? mean[0] : eps;
+    eps = pbar < eps ? pbar : eps;
+    // density
+    double rmin = mean[0];
+#pragma unroll 1
+    for (int pt = 0; pt < NPT; ++pt) {
+        double r = 0.0;
+#pragma unroll
+        for (int m = 0; m < NB; ++m) r = fma(kLimPts<D, P>.phi[pt][m], K[0][m], r);
+        rmin = r < rmin ? r : rmin;
+    }
+    double th1 = 1.0;
+    if (rmin < mean[0]) {
+        th1 = (mean[0] - eps) / (mean[0] - rmin);
+        th1 = th1 > 1.0 ? 1.0 : th1;
+    }
+    if (th1 < 1.0)
+#pragma unroll
+        for (int m = 1; m < NB; ++m) K[0][m] *= th1;
+    // pressure
+    double th2 = 1.0;
+#pragma unroll 1
+    for (int pt = 0; pt < NPT; ++pt) {
+        double U[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) s = fma(kLimPts<D, P>.phi[pt][m], K[v][m], s);
+            U[v] = s;
+        }
+        if (pressure<D>(U, gm1) < eps) {
+            double dr = U[0] - mean[0], dE = U[D + 1] - mean[D + 1];
+            double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                double dm = U[1 + a] - mean[1 + a];
+                dm2 += dm * dm;
+                mdm += mean[1 + a] * dm;
+                m2 += mean[1 + a] * mean[1 + a];
+            }
+            double A = dr * dE - 0.5 * dm2;
+            double B = mean[0] * dE + mean[D + 1] * dr - mdm - eps * dr / gm1;
+            double C = mean[0] * mean[D + 1] - 0.5 * m2 - eps * mean[0] / gm1;
+            double tq = 0.0;
+            if (C > 0.0) {
+                double disc = B * B - 4.0 * A * C;
+                disc = disc < 0.0 ? 0.0 : disc;
+                double den = -B + sqrt(disc);
+                tq = den > 0.0 ? 2.0 * C / den : 0.0;
+                tq = tq > 1.0 ? 1.0 : (tq < 0.0 ? 0.0 : tq);
+            }
+            th2 = tq < th2 ? tq : th2;
+        }
+    }
+    if (th1 < 1.0)
+#pragma unroll
+        for (int m = 1; m < NB; ++m) u[base + m * ncell] = K[0][m];
+    if (th2 < 1.0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 1; m < NB; ++m) u[base + v * sv + m * ncell] = K[v][m] * th2;
+}
+
+// ------------------------------------------------------------------ initial conditions
+// Analytic states (same definitions as the test workloads):
+//  VORTEX  eps, xc, yc, u_inf, v_inf, period_x, period_y: isentropic vortex
+//          with mean (rho,u,v,p) = (1,u_inf,v_inf,1), extruded in 3-D
+//  SEDOV   p_ambient, p_centre, cx, cy, cz: rho = 1, u = 0, p = p_centre
+//          within one finest cell edge of the centre along every axis
+//  UNIFORM rho, u, v, w, p
+//  XWAVE   amplitude, u, period_x: rho = 1 + A sin(2 pi (x - u t)/Lx),
+//          velocity (u,0,0), p = 1
+__device__ __forceinline__ double wrap_half(double d, double period)
+{
+    if (period <= 0.0) return d;
+    while (d >= 0.5 * period) d -= period;
+    while (d < -0.5 * period) d += period;
+    return d;
+}
+
+template <int D>
+__device__ void analytic(int kind, const IcParams &P, double t, double gamma, const double *x, const double *hmin,
+                         double *U)
+{
+    const double pi = 3.14159265358979323846;
+    double vel[3] = {0.0, 0.0, 0.0}, rho = 1.0, p = 1.0;
+    if (kind == DGAMR_IC_VORTEX) {
+        double eps = P.p[0];
+        double dx = wrap_half(x[0] - P.p[1] - P.p[3] * t, P.p[5]);
+        double dy = wrap_half(x[1] - P.p[2] - P.p[4] * t, P.p[6]);
+        double r2 = dx * dx + dy * dy;
+        double e1 = exp(0.5 * (1.0 - r2));
+        vel[0] = P.p[3] - eps / (2.0 * pi) * e1 * dy;
+        vel[1] = P.p[4] + eps / (2.0 * pi) * e1 * dx;
+        double T = 1.0 - (gamma - 1.0) * eps * eps / (8.0 * gamma * pi * pi) * exp(1.0 - r2);
+        rho = pow(T, 1.0 / (gamma - 1.0));
+        p = pow(rho, gamma);
+    } else if (kind == DGAMR_IC_SEDOV) {
+        bool inside = true;
+        for (int a = 0; a < D; ++a) inside = inside && fabs(x[a] - P.p[2 + a]) < hmin[a];
+        p = inside ? P.p[1] : P.p[0];
+    } else if (kind == DGAMR_IC_UNIFORM) {
+        rho = P.p[0];
+        for (int a = 0; a < D; ++a) vel[a] = P.p[1 + a];
+        p = P.p[4];
+    } else {
+        rho = 1.0 + P.p[0] * sin(2.0 * pi * (x[0] - P.p[1] * t) / P.p[2]);
+        vel[0] = P.p[1];
+    }
+    double ke = 0.0;
+    U[0] = rho;
+    for (int a = 0; a < D; ++a) {
+        U[1 + a] = rho * vel[a];
+        ke += vel[a] * vel[a];
+    }
+    U[D + 1] = p / (gamma - 1.0) + 0.5 * rho * ke;
+}
+
+// Gauss points (p+3 per axis) and Legendre values there, for the
+// initial-condition projection.
+template <int P>
+struct IcTab {
+    static constexpr int QI = P + 3;
+    double x[QI] = {}, w[QI] = {}, leg1[QI][P + 1] = {};
+    constexpr IcTab()
+    {
+        for (int q = 0; q < QI; ++q) {
+            x[q] = gl_x(QI, q);
+            w[q] = gl_w(QI, q);
+            for (int n = 0; n <= P; ++n) leg1[q][n] = leg(n, x[q]);
+        }
+    }
+};
+template <int P>
+inline constexpr IcTab<P> kIcTab{};
+
+// K_m = (1/M_m) int phi_m U0 dV with p+3 Gauss points per axis
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_project_ic(double *u, const LeafGeo *geo, int N, long ncell_total, int kind,
+                                                    IcParams prm, double t, double gamma, double hmin0, double hmin1,
+                                                    double hmin2)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB, QI = P + 3;
+    const int ncell = D == 2 ? N * N : N * N * N;
+    const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= ncell_total) return;
+    const long leaf = gid / ncell;
+    const int c = int(gid % ncell);
+    int ijk[3];
+    cell_ijk(c, N, D, ijk);
+    const LeafGeo G = geo[leaf];
+    const double hmin[3] = {hmin0, hmin1, hmin2};
+    double acc[NV][NB];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NB; ++m) acc[v][m] = 0.0;
+    constexpr int NQI = ipow(QI, D);
+#pragma unroll 1
+    for (int q = 0; q < NQI; ++q) {
+        const int qi[3] = {q % QI, (q / QI) % QI, q / (QI * QI)};
+        double x[3] = {0, 0, 0}, w = 1.0;
+        for (int a = 0; a < D; ++a) {
+            w *= kIcTab<P>.w[qi[a]];
+            x[a] = G.lo[a] + (ijk[a] + 0.5 * (kIcTab<P>.x[qi[a]] + 1.0)) * G.h[a];
+        }
+        double U[NV];
+        analytic<D>(kind, prm, t, gamma, x, hmin, U);
+#pragma unroll
+        for (int m = 0; m < NB; ++m) {
+            double ph = w;
+#pragma unroll
+            for (int a = 0; a < D; ++a) ph *= kIcTab<P>.leg1[qi[a]][kTab<D, P>.e[m][a]];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) acc[v][m] = fma(ph, U[v], acc[v][m]);
+        }
+    }
+    const long sv = long(NB) * ncell, base = leaf * NV * sv + c;
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NB; ++m) u[base + v * sv + m * ncell] = acc[v][m] * kTab<D, P>.inv_mass[m];
+}
+
+// ------------------------------------------------------------------ inheritance
+// Eq. 11-14 on a refinement switch: copy, split (child cells of a refined
+// leaf from the parent cells) or combine (cells of a coarsened parent from
+// its 2^d children's cells).
+template <int D, int P>
+__global__ __launch_bounds__(256) void k_inherit(const double *uold, double *unew, const Inherit *inh, int N,
+                                                 long ncell_total)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    const int ncell = D == 2 ? N * N : N * N * N;
+    const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= ncell_total) return;
+    const long leaf = gid / ncell;
+    const int c = int(gid % ncell);
+    int ijk[3];
+    cell_ijk(c, N, D, ijk);
+    const Inherit I = inh[leaf];
+    const long sv = long(NB) * ncell;
+    double *out = unew + leaf * NV * sv + c;
+    if (I.type == dgamr::INH_COPY) {
+        const double *src = uold + long(I.src[0]) * NV * sv + c;
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) out[v * sv + m * ncell] = src[v * sv + m * ncell];
+    } else if (I.type == dgamr::INH_SPLIT) {
+        int pijk[3] = {0, 0, 0}, child = 0;
+        for (int a = 0; a < D; ++a) {
+            const int gi = ((I.child >> a) & 1) * N + ijk[a];
+            pijk[a] = gi >> 1;
+            child |= (gi & 1) << a;
+        }
+        const int pc = pijk[0] + N * (pijk[1] + N * pijk[2]);
+        const double *src = uold + long(I.src[0]) * NV * sv + pc;
+        // apply_split writes out[(v*NB + m)*stride]: with stride = ncell it
+        // addresses U[leaf][v][m][cell] relative to this cell
+        for (int v = 0; v < NV; ++v) {
+            double ks[NB];
+#pragma unroll
+            for (int n = 0; n < NB; ++n) ks[n] = src[v * sv + n * ncell];
+            switch (child) {
+            case 0: apply_split<D, P, 0>(ks, out, ncell, v); break;
+            case 1: apply_split<D, P, 1>(ks, out, ncell, v); break;
+            case 2: apply_split<D, P, 2>(ks, out, ncell, v); break;
+            case 3: apply_split<D, P, 3>(ks, out, ncell, v); break;
+            case 4: if constexpr (D == 3) apply_split<D, P, 4>(ks, out, ncell, v); break;
+            case 5: if constexpr (D == 3) apply_split<D, P, 5>(ks, out, ncell, v); break;
+            case 6: if constexpr (D == 3) apply_split<D, P, 6>(ks, out, ncell, v); break;
+            default: if constexpr (D == 3) apply_split<D, P, 7>(ks, out, ncell, v); break;
+            }
+        }
+    } else {
+        int cl = 0, fbase[3] = {0, 0, 0};
+        for (int a = 0; a < D; ++a) {
+            const int gi = 2 * ijk[a];
+            cl |= (gi / N) << a;
+            fbase[a] = gi % N;
+        }
+        const double *src = uold + long(I.src[cl]) * NV * sv;
+        for (int v = 0; v < NV; ++v) {
+            double acc[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) acc[m] = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < (1 << D); ++ch) {
+                const int fc = (fbase[0] + (ch & 1)) +
+                               N * ((fbase[1] + ((ch >> 1) & 1)) + (D == 3 ? N * (fbase[2] + ((ch >> 2) & 1)) : 0));
+                double ks[NB];
+#pragma unroll
+                for (int n = 0; n < NB; ++n) ks[n] = src[v * sv + n * ncell + fc];
+#pragma unroll
+                for (int m = 0; m < NB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) {
+                        const double cc = kTab<D, P>.comb[ch][m][n];
+                        if (cc != 0.0) acc[m] = fma(cc, ks[n], acc[m]);
+                    }
+            }
+#pragma unroll
+            for (int m = 0; m < NB; ++m) out[v * sv + m * ncell] = acc[m];
+        }
+    }
+}
+
+} // namespace dgk

@@ -1,0 +1,27 @@
+// Launch entry points of the degree-templated kernels.  Each (dim, degree)
+// pair is compiled in its own translation unit (inst.hip with DG_D, DG_P),
+// so the host API sees only these declarations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "kernel_common.hpp"
+
+namespace dgk {
+
+// residual / fused stage: grid = one workgroup per leaf, N^d threads
+template <int D, int P>
+hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, hipStream_t s);
+// guard fill: one thread per guard cell of the listed faces
+template <int D, int P>
+hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s);
+template <int D, int P>
+hipError_t launch_limit(double *u, int N, long ncell_total, double gamma, hipStream_t s);
+template <int D, int P>
+hipError_t launch_project_ic(double *u, const LeafGeo *geo, int N, long ncell_total, int kind, const IcParams &prm,
+                             double t, double gamma, const double *hmin, hipStream_t s);
+template <int D, int P>
+hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, int N, long ncell_total,
+                          hipStream_t s);
+
+} // namespace dgk

@@ -1,0 +1,232 @@
+"""Thin Python binding of the dgamr C-ABI (``include/dgamr.h``).
+
+Argument marshalling only: every step of the DG path runs in the HIP
+library ``libdgamr.so``.  PyTorch supplies device memory and the current
+HIP stream.  There is no fallback: if the library is missing, importing the
+binding's entry points raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdgamr.so")
+
+OK, EINVAL, EUNSUPPORTED, EBALANCE, EHIP, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5, -6
+BC_PERIODIC, BC_OUTFLOW = 0, 1
+FP64, FP32_MFMA = 0, 1
+HANG_PAPER, HANG_CONSERVATIVE = 0, 1
+LIMITER_NONE, LIMITER_POSITIVITY = 0, 1
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE = 0, 1, 2, 3
+
+EXPORTS = [
+    "dgamr_create_forest", "dgamr_destroy_forest", "dgamr_num_leaves", "dgamr_leaf_keys",
+    "dgamr_state_bytes", "dgamr_set_refinement", "dgamr_apply_refinement",
+    "dgamr_fill_guardcells", "dgamr_dg_residual", "dgamr_rk_stage", "dgamr_compute_dt",
+    "dgamr_step", "dgamr_conserved_totals", "dgamr_limit_positivity", "dgamr_indicator",
+    "dgamr_project_ic", "dgamr_check_state", "dgamr_last_error",
+]
+
+
+class DgamrError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"dgamr error {code}: {msg}")
+        self.code = code
+
+
+class ForestDesc(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int), ("degree", ctypes.c_int), ("n_cell", ctypes.c_int),
+        ("roots", ctypes.c_int * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
+        ("bc", ctypes.c_int * 3), ("max_level", ctypes.c_int), ("gamma", ctypes.c_double),
+        ("precision", ctypes.c_int), ("hanging", ctypes.c_int), ("limiter", ctypes.c_int),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdgamr.so (built by paper_2502_12620_amd.build)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run paper_2502_12620_amd.build.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64p, sz = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_size_t)
+        L.dgamr_create_forest.argtypes = [ctypes.POINTER(ForestDesc), ctypes.POINTER(vp)]
+        L.dgamr_destroy_forest.argtypes = [vp]
+        L.dgamr_num_leaves.argtypes = [vp, i64p]
+        L.dgamr_leaf_keys.argtypes = [vp, vp]
+        L.dgamr_state_bytes.argtypes = [vp, sz, sz, sz, sz]
+        L.dgamr_set_refinement.argtypes = [vp, vp, i64p]
+        L.dgamr_apply_refinement.argtypes = [vp, vp, vp, vp]
+        L.dgamr_fill_guardcells.argtypes = [vp, vp, vp, vp]
+        L.dgamr_dg_residual.argtypes = [vp, vp, vp, vp, vp]
+        L.dgamr_rk_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
+        L.dgamr_compute_dt.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
+        L.dgamr_step.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
+        L.dgamr_conserved_totals.argtypes = [vp, vp, vp, vp, vp]
+        L.dgamr_limit_positivity.argtypes = [vp, vp, vp]
+        L.dgamr_indicator.argtypes = [vp, vp, vp, vp, vp]
+        L.dgamr_project_ic.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp, vp]
+        L.dgamr_check_state.argtypes = [vp, vp, i64p, vp, vp]
+        L.dgamr_last_error.restype = ctypes.c_char_p
+        for name in EXPORTS:
+            if name != "dgamr_last_error":
+                getattr(L, name).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != OK:
+        raise DgamrError(rc, lib().dgamr_last_error().decode())
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+class Forest:
+    """A device-resident forest of DG blocks (``dgamr_forest``)."""
+
+    def __init__(self, dim, degree, n_cell, roots, lo, hi, bc, max_level, gamma=1.4,
+                 precision=FP64, hanging=HANG_PAPER, limiter=LIMITER_NONE):
+        d = ForestDesc()
+        d.dim, d.degree, d.n_cell = dim, degree, n_cell
+        roots, lo, hi, bc = (list(x) for x in (roots, lo, hi, bc))
+        for a in range(3):
+            d.roots[a] = roots[a] if a < dim else 1
+            d.lo[a] = lo[a] if a < dim else 0.0
+            d.hi[a] = hi[a] if a < dim else 1.0
+            d.bc[a] = bc[a] if a < dim else BC_PERIODIC
+        d.max_level, d.gamma = max_level, gamma
+        d.precision, d.hanging, d.limiter = precision, hanging, limiter
+        self.desc = d
+        self.dim, self.degree, self.N = dim, degree, n_cell
+        self.nv = dim + 2
+        self.nb = {2: [1, 3, 6, 10], 3: [1, 4, 10, 20]}[dim][degree]
+        self.precision = precision
+        h = ctypes.c_void_p()
+        _check(lib().dgamr_create_forest(ctypes.byref(d), ctypes.byref(h)))
+        self.h = h
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dgamr_destroy_forest(self.h)
+            self.h = None
+
+    # ---- queries
+    @property
+    def n_leaves(self) -> int:
+        n = ctypes.c_int64()
+        _check(lib().dgamr_num_leaves(self.h, ctypes.byref(n)))
+        return n.value
+
+    @property
+    def ncell(self) -> int:
+        return self.N ** self.dim
+
+    def keys(self):
+        k = torch.zeros((self.n_leaves, 5), dtype=torch.int32)
+        _check(lib().dgamr_leaf_keys(self.h, _ptr(k)))
+        return k.numpy()
+
+    def sizes(self):
+        u, g, r, w = (ctypes.c_size_t() for _ in range(4))
+        _check(lib().dgamr_state_bytes(self.h, ctypes.byref(u), ctypes.byref(g), ctypes.byref(r), ctypes.byref(w)))
+        return u.value, g.value, r.value, w.value
+
+    # ---- allocation helpers (caller-owned device buffers)
+    def state_shape(self):
+        return (self.n_leaves, self.nv, self.nb, self.ncell)
+
+    def guard_shape(self):
+        return (self.n_leaves, 2 * self.dim, self.nv, self.nb, self.N ** (self.dim - 1))
+
+    def new_state(self, device="cuda"):
+        return torch.zeros(self.state_shape(), dtype=torch.float64, device=device)
+
+    def new_guard(self, device="cuda"):
+        return torch.zeros(self.guard_shape(), dtype=torch.float64, device=device)
+
+    def new_residual(self, device="cuda"):
+        dt = torch.float32 if self.precision == FP32_MFMA else torch.float64
+        return torch.zeros(self.state_shape(), dtype=dt, device=device)
+
+    def new_work(self, device="cuda"):
+        return torch.zeros(self.sizes()[3] // 8, dtype=torch.float64, device=device)
+
+    # ---- C-ABI calls
+    def set_refinement(self, flags) -> int:
+        f = torch.as_tensor(flags, dtype=torch.int8).contiguous()
+        assert f.numel() == self.n_leaves
+        n = ctypes.c_int64()
+        _check(lib().dgamr_set_refinement(self.h, _ptr(f), ctypes.byref(n)))
+        return n.value
+
+    def apply_refinement(self, u_old, u_new, stream=None):
+        """u_new: caller-allocated state of the size set_refinement returned."""
+        _check(lib().dgamr_apply_refinement(self.h, _ptr(u_old), _ptr(u_new), _stream(stream)))
+
+    def adapt(self, flags, u_old, stream=None):
+        """set_refinement + apply_refinement; returns the new state tensor."""
+        n_new = self.set_refinement(flags)
+        u_new = torch.zeros((n_new, self.nv, self.nb, self.ncell), dtype=torch.float64, device=u_old.device)
+        self.apply_refinement(u_old, u_new, stream)
+        return u_new
+
+    def fill_guardcells(self, u, guard, stream=None):
+        _check(lib().dgamr_fill_guardcells(self.h, _ptr(u), _ptr(guard), _stream(stream)))
+
+    def dg_residual(self, u, guard, r, stream=None):
+        _check(lib().dgamr_dg_residual(self.h, _ptr(u), _ptr(guard), _ptr(r), _stream(stream)))
+
+    def rk_stage(self, stage, dt_dev, u_n, u_s, r, u_next, stream=None):
+        _check(lib().dgamr_rk_stage(self.h, stage, _ptr(dt_dev), _ptr(u_n), _ptr(u_s), _ptr(r), _ptr(u_next),
+                                    _stream(stream)))
+
+    def compute_dt(self, cfl, u, dt_dev, work, stream=None):
+        _check(lib().dgamr_compute_dt(self.h, cfl, _ptr(u), _ptr(dt_dev), _ptr(work), _stream(stream)))
+
+    def step(self, u, work, dt_dev, cfl=0.1, stream=None):
+        """One SSP-RK3 step in place; cfl <= 0 uses the dt already in dt_dev."""
+        _check(lib().dgamr_step(self.h, cfl, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
+
+    def conserved_totals(self, u, work, stream=None):
+        t = torch.zeros(self.nv, dtype=torch.float64, device=u.device)
+        _check(lib().dgamr_conserved_totals(self.h, _ptr(u), _ptr(t), _ptr(work), _stream(stream)))
+        return t
+
+    def limit_positivity(self, u, stream=None):
+        _check(lib().dgamr_limit_positivity(self.h, _ptr(u), _stream(stream)))
+
+    def indicator(self, u, work, stream=None):
+        eta = torch.zeros(self.n_leaves, dtype=torch.float64, device=u.device)
+        _check(lib().dgamr_indicator(self.h, _ptr(u), _ptr(eta), _ptr(work), _stream(stream)))
+        return eta
+
+    def project_ic(self, kind, params, t=0.0, u=None, stream=None):
+        if u is None:
+            u = self.new_state()
+        prm = (ctypes.c_double * 8)(*(list(params) + [0.0] * (8 - len(params))))
+        _check(lib().dgamr_project_ic(self.h, kind, prm, t, _ptr(u), _stream(stream)))
+        return u
+
+    def check_state(self, u, work, stream=None) -> int:
+        bad = ctypes.c_int64()
+        rc = lib().dgamr_check_state(self.h, _ptr(u), ctypes.byref(bad), _ptr(work), _stream(stream))
+        if rc not in (OK, ENONPHYSICAL):
+            _check(rc)
+        return bad.value

@@ -1,0 +1,179 @@
+"""Seeded, synthetic workload descriptions shared by the GPU path, the tests
+and the benchmark.
+
+This module holds no arithmetic of the DG method: only forest shapes,
+initial-refinement rules (by root/leaf geometry), analytic initial-condition
+parameters, step counts and the random draws of the batched and served
+workloads.  Every workload is synthetic; there is no dataset.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+PERIODIC, OUTFLOW = 0, 1
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE = 0, 1, 2, 3
+
+
+@dataclass
+class Workload:
+    name: str
+    dim: int
+    degree: int
+    n_cell: int
+    roots: tuple
+    lo: tuple
+    hi: tuple
+    bc: tuple
+    max_level: int
+    ic_kind: int
+    ic_params: list
+    steps: int
+    cfl: float = 0.1
+    gamma: float = 1.4
+    limiter: bool = False
+    regrid_every: int = 0
+    refine_above: float = 1.2
+    coarsen_below: float = 1.01
+    # list of refinement passes; each pass maps leaf keys -> flags
+    initial_refinement: list = field(default_factory=list)
+
+    def desc(self) -> dict:
+        return dict(dim=self.dim, degree=self.degree, n_cell=self.n_cell, roots=self.roots, lo=self.lo,
+                    hi=self.hi, bc=self.bc, max_level=self.max_level, gamma=self.gamma)
+
+    def leaf_boxes(self, keys):
+        """Physical (lower corner, edge) of each leaf key (tree, level, i, j, k)."""
+        d = self.dim
+        roots = list(self.roots) + [1] * (3 - d)
+        out = []
+        for tree, level, i, j, k in np.asarray(keys):
+            r = [tree % roots[0], (tree // roots[0]) % roots[1], tree // (roots[0] * roots[1])]
+            idx = [i, j, k]
+            root_edge = [(self.hi[a] - self.lo[a]) / roots[a] for a in range(d)]
+            edge = np.array([root_edge[a] / 2 ** (level - 1) for a in range(d)])
+            lo = np.array([self.lo[a] + r[a] * root_edge[a] + idx[a] * edge[a] for a in range(d)])
+            out.append((lo, edge, int(level)))
+        return out
+
+    def dofs(self, n_leaves) -> int:
+        nb = math.comb(self.degree + self.dim, self.dim)
+        return n_leaves * (self.dim + 2) * nb * self.n_cell ** self.dim
+
+
+def refine_roots_near(centre, radius):
+    """Flags +1 for the leaves whose centre lies within `radius` of `centre`."""
+    def rule(w: Workload, keys):
+        fl = []
+        for lo, edge, _ in w.leaf_boxes(keys):
+            c = lo + 0.5 * edge
+            fl.append(1 if np.hypot(*(c - np.asarray(centre))) <= radius else 0)
+        return np.array(fl, dtype=np.int8)
+    return rule
+
+
+def refine_touching(point, level=None):
+    """Flags +1 for the leaves (optionally of one level) whose closed box
+    contains `point`."""
+    def rule(w: Workload, keys):
+        fl = []
+        for lo, edge, lv in w.leaf_boxes(keys):
+            inside = all(lo[a] <= point[a] <= lo[a] + edge[a] for a in range(w.dim))
+            fl.append(1 if inside and (level is None or lv == level) else 0)
+        return np.array(fl, dtype=np.int8)
+    return rule
+
+
+# ---------------------------------------------------------------- the fixed workloads
+def vortex_c1() -> Workload:
+    """2-D isentropic vortex (strength 5, periodic [0,10]^2), single level:
+    4x4 roots of 8x8 cells, P1, CFL 0.1, 20 steps."""
+    return Workload("c1_vortex2d_p1_single_level", 2, 1, 8, (4, 4), (0.0, 0.0), (10.0, 10.0),
+                    (PERIODIC, PERIODIC), 1, IC_VORTEX, [5.0, 5.0, 5.0, 1.0, 1.0, 10.0, 10.0], 20)
+
+
+def vortex_c2() -> Workload:
+    """2-D vortex, 2-level static AMR: 8x8 roots of 16x16 cells, roots with
+    centre within 2.5 of (5,5) refined once (100 leaves), P2, 200 steps."""
+    return Workload("c2_vortex2d_p2_two_level", 2, 2, 16, (8, 8), (0.0, 0.0), (10.0, 10.0),
+                    (PERIODIC, PERIODIC), 2, IC_VORTEX, [5.0, 5.0, 5.0, 1.0, 1.0, 10.0, 10.0], 200,
+                    initial_refinement=[refine_roots_near((5.0, 5.0), 2.5)])
+
+
+def sedov_c3() -> Workload:
+    """3-D Sedov-style blast on [0,1]^3: 4^3 roots of 8^3 cells, levels 1..3
+    (176 leaves initially), rho = 1, p = 1e-5 except 1e3 in the 8 finest
+    cells at the centre, outflow, P2, positivity limiter, regrid every 10
+    steps, 100 steps."""
+    c = (0.5, 0.5, 0.5)
+    return Workload("c3_sedov3d_p2_amr", 3, 2, 8, (4, 4, 4), (0.0, 0.0, 0.0), (1.0, 1.0, 1.0),
+                    (OUTFLOW, OUTFLOW, OUTFLOW), 3, IC_SEDOV, [1e-5, 1e3, 0.5, 0.5, 0.5], 100,
+                    limiter=True, regrid_every=10,
+                    initial_refinement=[refine_touching(c), refine_touching(c, level=2)])
+
+
+def roofline_2d(k: int, degree: int) -> Workload:
+    """Uniform 2-D vortex forest of k x k roots of 16x16 cells (roofline sweep)."""
+    L = 2.5 * k
+    return Workload(f"rs_vortex2d_k{k}_p{degree}", 2, degree, 16, (k, k), (0.0, 0.0), (L, L),
+                    (PERIODIC, PERIODIC), 1, IC_VORTEX, [5.0, L / 2, L / 2, 1.0, 1.0, L, L], 10)
+
+
+def roofline_3d(k: int, degree: int) -> Workload:
+    """Uniform 3-D extruded-vortex forest of k^3 roots of 8^3 cells."""
+    L = 1.25 * k
+    return Workload(f"rs_vortex3d_k{k}_p{degree}", 3, degree, 8, (k, k, k), (0.0, 0.0, 0.0), (L, L, L),
+                    (PERIODIC, PERIODIC, PERIODIC), 1, IC_VORTEX, [5.0, L / 2, L / 2, 1.0, 1.0, L, L], 10)
+
+
+def batched_forests(n: int = 512, seed: int = 2502):
+    """The batched workload: n independent 2-D vortex forests.  Root count
+    R ~ U{4..256} as nx x ny (nx the largest divisor of R not above sqrt R),
+    root edge 2.5, 16x16 cells, degree ~ U{1,2,3}, strength ~ U[1,5],
+    centre ~ U(domain), 20 steps."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        R = int(rng.integers(4, 257))
+        nx = max(d for d in range(1, int(math.isqrt(R)) + 1) if R % d == 0)
+        ny = R // nx
+        p = int(rng.integers(1, 4))
+        eps = float(rng.uniform(1.0, 5.0))
+        Lx, Ly = 2.5 * nx, 2.5 * ny
+        cx, cy = float(rng.uniform(0, Lx)), float(rng.uniform(0, Ly))
+        out.append(Workload(f"batch{i}", 2, p, 16, (nx, ny), (0.0, 0.0), (Lx, Ly), (PERIODIC, PERIODIC), 1,
+                            IC_VORTEX, [eps, cx, cy, 1.0, 1.0, Lx, Ly], 20))
+    return out
+
+
+def served_requests(n: int = 1000, seed: int = 12620, rate: float = 200.0):
+    """The served workload: a Poisson stream (mean `rate` requests/s) of
+    2-D/3-D vortex solves.  Blocks ~ log-uniform in [16, 2048] (2-D 16x16
+    cells, 3-D 8^3), degree ~ U{1,2,3}, steps ~ U{50..500}.  Returns
+    (arrival_time_s, Workload) pairs."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for i in range(n):
+        t += float(rng.exponential(1.0 / rate))
+        dim = int(rng.integers(2, 4))
+        blocks = int(round(math.exp(rng.uniform(math.log(16), math.log(2048)))))
+        p = int(rng.integers(1, 4))
+        steps = int(rng.integers(50, 501))
+        if dim == 2:
+            nx = max(d for d in range(1, int(math.isqrt(blocks)) + 1) if blocks % d == 0)
+            roots = (nx, blocks // nx)
+            Lx, Ly = 2.5 * roots[0], 2.5 * roots[1]
+            w = Workload(f"req{i}", 2, p, 16, roots, (0.0, 0.0), (Lx, Ly), (PERIODIC, PERIODIC), 1, IC_VORTEX,
+                         [3.0, Lx / 2, Ly / 2, 1.0, 1.0, Lx, Ly], steps)
+        else:
+            c = round(blocks ** (1.0 / 3.0))
+            c = max(2, c)
+            roots = (c, c, max(1, blocks // (c * c)))
+            L = [1.25 * r for r in roots]
+            w = Workload(f"req{i}", 3, p, 8, roots, (0.0, 0.0, 0.0), tuple(L), (PERIODIC,) * 3, 1, IC_VORTEX,
+                         [3.0, L[0] / 2, L[1] / 2, 1.0, 1.0, L[0], L[1]], steps)
+        out.append((t, w))
+    return out
