@@ -1,0 +1,172 @@
+"""Benchmark of the block-AMR DG hot path on one MI355X.
+
+One step = one full SSP-RK3 time step of the 2-D Euler two-level AMR vortex
+workload (8x8 roots of 16x16 cells, the 12 roots near the vortex refined
+once -> 100 leaves, degree 2, FP64): the CFL time step and, per stage, the
+guard traces, the residual and the stage update.  The timed steps run
+through dgamr_run: three fused stage kernels per step, the CFL reduction
+folded into the previous step's last stage.
+
+Prints one JSON line: DOF-stage updates/s over exactly --steps timed steps
+(inputs resident in HBM), the roofline of the dominant kernel (the fused
+stage kernel, timed live with HIP events around each of its launches), and
+the oracle's rate on the host cores for a bounded sample of the same
+workload.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+STAGE_SOURCES = ["kernels.hpp", "kernel_common.hpp", "dg_tables.hpp", "inst.hip"]
+
+
+def kernel_hash() -> str:
+    h = hashlib.sha256()
+    for f in STAGE_SOURCES:
+        with open(os.path.join(ROOT, "paper_2502_12620_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes_per_stage(w, n_leaves: int) -> dict:
+    """Bytes the fused stage kernel must move, per launch, averaged over the
+    three stages: read U_s, read U_n on stages 2 and 3, write U_next, and
+    read the neighbours' face cells (one cell layer per block face)."""
+    dof = w.dofs(n_leaves)
+    face_dof = dof * 2 * w.dim / w.n_cell
+    per_stage = [8 * dof + 8 * face_dof + 8 * dof,            # stage 1: a = 0, U_n not read
+                 16 * dof + 8 * face_dof + 8 * dof,
+                 16 * dof + 8 * face_dof + 8 * dof]
+    return {"dof": dof, "bytes_per_launch": sum(per_stage) / 3.0,
+            "bytes_per_dof": sum(per_stage) / 3.0 / dof}
+
+
+def read_counter_traffic(workload_name: str):
+    """HBM traffic per launch of the stage kernel from the committed counter
+    summary, if it was taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", "stage_kernel_c2_counters.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel_sources_sha256_16:\s*([0-9a-f]+)", txt)
+    m_bytes = re.search(r"hbm_bytes_per_launch:\s*([0-9.eE+]+)", txt)
+    m_wl = re.search(r"workload:\s*(\S+)", txt)
+    if not (m_hash and m_bytes and m_wl) or m_hash.group(1) != kernel_hash() or m_wl.group(1) != workload_name:
+        return None
+    return float(m_bytes.group(1))
+
+
+def cpu_baseline(w, budget_s: float):
+    """The oracle (as it stands) on the host cores: whole SSP-RK3 steps of the
+    same workload from the same initial state, as many as fit the budget."""
+    import oracle as O
+
+    f = O.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
+    for rule in w.initial_refinement:
+        f.adapt(rule(w, f.keys()))
+    u = f.project_ic(O.IC_VORTEX, w.ic_params)
+    dof = w.dofs(f.n_leaves)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        f.step(u, w.cfl)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > budget_s or steps >= w.steps:
+            break
+    return {"value": dof * 3 * steps / el, "unit": "DOF-stage updates/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"{steps} SSP-RK3 steps of {w.name} ({f.n_leaves} leaves, {dof} DOF) from the vortex "
+                      f"initial state, {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--hanging", choices=["paper", "conservative"], default="paper")
+    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the whole forest lives on one "
+              "MI355X; sharding is described in DESIGN.md, not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2502_12620_amd import dgamr as G
+    from paper_2502_12620_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    w = W.vortex_c2()
+    hang = G.HANG_PAPER if args.hanging == "paper" else G.HANG_CONSERVATIVE
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, hanging=hang)
+    z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
+    for rule in w.initial_refinement:
+        z = f.adapt(rule(w, f.keys()), z)
+    u = f.project_ic(G.IC_VORTEX, w.ic_params)
+    work = f.new_work()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    n = f.n_leaves
+    ab = algorithmic_bytes_per_stage(w, n)
+    dof = ab["dof"]
+
+    f.run(u, work, dt, args.warmup, w.cfl)
+    torch.cuda.synchronize()
+    f.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.run(u, work, dt, args.steps, w.cfl)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    f.profile_enable(False)
+    stage_ms, launches = f.profile_read()
+    bad = f.check_state(u, work)
+    if bad:
+        print(f"non-physical state after the timed steps ({bad} cells)", file=sys.stderr)
+        sys.exit(3)
+
+    value = dof * 3 * args.steps / elapsed
+    avg_s = stage_ms / 1e3 / max(launches, 1)
+    achieved = ab["bytes_per_launch"] / avg_s / 1e9
+    traffic = read_counter_traffic(w.name)
+    out = {
+        "metric": "DOF-stage updates/s",
+        "value": value,
+        "unit": "DOF-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "leaves": n, "cells": n * w.n_cell ** w.dim, "dofs": dof,
+                   "degree": w.degree, "n_cell": w.n_cell, "hanging": args.hanging, "precision": "fp64"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_stage (fused residual + RK stage)",
+                     "avg_launch_us": avg_s * 1e6, "launches": launches,
+                     "algorithmic_bytes_per_launch": ab["bytes_per_launch"],
+                     "algorithmic_bytes_per_dof": ab["bytes_per_dof"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

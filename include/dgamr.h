@@ -135,9 +135,20 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
 /* Sec. 4.3 step 2: one SSP-RK3 time step, in place on u: dt from the CFL
  * condition (cfl > 0) or taken from dt_dev (cfl <= 0), then per stage the
  * guard fill, the residual and the stage update (and the positivity limiter
- * when the forest asks for it).  Asynchronous; captures into a HIP graph. */
+ * when the forest asks for it).  The guard traces are computed inside the
+ * stage kernel straight from the neighbours' cells (same values as
+ * dgamr_fill_guardcells).  Asynchronous; captures into a HIP graph. */
 int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev,
                hipStream_t stream);
+
+/* Sec. 4.3 step 2 repeated: nsteps SSP-RK3 steps in place on u, three
+ * kernel launches per step.  With cfl > 0 the CFL time step of each step
+ * after the first is folded into the previous step's last stage (its
+ * new-state wave speeds are max-reduced on the device), so the results
+ * equal nsteps calls of dgamr_step; dt_dev holds the last step's dt.  With
+ * cfl <= 0 every step uses the dt already in dt_dev. */
+int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev,
+              hipStream_t stream);
 
 /* Conserved totals T_v = sum over cells |cell| * mean_v (FP64), written to
  * totals_dev[n_var]; a fixed-order reduction. */
@@ -161,6 +172,14 @@ int dgamr_project_ic(dgamr_forest *f, int kind, const double *params /* 8 */, do
 /* Non-physical state check: sets *bad (host) to the number of cells with a
  * non-finite value or a non-positive mean density or pressure.  Synchronous. */
 int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work, hipStream_t stream);
+
+/* Measurement hook: while enabled, every launch of the fused stage kernel
+ * inside dgamr_step is bracketed by two HIP events on the caller's stream
+ * (not usable under HIP graph capture).  dgamr_profile_read waits for the
+ * recorded events, returns the summed kernel time in milliseconds and the
+ * number of launches, and clears the record. */
+int dgamr_profile_enable(dgamr_forest *f, int enable);
+int dgamr_profile_read(dgamr_forest *f, double *stage_ms, int64_t *stage_launches);
 
 const char *dgamr_last_error(void);
 

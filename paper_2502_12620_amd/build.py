@@ -35,11 +35,19 @@ def _run(cmd):
 def build(verbose: bool = False) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     jobs = []
+    objs_keep = []
     for s in HIP_SOURCES:
         o = os.path.join(OBJDIR, s + ".o")
         jobs.append(["hipcc", *HIPFLAGS, "-c", os.path.join(CSRC, s), "-o", o])
+    # DGAMR_BUILD_ONLY="2_2,api" recompiles only those units and relinks the
+    # existing objects of the others (a development shortcut; the default
+    # compiles everything)
+    only = [x for x in os.environ.get("DGAMR_BUILD_ONLY", "").split(",") if x]
     for d, p in INSTANCES:
         o = os.path.join(OBJDIR, f"inst_{d}_{p}.o")
+        if only and f"{d}_{p}" not in only and os.path.exists(o):
+            objs_keep.append(o)
+            continue
         jobs.append(["hipcc", *HIPFLAGS, f"-DDG_D={d}", f"-DDG_P={p}", "-c", os.path.join(CSRC, "inst.hip"), "-o", o])
     for s in CXX_SOURCES:
         o = os.path.join(OBJDIR, s + ".o")
@@ -52,7 +60,7 @@ def build(verbose: bool = False) -> str:
     if verbose:
         for l in logs:
             sys.stderr.write(l)
-    objs = [j[-1] for j in jobs]
+    objs = [j[-1] for j in jobs] + objs_keep
     _run(["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp", *objs])
     os.replace(LIB + ".tmp", LIB)
     return LIB

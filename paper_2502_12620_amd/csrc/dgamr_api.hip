@@ -43,6 +43,9 @@ struct dgamr_forest {
     int n_hang = 0;
     int cap = 0;             // leaves the device tables can hold
     int hang_cap = 0;
+    bool prof = false;       // bracket stage launches with events
+    std::vector<hipEvent_t> ev_free;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
     explicit dgamr_forest(const dgamr_forest_desc &d) : topo(d) {}
 };
 
@@ -148,7 +151,7 @@ int launch_fill(dgamr_forest *f, const double *u, double *guard, bool hanging_on
     });
 }
 
-int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t s)
+int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t s, bool lim = false)
 {
     a.nleaves = f->topo.n();
     a.N = f->topo.desc().n_cell;
@@ -159,7 +162,7 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     if (a.nleaves == 0) return DGAMR_OK;
     if (f->topo.desc().precision == DGAMR_FP32_MFMA) return fail(DGAMR_EUNSUPPORTED, "FP32-MFMA residual not built");
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, s)));
+        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, s)));
         return DGAMR_OK;
     });
 }
@@ -189,6 +192,17 @@ int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, cons
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(dgk::k_dt_final, dim3(1), dim3(1024), 0, s, w.leafmax, n, cfl, dt_dev);
     HIP_TRY(hipGetLastError());
+    return DGAMR_OK;
+}
+
+int take_event(dgamr_forest *f, hipEvent_t &e)
+{
+    if (f->ev_free.empty()) {
+        HIP_TRY(hipEventCreate(&e));
+    } else {
+        e = f->ev_free.back();
+        f->ev_free.pop_back();
+    }
     return DGAMR_OK;
 }
 
@@ -248,6 +262,11 @@ int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out)
 int dgamr_destroy_forest(dgamr_forest *f)
 {
     if (!f) return DGAMR_OK;
+    for (auto e : f->ev_free) (void)hipEventDestroy(e);
+    for (auto &pr : f->ev_rec) {
+        (void)hipEventDestroy(pr.first);
+        (void)hipEventDestroy(pr.second);
+    }
     (void)hipFree(f->d_geo);
     (void)hipFree(f->d_links);
     (void)hipFree(f->d_hang);
@@ -384,6 +403,46 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
     return launch_dt(f, cfl, u, dt_dev, carve(f, work), stream);
 }
 
+// One SSP-RK3 step as three fused stage launches (guard traces computed
+// inline, limiter fused).  rate_in / rate_clear / rate_out select the CFL
+// time step folded into the stages (see StageArgs).
+int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_dev,
+             const unsigned long long *rate_in, unsigned long long *rate_clear, unsigned long long *rate_out,
+             hipStream_t stream)
+{
+    const bool lim = f->topo.desc().limiter == DGAMR_LIMITER_POSITIVITY;
+    static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
+    const double *us = u;
+    double *outs[3] = {w.u1, w.u2, u};
+    for (int s = 0; s < 3; ++s) {
+        dgk::StageArgs a{};
+        a.us = us;
+        a.un = u;
+        a.out64 = outs[s];
+        a.dt = dt_dev;
+        a.rk_a = A[s];
+        a.rk_b = B[s];
+        a.cfl = cfl;
+        a.rate_in = s == 0 ? rate_in : nullptr;
+        a.rate_clear = s == 0 ? rate_clear : nullptr;
+        a.dt_out = dt_dev;
+        a.rate_out = s == 2 ? rate_out : nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (f->prof) {
+            CHECK(take_event(f, e0));
+            CHECK(take_event(f, e1));
+            HIP_TRY(hipEventRecord(e0, stream));
+        }
+        CHECK(launch_stage(f, a, dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
+        if (f->prof) {
+            HIP_TRY(hipEventRecord(e1, stream));
+            f->ev_rec.emplace_back(e0, e1);
+        }
+        us = outs[s];
+    }
+    return DGAMR_OK;
+}
+
 int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev, hipStream_t stream)
 {
     CHECK(check_ptr(f, "forest"));
@@ -392,23 +451,29 @@ int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_de
     CHECK(check_ptr(dt_dev, "dt_dev"));
     Work w = carve(f, work);
     if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
-    const bool lim = f->topo.desc().limiter == DGAMR_LIMITER_POSITIVITY;
-    static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
-    const double *us = u;
-    double *outs[3] = {w.u1, w.u2, u};
-    for (int s = 0; s < 3; ++s) {
-        CHECK(launch_fill(f, us, w.guard, true, stream));
-        dgk::StageArgs a{};
-        a.us = us;
-        a.un = u;
-        a.guard = w.guard;
-        a.out64 = outs[s];
-        a.dt = dt_dev;
-        a.rk_a = A[s];
-        a.rk_b = B[s];
-        CHECK(launch_stage(f, a, dgk::GUARD_INLINE, dgk::OUT_RK, stream));
-        if (lim) CHECK(launch_limit(f, outs[s], stream));
-        us = outs[s];
+    return run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream);
+}
+
+int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev, hipStream_t stream)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(u, "u"));
+    CHECK(check_ptr(work, "work"));
+    CHECK(check_ptr(dt_dev, "dt_dev"));
+    if (nsteps < 0) return fail(DGAMR_EINVAL, "nsteps must be >= 0");
+    if (nsteps == 0) return DGAMR_OK;
+    Work w = carve(f, work);
+    auto *slot = reinterpret_cast<unsigned long long *>(w.scal + 2);
+    if (cfl <= 0.0) {
+        for (int s = 0; s < nsteps; ++s) CHECK(run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream));
+        return DGAMR_OK;
+    }
+    CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
+    for (int s = 0; s < nsteps; ++s) {
+        const int rd = s & 1, wr = rd ^ 1;
+        const bool last = s == nsteps - 1;
+        CHECK(run_step(f, cfl, u, w, dt_dev, s == 0 ? nullptr : slot + rd, last ? nullptr : slot + wr,
+                       last ? nullptr : slot + wr, stream));
     }
     return DGAMR_OK;
 }
@@ -509,6 +574,33 @@ int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work
     HIP_TRY(hipStreamSynchronize(stream));
     *bad = int64_t(h);
     return h ? fail(DGAMR_ENONPHYSICAL, "non-physical state: " + std::to_string(h) + " cells") : DGAMR_OK;
+}
+
+int dgamr_profile_enable(dgamr_forest *f, int enable)
+{
+    CHECK(check_ptr(f, "forest"));
+    f->prof = enable != 0;
+    return DGAMR_OK;
+}
+
+int dgamr_profile_read(dgamr_forest *f, double *stage_ms, int64_t *stage_launches)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(stage_ms, "stage_ms"));
+    CHECK(check_ptr(stage_launches, "stage_launches"));
+    double total = 0.0;
+    for (auto &pr : f->ev_rec) {
+        HIP_TRY(hipEventSynchronize(pr.second));
+        float ms = 0.0f;
+        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
+        total += ms;
+        f->ev_free.push_back(pr.first);
+        f->ev_free.push_back(pr.second);
+    }
+    *stage_ms = total;
+    *stage_launches = int64_t(f->ev_rec.size());
+    f->ev_rec.clear();
+    return DGAMR_OK;
 }
 
 } // extern "C"

@@ -1,6 +1,7 @@
 // One (dim, degree) instantiation of the degree-templated kernels and their
 // launchers; compiled once per pair with -DDG_D=<dim> -DDG_P=<degree>.
 #include "kernels.hpp"
+#include "kernels_2d.hpp"
 #include "kernels_aux.hpp"
 #include "launch.hpp"
 
@@ -13,18 +14,45 @@
 
 namespace dgk {
 
-template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int gm, int om, hipStream_t s)
+// 2-D without the limiter: one lane per (cell, variable), a slab of rows
+// per workgroup, with enough slabs to give every compute unit work.
+template <int P>
+hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s)
 {
+    int rows = a.N;
+    while (rows * a.N * 4 > 512) rows /= 2;
+    while (rows % 2 == 0 && rows > 1 && long(a.nleaves) * (a.N / rows) < 256) rows /= 2;
+    const int slabs = a.N / rows;
+    const size_t lds = sizeof(double) * (P + 1) * rows * a.N * 4;
+    const dim3 grid(unsigned(a.nleaves * slabs)), block(rows * a.N * 4);
+    if (gm == GUARD_BUFFER && om == OUT_RES64)
+        hipLaunchKernelGGL((k_stage2v<P, GUARD_BUFFER, OUT_RES64>), grid, block, lds, s, a, rows);
+    else if (gm == GUARD_BUFFER && om == OUT_RES32)
+        hipLaunchKernelGGL((k_stage2v<P, GUARD_BUFFER, OUT_RES32>), grid, block, lds, s, a, rows);
+    else if (gm == GUARD_INLINE && om == OUT_RK)
+        hipLaunchKernelGGL((k_stage2v<P, GUARD_INLINE, OUT_RK>), grid, block, lds, s, a, rows);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+template <int D, int P>
+hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, hipStream_t s)
+{
+    if constexpr (D == 2) {
+        if (!lim) return launch_stage_2v<P>(a, gm, om, s);
+    }
     const int ncell = D == 2 ? a.N * a.N : a.N * a.N * a.N;
     const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * ncell;
     const dim3 grid(a.nleaves), block(ncell);
-    if (gm == GUARD_BUFFER && om == OUT_RES64)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64>), grid, block, lds, s, a);
-    else if (gm == GUARD_BUFFER && om == OUT_RES32)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32>), grid, block, lds, s, a);
-    else if (gm == GUARD_INLINE && om == OUT_RK)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK>), grid, block, lds, s, a);
+    if (D == 3 && gm == GUARD_BUFFER && om == OUT_RES64)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false>), grid, block, lds, s, a);
+    else if (D == 3 && gm == GUARD_BUFFER && om == OUT_RES32)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false>), grid, block, lds, s, a);
+    else if (D == 3 && gm == GUARD_INLINE && om == OUT_RK && !lim)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, false>), grid, block, lds, s, a);
+    else if (gm == GUARD_INLINE && om == OUT_RK && lim)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, true>), grid, block, lds, s, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -62,7 +90,7 @@ hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, 
     return hipGetLastError();
 }
 
-template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, hipStream_t);
+template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, hipStream_t);
 template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t);
 template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStream_t);
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,

@@ -53,6 +53,13 @@ __device__ __forceinline__ int face_cell(int a, int n, int t, int N, int D)
     return i + N * (j + N * k);
 }
 
+// k-th neighbour of a face link, selected without indexing the struct (a
+// runtime index into a local copy would put it in scratch memory)
+__device__ __forceinline__ int link_nbr(const FaceLink &L, int k)
+{
+    return k == 0 ? L.nbr[0] : (k == 1 ? L.nbr[1] : (k == 2 ? L.nbr[2] : L.nbr[3]));
+}
+
 // Euler flux along axis A (Eq. 2 and its 3-D analogue; EOS Eq. 23).
 template <int D, int A>
 __device__ __forceinline__ void euler_flux(const double *U, double ua, double p, double *F)
@@ -73,6 +80,16 @@ __device__ __forceinline__ double pressure(const double *U, double gm1)
     return gm1 * (U[D + 1] - 0.5 * ke / U[0]);
 }
 
+// the same with 1/rho already known
+template <int D>
+__device__ __forceinline__ double pressure_r(const double *U, double gm1, double rinv)
+{
+    double ke = 0.0;
+#pragma unroll
+    for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b];
+    return gm1 * (U[D + 1] - 0.5 * ke * rinv);
+}
+
 // Eq. 5, dissipative sign, flux in the +e_A direction between the left
 // state UL and the right state UR; alpha = max(|u_A| + c) of both sides.
 template <int D, int A>
@@ -81,7 +98,7 @@ __device__ __forceinline__ void rusanov(const double *UL, const double *UR, doub
     constexpr int NV = D + 2;
     const double gm1 = gamma - 1.0;
     double rl = 1.0 / UL[0], rr = 1.0 / UR[0];
-    double pl = pressure<D>(UL, gm1), pr = pressure<D>(UR, gm1);
+    double pl = pressure_r<D>(UL, gm1, rl), pr = pressure_r<D>(UR, gm1, rr);
     double ul = UL[1 + A] * rl, ur = UR[1 + A] * rr;
     double cl = sqrt(gamma * pl * rl), cr = sqrt(gamma * pr * rr);
     double al = fabs(ul) + cl, ar = fabs(ur) + cr;
@@ -96,8 +113,9 @@ __device__ __forceinline__ void rusanov(const double *UL, const double *UR, doub
 // ------------------------------------------------------------------ argument blocks
 enum GuardMode : int {
     GUARD_BUFFER = 0, // every block face from the guard buffer
-    GUARD_INLINE = 1  // same-level and outflow faces straight from the
-                      // neighbour's state; hanging faces from the guard buffer
+    GUARD_INLINE = 1  // every block face straight from the neighbours' cells:
+                      // copy, split of the coarser cell or combine of the
+                      // finer cells computed on the fly (no guard buffer)
 };
 enum OutMode : int { OUT_RES64 = 0, OUT_RES32 = 1, OUT_RK = 2 };
 
@@ -114,6 +132,19 @@ struct StageArgs {
     double gamma;
     int nleaves, N;
     int conservative;     // mortar on hanging coarse faces
+    // CFL time step fused into the stages (OUT_RK only): when rate_in is
+    // set, dt = cfl / max rate read from *rate_in (written by the previous
+    // step's last stage) and workgroup 0 stores it to dt_out; otherwise dt
+    // is read from *dt.  When rate_clear is set, workgroup 0 zeroes it (the
+    // slot this step's last stage will fill).  When rate_out is set, every
+    // workgroup folds the max over its cells of sum_a (|u_a| + c)/h_a of the
+    // new state into *rate_out (atomic max on the bit pattern of a
+    // non-negative double).
+    double cfl;
+    const unsigned long long *rate_in;
+    unsigned long long *rate_clear;
+    double *dt_out;
+    unsigned long long *rate_out;
 };
 
 struct FillArgs {

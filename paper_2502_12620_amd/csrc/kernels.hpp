@@ -15,6 +15,10 @@
 
 namespace dgk {
 
+// one cell's coefficients (or residual) per variable and mode
+template <int D, int P>
+using CellCoef = double[D + 2][Tab<D, P>::NB];
+
 // Number of face points exchanged through LDS at once: all of them in 2-D,
 // one at a time in 3-D (keeps the register budget to one cell's state and
 // residual).
@@ -68,7 +72,7 @@ __device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, lo
 // mapped points (tangential xi = (xi_fine + sigma)/2).
 template <int D, int P, int A>
 __device__ void mortar_lift(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB],
-                            double (&R)[D + 2][Tab<D, P>::NB], int side, const FaceLink &L, int t, double scale)
+                            double (&R)[D + 2][Tab<D, P>::NB], int side, const FaceLink L, int t, double scale)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, Q = P + 1, NF = Tab<D, P>::NF;
     constexpr int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2; // tangential axes, lower first
@@ -76,7 +80,7 @@ __device__ void mortar_lift(const StageArgs &g, const double (&K)[D + 2][Tab<D, 
     const long sv = long(NB) * ncell;
     const int t0 = t % N, t1 = t / N;
     const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
-    const int fleaf = L.nbr[h0 + 2 * h1];
+    const int fleaf = link_nbr(L, h0 + 2 * h1);
     const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
     const int fn = side > 0 ? 0 : N - 1;
     const double sub = D == 2 ? 0.5 : 0.25; // fine face Jacobian / coarse face Jacobian
@@ -130,46 +134,234 @@ __device__ void mortar_lift(const StageArgs &g, const double (&K)[D + 2][Tab<D, 
     }
 }
 
-// Trace, at face point F of block face (A, side), of the polynomial on the
-// far side of the face for the cell with tangential index t: the guard
-// cell, the same-level neighbour cell (inline mode) or, at an outflow
-// boundary, the mirror image, whose trace is the own trace.
-template <int D, int P, int A, int GM>
-__device__ __forceinline__ void far_trace(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB], int leaf,
-                                          int side, int t, const FaceLink &L, int F, double *T)
+// Coefficients of the split of a coarse cell for child CH (Eq. 11-12):
+// g = S_CH k, one variable at a time.
+template <int D, int P, int CH>
+__device__ __forceinline__ void split_coeffs(const double *k, double *gk)
+{
+    constexpr int NB = Tab<D, P>::NB;
+#pragma unroll
+    for (int m = 0; m < NB; ++m) {
+        double s = 0.0;
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const double c = kTab<D, P>.split[CH][m][n];
+            if (c != 0.0) s = fma(c, k[n], s);
+        }
+        gk[m] = s;
+    }
+}
+
+template <int D, int P>
+__device__ __forceinline__ void split_any(int child, const double *k, double *gk)
+{
+    switch (child) {
+    case 0: split_coeffs<D, P, 0>(k, gk); break;
+    case 1: split_coeffs<D, P, 1>(k, gk); break;
+    case 2: split_coeffs<D, P, 2>(k, gk); break;
+    case 3: split_coeffs<D, P, 3>(k, gk); break;
+    case 4: if constexpr (D == 3) split_coeffs<D, P, 4>(k, gk); break;
+    case 5: if constexpr (D == 3) split_coeffs<D, P, 5>(k, gk); break;
+    case 6: if constexpr (D == 3) split_coeffs<D, P, 6>(k, gk); break;
+    default: if constexpr (D == 3) split_coeffs<D, P, 7>(k, gk); break;
+    }
+}
+
+// Far-side traces of block face (A, side) at the FCH face points starting
+// at f0, for the cell with tangential index t (the far polynomial touches
+// the face with its -side side):
+//  - guard-buffer mode: the stored guard cell;
+//  - inline mode: the same-level neighbour cell (Eq. 15), the split of the
+//    coarser neighbour cell (Eq. 16), the combine of the 2^d finer cells
+//    (Eq. 17), or at an outflow boundary the mirror image, whose trace is
+//    the own trace.
+template <int D, int P, int A, int GM, int FCH>
+__device__ __forceinline__ void far_traces(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB], int leaf,
+                                           int side, int t, const FaceLink &L, int f0, double (&T)[FCH][D + 2])
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB;
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
+    const long sv = long(NB) * ncell;
     const int face = 2 * A + (side > 0);
-    // the far polynomial touches the face with its -side side
-    if (GM == GUARD_INLINE && L.type == dgamr::LINK_SAME) {
-        const int c = face_cell(A, side > 0 ? 0 : N - 1, t, N, D);
-        const double *nk = g.us + long(L.nbr[0]) * NV * NB * ncell + c;
+    auto traces_of = [&](const double *kv, int v, int poly_side) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
+        for (int fi = 0; fi < FCH; ++fi) {
             double e, o;
-            trace_eo_mem<D, P>(nk + long(v) * NB * ncell, ncell, A, F, e, o);
-            T[v] = side > 0 ? e - o : e + o;
+            trace_eo<D, P>(kv, A, f0 + fi, e, o);
+            T[fi][v] = poly_side > 0 ? e + o : e - o;
         }
-    } else if (GM == GUARD_INLINE && L.type == dgamr::LINK_BOUNDARY) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double e, o;
-            trace_eo<D, P>(K[v], A, F, e, o);
-            T[v] = side > 0 ? e + o : e - o;
-        }
-    } else {
+    };
+    if (GM == GUARD_BUFFER) {
         const double *gk = g.guard + ((long(leaf) * 2 * D + face) * NV * NB) * nfc + t;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double e, o;
-            trace_eo_mem<D, P>(gk + long(v) * NB * nfc, nfc, A, F, e, o);
-            T[v] = side > 0 ? e - o : e + o;
+            double kv[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) kv[m] = gk[(long(v) * NB + m) * nfc];
+            traces_of(kv, v, -side);
+        }
+        return;
+    }
+    const int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2;
+    if (L.type == dgamr::LINK_BOUNDARY) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) traces_of(K[v], v, side);
+    } else if (L.type == dgamr::LINK_SAME) {
+        const int c = face_cell(A, side > 0 ? 0 : N - 1, t, N, D);
+        const double *nk = g.us + long(L.nbr[0]) * NV * sv + c;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double kv[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) kv[m] = nk[v * sv + m * ncell];
+            traces_of(kv, v, -side);
+        }
+    } else if (L.type == dgamr::LINK_COARSE) {
+        const int t0 = t % N, t1 = t / N;
+        const int c0 = (L.off[0] * N + t0) / 2, c1 = D == 3 ? (L.off[1] * N + t1) / 2 : 0;
+        const int c = face_cell(A, side > 0 ? 0 : N - 1, c0 + N * c1, N, D);
+        const int child = ((side > 0 ? 0 : 1) << A) | ((t0 & 1) << TA) | (D == 3 ? ((t1 & 1) << TBX) : 0);
+        const double *ck = g.us + long(L.nbr[0]) * NV * sv + c;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double kv[NB], gv[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) kv[m] = ck[v * sv + m * ncell];
+            split_any<D, P>(child, kv, gv);
+            traces_of(gv, v, -side);
+        }
+    } else { // LINK_FINE
+        const int t0 = t % N, t1 = t / N;
+        const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
+        const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
+        const double *fk = g.us + long(link_nbr(L, h0 + 2 * h1)) * NV * sv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double gv[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) gv[m] = 0.0;
+#pragma unroll
+            for (int ch = 0; ch < (1 << D); ++ch) {
+                const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
+                const int nidx = side > 0 ? bits[A] : N - 2 + bits[A];
+                const int fc = face_cell(A, nidx, (ft0 + bits[TA]) + N * (ft1 + (D == 3 ? bits[TBX] : 0)), N, D);
+                double kv[NB];
+#pragma unroll
+                for (int n = 0; n < NB; ++n) kv[n] = fk[v * sv + n * ncell + fc];
+#pragma unroll
+                for (int m = 0; m < NB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) {
+                        const double cc = kTab<D, P>.comb[ch][m][n];
+                        if (cc != 0.0) gv[m] = fma(cc, kv[n], gv[m]);
+                    }
+            }
+            traces_of(gv, v, -side);
         }
     }
 }
 
-template <int D, int P, int GM, int OM>
+// ------------------------------------------------------------------ positivity limiter
+// Point set of the limiter: volume Gauss points, then the face Gauss
+// points of every face (basis values with the face side's sign).
+template <int D, int P>
+struct LimiterPoints {
+    static constexpr int NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF, NB = Tab<D, P>::NB;
+    static constexpr int NPT = NQ + 2 * D * NF;
+    double phi[NPT][NB] = {};
+    constexpr LimiterPoints()
+    {
+        for (int q = 0; q < NQ; ++q)
+            for (int m = 0; m < NB; ++m) phi[q][m] = kTab<D, P>.phi_v[q][m];
+        int n = NQ;
+        for (int face = 0; face < 2 * D; ++face) {
+            const int a = face / 2;
+            const bool minus = (face & 1) == 0;
+            for (int f = 0; f < NF; ++f, ++n)
+                for (int m = 0; m < NB; ++m)
+                    phi[n][m] = kTab<D, P>.phi_f[a][f][m] * ((minus && kTab<D, P>.e[m][a] % 2) ? -1.0 : 1.0);
+        }
+    }
+};
+template <int D, int P>
+inline constexpr LimiterPoints<D, P> kLimPts{};
+
+// Zhang-Shu scaling limiter (named in Sec. 5.3.2) on one cell, in place,
+// with eps = min(1e-13, mean rho, p(mean)):
+//   theta1 = min(1, (rho_mean - eps)/(rho_mean - min_S rho)) scales the
+//   non-mean density modes; then theta2 = min over S of the root t in
+//   [0,1) of p(Ubar + t(U - Ubar)) = eps (1 where p >= eps) scales all
+//   non-mean modes.  The cell mean is never changed.
+template <int D, int P>
+__device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB, NPT = LimiterPoints<D, P>::NPT;
+    const double gm1 = gamma - 1.0;
+    double mean[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) mean[v] = K[v][0];
+    const double pbar = pressure<D>(mean, gm1);
+    double eps = 1e-13;
+    eps = mean[0] < eps ? mean[0] : eps;
+    eps = pbar < eps ? pbar : eps;
+    double rmin = mean[0];
+#pragma unroll 1
+    for (int pt = 0; pt < NPT; ++pt) {
+        double r = 0.0;
+#pragma unroll
+        for (int m = 0; m < NB; ++m) r = fma(kLimPts<D, P>.phi[pt][m], K[0][m], r);
+        rmin = r < rmin ? r : rmin;
+    }
+    if (rmin < mean[0]) {
+        double th1 = (mean[0] - eps) / (mean[0] - rmin);
+        if (th1 < 1.0)
+#pragma unroll
+            for (int m = 1; m < NB; ++m) K[0][m] *= th1;
+    }
+    double th2 = 1.0;
+#pragma unroll 1
+    for (int pt = 0; pt < NPT; ++pt) {
+        double U[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double s = 0.0;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) s = fma(kLimPts<D, P>.phi[pt][m], K[v][m], s);
+            U[v] = s;
+        }
+        if (pressure<D>(U, gm1) < eps) {
+            const double dr = U[0] - mean[0], dE = U[D + 1] - mean[D + 1];
+            double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+                const double dm = U[1 + a] - mean[1 + a];
+                dm2 += dm * dm;
+                mdm += mean[1 + a] * dm;
+                m2 += mean[1 + a] * mean[1 + a];
+            }
+            const double A = dr * dE - 0.5 * dm2;
+            const double B = mean[0] * dE + mean[D + 1] * dr - mdm - eps * dr / gm1;
+            const double C = mean[0] * mean[D + 1] - 0.5 * m2 - eps * mean[0] / gm1;
+            double tq = 0.0;
+            if (C > 0.0) {
+                double disc = B * B - 4.0 * A * C;
+                disc = disc < 0.0 ? 0.0 : disc;
+                const double den = -B + sqrt(disc);
+                tq = den > 0.0 ? 2.0 * C / den : 0.0;
+                tq = tq > 1.0 ? 1.0 : (tq < 0.0 ? 0.0 : tq);
+            }
+            th2 = tq < th2 ? tq : th2;
+        }
+    }
+    if (th2 < 1.0)
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 1; m < NB; ++m) K[v][m] *= th2;
+}
+
+// ------------------------------------------------------------------ stage kernel
+template <int D, int P, int GM, int OM, bool LIM>
 __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
@@ -210,7 +402,7 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
             U[v] = s;
         }
         const double rinv = 1.0 / U[0];
-        const double p = pressure<D>(U, gm1);
+        const double p = pressure_r<D>(U, gm1, rinv);
         static_for<0, D>([&](auto Ai) {
             constexpr int A = Ai;
             double F[NV];
@@ -249,7 +441,8 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
         if (mort_p) mortar_lift<D, P, A>(g, K, R, +1, Lp, t, sc);
         auto face_chunk_body = [&](auto cv) {
             const int f0 = int(cv) * FCH;
-            // own + traces of this chunk -> LDS
+            // own traces of this chunk: + side to LDS, - side kept
+            double Tm[FCH][NV];
             __syncthreads();
 #pragma unroll
             for (int fi = 0; fi < FCH; ++fi)
@@ -258,29 +451,29 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
                     double e, o;
                     trace_eo<D, P>(K[v], A, f0 + fi, e, o);
                     lds[(v * FCH + fi) * ncell + cell] = e + o;
+                    Tm[fi][v] = e - o;
                 }
             __syncthreads();
             // flux on the - face: left state = the left neighbour's + trace
             double Fm[FCH][NV];
+            if (ia > 0) {
 #pragma unroll
-            for (int fi = 0; fi < FCH; ++fi) {
-                double TL[NV], TR[NV];
-#pragma unroll
-                for (int v = 0; v < NV; ++v) {
-                    double e, o;
-                    trace_eo<D, P>(K[v], A, f0 + fi, e, o);
-                    TR[v] = e - o;
-                }
-                if (ia > 0) {
+                for (int fi = 0; fi < FCH; ++fi) {
+                    double TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * ncell + cell - stride];
-                } else if (!mort_m) {
-                    far_trace<D, P, A, GM>(g, K, leaf, -1, t, Lm, f0 + fi, TL);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) TL[v] = TR[v];
+                    rusanov<D, A>(TL, Tm[fi], g.gamma, Fm[fi]);
                 }
-                rusanov<D, A>(TL, TR, g.gamma, Fm[fi]);
+            } else if (!mort_m) {
+                double TL[FCH][NV];
+                far_traces<D, P, A, GM, FCH>(g, K, leaf, -1, t, Lm, f0, TL);
+#pragma unroll
+                for (int fi = 0; fi < FCH; ++fi) rusanov<D, A>(TL[fi], Tm[fi], g.gamma, Fm[fi]);
+            } else {
+#pragma unroll
+                for (int fi = 0; fi < FCH; ++fi)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Fm[fi][v] = 0.0;
             }
             __syncthreads();
 #pragma unroll
@@ -288,32 +481,39 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) lds[(v * FCH + fi) * ncell + cell] = Fm[fi][v];
             __syncthreads();
+            double Fp[FCH][NV];
+            if (ia < N - 1) {
 #pragma unroll
-            for (int fi = 0; fi < FCH; ++fi) {
-                const int F = f0 + fi;
-                double Fp[NV];
-                if (ia < N - 1) {
+                for (int fi = 0; fi < FCH; ++fi)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Fp[v] = lds[(v * FCH + fi) * ncell + cell + stride];
-                } else if (!mort_p) {
-                    double TL[NV], TR[NV];
+                    for (int v = 0; v < NV; ++v) Fp[fi][v] = lds[(v * FCH + fi) * ncell + cell + stride];
+            } else if (!mort_p) {
+                double TR[FCH][NV];
+                far_traces<D, P, A, GM, FCH>(g, K, leaf, +1, t, Lp, f0, TR);
+#pragma unroll
+                for (int fi = 0; fi < FCH; ++fi) {
+                    double TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         double e, o;
-                        trace_eo<D, P>(K[v], A, F, e, o);
+                        trace_eo<D, P>(K[v], A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
-                    far_trace<D, P, A, GM>(g, K, leaf, +1, t, Lp, F, TR);
-                    rusanov<D, A>(TL, TR, g.gamma, Fp);
-                } else {
-#pragma unroll
-                    for (int v = 0; v < NV; ++v) Fp[v] = 0.0;
+                    rusanov<D, A>(TL, TR[fi], g.gamma, Fp[fi]);
                 }
-                // lift: R_m += s_a w phi_m(+1)/M_m ((-1)^{m_A} Phi_- - Phi_+)
-                const double wm = mort_m ? 0.0 : sc, wp = mort_p ? 0.0 : sc;
+            } else {
+#pragma unroll
+                for (int fi = 0; fi < FCH; ++fi)
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) Fp[fi][v] = 0.0;
+            }
+            // lift: R_m += s_a w phi_m(+1)/M_m ((-1)^{m_A} Phi_- - Phi_+)
+#pragma unroll
+            for (int fi = 0; fi < FCH; ++fi) {
+                const int F = f0 + fi;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double dm = wm * Fm[fi][v], dp = wp * Fp[v];
+                    const double dm = sc * Fm[fi][v], dp = sc * Fp[fi][v];
                     const double even = dm - dp, odd = -(dm + dp);
 #pragma unroll
                     for (int m = 0; m < NB; ++m) {
@@ -343,15 +543,51 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
 #pragma unroll
             for (int m = 0; m < NB; ++m) g.out32[base + v * sv + m * ncell] = float(R[v][m]);
     } else {
-        const double dt = *g.dt, a = g.rk_a, b = g.rk_b;
+        double dt;
+        if (g.rate_in) {
+            const double rate = __longlong_as_double((long long)*g.rate_in);
+            dt = g.cfl / rate;
+            if (blockIdx.x == 0 && threadIdx.x == 0) *g.dt_out = dt;
+        } else {
+            dt = *g.dt;
+        }
+        if (g.rate_clear && blockIdx.x == 0 && threadIdx.x == 0) *g.rate_clear = 0ULL;
+        const double a = g.rk_a, b = g.rk_b;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
                 const long idx = base + v * sv + m * ncell;
                 const double un = a != 0.0 ? g.un[idx] : 0.0;
-                g.out64[idx] = a * un + b * (K[v][m] + dt * R[v][m]);
+                K[v][m] = a * un + b * (K[v][m] + dt * R[v][m]);
             }
+        if constexpr (LIM) limit_cell<D, P>(K, g.gamma);
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = K[v][m];
+        if (g.rate_out) {
+            // CFL rate of the new state from its cell mean, folded over the block
+            double U[NV];
+#pragma unroll
+            for (int v = 0; v < NV; ++v) U[v] = K[v][0];
+            const double rinv = 1.0 / U[0];
+            const double cs = sqrt(g.gamma * pressure_r<D>(U, gm1, rinv) * rinv);
+            double rate = 0.0;
+#pragma unroll
+            for (int a2 = 0; a2 < D; ++a2) rate += (fabs(U[1 + a2] * rinv) + cs) / g.geo[leaf].h[a2];
+            __syncthreads();
+            lds[cell] = rate;
+            __syncthreads();
+            for (int s = 1; s < ncell; s <<= 1) {
+                if ((cell % (2 * s)) == 0 && cell + s < ncell) {
+                    const double o = lds[cell + s];
+                    lds[cell] = o > lds[cell] || o != o ? o : lds[cell];
+                }
+                __syncthreads();
+            }
+            if (cell == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds[0]));
+        }
     }
 }
 
@@ -434,7 +670,7 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
     } else { // LINK_FINE: 2^d fine cells, 2 along a and 2^(d-1) tangential
         const int t0 = t % N, t1 = t / N;
         const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
-        const int fleaf = L.nbr[h0 + 2 * h1];
+        const int fleaf = link_nbr(L, h0 + 2 * h1);
         const int f0 = (2 * t0) % N, f1 = D == 3 ? (2 * t1) % N : 0;
         const double *base = g.u + long(fleaf) * NV * sv;
         for (int v = 0; v < NV; ++v) {

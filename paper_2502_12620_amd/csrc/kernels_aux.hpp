@@ -6,121 +6,26 @@
 
 namespace dgk {
 
-// ------------------------------------------------------------------ positivity limiter
-// Zhang-Shu scaling limiter (named in Sec. 5.3.2), per cell, on the point
-// set S = volume Gauss points + face Gauss points of all faces,
-// eps = min(1e-13, mean rho, p(mean)):
-//   theta1 = min(1, (rho_mean - eps)/(rho_mean - min_S rho)) scales the
-//   non-mean density modes; then theta2 = min over S of the root t in
-//   [0,1) of p(Ubar + t(U - Ubar)) = eps (1 where p >= eps) scales all
-//   non-mean modes.  The cell mean is never changed.
-template <int D, int P>
-struct LimiterPoints {
-    static constexpr int NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF, NB = Tab<D, P>::NB;
-    static constexpr int NPT = NQ + 2 * D * NF;
-    double phi[NPT][NB] = {};
-    constexpr LimiterPoints()
-    {
-            for (int q = 0; q < NQ; ++q)
-            for (int m = 0; m < NB; ++m) phi[q][m] = kTab<D, P>.phi_v[q][m];
-        int n = NQ;
-        for (int face = 0; face < 2 * D; ++face) {
-            int a = face / 2;
-            double sg = (face & 1) ? 1.0 : -1.0;
-            for (int f = 0; f < NF; ++f, ++n)
-                for (int m = 0; m < NB; ++m)
-                    phi[n][m] = kTab<D, P>.phi_f[a][f][m] * ((kTab<D, P>.e[m][a] % 2 && sg < 0) ? -1.0 : 1.0);
-        }
-    }
-};
-template <int D, int P>
-inline constexpr LimiterPoints<D, P> kLimPts{};
-
 template <int D, int P>
 __global__ __launch_bounds__(256) void k_limit(double *u, int N, long ncell_total, double gamma)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB;
-    constexpr int NPT = LimiterPoints<D, P>::NPT;
     const int ncell = D == 2 ? N * N : N * N * N;
-    long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= ncell_total) return;
-    long leaf = gid / ncell;
-    int c = int(gid % ncell);
+    const long leaf = gid / ncell;
+    const int c = int(gid % ncell);
     const long sv = long(NB) * ncell, base = leaf * NV * sv + c;
     double K[NV][NB];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < NB; ++m) K[v][m] = u[base + v * sv + m * ncell];
-    const double gm1 = gamma - 1.0;
-    double mean[NV];
+    limit_cell<D, P>(K, gamma);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) mean[v] = K[v][0];
-    double pbar = pressure<D>(mean, gm1);
-    double eps = 1e-13;
-    eps = mean[0] < eps ? mean[0] : eps;
-    eps = pbar < eps ? pbar : eps;
-    // density
-    double rmin = mean[0];
-#pragma unroll 1
-    for (int pt = 0; pt < NPT; ++pt) {
-        double r = 0.0;
+    for (int v = 0; v < NV; ++v)
 #pragma unroll
-        for (int m = 0; m < NB; ++m) r = fma(kLimPts<D, P>.phi[pt][m], K[0][m], r);
-        rmin = r < rmin ? r : rmin;
-    }
-    double th1 = 1.0;
-    if (rmin < mean[0]) {
-        th1 = (mean[0] - eps) / (mean[0] - rmin);
-        th1 = th1 > 1.0 ? 1.0 : th1;
-    }
-    if (th1 < 1.0)
-#pragma unroll
-        for (int m = 1; m < NB; ++m) K[0][m] *= th1;
-    // pressure
-    double th2 = 1.0;
-#pragma unroll 1
-    for (int pt = 0; pt < NPT; ++pt) {
-        double U[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            double s = 0.0;
-#pragma unroll
-            for (int m = 0; m < NB; ++m) s = fma(kLimPts<D, P>.phi[pt][m], K[v][m], s);
-            U[v] = s;
-        }
-        if (pressure<D>(U, gm1) < eps) {
-            double dr = U[0] - mean[0], dE = U[D + 1] - mean[D + 1];
-            double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                double dm = U[1 + a] - mean[1 + a];
-                dm2 += dm * dm;
-                mdm += mean[1 + a] * dm;
-                m2 += mean[1 + a] * mean[1 + a];
-            }
-            double A = dr * dE - 0.5 * dm2;
-            double B = mean[0] * dE + mean[D + 1] * dr - mdm - eps * dr / gm1;
-            double C = mean[0] * mean[D + 1] - 0.5 * m2 - eps * mean[0] / gm1;
-            double tq = 0.0;
-            if (C > 0.0) {
-                double disc = B * B - 4.0 * A * C;
-                disc = disc < 0.0 ? 0.0 : disc;
-                double den = -B + sqrt(disc);
-                tq = den > 0.0 ? 2.0 * C / den : 0.0;
-                tq = tq > 1.0 ? 1.0 : (tq < 0.0 ? 0.0 : tq);
-            }
-            th2 = tq < th2 ? tq : th2;
-        }
-    }
-    if (th1 < 1.0)
-#pragma unroll
-        for (int m = 1; m < NB; ++m) u[base + m * ncell] = K[0][m];
-    if (th2 < 1.0)
-#pragma unroll
-        for (int v = 0; v < NV; ++v)
-#pragma unroll
-            for (int m = 1; m < NB; ++m) u[base + v * sv + m * ncell] = K[v][m] * th2;
+        for (int m = 1; m < NB; ++m) u[base + v * sv + m * ncell] = K[v][m];
 }
 
 // ------------------------------------------------------------------ initial conditions

@@ -11,7 +11,7 @@ namespace dgk {
 
 // residual / fused stage: grid = one workgroup per leaf, N^d threads
 template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, hipStream_t s);
+hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, hipStream_t s);
 // guard fill: one thread per guard cell of the listed faces
 template <int D, int P>
 hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s);

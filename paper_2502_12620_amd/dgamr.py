@@ -26,8 +26,9 @@ EXPORTS = [
     "dgamr_create_forest", "dgamr_destroy_forest", "dgamr_num_leaves", "dgamr_leaf_keys",
     "dgamr_state_bytes", "dgamr_set_refinement", "dgamr_apply_refinement",
     "dgamr_fill_guardcells", "dgamr_dg_residual", "dgamr_rk_stage", "dgamr_compute_dt",
-    "dgamr_step", "dgamr_conserved_totals", "dgamr_limit_positivity", "dgamr_indicator",
-    "dgamr_project_ic", "dgamr_check_state", "dgamr_last_error",
+    "dgamr_step", "dgamr_run", "dgamr_conserved_totals", "dgamr_limit_positivity", "dgamr_indicator",
+    "dgamr_project_ic", "dgamr_check_state", "dgamr_profile_enable", "dgamr_profile_read",
+    "dgamr_last_error",
 ]
 
 
@@ -69,11 +70,14 @@ def lib():
         L.dgamr_rk_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.dgamr_compute_dt.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
         L.dgamr_step.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
+        L.dgamr_run.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
         L.dgamr_conserved_totals.argtypes = [vp, vp, vp, vp, vp]
         L.dgamr_limit_positivity.argtypes = [vp, vp, vp]
         L.dgamr_indicator.argtypes = [vp, vp, vp, vp, vp]
         L.dgamr_project_ic.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp, vp]
         L.dgamr_check_state.argtypes = [vp, vp, i64p, vp, vp]
+        L.dgamr_profile_enable.argtypes = [vp, ctypes.c_int]
+        L.dgamr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
         L.dgamr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name != "dgamr_last_error":
@@ -204,6 +208,10 @@ class Forest:
         """One SSP-RK3 step in place; cfl <= 0 uses the dt already in dt_dev."""
         _check(lib().dgamr_step(self.h, cfl, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
 
+    def run(self, u, work, dt_dev, nsteps, cfl=0.1, stream=None):
+        """nsteps SSP-RK3 steps in place, three launches per step."""
+        _check(lib().dgamr_run(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
+
     def conserved_totals(self, u, work, stream=None):
         t = torch.zeros(self.nv, dtype=torch.float64, device=u.device)
         _check(lib().dgamr_conserved_totals(self.h, _ptr(u), _ptr(t), _ptr(work), _stream(stream)))
@@ -230,3 +238,12 @@ class Forest:
         if rc not in (OK, ENONPHYSICAL):
             _check(rc)
         return bad.value
+
+    def profile_enable(self, enable=True):
+        _check(lib().dgamr_profile_enable(self.h, 1 if enable else 0))
+
+    def profile_read(self):
+        """(summed stage-kernel milliseconds, launches) since the last read."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().dgamr_profile_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value

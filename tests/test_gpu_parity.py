@@ -212,6 +212,23 @@ def test_c2_shape_200_steps(hanging):
         assert np.all(drift <= 1e-14 * 200 * np.abs(t0) + 1e-12)
 
 
+@pytest.mark.parametrize("hanging", [0, 1])
+def test_run_folds_the_cfl_step_into_the_stages(hanging):
+    w = small_c2(8)
+    orc, gpu = make_pair(w, hanging=hanging)
+    u = orc.project_ic(O.IC_VORTEX, w.ic_params)
+    ud, ud2 = _cuda(u), _cuda(u)
+    work, dt, dt2 = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda"), \
+        torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(15):
+        dref = orc.step(u, w.cfl)
+        gpu.step(ud, work, dt, w.cfl)
+    gpu.run(ud2, work, dt2, 15, w.cfl)
+    assert rel_diff(_host(ud2), _host(ud)).max() <= 1e-14
+    assert abs(_host(dt2)[0] - dref) <= 1e-14 * dref
+    assert rel_diff(_host(ud2), u).max() <= TOL
+
+
 def test_fused_step_matches_unfused_entry_points():
     w = _forest(2, 2, 8, 3, hanging=0)
     orc, gpu = make_pair(w, hanging=1)
