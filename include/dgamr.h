@@ -173,6 +173,16 @@ int dgamr_project_ic(dgamr_forest *f, int kind, const double *params /* 8 */, do
  * non-finite value or a non-positive mean density or pressure.  Synchronous. */
 int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work, hipStream_t stream);
 
+/* Kernel tuning (for the autotuner and measurements; results do not
+ * depend on it beyond floating-point rounding):
+ *   DGAMR_TUNE_STAGE_VARIANT: 2-D stage kernel, -1 automatic (default),
+ *     0 one lane per (cell, variable) in row slabs (latency-bound small
+ *     forests), 1 one thread per cell (throughput on large forests);
+ *   DGAMR_TUNE_VAR_SPLIT_MAX_CELLS: the automatic choice uses variant 0 up
+ *     to this many cells (default 131072). */
+enum { DGAMR_TUNE_STAGE_VARIANT = 0, DGAMR_TUNE_VAR_SPLIT_MAX_CELLS = 1 };
+int dgamr_set_tuning(dgamr_forest *f, int knob, long value);
+
 /* Measurement hook: while enabled, every launch of the fused stage kernel
  * inside dgamr_step is bracketed by two HIP events on the caller's stream
  * (not usable under HIP graph capture).  dgamr_profile_read waits for the

@@ -44,6 +44,8 @@ struct dgamr_forest {
     int cap = 0;             // leaves the device tables can hold
     int hang_cap = 0;
     bool prof = false;       // bracket stage launches with events
+    int stage_variant = -1;  // 2-D stage kernel: -1 auto, 0 lane per (cell, var), 1 thread per cell
+    long var_split_max_cells = 131072; // auto: lane per (cell, var) up to this many cells
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
     explicit dgamr_forest(const dgamr_forest_desc &d) : topo(d) {}
@@ -151,6 +153,12 @@ int launch_fill(dgamr_forest *f, const double *u, double *guard, bool hanging_on
     });
 }
 
+int stage_variant(const dgamr_forest *f)
+{
+    if (f->stage_variant >= 0) return f->stage_variant;
+    return long(f->topo.n()) * ncell_of(f) <= f->var_split_max_cells ? 0 : 1;
+}
+
 int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t s, bool lim = false)
 {
     a.nleaves = f->topo.n();
@@ -162,7 +170,7 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     if (a.nleaves == 0) return DGAMR_OK;
     if (f->topo.desc().precision == DGAMR_FP32_MFMA) return fail(DGAMR_EUNSUPPORTED, "FP32-MFMA residual not built");
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, s)));
+        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, stage_variant(f), s)));
         return DGAMR_OK;
     });
 }
@@ -427,13 +435,19 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         a.rate_clear = s == 0 ? rate_clear : nullptr;
         a.dt_out = dt_dev;
         a.rate_out = s == 2 ? rate_out : nullptr;
+        // 3-D reads the far side of every block face from the guard buffer
+        const bool guard3 = f->topo.dim() == 3;
+        if (guard3) {
+            a.guard = w.guard;
+            CHECK(launch_fill(f, us, w.guard, false, stream));
+        }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (f->prof) {
             CHECK(take_event(f, e0));
             CHECK(take_event(f, e1));
             HIP_TRY(hipEventRecord(e0, stream));
         }
-        CHECK(launch_stage(f, a, dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
+        CHECK(launch_stage(f, a, guard3 ? dgk::GUARD_BUFFER : dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
         if (f->prof) {
             HIP_TRY(hipEventRecord(e1, stream));
             f->ev_rec.emplace_back(e0, e1);
@@ -574,6 +588,21 @@ int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work
     HIP_TRY(hipStreamSynchronize(stream));
     *bad = int64_t(h);
     return h ? fail(DGAMR_ENONPHYSICAL, "non-physical state: " + std::to_string(h) + " cells") : DGAMR_OK;
+}
+
+int dgamr_set_tuning(dgamr_forest *f, int knob, long value)
+{
+    CHECK(check_ptr(f, "forest"));
+    if (knob == DGAMR_TUNE_STAGE_VARIANT) {
+        if (value < -1 || value > 1) return fail(DGAMR_EINVAL, "stage variant must be -1, 0 or 1");
+        f->stage_variant = int(value);
+    } else if (knob == DGAMR_TUNE_VAR_SPLIT_MAX_CELLS) {
+        if (value < 0) return fail(DGAMR_EINVAL, "cell count must be >= 0");
+        f->var_split_max_cells = value;
+    } else {
+        return fail(DGAMR_EINVAL, "unknown tuning knob");
+    }
+    return DGAMR_OK;
 }
 
 int dgamr_profile_enable(dgamr_forest *f, int enable)

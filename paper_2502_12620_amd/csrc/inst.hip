@@ -37,22 +37,34 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s)
 }
 
 template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, hipStream_t s)
+hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, int variant, hipStream_t s)
 {
     if constexpr (D == 2) {
-        if (!lim) return launch_stage_2v<P>(a, gm, om, s);
+        // one lane per (cell, variable) unless the caller asks for one
+        // thread per cell (variant 1) or needs the limiter
+        if (!lim && (variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s);
     }
-    const int ncell = D == 2 ? a.N * a.N : a.N * a.N * a.N;
-    const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * ncell;
-    const dim3 grid(a.nleaves), block(ncell);
+    // slab of `rows` layers along the last axis with at most 256 cells
+    const int layer = D == 2 ? a.N : a.N * a.N;
+    int rows = a.N;
+    while (rows % 2 == 0 && rows * layer > stage_threads<D, P>()) rows /= 2;
+    const int nslab = rows * layer;
+    const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * nslab;
+    const dim3 grid(unsigned(a.nleaves * (a.N / rows))), block(nslab);
+    // 3-D reads every block face from the guard buffer (the stage path runs
+    // the fill kernel first); 2-D takes the far side inline
     if (D == 3 && gm == GUARD_BUFFER && om == OUT_RES64)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false>), grid, block, lds, s, a);
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false>), grid, block, lds, s, a, rows);
     else if (D == 3 && gm == GUARD_BUFFER && om == OUT_RES32)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false>), grid, block, lds, s, a);
-    else if (D == 3 && gm == GUARD_INLINE && om == OUT_RK && !lim)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, false>), grid, block, lds, s, a);
-    else if (gm == GUARD_INLINE && om == OUT_RK && lim)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, true>), grid, block, lds, s, a);
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false>), grid, block, lds, s, a, rows);
+    else if (D == 3 && gm == GUARD_BUFFER && om == OUT_RK && !lim)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RK, false>), grid, block, lds, s, a, rows);
+    else if (D == 3 && gm == GUARD_BUFFER && om == OUT_RK && lim)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RK, true>), grid, block, lds, s, a, rows);
+    else if (D == 2 && gm == GUARD_INLINE && om == OUT_RK && !lim)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, false>), grid, block, lds, s, a, rows);
+    else if (D == 2 && gm == GUARD_INLINE && om == OUT_RK && lim)
+        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, true>), grid, block, lds, s, a, rows);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -90,7 +102,7 @@ hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, 
     return hipGetLastError();
 }
 
-template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, hipStream_t);
+template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, int, hipStream_t);
 template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t);
 template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStream_t);
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,

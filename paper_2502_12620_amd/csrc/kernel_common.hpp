@@ -60,9 +60,10 @@ __device__ __forceinline__ int link_nbr(const FaceLink &L, int k)
     return k == 0 ? L.nbr[0] : (k == 1 ? L.nbr[1] : (k == 2 ? L.nbr[2] : L.nbr[3]));
 }
 
-// Euler flux along axis A (Eq. 2 and its 3-D analogue; EOS Eq. 23).
-template <int D, int A>
-__device__ __forceinline__ void euler_flux(const double *U, double ua, double p, double *F)
+// Euler flux along axis A (Eq. 2 and its 3-D analogue; EOS Eq. 23), in the
+// arithmetic type T of the residual (FP64, or FP32 for the FP32 path).
+template <int D, int A, typename T = double>
+__device__ __forceinline__ void euler_flux(const T *U, T ua, T p, T *F)
 {
     F[0] = U[1 + A];
 #pragma unroll
@@ -81,33 +82,33 @@ __device__ __forceinline__ double pressure(const double *U, double gm1)
 }
 
 // the same with 1/rho already known
-template <int D>
-__device__ __forceinline__ double pressure_r(const double *U, double gm1, double rinv)
+template <int D, typename T = double>
+__device__ __forceinline__ T pressure_r(const T *U, T gm1, T rinv)
 {
-    double ke = 0.0;
+    T ke = T(0);
 #pragma unroll
     for (int b = 0; b < D; ++b) ke += U[1 + b] * U[1 + b];
-    return gm1 * (U[D + 1] - 0.5 * ke * rinv);
+    return gm1 * (U[D + 1] - T(0.5) * ke * rinv);
 }
 
 // Eq. 5, dissipative sign, flux in the +e_A direction between the left
 // state UL and the right state UR; alpha = max(|u_A| + c) of both sides.
-template <int D, int A>
-__device__ __forceinline__ void rusanov(const double *UL, const double *UR, double gamma, double *Phi)
+template <int D, int A, typename T = double>
+__device__ __forceinline__ void rusanov(const T *UL, const T *UR, T gamma, T *Phi)
 {
     constexpr int NV = D + 2;
-    const double gm1 = gamma - 1.0;
-    double rl = 1.0 / UL[0], rr = 1.0 / UR[0];
-    double pl = pressure_r<D>(UL, gm1, rl), pr = pressure_r<D>(UR, gm1, rr);
-    double ul = UL[1 + A] * rl, ur = UR[1 + A] * rr;
-    double cl = sqrt(gamma * pl * rl), cr = sqrt(gamma * pr * rr);
-    double al = fabs(ul) + cl, ar = fabs(ur) + cr;
-    double alpha = al > ar ? al : ar;
-    double FL[NV], FR[NV];
-    euler_flux<D, A>(UL, ul, pl, FL);
-    euler_flux<D, A>(UR, ur, pr, FR);
+    const T gm1 = gamma - T(1);
+    const T rl = T(1) / UL[0], rr = T(1) / UR[0];
+    const T pl = pressure_r<D, T>(UL, gm1, rl), pr = pressure_r<D, T>(UR, gm1, rr);
+    const T ul = UL[1 + A] * rl, ur = UR[1 + A] * rr;
+    const T cl = sqrt(gamma * pl * rl), cr = sqrt(gamma * pr * rr);
+    const T al = fabs(ul) + cl, ar = fabs(ur) + cr;
+    const T alpha = al > ar ? al : ar;
+    T FL[NV], FR[NV];
+    euler_flux<D, A, T>(UL, ul, pl, FL);
+    euler_flux<D, A, T>(UR, ur, pr, FR);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) Phi[v] = 0.5 * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
+    for (int v = 0; v < NV; ++v) Phi[v] = T(0.5) * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
 }
 
 // ------------------------------------------------------------------ argument blocks

@@ -23,13 +23,15 @@ using CellCoef = double[D + 2][Tab<D, P>::NB];
 // one at a time in 3-D (keeps the register budget to one cell's state and
 // residual).
 template <int D, int P>
-constexpr int face_chunk() { return D == 2 ? Tab<D, P>::NF : 1; }
+constexpr int face_chunk() { return D == 2 ? (P == 3 ? 2 : Tab<D, P>::NF) : 1; }
 
 // Full unrolling over the quadrature points makes every table entry an
-// immediate; for 3-D degree 3 (64 volume points, 20 modes) the unrolled
-// code is too large, so its point loops stay loops over tables in memory.
+// immediate.  In 3-D the unrolled code and its live ranges outgrow the
+// register file (one cell's state and residual already take 4 NB VGPRs per
+// variable), so there the point loops stay loops over tables read with
+// scalar loads.
 template <int D, int P>
-constexpr bool unroll_points() { return !(D == 3 && P == 3); }
+constexpr bool unroll_points() { return D == 2; }
 
 // even / odd parts (in the normal mode index) of the trace of K at face
 // point f of axis a: the trace at xi_a = +1 is e + o, at xi_a = -1 it is e - o.
@@ -71,7 +73,7 @@ __device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, lo
 // fine cells' own traces, and lifts it with its own basis evaluated at the
 // mapped points (tangential xi = (xi_fine + sigma)/2).
 template <int D, int P, int A>
-__device__ void mortar_lift(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB],
+__device__ __forceinline__ void mortar_lift(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB],
                             double (&R)[D + 2][Tab<D, P>::NB], int side, const FaceLink L, int t, double scale)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, Q = P + 1, NF = Tab<D, P>::NF;
@@ -361,16 +363,30 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 }
 
 // ------------------------------------------------------------------ stage kernel
+// One thread per cell.  A workgroup covers a slab of `rows` layers of the
+// leaf along its last axis (the whole leaf in 2-D; in 3-D slabs of at most
+// 256 cells, so a thread may keep its cell's state and residual in up to
+// 512 registers); faces on a slab edge inside the leaf read the adjacent
+// layer straight from the stage input.
+// threads per workgroup: 3-D degree <= 1 keeps whole 512-cell leaves (its
+// state fits 256 registers); every other case uses slabs of <= 256 cells
+template <int D, int P>
+constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
+
 template <int D, int P, int GM, int OM, bool LIM>
-__global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
+__global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, int rows)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
     constexpr int FCH = face_chunk<D, P>();
     extern __shared__ double lds[];
 
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N;
-    const int leaf = xcd_leaf(blockIdx.x, g.nleaves);
-    const int cell = threadIdx.x;
+    const int layer = D == 2 ? N : N * N; // cells per layer of the last axis
+    const int slabs = N / rows;
+    const int wg = xcd_leaf(blockIdx.x, g.nleaves * slabs);
+    const int leaf = wg / slabs, k0 = (wg % slabs) * rows;
+    const int lc = threadIdx.x, nslab = rows * layer;
+    const int cell = lc + k0 * layer;
     int ijk[3];
     cell_ijk(cell, N, D, ijk);
     const double scale[3] = {g.geo[leaf].scale[0], g.geo[leaf].scale[1], g.geo[leaf].scale[2]};
@@ -388,7 +404,7 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
 
     // ---- volume integral: sum_q w_q F_a(U_q) (2/h_a) dphi_m/dxi_a / M_m
     const double gm1 = g.gamma - 1.0;
-    auto vol_point = [&](auto qv) {
+    auto vol_point = [&](auto qv) __attribute__((always_inline)) {
         const int q = qv;
         double U[NV];
 #pragma unroll
@@ -403,7 +419,7 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
         }
         const double rinv = 1.0 / U[0];
         const double p = pressure_r<D>(U, gm1, rinv);
-        static_for<0, D>([&](auto Ai) {
+        static_for<0, D>([&](auto Ai) __attribute__((always_inline)) {
             constexpr int A = Ai;
             double F[NV];
             euler_flux<D, A>(U, U[1 + A] * rinv, p, F);
@@ -427,10 +443,13 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
     }
 
     // ---- surface integrals, one axis at a time
-    static_for<0, D>([&](auto Ai) {
+    static_for<0, D>([&](auto Ai) __attribute__((always_inline)) {
         constexpr int A = Ai;
         const int stride = A == 0 ? 1 : (A == 1 ? N : N * N);
         const int ia = ijk[A];
+        // neighbours reachable through LDS (inside this slab)
+        const bool in_m = A == D - 1 ? ia > k0 : ia > 0;
+        const bool in_p = A == D - 1 ? ia < k0 + rows - 1 : ia < N - 1;
         const int t = face_t(ijk, A, N, D);
         const double sc = scale[A];
         const FaceLink Lm = g.links[leaf * 2 * D + 2 * A];
@@ -439,7 +458,7 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
         const bool mort_p = g.conservative && ia == N - 1 && Lp.type == dgamr::LINK_FINE;
         if (mort_m) mortar_lift<D, P, A>(g, K, R, -1, Lm, t, sc);
         if (mort_p) mortar_lift<D, P, A>(g, K, R, +1, Lp, t, sc);
-        auto face_chunk_body = [&](auto cv) {
+        auto face_chunk_body = [&](auto cv) __attribute__((always_inline)) {
             const int f0 = int(cv) * FCH;
             // own traces of this chunk: + side to LDS, - side kept
             double Tm[FCH][NV];
@@ -450,18 +469,30 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
                 for (int v = 0; v < NV; ++v) {
                     double e, o;
                     trace_eo<D, P>(K[v], A, f0 + fi, e, o);
-                    lds[(v * FCH + fi) * ncell + cell] = e + o;
+                    lds[(v * FCH + fi) * nslab + lc] = e + o;
                     Tm[fi][v] = e - o;
                 }
             __syncthreads();
             // flux on the - face: left state = the left neighbour's + trace
             double Fm[FCH][NV];
-            if (ia > 0) {
+            if (in_m) {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
                     double TL[NV];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * ncell + cell - stride];
+                    for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * nslab + lc - stride];
+                    rusanov<D, A>(TL, Tm[fi], g.gamma, Fm[fi]);
+                }
+            } else if (ia > 0) { // slab edge inside the leaf: the layer below
+#pragma unroll
+                for (int fi = 0; fi < FCH; ++fi) {
+                    double TL[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        double e, o;
+                        trace_eo_mem<D, P>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
+                        TL[v] = e + o;
+                    }
                     rusanov<D, A>(TL, Tm[fi], g.gamma, Fm[fi]);
                 }
             } else if (!mort_m) {
@@ -479,14 +510,28 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
 #pragma unroll
             for (int fi = 0; fi < FCH; ++fi)
 #pragma unroll
-                for (int v = 0; v < NV; ++v) lds[(v * FCH + fi) * ncell + cell] = Fm[fi][v];
+                for (int v = 0; v < NV; ++v) lds[(v * FCH + fi) * nslab + lc] = Fm[fi][v];
             __syncthreads();
             double Fp[FCH][NV];
-            if (ia < N - 1) {
+            if (in_p) {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Fp[fi][v] = lds[(v * FCH + fi) * ncell + cell + stride];
+                    for (int v = 0; v < NV; ++v) Fp[fi][v] = lds[(v * FCH + fi) * nslab + lc + stride];
+            } else if (ia < N - 1) { // slab edge inside the leaf: the layer above
+#pragma unroll
+                for (int fi = 0; fi < FCH; ++fi) {
+                    double TL[NV], TR[NV];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        double e, o;
+                        trace_eo<D, P>(K[v], A, f0 + fi, e, o);
+                        TL[v] = e + o;
+                        trace_eo_mem<D, P>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
+                        TR[v] = e - o;
+                    }
+                    rusanov<D, A>(TL, TR, g.gamma, Fp[fi]);
+                }
             } else if (!mort_p) {
                 double TR[FCH][NV];
                 far_traces<D, P, A, GM, FCH>(g, K, leaf, +1, t, Lp, f0, TR);
@@ -577,16 +622,16 @@ __global__ __launch_bounds__(D == 2 ? 256 : 512) void k_stage(StageArgs g)
 #pragma unroll
             for (int a2 = 0; a2 < D; ++a2) rate += (fabs(U[1 + a2] * rinv) + cs) / g.geo[leaf].h[a2];
             __syncthreads();
-            lds[cell] = rate;
+            lds[lc] = rate;
             __syncthreads();
-            for (int s = 1; s < ncell; s <<= 1) {
-                if ((cell % (2 * s)) == 0 && cell + s < ncell) {
-                    const double o = lds[cell + s];
-                    lds[cell] = o > lds[cell] || o != o ? o : lds[cell];
+            for (int s = 1; s < nslab; s <<= 1) {
+                if ((lc % (2 * s)) == 0 && lc + s < nslab) {
+                    const double o = lds[lc + s];
+                    lds[lc] = o > lds[lc] || o != o ? o : lds[lc];
                 }
                 __syncthreads();
             }
-            if (cell == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds[0]));
+            if (lc == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds[0]));
         }
     }
 }

@@ -137,7 +137,7 @@ __device__ __forceinline__ void far_coeffs_v(const StageArgs &g, const double *K
 // fine sub-faces' Gauss points with the fine cells' own traces, lifted with
 // the own basis at the mapped points.
 template <int P, int A>
-__device__ void mortar_lift_v(const StageArgs &g, const double *K, double *R, int v, int side, const FaceLink L,
+__device__ __forceinline__ void mortar_lift_v(const StageArgs &g, const double *K, double *R, int v, int side, const FaceLink L,
                               int t, double scale, double isM, double isE)
 {
     constexpr int NV = 4, NB = Tab<2, P>::NB, Q = P + 1;

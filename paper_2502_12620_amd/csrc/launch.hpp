@@ -9,9 +9,10 @@
 
 namespace dgk {
 
-// residual / fused stage: grid = one workgroup per leaf, N^d threads
+// residual / fused stage.  variant (2-D, fused stage without limiter):
+// 0 = one lane per (cell, variable) in row slabs, 1 = one thread per cell.
 template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, hipStream_t s);
+hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, int variant, hipStream_t s);
 // guard fill: one thread per guard cell of the listed faces
 template <int D, int P>
 hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s);

@@ -21,13 +21,14 @@ FP64, FP32_MFMA = 0, 1
 HANG_PAPER, HANG_CONSERVATIVE = 0, 1
 LIMITER_NONE, LIMITER_POSITIVITY = 0, 1
 IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE = 0, 1, 2, 3
+TUNE_STAGE_VARIANT, TUNE_VAR_SPLIT_MAX_CELLS = 0, 1
 
 EXPORTS = [
     "dgamr_create_forest", "dgamr_destroy_forest", "dgamr_num_leaves", "dgamr_leaf_keys",
     "dgamr_state_bytes", "dgamr_set_refinement", "dgamr_apply_refinement",
     "dgamr_fill_guardcells", "dgamr_dg_residual", "dgamr_rk_stage", "dgamr_compute_dt",
     "dgamr_step", "dgamr_run", "dgamr_conserved_totals", "dgamr_limit_positivity", "dgamr_indicator",
-    "dgamr_project_ic", "dgamr_check_state", "dgamr_profile_enable", "dgamr_profile_read",
+    "dgamr_project_ic", "dgamr_check_state", "dgamr_set_tuning", "dgamr_profile_enable", "dgamr_profile_read",
     "dgamr_last_error",
 ]
 
@@ -76,6 +77,7 @@ def lib():
         L.dgamr_indicator.argtypes = [vp, vp, vp, vp, vp]
         L.dgamr_project_ic.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_double, vp, vp]
         L.dgamr_check_state.argtypes = [vp, vp, i64p, vp, vp]
+        L.dgamr_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_long]
         L.dgamr_profile_enable.argtypes = [vp, ctypes.c_int]
         L.dgamr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
         L.dgamr_last_error.restype = ctypes.c_char_p
@@ -238,6 +240,9 @@ class Forest:
         if rc not in (OK, ENONPHYSICAL):
             _check(rc)
         return bad.value
+
+    def set_tuning(self, knob, value):
+        _check(lib().dgamr_set_tuning(self.h, knob, value))
 
     def profile_enable(self, enable=True):
         _check(lib().dgamr_profile_enable(self.h, 1 if enable else 0))

@@ -229,6 +229,29 @@ def test_run_folds_the_cfl_step_into_the_stages(hanging):
     assert rel_diff(_host(ud2), u).max() <= TOL
 
 
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("hanging", [0, 1])
+def test_2d_stage_variants_agree_with_the_oracle(p, hanging):
+    """Both 2-D stage kernels (one lane per cell and variable; one thread per
+    cell) on a three-level forest with ragged N, against the oracle."""
+    G = _hip()
+    w = _forest(2, p, 6, 3)
+    orc, gpu = make_pair(w, hanging=hanging)
+    u = _physical_state(orc, w, seed=20 + p)
+    work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    outs = []
+    for variant in (0, 1):
+        gpu.set_tuning(G.TUNE_STAGE_VARIANT, variant)
+        ud = _cuda(u)
+        for _ in range(3):
+            gpu.step(ud, work, dt, 0.1)
+        outs.append(_host(ud))
+    for _ in range(3):
+        orc.step(u, 0.1)
+    for o in outs:
+        assert rel_diff(o, u).max() <= TOL
+
+
 def test_fused_step_matches_unfused_entry_points():
     w = _forest(2, 2, 8, 3, hanging=0)
     orc, gpu = make_pair(w, hanging=1)
