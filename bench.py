@@ -9,9 +9,11 @@ folded into the previous step's last stage.
 
 Prints one JSON line: DOF-stage updates/s over exactly --steps timed steps
 (inputs resident in HBM), the roofline of the dominant kernel (the fused
-stage kernel, timed live with HIP events around each of its launches), and
-the oracle's rate on the host cores for a bounded sample of the same
-workload.
+stage kernel, timed live with HIP events around each of its launches), the
+same run with FP32 residual arithmetic (FP64 state), the oracle's rate on
+the host cores for a bounded sample of the same workload, and the L1 / L2
+density difference and mass drift of both GPU runs against the oracle after
+the same number of steps.
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
-STAGE_SOURCES = ["kernels.hpp", "kernel_common.hpp", "dg_tables.hpp", "inst.hip"]
+STAGE_SOURCES = ["kernels_2d.hpp", "kernels.hpp", "kernel_common.hpp", "dg_tables.hpp", "inst.hip"]
 
 
 def kernel_hash() -> str:
@@ -66,27 +68,79 @@ def read_counter_traffic(workload_name: str):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(w, budget_s: float):
+def cpu_baseline(w, n_ref_steps: int, budget_s: float):
     """The oracle (as it stands) on the host cores: whole SSP-RK3 steps of the
-    same workload from the same initial state, as many as fit the budget."""
+    same workload from the same initial state.  Returns the rate over at least
+    budget_s seconds of steps, and the oracle state after n_ref_steps steps
+    (the reference for the accuracy of the GPU results)."""
     import oracle as O
 
     f = O.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
     for rule in w.initial_refinement:
         f.adapt(rule(w, f.keys()))
     u = f.project_ic(O.IC_VORTEX, w.ic_params)
+    t0 = f.totals(u)
     dof = w.dofs(f.n_leaves)
-    t0 = time.perf_counter()
+    ref = None
+    start = time.perf_counter()
     steps = 0
     while True:
         f.step(u, w.cfl)
         steps += 1
-        el = time.perf_counter() - t0
-        if el > budget_s or steps >= w.steps:
+        if steps == n_ref_steps:
+            ref = (u.copy(), f.totals(u))
+        el = time.perf_counter() - start
+        if steps >= n_ref_steps and el > budget_s:
             break
-    return {"value": dof * 3 * steps / el, "unit": "DOF-stage updates/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"{steps} SSP-RK3 steps of {w.name} ({f.n_leaves} leaves, {dof} DOF) from the vortex "
-                      f"initial state, {el:.1f} s"}
+    out = {"value": dof * 3 * steps / el, "unit": "DOF-stage updates/s", "cores": O.threads(), "kind": "oracle",
+           "sample": f"{steps} SSP-RK3 steps of {w.name} ({f.n_leaves} leaves, {dof} DOF) from the vortex "
+                     f"initial state, {el:.1f} s"}
+    return out, ref[0], ref[1], t0
+
+
+def accuracy(u_gpu, tot_gpu, u_ref, tot_ref, tot0):
+    """Relative L1 / L2 difference of the density coefficients against the
+    oracle state, and the relative mass drift of both runs."""
+    import numpy as np
+
+    d = u_gpu[:, 0] - u_ref[:, 0]
+    return {"rel_l1_density": float(np.abs(d).sum() / np.abs(u_ref[:, 0]).sum()),
+            "rel_l2_density": float(np.linalg.norm(d) / np.linalg.norm(u_ref[:, 0])),
+            "rel_max_all": float(np.abs(u_gpu - u_ref).max() / np.abs(u_ref).max()),
+            "mass_drift_gpu": float(abs(tot_gpu[0] - tot0[0]) / abs(tot0[0])),
+            "mass_drift_oracle": float(abs(tot_ref[0] - tot0[0]) / abs(tot0[0]))}
+
+
+def time_path(G, w, precision, hang, steps, warmup):
+    """warmup + steps SSP-RK3 steps through dgamr_run from the vortex initial
+    state; the last `steps` timed, stage kernels timed with HIP events."""
+    import torch
+
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, hanging=hang,
+                 precision=precision)
+    z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
+    for rule in w.initial_refinement:
+        z = f.adapt(rule(w, f.keys()), z)
+    u = f.project_ic(G.IC_VORTEX, w.ic_params)
+    work = f.new_work()
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
+    f.run(u, work, dt, warmup, w.cfl)
+    torch.cuda.synchronize()
+    f.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    f.run(u, work, dt, steps, w.cfl)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    f.profile_enable(False)
+    stage_ms, launches = f.profile_read()
+    bad = f.check_state(u, work)
+    if bad:
+        print(f"non-physical state after the timed steps ({bad} cells)", file=sys.stderr)
+        sys.exit(3)
+    tot = f.conserved_totals(u, work).cpu().numpy()
+    return {"f": f, "u": u.cpu().numpy(), "totals": tot, "elapsed": elapsed,
+            "avg_launch_s": stage_ms / 1e3 / max(launches, 1), "launches": launches}
 
 
 def main():
@@ -95,8 +149,9 @@ def main():
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--hanging", choices=["paper", "conservative"], default="paper")
-    ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle time for cpu_baseline")
+    ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-residual run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the whole forest lives on one "
@@ -111,34 +166,14 @@ def main():
     torch.cuda.set_device(0)
     w = W.vortex_c2()
     hang = G.HANG_PAPER if args.hanging == "paper" else G.HANG_CONSERVATIVE
-    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, hanging=hang)
-    z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
-    for rule in w.initial_refinement:
-        z = f.adapt(rule(w, f.keys()), z)
-    u = f.project_ic(G.IC_VORTEX, w.ic_params)
-    work = f.new_work()
-    dt = torch.zeros(1, dtype=torch.float64, device="cuda")
-    n = f.n_leaves
+    r64 = time_path(G, w, G.FP64, hang, args.steps, args.warmup)
+    n = r64["f"].n_leaves
     ab = algorithmic_bytes_per_stage(w, n)
     dof = ab["dof"]
+    r32 = time_path(G, w, G.FP32_MFMA, hang, args.steps, args.warmup) if not args.no_fp32 else None
 
-    f.run(u, work, dt, args.warmup, w.cfl)
-    torch.cuda.synchronize()
-    f.profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    f.run(u, work, dt, args.steps, w.cfl)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    f.profile_enable(False)
-    stage_ms, launches = f.profile_read()
-    bad = f.check_state(u, work)
-    if bad:
-        print(f"non-physical state after the timed steps ({bad} cells)", file=sys.stderr)
-        sys.exit(3)
-
-    value = dof * 3 * args.steps / elapsed
-    avg_s = stage_ms / 1e3 / max(launches, 1)
+    value = dof * 3 * args.steps / r64["elapsed"]
+    avg_s = r64["avg_launch_s"]
     achieved = ab["bytes_per_launch"] / avg_s / 1e9
     traffic = read_counter_traffic(w.name)
     out = {
@@ -148,7 +183,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": elapsed / args.steps * 1e3,
+        "ms_per_step": r64["elapsed"] / args.steps * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -158,13 +193,25 @@ def main():
                    "degree": w.degree, "n_cell": w.n_cell, "hanging": args.hanging, "precision": "fp64"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_stage (fused residual + RK stage)",
-                     "avg_launch_us": avg_s * 1e6, "launches": launches,
+                     "kernel": "k_stage2v (fused residual + RK stage, one lane per cell and variable)",
+                     "avg_launch_us": avg_s * 1e6, "launches": r64["launches"],
                      "algorithmic_bytes_per_launch": ab["bytes_per_launch"],
                      "algorithmic_bytes_per_dof": ab["bytes_per_dof"]},
     }
+    if r32 is not None:
+        out["fp32_residual"] = {
+            "value": dof * 3 * args.steps / r32["elapsed"], "unit": "DOF-stage updates/s",
+            "ms_per_step": r32["elapsed"] / args.steps * 1e3, "dtype": "f32 residual, f64 state",
+            "kernel": "k_stage<float> (fused residual + RK stage, one thread per cell)",
+            "avg_launch_us": r32["avg_launch_s"] * 1e6,
+            "achieved_GBs": ab["bytes_per_launch"] / r32["avg_launch_s"] / 1e9}
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        cpu, u_ref, tot_ref, tot0 = cpu_baseline(w, args.warmup + args.steps, args.cpu_budget)
+        out["cpu_baseline"] = cpu
+        out["accuracy_vs_oracle"] = {"steps": args.warmup + args.steps,
+                                     "fp64": accuracy(r64["u"], r64["totals"], u_ref, tot_ref, tot0)}
+        if r32 is not None:
+            out["accuracy_vs_oracle"]["fp32_residual"] = accuracy(r32["u"], r32["totals"], u_ref, tot_ref, tot0)
     print(json.dumps(out))
 
 

@@ -39,10 +39,7 @@ struct dgamr_forest {
     int device = 0;
     LeafGeo *d_geo = nullptr;
     FaceLink *d_links = nullptr;
-    int *d_hang = nullptr;   // (leaf*2d + face) of every coarse or fine link
-    int n_hang = 0;
     int cap = 0;             // leaves the device tables can hold
-    int hang_cap = 0;
     bool prof = false;       // bracket stage launches with events
     int stage_variant = -1;  // 2-D stage kernel: -1 auto, 0 lane per (cell, var), 1 thread per cell
     long var_split_max_cells = 131072; // auto: lane per (cell, var) up to this many cells
@@ -109,18 +106,6 @@ int upload(dgamr_forest *f)
     std::vector<LeafGeo> geo = f->topo.geometry();
     HIP_TRY(hipMemcpy(f->d_geo, geo.data(), sizeof(LeafGeo) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(f->d_links, f->topo.links().data(), sizeof(FaceLink) * size_t(n) * nf, hipMemcpyHostToDevice));
-    std::vector<int> hang;
-    for (int i = 0; i < n * nf; ++i) {
-        int ty = f->topo.links()[i].type;
-        if (ty == dgamr::LINK_COARSE || ty == dgamr::LINK_FINE) hang.push_back(i);
-    }
-    f->n_hang = int(hang.size());
-    if (f->n_hang > f->hang_cap) {
-        if (f->d_hang) HIP_TRY(hipFree(f->d_hang));
-        f->hang_cap = f->n_hang + 64;
-        HIP_TRY(hipMalloc(&f->d_hang, sizeof(int) * f->hang_cap));
-    }
-    if (f->n_hang) HIP_TRY(hipMemcpy(f->d_hang, hang.data(), sizeof(int) * f->n_hang, hipMemcpyHostToDevice));
     return DGAMR_OK;
 }
 
@@ -141,11 +126,12 @@ int dispatch(int d, int p, Fn &&fn)
     }
 }
 
-int launch_fill(dgamr_forest *f, const double *u, double *guard, bool hanging_only, hipStream_t s)
+// guard cells of every block face, as coefficients or (traces) as their
+// values at the face points
+int launch_fill(dgamr_forest *f, const double *u, double *guard, bool traces, hipStream_t s)
 {
     int nf = 2 * f->topo.dim();
-    dgk::FillArgs a{u, guard, f->d_links, hanging_only ? f->d_hang : nullptr,
-                    hanging_only ? f->n_hang : f->topo.n() * nf, f->topo.desc().n_cell};
+    dgk::FillArgs a{u, guard, f->d_links, nullptr, f->topo.n() * nf, f->topo.desc().n_cell, traces ? 1 : 0};
     if (a.nfaces == 0) return DGAMR_OK;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
         HIP_TRY((dgk::launch_fill<D, P>(a, nfc_of(f), s)));
@@ -168,9 +154,9 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     a.links = f->d_links;
     a.conservative = f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE;
     if (a.nleaves == 0) return DGAMR_OK;
-    if (f->topo.desc().precision == DGAMR_FP32_MFMA) return fail(DGAMR_EUNSUPPORTED, "FP32-MFMA residual not built");
+    const bool fp32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, stage_variant(f), s)));
+        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, stage_variant(f), fp32, s)));
         return DGAMR_OK;
     });
 }
@@ -277,7 +263,6 @@ int dgamr_destroy_forest(dgamr_forest *f)
     }
     (void)hipFree(f->d_geo);
     (void)hipFree(f->d_links);
-    (void)hipFree(f->d_hang);
     delete f;
     return DGAMR_OK;
 }
@@ -435,11 +420,12 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         a.rate_clear = s == 0 ? rate_clear : nullptr;
         a.dt_out = dt_dev;
         a.rate_out = s == 2 ? rate_out : nullptr;
-        // 3-D reads the far side of every block face from the guard buffer
+        // 3-D reads the far side of every block face as traces from the
+        // guard buffer; 2-D computes it inline
         const bool guard3 = f->topo.dim() == 3;
         if (guard3) {
             a.guard = w.guard;
-            CHECK(launch_fill(f, us, w.guard, false, stream));
+            CHECK(launch_fill(f, us, w.guard, true, stream));
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (f->prof) {
@@ -447,7 +433,7 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
             CHECK(take_event(f, e1));
             HIP_TRY(hipEventRecord(e0, stream));
         }
-        CHECK(launch_stage(f, a, guard3 ? dgk::GUARD_BUFFER : dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
+        CHECK(launch_stage(f, a, guard3 ? dgk::GUARD_TRACE : dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
         if (f->prof) {
             HIP_TRY(hipEventRecord(e1, stream));
             f->ev_rec.emplace_back(e0, e1);

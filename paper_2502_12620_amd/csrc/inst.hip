@@ -27,8 +27,6 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s)
     const dim3 grid(unsigned(a.nleaves * slabs)), block(rows * a.N * 4);
     if (gm == GUARD_BUFFER && om == OUT_RES64)
         hipLaunchKernelGGL((k_stage2v<P, GUARD_BUFFER, OUT_RES64>), grid, block, lds, s, a, rows);
-    else if (gm == GUARD_BUFFER && om == OUT_RES32)
-        hipLaunchKernelGGL((k_stage2v<P, GUARD_BUFFER, OUT_RES32>), grid, block, lds, s, a, rows);
     else if (gm == GUARD_INLINE && om == OUT_RK)
         hipLaunchKernelGGL((k_stage2v<P, GUARD_INLINE, OUT_RK>), grid, block, lds, s, a, rows);
     else
@@ -36,38 +34,49 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s)
     return hipGetLastError();
 }
 
-template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, int variant, hipStream_t s)
+template <int D, int P, typename T>
+hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, hipStream_t s)
 {
-    if constexpr (D == 2) {
-        // one lane per (cell, variable) unless the caller asks for one
-        // thread per cell (variant 1) or needs the limiter
-        if (!lim && (variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s);
-    }
-    // slab of `rows` layers along the last axis with at most 256 cells
+    // slab of `rows` layers along the last axis within the thread budget
     const int layer = D == 2 ? a.N : a.N * a.N;
     int rows = a.N;
     while (rows % 2 == 0 && rows * layer > stage_threads<D, P>()) rows /= 2;
     const int nslab = rows * layer;
     const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * nslab;
     const dim3 grid(unsigned(a.nleaves * (a.N / rows))), block(nslab);
-    // 3-D reads every block face from the guard buffer (the stage path runs
-    // the fill kernel first); 2-D takes the far side inline
-    if (D == 3 && gm == GUARD_BUFFER && om == OUT_RES64)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false>), grid, block, lds, s, a, rows);
-    else if (D == 3 && gm == GUARD_BUFFER && om == OUT_RES32)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false>), grid, block, lds, s, a, rows);
-    else if (D == 3 && gm == GUARD_BUFFER && om == OUT_RK && !lim)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RK, false>), grid, block, lds, s, a, rows);
-    else if (D == 3 && gm == GUARD_BUFFER && om == OUT_RK && lim)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RK, true>), grid, block, lds, s, a, rows);
-    else if (D == 2 && gm == GUARD_INLINE && om == OUT_RK && !lim)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, false>), grid, block, lds, s, a, rows);
-    else if (D == 2 && gm == GUARD_INLINE && om == OUT_RK && lim)
-        hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, true>), grid, block, lds, s, a, rows);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
+    // the fused 3-D stage reads every block face as traces from the guard
+    // buffer (the step runs the fill kernel first); the fused 2-D stage
+    // takes the far side inline
+    constexpr int GMRK = D == 3 ? GUARD_TRACE : GUARD_INLINE;
+    if (gm == GMRK && om == OUT_RK) {
+        if (lim) hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T>), grid, block, lds, s, a, rows);
+        else hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T>), grid, block, lds, s, a, rows);
+        return hipGetLastError();
+    }
+    if constexpr (std::is_same<T, float>::value) {
+        if (gm == GUARD_BUFFER && om == OUT_RES32) {
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false, T>), grid, block, lds, s, a, rows);
+            return hipGetLastError();
+        }
+    } else if constexpr (D == 3) { // the 2-D FP64 residual runs one lane per (cell, variable)
+        if (gm == GUARD_BUFFER && om == OUT_RES64) {
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false, T>), grid, block, lds, s, a, rows);
+            return hipGetLastError();
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int D, int P>
+hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, int variant, bool fp32, hipStream_t s)
+{
+    if (fp32) return launch_stage_cell<D, P, float>(a, gm, om, lim, s);
+    if constexpr (D == 2) {
+        // one lane per (cell, variable) unless the caller asks for one
+        // thread per cell (variant 1) or needs the limiter
+        if (!lim && (variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s);
+    }
+    return launch_stage_cell<D, P, double>(a, gm, om, lim, s);
 }
 
 template <int D, int P>
@@ -102,7 +111,7 @@ hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, 
     return hipGetLastError();
 }
 
-template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, int, hipStream_t);
+template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, int, bool, hipStream_t);
 template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t);
 template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStream_t);
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,

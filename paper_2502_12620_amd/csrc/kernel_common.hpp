@@ -101,7 +101,10 @@ __device__ __forceinline__ void rusanov(const T *UL, const T *UR, T gamma, T *Ph
     const T rl = T(1) / UL[0], rr = T(1) / UR[0];
     const T pl = pressure_r<D, T>(UL, gm1, rl), pr = pressure_r<D, T>(UR, gm1, rr);
     const T ul = UL[1 + A] * rl, ur = UR[1 + A] * rr;
-    const T cl = sqrt(gamma * pl * rl), cr = sqrt(gamma * pr * rr);
+    // a pressure rounded below zero (FP32 traces of a near-vacuum state)
+    // enters the wave speed as zero; exact arithmetic never takes this branch
+    // on a state the positivity limiter has passed
+    const T cl = sqrt(gamma * (pl > T(0) ? pl : T(0)) * rl), cr = sqrt(gamma * (pr > T(0) ? pr : T(0)) * rr);
     const T al = fabs(ul) + cl, ar = fabs(ur) + cr;
     const T alpha = al > ar ? al : ar;
     T FL[NV], FR[NV];
@@ -113,10 +116,12 @@ __device__ __forceinline__ void rusanov(const T *UL, const T *UR, T gamma, T *Ph
 
 // ------------------------------------------------------------------ argument blocks
 enum GuardMode : int {
-    GUARD_BUFFER = 0, // every block face from the guard buffer
-    GUARD_INLINE = 1  // every block face straight from the neighbours' cells:
+    GUARD_BUFFER = 0, // every block face from the guard buffer (coefficients)
+    GUARD_INLINE = 1, // every block face straight from the neighbours' cells:
                       // copy, split of the coarser cell or combine of the
                       // finer cells computed on the fly (no guard buffer)
+    GUARD_TRACE = 2   // every block face from the guard buffer holding the
+                      // guard cells' traces at the face points
 };
 enum OutMode : int { OUT_RES64 = 0, OUT_RES32 = 1, OUT_RK = 2 };
 
@@ -155,6 +160,8 @@ struct FillArgs {
     const int *faces;  // optional list of (leaf*2d + face) to fill; null = all
     int nfaces;        // number of faces to fill
     int N;
+    int traces;        // 0: guard coefficients G[leaf][face][var][mode][t];
+                       // 1: their traces on the face, G[leaf][face][var][point][t]
 };
 
 struct IcParams {

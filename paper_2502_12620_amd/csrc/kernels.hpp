@@ -11,6 +11,8 @@
 // sends it back through LDS.
 #pragma once
 
+#include <type_traits>
+
 #include "kernel_common.hpp"
 
 namespace dgk {
@@ -35,35 +37,34 @@ constexpr bool unroll_points() { return D == 2; }
 
 // even / odd parts (in the normal mode index) of the trace of K at face
 // point f of axis a: the trace at xi_a = +1 is e + o, at xi_a = -1 it is e - o.
-template <int D, int P>
-__device__ __forceinline__ void trace_eo(const double *K, int a, int f, double &e, double &o)
+template <int D, int P, typename T>
+__device__ __forceinline__ void trace_eo(const T *K, int a, int f, T &e, T &o)
 {
-    e = 0.0;
-    o = 0.0;
+    e = T(0);
+    o = T(0);
 #pragma unroll
     for (int m = 0; m < Tab<D, P>::NB; ++m) {
         const double c = kTab<D, P>.phi_f[a][f][m];
         if (c != 0.0) {
-            if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(c, K[m], e);
-            else o = fma(c, K[m], o);
+            if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(T(c), K[m], e);
+            else o = fma(T(c), K[m], o);
         }
     }
 }
 
 // the same for coefficients streamed from memory (coef[m*sm])
-template <int D, int P>
-__device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, long sm, int a, int f, double &e,
-                                             double &o)
+template <int D, int P, typename T>
+__device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, long sm, int a, int f, T &e, T &o)
 {
-    e = 0.0;
-    o = 0.0;
+    e = T(0);
+    o = T(0);
 #pragma unroll
     for (int m = 0; m < Tab<D, P>::NB; ++m) {
         const double c = kTab<D, P>.phi_f[a][f][m];
         if (c != 0.0) {
-            const double k = coef[m * sm];
-            if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(c, k, e);
-            else o = fma(c, k, o);
+            const T k = T(coef[m * sm]);
+            if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(T(c), k, e);
+            else o = fma(T(c), k, o);
         }
     }
 }
@@ -72,9 +73,9 @@ __device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, lo
 // flux over the 2^(d-1) fine sub-faces at the fine Gauss points, with the
 // fine cells' own traces, and lifts it with its own basis evaluated at the
 // mapped points (tangential xi = (xi_fine + sigma)/2).
-template <int D, int P, int A>
-__device__ __forceinline__ void mortar_lift(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB],
-                            double (&R)[D + 2][Tab<D, P>::NB], int side, const FaceLink L, int t, double scale)
+template <int D, int P, int A, typename T>
+__device__ __forceinline__ void mortar_lift(const StageArgs &g, const T (&K)[D + 2][Tab<D, P>::NB],
+                                            T (&R)[D + 2][Tab<D, P>::NB], int side, const FaceLink L, int t, T scale)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, Q = P + 1, NF = Tab<D, P>::NF;
     constexpr int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2; // tangential axes, lower first
@@ -99,36 +100,36 @@ __device__ __forceinline__ void mortar_lift(const StageArgs &g, const double (&K
             const double x0 = 0.5 * (gl_x(Q, q0) + (s0 ? 1.0 : -1.0));
             const double x1 = 0.5 * (gl_x(Q, q1) + (s1 ? 1.0 : -1.0));
             const double w = gl_w(Q, q0) * (D == 3 ? gl_w(Q, q1) : 1.0);
-            double Uf[NV], Uc[NV], Phi[NV];
+            T Uf[NV], Uc[NV], Phi[NV];
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                double e, o;
-                trace_eo_mem<D, P>(fk + v * sv, ncell, A, F, e, o);
+                T e, o;
+                trace_eo_mem<D, P, T>(fk + v * sv, ncell, A, F, e, o);
                 Uf[v] = side > 0 ? e - o : e + o; // the fine cell touches the face with its -side side
-                double ec = 0.0, oc = 0.0;
+                T ec = T(0), oc = T(0);
 #pragma unroll
                 for (int m = 0; m < NB; ++m) {
                     const double c = leg(kTab<D, P>.e[m][TA], x0) * (D == 3 ? leg(kTab<D, P>.e[m][TBX], x1) : 1.0);
                     if (c != 0.0) {
-                        if (kTab<D, P>.e[m][A] % 2 == 0) ec = fma(c, K[v][m], ec);
-                        else oc = fma(c, K[v][m], oc);
+                        if (kTab<D, P>.e[m][A] % 2 == 0) ec = fma(T(c), K[v][m], ec);
+                        else oc = fma(T(c), K[v][m], oc);
                     }
                 }
                 Uc[v] = side > 0 ? ec + oc : ec - oc;
             }
-            if (side > 0) rusanov<D, A>(Uc, Uf, g.gamma, Phi);
-            else rusanov<D, A>(Uf, Uc, g.gamma, Phi);
+            if (side > 0) rusanov<D, A, T>(Uc, Uf, T(g.gamma), Phi);
+            else rusanov<D, A, T>(Uf, Uc, T(g.gamma), Phi);
             // +face: -int Phi phi ; -face: +int Phi phi with phi(-1) = (-1)^{m_A} phi(+1)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
-                const double f = scale * sub * w * Phi[v];
+                const T f = scale * T(sub * w) * Phi[v];
 #pragma unroll
                 for (int m = 0; m < NB; ++m) {
                     const double c = leg(kTab<D, P>.e[m][TA], x0) * (D == 3 ? leg(kTab<D, P>.e[m][TBX], x1) : 1.0) *
                                      kTab<D, P>.inv_mass[m];
                     if (c != 0.0) {
                         const double sg = side > 0 ? -1.0 : ((kTab<D, P>.e[m][A] % 2) ? -1.0 : 1.0);
-                        R[v][m] = fma(sg * c, f, R[v][m]);
+                        R[v][m] = fma(T(sg * c), f, R[v][m]);
                     }
                 }
             }
@@ -138,34 +139,34 @@ __device__ __forceinline__ void mortar_lift(const StageArgs &g, const double (&K
 
 // Coefficients of the split of a coarse cell for child CH (Eq. 11-12):
 // g = S_CH k, one variable at a time.
-template <int D, int P, int CH>
-__device__ __forceinline__ void split_coeffs(const double *k, double *gk)
+template <int D, int P, int CH, typename T>
+__device__ __forceinline__ void split_coeffs(const T *k, T *gk)
 {
     constexpr int NB = Tab<D, P>::NB;
 #pragma unroll
     for (int m = 0; m < NB; ++m) {
-        double s = 0.0;
+        T s = T(0);
 #pragma unroll
         for (int n = 0; n < NB; ++n) {
             const double c = kTab<D, P>.split[CH][m][n];
-            if (c != 0.0) s = fma(c, k[n], s);
+            if (c != 0.0) s = fma(T(c), k[n], s);
         }
         gk[m] = s;
     }
 }
 
-template <int D, int P>
-__device__ __forceinline__ void split_any(int child, const double *k, double *gk)
+template <int D, int P, typename T>
+__device__ __forceinline__ void split_any(int child, const T *k, T *gk)
 {
     switch (child) {
-    case 0: split_coeffs<D, P, 0>(k, gk); break;
-    case 1: split_coeffs<D, P, 1>(k, gk); break;
-    case 2: split_coeffs<D, P, 2>(k, gk); break;
-    case 3: split_coeffs<D, P, 3>(k, gk); break;
-    case 4: if constexpr (D == 3) split_coeffs<D, P, 4>(k, gk); break;
-    case 5: if constexpr (D == 3) split_coeffs<D, P, 5>(k, gk); break;
-    case 6: if constexpr (D == 3) split_coeffs<D, P, 6>(k, gk); break;
-    default: if constexpr (D == 3) split_coeffs<D, P, 7>(k, gk); break;
+    case 0: split_coeffs<D, P, 0, T>(k, gk); break;
+    case 1: split_coeffs<D, P, 1, T>(k, gk); break;
+    case 2: split_coeffs<D, P, 2, T>(k, gk); break;
+    case 3: split_coeffs<D, P, 3, T>(k, gk); break;
+    case 4: if constexpr (D == 3) split_coeffs<D, P, 4, T>(k, gk); break;
+    case 5: if constexpr (D == 3) split_coeffs<D, P, 5, T>(k, gk); break;
+    case 6: if constexpr (D == 3) split_coeffs<D, P, 6, T>(k, gk); break;
+    default: if constexpr (D == 3) split_coeffs<D, P, 7, T>(k, gk); break;
     }
 }
 
@@ -177,29 +178,38 @@ __device__ __forceinline__ void split_any(int child, const double *k, double *gk
 //    coarser neighbour cell (Eq. 16), the combine of the 2^d finer cells
 //    (Eq. 17), or at an outflow boundary the mirror image, whose trace is
 //    the own trace.
-template <int D, int P, int A, int GM, int FCH>
-__device__ __forceinline__ void far_traces(const StageArgs &g, const double (&K)[D + 2][Tab<D, P>::NB], int leaf,
-                                           int side, int t, const FaceLink &L, int f0, double (&T)[FCH][D + 2])
+template <int D, int P, int A, int GM, int FCH, typename T>
+__device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[D + 2][Tab<D, P>::NB], int leaf, int side,
+                                           int t, const FaceLink &L, int f0, T (&Tr)[FCH][D + 2])
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB;
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
     const long sv = long(NB) * ncell;
     const int face = 2 * A + (side > 0);
-    auto traces_of = [&](const double *kv, int v, int poly_side) {
+    auto traces_of = [&](const T *kv, int v, int poly_side) {
 #pragma unroll
         for (int fi = 0; fi < FCH; ++fi) {
-            double e, o;
-            trace_eo<D, P>(kv, A, f0 + fi, e, o);
-            T[fi][v] = poly_side > 0 ? e + o : e - o;
+            T e, o;
+            trace_eo<D, P, T>(kv, A, f0 + fi, e, o);
+            Tr[fi][v] = poly_side > 0 ? e + o : e - o;
         }
     };
+    if (GM == GUARD_TRACE) {
+        constexpr int NF = Tab<D, P>::NF;
+        const double *gt = g.guard + ((long(leaf) * 2 * D + face) * NV * NF) * nfc + t;
+#pragma unroll
+        for (int fi = 0; fi < FCH; ++fi)
+#pragma unroll
+            for (int v = 0; v < NV; ++v) Tr[fi][v] = T(gt[(long(v) * NF + f0 + fi) * nfc]);
+        return;
+    }
     if (GM == GUARD_BUFFER) {
         const double *gk = g.guard + ((long(leaf) * 2 * D + face) * NV * NB) * nfc + t;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double kv[NB];
+            T kv[NB];
 #pragma unroll
-            for (int m = 0; m < NB; ++m) kv[m] = gk[(long(v) * NB + m) * nfc];
+            for (int m = 0; m < NB; ++m) kv[m] = T(gk[(long(v) * NB + m) * nfc]);
             traces_of(kv, v, -side);
         }
         return;
@@ -213,9 +223,9 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const double (&K)
         const double *nk = g.us + long(L.nbr[0]) * NV * sv + c;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double kv[NB];
+            T kv[NB];
 #pragma unroll
-            for (int m = 0; m < NB; ++m) kv[m] = nk[v * sv + m * ncell];
+            for (int m = 0; m < NB; ++m) kv[m] = T(nk[v * sv + m * ncell]);
             traces_of(kv, v, -side);
         }
     } else if (L.type == dgamr::LINK_COARSE) {
@@ -226,10 +236,10 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const double (&K)
         const double *ck = g.us + long(L.nbr[0]) * NV * sv + c;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double kv[NB], gv[NB];
+            T kv[NB], gv[NB];
 #pragma unroll
-            for (int m = 0; m < NB; ++m) kv[m] = ck[v * sv + m * ncell];
-            split_any<D, P>(child, kv, gv);
+            for (int m = 0; m < NB; ++m) kv[m] = T(ck[v * sv + m * ncell]);
+            split_any<D, P, T>(child, kv, gv);
             traces_of(gv, v, -side);
         }
     } else { // LINK_FINE
@@ -239,23 +249,23 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const double (&K)
         const double *fk = g.us + long(link_nbr(L, h0 + 2 * h1)) * NV * sv;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double gv[NB];
+            T gv[NB];
 #pragma unroll
-            for (int m = 0; m < NB; ++m) gv[m] = 0.0;
+            for (int m = 0; m < NB; ++m) gv[m] = T(0);
 #pragma unroll
             for (int ch = 0; ch < (1 << D); ++ch) {
                 const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
                 const int nidx = side > 0 ? bits[A] : N - 2 + bits[A];
                 const int fc = face_cell(A, nidx, (ft0 + bits[TA]) + N * (ft1 + (D == 3 ? bits[TBX] : 0)), N, D);
-                double kv[NB];
+                T kv[NB];
 #pragma unroll
-                for (int n = 0; n < NB; ++n) kv[n] = fk[v * sv + n * ncell + fc];
+                for (int n = 0; n < NB; ++n) kv[n] = T(fk[v * sv + n * ncell + fc]);
 #pragma unroll
                 for (int m = 0; m < NB; ++m)
 #pragma unroll
                     for (int n = 0; n < NB; ++n) {
                         const double cc = kTab<D, P>.comb[ch][m][n];
-                        if (cc != 0.0) gv[m] = fma(cc, kv[n], gv[m]);
+                        if (cc != 0.0) gv[m] = fma(T(cc), kv[n], gv[m]);
                     }
             }
             traces_of(gv, v, -side);
@@ -373,12 +383,16 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 template <int D, int P>
 constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
 
-template <int D, int P, int GM, int OM, bool LIM>
+// T is the arithmetic type of the residual: double, or float for the FP32
+// path (state read as FP64 and rounded; the stage update, limiter and CFL
+// rate stay FP64).
+template <int D, int P, int GM, int OM, bool LIM, typename T = double>
 __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, int rows)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
     constexpr int FCH = face_chunk<D, P>();
-    extern __shared__ double lds[];
+    extern __shared__ double lds_d[];
+    T *lds = reinterpret_cast<T *>(lds_d);
 
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N;
     const int layer = D == 2 ? N : N * N; // cells per layer of the last axis
@@ -389,40 +403,40 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
     const int cell = lc + k0 * layer;
     int ijk[3];
     cell_ijk(cell, N, D, ijk);
-    const double scale[3] = {g.geo[leaf].scale[0], g.geo[leaf].scale[1], g.geo[leaf].scale[2]};
+    const T scale[3] = {T(g.geo[leaf].scale[0]), T(g.geo[leaf].scale[1]), T(g.geo[leaf].scale[2])};
     const long sv = long(NB) * ncell;
     const long base = long(leaf) * NV * sv + cell;
 
-    double K[NV][NB], R[NV][NB];
+    T K[NV][NB], R[NV][NB];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
-            K[v][m] = g.us[base + v * sv + m * ncell];
-            R[v][m] = 0.0;
+            K[v][m] = T(g.us[base + v * sv + m * ncell]);
+            R[v][m] = T(0);
         }
 
     // ---- volume integral: sum_q w_q F_a(U_q) (2/h_a) dphi_m/dxi_a / M_m
-    const double gm1 = g.gamma - 1.0;
+    const T gamma = T(g.gamma), gm1 = T(g.gamma - 1.0);
     auto vol_point = [&](auto qv) __attribute__((always_inline)) {
         const int q = qv;
-        double U[NV];
+        T U[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
-            double s = 0.0;
+            T s = T(0);
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
                 const double c = kTab<D, P>.phi_v[q][m];
-                if (c != 0.0) s = fma(c, K[v][m], s);
+                if (c != 0.0) s = fma(T(c), K[v][m], s);
             }
             U[v] = s;
         }
-        const double rinv = 1.0 / U[0];
-        const double p = pressure_r<D>(U, gm1, rinv);
+        const T rinv = T(1) / U[0];
+        const T p = pressure_r<D, T>(U, gm1, rinv);
         static_for<0, D>([&](auto Ai) __attribute__((always_inline)) {
             constexpr int A = Ai;
-            double F[NV];
-            euler_flux<D, A>(U, U[1 + A] * rinv, p, F);
+            T F[NV];
+            euler_flux<D, A, T>(U, U[1 + A] * rinv, p, F);
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] *= scale[A];
 #pragma unroll
@@ -430,7 +444,7 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
                 const double c = kTab<D, P>.dproj[A][q][m];
                 if (c != 0.0) {
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) R[v][m] = fma(c, F[v], R[v][m]);
+                    for (int v = 0; v < NV; ++v) R[v][m] = fma(T(c), F[v], R[v][m]);
                 }
             }
         });
@@ -451,60 +465,60 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
         const bool in_m = A == D - 1 ? ia > k0 : ia > 0;
         const bool in_p = A == D - 1 ? ia < k0 + rows - 1 : ia < N - 1;
         const int t = face_t(ijk, A, N, D);
-        const double sc = scale[A];
+        const T sc = scale[A];
         const FaceLink Lm = g.links[leaf * 2 * D + 2 * A];
         const FaceLink Lp = g.links[leaf * 2 * D + 2 * A + 1];
         const bool mort_m = g.conservative && ia == 0 && Lm.type == dgamr::LINK_FINE;
         const bool mort_p = g.conservative && ia == N - 1 && Lp.type == dgamr::LINK_FINE;
-        if (mort_m) mortar_lift<D, P, A>(g, K, R, -1, Lm, t, sc);
-        if (mort_p) mortar_lift<D, P, A>(g, K, R, +1, Lp, t, sc);
+        if (mort_m) mortar_lift<D, P, A, T>(g, K, R, -1, Lm, t, sc);
+        if (mort_p) mortar_lift<D, P, A, T>(g, K, R, +1, Lp, t, sc);
         auto face_chunk_body = [&](auto cv) __attribute__((always_inline)) {
             const int f0 = int(cv) * FCH;
             // own traces of this chunk: + side to LDS, - side kept
-            double Tm[FCH][NV];
+            T Tm[FCH][NV];
             __syncthreads();
 #pragma unroll
             for (int fi = 0; fi < FCH; ++fi)
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    double e, o;
-                    trace_eo<D, P>(K[v], A, f0 + fi, e, o);
+                    T e, o;
+                    trace_eo<D, P, T>(K[v], A, f0 + fi, e, o);
                     lds[(v * FCH + fi) * nslab + lc] = e + o;
                     Tm[fi][v] = e - o;
                 }
             __syncthreads();
             // flux on the - face: left state = the left neighbour's + trace
-            double Fm[FCH][NV];
+            T Fm[FCH][NV];
             if (in_m) {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
-                    double TL[NV];
+                    T TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * nslab + lc - stride];
-                    rusanov<D, A>(TL, Tm[fi], g.gamma, Fm[fi]);
+                    rusanov<D, A, T>(TL, Tm[fi], gamma, Fm[fi]);
                 }
             } else if (ia > 0) { // slab edge inside the leaf: the layer below
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
-                    double TL[NV];
+                    T TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        double e, o;
-                        trace_eo_mem<D, P>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
+                        T e, o;
+                        trace_eo_mem<D, P, T>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
-                    rusanov<D, A>(TL, Tm[fi], g.gamma, Fm[fi]);
+                    rusanov<D, A, T>(TL, Tm[fi], gamma, Fm[fi]);
                 }
             } else if (!mort_m) {
-                double TL[FCH][NV];
-                far_traces<D, P, A, GM, FCH>(g, K, leaf, -1, t, Lm, f0, TL);
+                T TL[FCH][NV];
+                far_traces<D, P, A, GM, FCH, T>(g, K, leaf, -1, t, Lm, f0, TL);
 #pragma unroll
-                for (int fi = 0; fi < FCH; ++fi) rusanov<D, A>(TL[fi], Tm[fi], g.gamma, Fm[fi]);
+                for (int fi = 0; fi < FCH; ++fi) rusanov<D, A, T>(TL[fi], Tm[fi], gamma, Fm[fi]);
             } else {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Fm[fi][v] = 0.0;
+                    for (int v = 0; v < NV; ++v) Fm[fi][v] = T(0);
             }
             __syncthreads();
 #pragma unroll
@@ -512,7 +526,7 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
 #pragma unroll
                 for (int v = 0; v < NV; ++v) lds[(v * FCH + fi) * nslab + lc] = Fm[fi][v];
             __syncthreads();
-            double Fp[FCH][NV];
+            T Fp[FCH][NV];
             if (in_p) {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi)
@@ -521,36 +535,36 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
             } else if (ia < N - 1) { // slab edge inside the leaf: the layer above
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
-                    double TL[NV], TR[NV];
+                    T TL[NV], TR[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        double e, o;
-                        trace_eo<D, P>(K[v], A, f0 + fi, e, o);
+                        T e, o;
+                        trace_eo<D, P, T>(K[v], A, f0 + fi, e, o);
                         TL[v] = e + o;
-                        trace_eo_mem<D, P>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
+                        trace_eo_mem<D, P, T>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
                         TR[v] = e - o;
                     }
-                    rusanov<D, A>(TL, TR, g.gamma, Fp[fi]);
+                    rusanov<D, A, T>(TL, TR, gamma, Fp[fi]);
                 }
             } else if (!mort_p) {
-                double TR[FCH][NV];
-                far_traces<D, P, A, GM, FCH>(g, K, leaf, +1, t, Lp, f0, TR);
+                T TR[FCH][NV];
+                far_traces<D, P, A, GM, FCH, T>(g, K, leaf, +1, t, Lp, f0, TR);
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
-                    double TL[NV];
+                    T TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
-                        double e, o;
-                        trace_eo<D, P>(K[v], A, f0 + fi, e, o);
+                        T e, o;
+                        trace_eo<D, P, T>(K[v], A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
-                    rusanov<D, A>(TL, TR[fi], g.gamma, Fp[fi]);
+                    rusanov<D, A, T>(TL, TR[fi], gamma, Fp[fi]);
                 }
             } else {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi)
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) Fp[fi][v] = 0.0;
+                    for (int v = 0; v < NV; ++v) Fp[fi][v] = T(0);
             }
             // lift: R_m += s_a w phi_m(+1)/M_m ((-1)^{m_A} Phi_- - Phi_+)
 #pragma unroll
@@ -558,12 +572,12 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
                 const int F = f0 + fi;
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
-                    const double dm = sc * Fm[fi][v], dp = sc * Fp[fi][v];
-                    const double even = dm - dp, odd = -(dm + dp);
+                    const T dm = sc * Fm[fi][v], dp = sc * Fp[fi][v];
+                    const T even = dm - dp, odd = -(dm + dp);
 #pragma unroll
                     for (int m = 0; m < NB; ++m) {
                         const double c = kTab<D, P>.lift_f[A][F][m];
-                        if (c != 0.0) R[v][m] = fma(c, (kTab<D, P>.e[m][A] % 2 == 0) ? even : odd, R[v][m]);
+                        if (c != 0.0) R[v][m] = fma(T(c), (kTab<D, P>.e[m][A] % 2 == 0) ? even : odd, R[v][m]);
                     }
                 }
             }
@@ -581,7 +595,7 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = R[v][m];
+            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = double(R[v][m]);
     } else if constexpr (OM == OUT_RES32) {
 #pragma unroll
         for (int v = 0; v < NV; ++v)
@@ -598,40 +612,43 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
         }
         if (g.rate_clear && blockIdx.x == 0 && threadIdx.x == 0) *g.rate_clear = 0ULL;
         const double a = g.rk_a, b = g.rk_b;
+        // FP64 update; the FP32 path re-reads U_s at full precision
+        double Kn[NV][NB];
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
                 const long idx = base + v * sv + m * ncell;
                 const double un = a != 0.0 ? g.un[idx] : 0.0;
-                K[v][m] = a * un + b * (K[v][m] + dt * R[v][m]);
+                const double us = std::is_same<T, double>::value ? double(K[v][m]) : g.us[idx];
+                Kn[v][m] = a * un + b * (us + dt * double(R[v][m]));
             }
-        if constexpr (LIM) limit_cell<D, P>(K, g.gamma);
+        if constexpr (LIM) limit_cell<D, P>(Kn, g.gamma);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = K[v][m];
+            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = Kn[v][m];
         if (g.rate_out) {
             // CFL rate of the new state from its cell mean, folded over the block
             double U[NV];
 #pragma unroll
-            for (int v = 0; v < NV; ++v) U[v] = K[v][0];
+            for (int v = 0; v < NV; ++v) U[v] = Kn[v][0];
             const double rinv = 1.0 / U[0];
-            const double cs = sqrt(g.gamma * pressure_r<D>(U, gm1, rinv) * rinv);
+            const double cs = sqrt(g.gamma * pressure_r<D>(U, g.gamma - 1.0, rinv) * rinv);
             double rate = 0.0;
 #pragma unroll
             for (int a2 = 0; a2 < D; ++a2) rate += (fabs(U[1 + a2] * rinv) + cs) / g.geo[leaf].h[a2];
             __syncthreads();
-            lds[lc] = rate;
+            lds_d[lc] = rate;
             __syncthreads();
             for (int s = 1; s < nslab; s <<= 1) {
                 if ((lc % (2 * s)) == 0 && lc + s < nslab) {
-                    const double o = lds[lc + s];
-                    lds[lc] = o > lds[lc] || o != o ? o : lds[lc];
+                    const double o = lds_d[lc + s];
+                    lds_d[lc] = o > lds_d[lc] || o != o ? o : lds_d[lc];
                 }
                 __syncthreads();
             }
-            if (lc == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds[0]));
+            if (lc == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds_d[0]));
         }
     }
 }
@@ -639,27 +656,11 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
 // ------------------------------------------------------------------ guard fill
 // One thread per guard cell (leaf, face, t): Eq. 15 copy, Eq. 16 split of the
 // coarser neighbour cell, Eq. 17 combine of the 2^d finer cells, outflow
-// mirror K_m (-1)^{m_axis}.
-template <int D, int P, int CH>
-__device__ __forceinline__ void apply_split(const double *ks, double *out, int nfc, int v)
-{
-    constexpr int NB = Tab<D, P>::NB;
-#pragma unroll
-    for (int m = 0; m < NB; ++m) {
-        double s = 0.0;
-#pragma unroll
-        for (int n = 0; n < NB; ++n) {
-            const double c = kTab<D, P>.split[CH][m][n];
-            if (c != 0.0) s = fma(c, ks[n], s);
-        }
-        out[(v * NB + m) * nfc] = s;
-    }
-}
-
+// mirror K_m (-1)^{m_axis}; written as coefficients or as face traces.
 template <int D, int P>
 __global__ __launch_bounds__(256) void k_fill(FillArgs g)
 {
-    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB, NF = Tab<D, P>::NF;
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
     const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= long(g.nfaces) * nfc) return;
@@ -668,26 +669,53 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
     const int leaf = lf / (2 * D), face = lf % (2 * D);
     const int a = face / 2, side = (face & 1) ? 1 : -1;
     const FaceLink L = g.links[lf];
-    double *out = g.guard + (long(lf) * NV * NB) * nfc + t;
     const long sv = long(NB) * ncell;
     const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2;
+    // one variable of the guard cell -> coefficients, or its values at the
+    // face points (the guard cell touches the face with its -side side)
+    auto emit = [&](int v, const double *gk) __attribute__((always_inline)) {
+        if (g.traces) {
+            double *out = g.guard + (long(lf) * NV * NF) * nfc + t;
+            for (int f = 0; f < NF; ++f) {
+                double s = 0.0;
+#pragma unroll
+                for (int m = 0; m < NB; ++m) {
+                    const int ex = kTab<D, P>.e[m][0] * (a == 0) + kTab<D, P>.e[m][1] * (a == 1) +
+                                   kTab<D, P>.e[m][2] * (a == 2);
+                    const double c = kTab<D, P>.phi_f[a][f][m];
+                    s = fma((side > 0 && (ex % 2)) ? -c : c, gk[m], s);
+                }
+                out[(v * NF + f) * nfc] = s;
+            }
+        } else {
+            double *out = g.guard + (long(lf) * NV * NB) * nfc + t;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) out[(v * NB + m) * nfc] = gk[m];
+        }
+    };
     if (L.type == dgamr::LINK_SAME) {
         const int c = face_cell(a, side > 0 ? 0 : N - 1, t, N, D);
         const double *src = g.u + long(L.nbr[0]) * NV * sv + c;
-        for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v) {
+            double gk[NB];
 #pragma unroll
-            for (int m = 0; m < NB; ++m) out[(v * NB + m) * nfc] = src[v * sv + m * ncell];
+            for (int m = 0; m < NB; ++m) gk[m] = src[v * sv + m * ncell];
+            emit(v, gk);
+        }
     } else if (L.type == dgamr::LINK_BOUNDARY) {
         const int c = face_cell(a, side > 0 ? N - 1 : 0, t, N, D);
         const double *src = g.u + long(leaf) * NV * sv + c;
-        for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v) {
+            double gk[NB];
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
                 const double k = src[v * sv + m * ncell];
                 const int ex = kTab<D, P>.e[m][0] * (a == 0) + kTab<D, P>.e[m][1] * (a == 1) +
                                kTab<D, P>.e[m][2] * (a == 2);
-                out[(v * NB + m) * nfc] = (ex % 2) ? -k : k;
+                gk[m] = (ex % 2) ? -k : k;
             }
+            emit(v, gk);
+        }
     } else if (L.type == dgamr::LINK_COARSE) {
         // the guard cell (fine size) lies in one coarse cell; along a it is
         // the half nearest to this leaf
@@ -698,19 +726,11 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
         const int child = ((side > 0 ? 0 : 1) << a) | (b0 << ta) | (D == 3 ? (b1 << tb) : 0);
         const double *src = g.u + long(L.nbr[0]) * NV * sv + c;
         for (int v = 0; v < NV; ++v) {
-            double ks[NB];
+            double ks[NB], gk[NB];
 #pragma unroll
             for (int n = 0; n < NB; ++n) ks[n] = src[v * sv + n * ncell];
-            switch (child) {
-            case 0: apply_split<D, P, 0>(ks, out, nfc, v); break;
-            case 1: apply_split<D, P, 1>(ks, out, nfc, v); break;
-            case 2: apply_split<D, P, 2>(ks, out, nfc, v); break;
-            case 3: apply_split<D, P, 3>(ks, out, nfc, v); break;
-            case 4: if constexpr (D == 3) apply_split<D, P, 4>(ks, out, nfc, v); break;
-            case 5: if constexpr (D == 3) apply_split<D, P, 5>(ks, out, nfc, v); break;
-            case 6: if constexpr (D == 3) apply_split<D, P, 6>(ks, out, nfc, v); break;
-            default: if constexpr (D == 3) apply_split<D, P, 7>(ks, out, nfc, v); break;
-            }
+            split_any<D, P, double>(child, ks, gk);
+            emit(v, gk);
         }
     } else { // LINK_FINE: 2^d fine cells, 2 along a and 2^(d-1) tangential
         const int t0 = t % N, t1 = t / N;
@@ -739,8 +759,7 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
                         if (cc != 0.0) acc[m] = fma(cc, ks[n], acc[m]);
                     }
             }
-#pragma unroll
-            for (int m = 0; m < NB; ++m) out[(v * NB + m) * nfc] = acc[m];
+            emit(v, acc);
         }
     }
 }

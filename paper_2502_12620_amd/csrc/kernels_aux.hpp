@@ -2,7 +2,7 @@
 // initial-condition projection and L2 inheritance on refinement.
 #pragma once
 
-#include "kernels.hpp"  // apply_split
+#include "kernels.hpp"  // split_any
 
 namespace dgk {
 
@@ -182,22 +182,13 @@ __global__ __launch_bounds__(256) void k_inherit(const double *uold, double *une
         }
         const int pc = pijk[0] + N * (pijk[1] + N * pijk[2]);
         const double *src = uold + long(I.src[0]) * NV * sv + pc;
-        // apply_split writes out[(v*NB + m)*stride]: with stride = ncell it
-        // addresses U[leaf][v][m][cell] relative to this cell
         for (int v = 0; v < NV; ++v) {
-            double ks[NB];
+            double ks[NB], gk[NB];
 #pragma unroll
             for (int n = 0; n < NB; ++n) ks[n] = src[v * sv + n * ncell];
-            switch (child) {
-            case 0: apply_split<D, P, 0>(ks, out, ncell, v); break;
-            case 1: apply_split<D, P, 1>(ks, out, ncell, v); break;
-            case 2: apply_split<D, P, 2>(ks, out, ncell, v); break;
-            case 3: apply_split<D, P, 3>(ks, out, ncell, v); break;
-            case 4: if constexpr (D == 3) apply_split<D, P, 4>(ks, out, ncell, v); break;
-            case 5: if constexpr (D == 3) apply_split<D, P, 5>(ks, out, ncell, v); break;
-            case 6: if constexpr (D == 3) apply_split<D, P, 6>(ks, out, ncell, v); break;
-            default: if constexpr (D == 3) apply_split<D, P, 7>(ks, out, ncell, v); break;
-            }
+            split_any<D, P, double>(child, ks, gk);
+#pragma unroll
+            for (int m = 0; m < NB; ++m) out[v * sv + m * ncell] = gk[m];
         }
     } else {
         int cl = 0, fbase[3] = {0, 0, 0};

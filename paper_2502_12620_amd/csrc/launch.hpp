@@ -9,10 +9,12 @@
 
 namespace dgk {
 
-// residual / fused stage.  variant (2-D, fused stage without limiter):
+// residual / fused stage.  variant (2-D FP64, fused stage without limiter):
 // 0 = one lane per (cell, variable) in row slabs, 1 = one thread per cell.
+// fp32: residual arithmetic in FP32 (out_mode OUT_RES32 or OUT_RK).
 template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, int variant, hipStream_t s);
+hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, int variant, bool fp32,
+                        hipStream_t s);
 // guard fill: one thread per guard cell of the listed faces
 template <int D, int P>
 hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s);

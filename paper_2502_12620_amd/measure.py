@@ -62,7 +62,8 @@ def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1):
     bad = f.check_state(u, work)
     del f, u, work
     torch.cuda.empty_cache()
-    return {"workload": w.name, "variant": variant, "dim": w.dim, "degree": w.degree, "leaves": n, "dofs": dof,
+    return {"workload": w.name, "precision": "fp32" if precision == G.FP32_MFMA else "fp64", "variant": variant,
+            "dim": w.dim, "degree": w.degree, "leaves": n, "dofs": dof,
             "state_MB": dof * 8 / 1e6, "steps": steps, "dof_stage_per_s": dof * 3 * steps / el,
             "stage_kernel_us": avg * 1e6, "algorithmic_bytes_per_dof": bpd, "achieved_GBs": gbs,
             "hbm_frac": gbs / HBM_PEAK_GBS, "est_TFLOPs": flops, "fp64_frac": flops / FP64_PEAK_TFLOPS,
@@ -76,9 +77,10 @@ def cmd_sweep(args):
     for w in cases:
         if args.only and w.name not in args.only.split(","):
             continue
-        variants = [0, 1] if (w.dim == 2 and args.variants) else [-1]
+        prec = G.FP32_MFMA if args.precision == "fp32" else G.FP64
+        variants = [0, 1] if (w.dim == 2 and args.variants and prec == G.FP64) else [-1]
         for var in variants:
-            print(json.dumps(run_workload(w, args.steps, variant=var)), flush=True)
+            print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var)), flush=True)
 
 
 def cmd_copy(args):
@@ -106,6 +108,7 @@ def main(argv=None):
     s.add_argument("--steps", type=int, default=10)
     s.add_argument("--only", default="", help="comma-separated workload names")
     s.add_argument("--variants", action="store_true", help="2-D: time both stage kernels")
+    s.add_argument("--precision", choices=["fp64", "fp32"], default="fp64", help="residual arithmetic")
     c = sub.add_parser("copy")
     c.add_argument("--mb", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
