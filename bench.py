@@ -3,9 +3,9 @@
 One step = one full SSP-RK3 time step of the 2-D Euler two-level AMR vortex
 workload (8x8 roots of 16x16 cells, the 12 roots near the vortex refined
 once -> 100 leaves, degree 2, FP64): the CFL time step and, per stage, the
-guard traces, the residual and the stage update.  The timed steps run
-through dgamr_run: three fused stage kernels per step, the CFL reduction
-folded into the previous step's last stage.
+guard traces, the residual and the stage update.  The timed steps are one
+launch of a HIP graph holding them: three fused stage kernels per step, the
+CFL reduction folded into the previous step's last stage.
 
 Prints one JSON line: DOF-stage updates/s over exactly --steps timed steps
 (inputs resident in HBM), the roofline of the dominant kernel (the fused
@@ -112,8 +112,10 @@ def accuracy(u_gpu, tot_gpu, u_ref, tot_ref, tot0):
 
 
 def time_path(G, w, precision, hang, steps, warmup):
-    """warmup + steps SSP-RK3 steps through dgamr_run from the vortex initial
-    state; the last `steps` timed, stage kernels timed with HIP events."""
+    """warmup + steps SSP-RK3 steps from the vortex initial state: the
+    warm-up through dgamr_run, the timed `steps` as one launch of a HIP
+    graph captured beforehand (dgamr_run_capture), with every stage kernel
+    bracketed by graph-owned HIP events."""
     import torch
 
     f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, hanging=hang,
@@ -125,15 +127,13 @@ def time_path(G, w, precision, hang, steps, warmup):
     work = f.new_work()
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
     f.run(u, work, dt, warmup, w.cfl)
-    torch.cuda.synchronize()
-    f.profile_enable(True)
+    graph = f.capture_run(u, work, dt, steps, w.cfl, profile=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    f.run(u, work, dt, steps, w.cfl)
+    graph.launch()
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
-    f.profile_enable(False)
-    stage_ms, launches = f.profile_read()
+    stage_ms, launches = graph.profile()
     bad = f.check_state(u, work)
     if bad:
         print(f"non-physical state after the timed steps ({bad} cells)", file=sys.stderr)

@@ -53,7 +53,8 @@ enum {
     DGAMR_EBALANCE = -3,     /* topology violates 2:1 face balance */
     DGAMR_EHIP = -4,         /* a HIP runtime call failed */
     DGAMR_ENONPHYSICAL = -5, /* non-finite or non-positive density/pressure found */
-    DGAMR_ESTATE = -6        /* call out of order (e.g. apply before set) */
+    DGAMR_ESTATE = -6,       /* call out of order (e.g. apply before set) */
+    DGAMR_EFULL = -7         /* a pool has no free slot range or member id */
 };
 
 enum { DGAMR_BC_PERIODIC = 0, DGAMR_BC_OUTFLOW = 1 };
@@ -79,6 +80,8 @@ typedef struct {
 } dgamr_forest_desc;
 
 typedef struct dgamr_forest dgamr_forest;
+/* A captured HIP graph of solver steps (dgamr_run_capture, dgamr_pools_capture). */
+typedef struct dgamr_graph dgamr_graph;
 
 /* Sec. 3.1: a forest of root blocks at level 1 with periodic or outflow
  * links (Sec. 5.1, 5.3.1).  Builds the host topology, the device neighbour
@@ -150,6 +153,17 @@ int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_de
 int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev,
               hipStream_t stream);
 
+/* The same nsteps steps as dgamr_run (cfl > 0), captured once into a HIP
+ * graph and replayed with dgamr_graph_launch: each launch advances u by
+ * nsteps steps from its current contents, with the CFL time step of the
+ * first step computed inside the graph and every later one folded into the
+ * previous step's last stage; results equal dgamr_run's.  The graph holds
+ * the pointers u, work and dt_dev.  With profile != 0 every stage launch is
+ * bracketed by graph-owned events (dgamr_graph_profile reads them after a
+ * launch).  Launching after a refinement of f fails with DGAMR_ESTATE. */
+int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev,
+                      int profile, dgamr_graph **out);
+
 /* Conserved totals T_v = sum over cells |cell| * mean_v (FP64), written to
  * totals_dev[n_var]; a fixed-order reduction. */
 int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev, void *work,
@@ -190,6 +204,73 @@ int dgamr_set_tuning(dgamr_forest *f, int knob, long value);
  * number of launches, and clears the record. */
 int dgamr_profile_enable(dgamr_forest *f, int enable);
 int dgamr_profile_read(dgamr_forest *f, double *stage_ms, int64_t *stage_launches);
+
+/* ---------------------------------------------------------------------
+ * Pools: many forests stepped together (batched and served solves).
+ *
+ * Not a construct of the paper: it applies the same per-stage residual and
+ * SSP-RK3 update (Sec. 2-3) to many independent forests in each launch.  A
+ * pool is a device-resident arena of leaf slots for forests of one class:
+ * dim, degree, n_cell, gamma, precision, hanging and limiter of the class
+ * descriptor (its roots, lo, hi, bc and max_level are ignored).  Admitting
+ * a forest copies its topology into a contiguous range of free slots; the
+ * member's state lives in the caller's state arena at that range, in the
+ * layout of the forest's own state buffer (dgamr_state_bytes), and the
+ * caller writes it (e.g. dgamr_project_ic of the forest into the arena at
+ * slot_first).  A pool step advances every member by one SSP-RK3 step with
+ * its own CFL time step; a member's arithmetic does not depend on the other
+ * members, so its result is the same alone and in any mix.
+ *
+ * Ownership: the pool owns its topology tables (device and pinned host);
+ * the caller owns the state arena and the work buffer (sizes from
+ * dgamr_pool_bytes for the capacity).  Admit and release enqueue table
+ * uploads on the given stream; steps on the same stream see them in order.
+ * A released member's slots keep their contents until the next admission.
+ * Pools are not thread-safe.
+ * --------------------------------------------------------------------- */
+typedef struct dgamr_pool dgamr_pool;
+
+int dgamr_pool_create(const dgamr_forest_desc *cls, int64_t capacity_leaves, int32_t max_members,
+                      dgamr_pool **out);
+int dgamr_pool_destroy(dgamr_pool *p);
+/* bytes of the state arena (capacity leaves) and of the work buffer */
+int dgamr_pool_bytes(const dgamr_pool *p, size_t *state_bytes, size_t *work_bytes);
+/* Admit forest f (same class) with CFL number cfl: on success *member is its
+ * id (0 <= id < max_members) and *slot_first the first of its n_leaves
+ * consecutive slots.  DGAMR_EFULL when no free range or id is left. */
+int dgamr_pool_admit(dgamr_pool *p, const dgamr_forest *f, double cfl, int32_t *member, int64_t *slot_first,
+                     hipStream_t stream);
+int dgamr_pool_release(dgamr_pool *p, int32_t member, hipStream_t stream);
+/* One SSP-RK3 step of every member: per-member dt from the CFL condition,
+ * then three fused stage launches over the listed leaves of all members. */
+int dgamr_pool_step(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream);
+/* Device address of the per-member dt of the last step (max_members
+ * doubles inside work). */
+int dgamr_pool_dt(const dgamr_pool *p, void *work, double **dt_dev);
+/* Leaves in use and active members (host). */
+int dgamr_pool_stats(const dgamr_pool *p, int64_t *leaves_used, int32_t *members);
+/* Launch shape of the pool's stage kernel: rows = layers of the block's last
+ * axis per workgroup (0 = largest allowed), grid = workgroups of a
+ * persistent launch (0 = one per work item). */
+int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid);
+/* Autotuner: times the stage kernel on the pool's current members for every
+ * allowed (rows, grid) pair and keeps the fastest; writes the choice and its
+ * average launch time in microseconds.  Synchronous; the state arena is
+ * read, the work buffer overwritten. */
+int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream, int32_t *rows,
+                        int32_t *grid, double *best_us);
+
+/* HIP graph of nsteps steps of several pools (in the given order per step),
+ * captured once and replayed with dgamr_graph_launch.  A graph holds the
+ * pools' work-list lengths at capture: launching it after an admit or
+ * release on any of its pools fails with DGAMR_ESTATE. */
+int dgamr_pools_capture(dgamr_pool *const *pools, double *const *u_arenas, void *const *works, int32_t npools,
+                        int32_t nsteps, dgamr_graph **out);
+int dgamr_graph_launch(dgamr_graph *g, hipStream_t stream);
+/* Summed stage-kernel milliseconds and launch count of the last launch of
+ * a graph captured with profiling (waits for it). */
+int dgamr_graph_profile(dgamr_graph *g, double *stage_ms, int64_t *stage_launches);
+int dgamr_graph_destroy(dgamr_graph *g);
 
 const char *dgamr_last_error(void);
 

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgamr.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["dgamr_api.hip"]
+HIP_SOURCES = ["dgamr_api.hip", "pool_api.hip"]
 CXX_SOURCES = ["forest.cpp"]
 # degree-templated kernels: one translation unit per (dim, degree)
 INSTANCES = [(d, p) for d in (2, 3) for p in (0, 1, 2, 3)]

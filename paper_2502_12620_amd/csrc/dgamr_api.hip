@@ -8,7 +8,7 @@
 #include <string>
 #include <vector>
 
-#include "forest.hpp"
+#include "api_internal.hpp"
 #include "kernels_small.hpp"
 #include "launch.hpp"
 
@@ -16,37 +16,7 @@ using dgamr::FaceLink;
 using dgamr::Forest;
 using dgamr::Inherit;
 using dgamr::LeafGeo;
-
-namespace {
-thread_local std::string g_err;
-
-int fail(int code, const std::string &msg)
-{
-    g_err = msg;
-    return code;
-}
-
-#define HIP_TRY(expr)                                                                          \
-    do {                                                                                       \
-        hipError_t e_ = (expr);                                                                \
-        if (e_ != hipSuccess) return fail(DGAMR_EHIP, std::string(#expr ": ") + hipGetErrorString(e_)); \
-    } while (0)
-
-} // namespace
-
-struct dgamr_forest {
-    Forest topo;
-    int device = 0;
-    LeafGeo *d_geo = nullptr;
-    FaceLink *d_links = nullptr;
-    int cap = 0;             // leaves the device tables can hold
-    bool prof = false;       // bracket stage launches with events
-    int stage_variant = -1;  // 2-D stage kernel: -1 auto, 0 lane per (cell, var), 1 thread per cell
-    long var_split_max_cells = 131072; // auto: lane per (cell, var) up to this many cells
-    std::vector<hipEvent_t> ev_free;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
-    explicit dgamr_forest(const dgamr_forest_desc &d) : topo(d) {}
-};
+using namespace dgapi;
 
 namespace {
 
@@ -109,23 +79,6 @@ int upload(dgamr_forest *f)
     return DGAMR_OK;
 }
 
-// ---------------------------------------------------------------- dispatch
-template <class Fn>
-int dispatch(int d, int p, Fn &&fn)
-{
-    switch (d * 10 + p) {
-    case 20: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 0>{});
-    case 21: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 1>{});
-    case 22: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 2>{});
-    case 23: return fn(std::integral_constant<int, 2>{}, std::integral_constant<int, 3>{});
-    case 30: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 0>{});
-    case 31: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 1>{});
-    case 32: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 2>{});
-    case 33: return fn(std::integral_constant<int, 3>{}, std::integral_constant<int, 3>{});
-    default: return fail(DGAMR_EUNSUPPORTED, "unsupported (dim, degree)");
-    }
-}
-
 // guard cells of every block face, as coefficients or (traces) as their
 // values at the face points
 int launch_fill(dgamr_forest *f, const double *u, double *guard, bool traces, hipStream_t s)
@@ -155,8 +108,10 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     a.conservative = f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE;
     if (a.nleaves == 0) return DGAMR_OK;
     const bool fp32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
+    dgk::StageShape sh;
+    sh.variant = stage_variant(f);
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, stage_variant(f), fp32, s)));
+        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, fp32, sh, s)));
         return DGAMR_OK;
     });
 }
@@ -179,10 +134,10 @@ int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, cons
     while (block < ncell && block < 256) block <<= 1; // power of two for the tree reduction
     if (f->topo.dim() == 2)
         hipLaunchKernelGGL(dgk::k_rate<2>, dim3(n), dim3(block), 0, s, u, f->d_geo, f->topo.desc().n_cell, nb_of(f),
-                           f->topo.desc().gamma, w.leafmax);
+                           f->topo.desc().gamma, w.leafmax, nullptr);
     else
         hipLaunchKernelGGL(dgk::k_rate<3>, dim3(n), dim3(block), 0, s, u, f->d_geo, f->topo.desc().n_cell, nb_of(f),
-                           f->topo.desc().gamma, w.leafmax);
+                           f->topo.desc().gamma, w.leafmax, nullptr);
     HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(dgk::k_dt_final, dim3(1), dim3(1024), 0, s, w.leafmax, n, cfl, dt_dev);
     HIP_TRY(hipGetLastError());
@@ -200,32 +155,11 @@ int take_event(dgamr_forest *f, hipEvent_t &e)
     return DGAMR_OK;
 }
 
-int check_ptr(const void *p, const char *name)
-{
-    if (!p) return fail(DGAMR_EINVAL, std::string(name) + " is null");
-    return DGAMR_OK;
-}
-
-#define CHECK(x)                      \
-    do {                              \
-        int rc_ = (x);                \
-        if (rc_ != DGAMR_OK) return rc_; \
-    } while (0)
-
-#define GUARD_API(...)                                                      \
-    try {                                                                   \
-        __VA_ARGS__                                                         \
-    } catch (const std::exception &e) {                                     \
-        return fail(DGAMR_EINVAL, std::string("internal error: ") + e.what()); \
-    } catch (...) {                                                         \
-        return fail(DGAMR_EINVAL, "internal error");                        \
-    }
-
 } // namespace
 
 extern "C" {
 
-const char *dgamr_last_error(void) { return g_err.c_str(); }
+const char *dgamr_last_error(void) { return dgapi::g_err.c_str(); }
 
 int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out)
 {
@@ -337,6 +271,7 @@ int dgamr_apply_refinement(dgamr_forest *f, const double *u_old, double *u_new, 
         });
         HIP_TRY(hipStreamSynchronize(stream));
         HIP_TRY(hipFree(d_inh));
+        f->version += 1;
         if (rc != DGAMR_OK) return rc;
         return upload(f);
     })
@@ -429,15 +364,19 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (f->prof) {
-            CHECK(take_event(f, e0));
-            CHECK(take_event(f, e1));
+            if (f->capture_events) { // events owned by the graph being captured
+                HIP_TRY(hipEventCreate(&e0));
+                HIP_TRY(hipEventCreate(&e1));
+                f->capture_events->emplace_back(e0, e1);
+            } else {
+                CHECK(take_event(f, e0));
+                CHECK(take_event(f, e1));
+                f->ev_rec.emplace_back(e0, e1);
+            }
             HIP_TRY(hipEventRecord(e0, stream));
         }
         CHECK(launch_stage(f, a, guard3 ? dgk::GUARD_TRACE : dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
-        if (f->prof) {
-            HIP_TRY(hipEventRecord(e1, stream));
-            f->ev_rec.emplace_back(e0, e1);
-        }
+        if (f->prof) HIP_TRY(hipEventRecord(e1, stream));
         us = outs[s];
     }
     return DGAMR_OK;
@@ -476,6 +415,62 @@ int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, do
                        last ? nullptr : slot + wr, stream));
     }
     return DGAMR_OK;
+}
+
+int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev, int profile,
+                      dgamr_graph **out)
+{
+    GUARD_API({
+        CHECK(check_ptr(f, "forest"));
+        CHECK(check_ptr(u, "u"));
+        CHECK(check_ptr(work, "work"));
+        CHECK(check_ptr(dt_dev, "dt_dev"));
+        CHECK(check_ptr(out, "out"));
+        *out = nullptr;
+        if (!(cfl > 0.0)) return fail(DGAMR_EINVAL, "cfl must be positive");
+        if (nsteps <= 0) return fail(DGAMR_EINVAL, "nsteps must be positive");
+        Work w = carve(f, work);
+        auto *slot = reinterpret_cast<unsigned long long *>(w.scal + 2);
+        hipStream_t s;
+        HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        auto *g = new dgamr_graph;
+        const bool prof_was = f->prof;
+        f->prof = profile != 0;
+        f->capture_events = &g->events;
+        int rc = DGAMR_OK;
+        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(DGAMR_EHIP, "hipStreamBeginCapture failed");
+        } else {
+            // CFL rate of the input state into slot 0, then every step takes
+            // its dt from the slot its predecessor's last stage filled
+            rc = launch_dt(f, cfl, u, dt_dev, w, s);
+            if (rc == DGAMR_OK) {
+                hipLaunchKernelGGL(dgk::k_rate_slot, dim3(1), dim3(1024), 0, s, w.leafmax, f->topo.n(), slot);
+                if (hipGetLastError() != hipSuccess) rc = fail(DGAMR_EHIP, "k_rate_slot launch failed");
+            }
+            for (int st = 0; st < nsteps && rc == DGAMR_OK; ++st) {
+                const int rd = st & 1, wr = rd ^ 1;
+                const bool last = st == nsteps - 1;
+                rc = run_step(f, cfl, u, w, dt_dev, slot + rd, slot + wr, last ? nullptr : slot + wr, s);
+            }
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(s, &graph);
+            if (rc == DGAMR_OK && e != hipSuccess) rc = fail(DGAMR_EHIP, "hipStreamEndCapture failed");
+            g->graph = graph;
+            if (rc == DGAMR_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
+                rc = fail(DGAMR_EHIP, "hipGraphInstantiate failed");
+        }
+        f->capture_events = nullptr;
+        f->prof = prof_was;
+        (void)hipStreamDestroy(s);
+        if (rc != DGAMR_OK) {
+            delete g;
+            return rc;
+        }
+        g->versions.emplace_back(&f->version, f->version);
+        *out = g;
+        return DGAMR_OK;
+    })
 }
 
 int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev, void *work, hipStream_t stream)

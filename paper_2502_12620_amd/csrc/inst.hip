@@ -34,16 +34,37 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s)
     return hipGetLastError();
 }
 
+template <int D, int P>
+bool rows_ok(int N, int rows)
+{
+    const int layer = D == 2 ? N : N * N;
+    return rows >= 1 && N % rows == 0 && rows * layer <= stage_threads<D, P>();
+}
+
+template <int D, int P>
+int stage_rows_options(int N, int *rows, int max_options)
+{
+    int n = 0;
+    for (int r = N; r >= 1 && n < max_options; --r)
+        if (rows_ok<D, P>(N, r)) rows[n++] = r;
+    return n;
+}
+
 template <int D, int P, typename T>
-hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, hipStream_t s)
+hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const StageShape &sh, hipStream_t s)
 {
     // slab of `rows` layers along the last axis within the thread budget
     const int layer = D == 2 ? a.N : a.N * a.N;
-    int rows = a.N;
-    while (rows % 2 == 0 && rows * layer > stage_threads<D, P>()) rows /= 2;
+    int rows = sh.rows;
+    if (rows == 0) {
+        rows = a.N;
+        while (rows % 2 == 0 && rows * layer > stage_threads<D, P>()) rows /= 2;
+    }
+    if (!rows_ok<D, P>(a.N, rows)) return hipErrorInvalidValue;
     const int nslab = rows * layer;
+    const long items = long(a.nleaves) * (a.N / rows);
     const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * nslab;
-    const dim3 grid(unsigned(a.nleaves * (a.N / rows))), block(nslab);
+    const dim3 grid(unsigned(sh.grid > 0 && sh.grid < items ? sh.grid : items)), block(nslab);
     // the fused 3-D stage reads every block face as traces from the guard
     // buffer (the step runs the fill kernel first); the fused 2-D stage
     // takes the far side inline
@@ -68,15 +89,16 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, hipSt
 }
 
 template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, int variant, bool fp32, hipStream_t s)
+hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32, const StageShape &sh, hipStream_t s)
 {
-    if (fp32) return launch_stage_cell<D, P, float>(a, gm, om, lim, s);
+    if (a.nleaves == 0) return hipSuccess;
+    if (fp32) return launch_stage_cell<D, P, float>(a, gm, om, lim, sh, s);
     if constexpr (D == 2) {
         // one lane per (cell, variable) unless the caller asks for one
-        // thread per cell (variant 1) or needs the limiter
-        if (!lim && (variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s);
+        // thread per cell (variant 1), needs the limiter or a work list
+        if (!lim && !a.work && (sh.variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s);
     }
-    return launch_stage_cell<D, P, double>(a, gm, om, lim, s);
+    return launch_stage_cell<D, P, double>(a, gm, om, lim, sh, s);
 }
 
 template <int D, int P>
@@ -111,7 +133,8 @@ hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, 
     return hipGetLastError();
 }
 
-template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, int, bool, hipStream_t);
+template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, bool, const StageShape &, hipStream_t);
+template int stage_rows_options<DG_D, DG_P>(int, int *, int);
 template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t);
 template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStream_t);
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,

@@ -133,10 +133,12 @@ struct StageArgs {
     float *out32;         // residual (OUT_RES32)
     const LeafGeo *geo;
     const FaceLink *links;
-    const double *dt;     // device dt (OUT_RK)
+    const double *dt;     // device dt (OUT_RK), per member when leaf_member is set
     double rk_a, rk_b;
     double gamma;
-    int nleaves, N;
+    int nleaves, N;       // work items: leaves listed in work (or all leaves)
+    const int *work;      // leaf indices to process (null: 0 .. nleaves-1)
+    const int *leaf_member; // member forest of each leaf (indexes dt), or null
     int conservative;     // mortar on hanging coarse faces
     // CFL time step fused into the stages (OUT_RK only): when rate_in is
     // set, dt = cfl / max rate read from *rate_in (written by the previous
@@ -157,8 +159,8 @@ struct FillArgs {
     const double *u;
     double *guard;
     const FaceLink *links;
-    const int *faces;  // optional list of (leaf*2d + face) to fill; null = all
-    int nfaces;        // number of faces to fill
+    const int *work;   // leaves whose 2d faces are filled (null: all leaves)
+    int nfaces;        // number of faces to fill (2d per listed leaf)
     int N;
     int traces;        // 0: guard coefficients G[leaf][face][var][mode][t];
                        // 1: their traces on the face, G[leaf][face][var][point][t]

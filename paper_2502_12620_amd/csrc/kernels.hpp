@@ -386,8 +386,10 @@ constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
 // T is the arithmetic type of the residual: double, or float for the FP32
 // path (state read as FP64 and rounded; the stage update, limiter and CFL
 // rate stay FP64).
-template <int D, int P, int GM, int OM, bool LIM, typename T = double>
-__global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, int rows)
+// One work item: slab `item` of the leaf list (all leaves, or the listed
+// ones), for the thread's cell.
+template <int D, int P, int GM, int OM, bool LIM, typename T>
+__device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int item, int total)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
     constexpr int FCH = face_chunk<D, P>();
@@ -397,8 +399,9 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N;
     const int layer = D == 2 ? N : N * N; // cells per layer of the last axis
     const int slabs = N / rows;
-    const int wg = xcd_leaf(blockIdx.x, g.nleaves * slabs);
-    const int leaf = wg / slabs, k0 = (wg % slabs) * rows;
+    const int wg = xcd_leaf(item, total);
+    const int li = wg / slabs, k0 = (wg % slabs) * rows;
+    const int leaf = g.work ? g.work[li] : li;
     const int lc = threadIdx.x, nslab = rows * layer;
     const int cell = lc + k0 * layer;
     int ijk[3];
@@ -606,11 +609,11 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
         if (g.rate_in) {
             const double rate = __longlong_as_double((long long)*g.rate_in);
             dt = g.cfl / rate;
-            if (blockIdx.x == 0 && threadIdx.x == 0) *g.dt_out = dt;
+            if (item == 0 && threadIdx.x == 0) *g.dt_out = dt;
         } else {
-            dt = *g.dt;
+            dt = g.dt[g.leaf_member ? g.leaf_member[leaf] : 0];
         }
-        if (g.rate_clear && blockIdx.x == 0 && threadIdx.x == 0) *g.rate_clear = 0ULL;
+        if (g.rate_clear && item == 0 && threadIdx.x == 0) *g.rate_clear = 0ULL;
         const double a = g.rk_a, b = g.rk_b;
         // FP64 update; the FP32 path re-reads U_s at full precision
         double Kn[NV][NB];
@@ -653,6 +656,18 @@ __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, 
     }
 }
 
+// The stage kernel: one workgroup per (leaf, slab) work item, or, with a
+// grid smaller than the item count (a persistent launch), each workgroup
+// walks the items with a stride of the grid size.  With a grid that is a
+// multiple of the XCD count every item a workgroup takes maps to the same
+// XCD's leaf range.
+template <int D, int P, int GM, int OM, bool LIM, typename T = double>
+__global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, int rows)
+{
+    const int total = g.nleaves * (g.N / rows);
+    for (int item = blockIdx.x; item < total; item += gridDim.x) stage_item<D, P, GM, OM, LIM, T>(g, rows, item, total);
+}
+
 // ------------------------------------------------------------------ guard fill
 // One thread per guard cell (leaf, face, t): Eq. 15 copy, Eq. 16 split of the
 // coarser neighbour cell, Eq. 17 combine of the 2^d finer cells, outflow
@@ -665,7 +680,7 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
     const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= long(g.nfaces) * nfc) return;
     const int fi = int(gid / nfc), t = int(gid % nfc);
-    const int lf = g.faces ? g.faces[fi] : fi;
+    const int lf = g.work ? g.work[fi / (2 * D)] * 2 * D + fi % (2 * D) : fi;
     const int leaf = lf / (2 * D), face = lf % (2 * D);
     const int a = face / 2, side = (face & 1) ? 1 : -1;
     const FaceLink L = g.links[lf];

@@ -17,7 +17,7 @@ struct RkArgs {
     int r32;
 };
 
-__global__ __launch_bounds__(256) void k_rk(RkArgs g)
+static __global__ __launch_bounds__(256) void k_rk(RkArgs g)
 {
     const double dt = *g.dt;
     for (long i = long(blockIdx.x) * blockDim.x + threadIdx.x; i < g.n; i += long(gridDim.x) * blockDim.x) {
@@ -29,13 +29,14 @@ __global__ __launch_bounds__(256) void k_rk(RkArgs g)
 
 // ------------------------------------------------------------------ CFL, totals, checks
 // Per leaf: max over cells of sum_a (|u_a| + c)/h_a from the cell means.
+// One workgroup per leaf (or per listed leaf of `work`).
 template <int D>
 __global__ __launch_bounds__(256) void k_rate(const double *u, const LeafGeo *geo, int N, int nb, double gamma,
-                                              double *leaf_max)
+                                              double *leaf_max, const int *work)
 {
     constexpr int NV = D + 2;
     __shared__ double red[256];
-    const int leaf = blockIdx.x, ncell = D == 2 ? N * N : N * N * N;
+    const int leaf = work ? work[blockIdx.x] : int(blockIdx.x), ncell = D == 2 ? N * N : N * N * N;
     const long sv = long(nb) * ncell, base = long(leaf) * NV * sv;
     const LeafGeo G = geo[leaf];
     double mx = 0.0;
@@ -58,7 +59,7 @@ __global__ __launch_bounds__(256) void k_rate(const double *u, const LeafGeo *ge
 }
 
 // dt = cfl / max over leaves (one workgroup; max is order independent)
-__global__ __launch_bounds__(1024) void k_dt_final(const double *leaf_max, int n, double cfl, double *dt)
+static __global__ __launch_bounds__(1024) void k_dt_final(const double *leaf_max, int n, double cfl, double *dt)
 {
     __shared__ double red[1024];
     double mx = 0.0;
@@ -70,6 +71,49 @@ __global__ __launch_bounds__(1024) void k_dt_final(const double *leaf_max, int n
         __syncthreads();
     }
     if (threadIdx.x == 0) *dt = cfl / red[0];
+}
+
+// The max over leaves of the CFL rate, stored as the bit pattern of the
+// (non-negative) double in a rate slot of the fused-time-step scheme.
+static __global__ __launch_bounds__(1024) void k_rate_slot(const double *leaf_max, int n, unsigned long long *slot)
+{
+    __shared__ double red[1024];
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) mx = leaf_max[i] > mx ? leaf_max[i] : mx;
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + s] ? red[threadIdx.x] : red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *slot = (unsigned long long)__double_as_longlong(red[0]);
+}
+
+// Per member forest of a pool: dt_m = cfl_m / max over the member's leaf
+// range [first, first + count) (one workgroup per member; count 0 = empty
+// member slot, left alone).
+struct MemberDesc {
+    int first, count;
+    double cfl;
+};
+
+static __global__ __launch_bounds__(256) void k_dt_members(const double *leaf_max, const MemberDesc *members, double *dt)
+{
+    __shared__ double red[256];
+    const MemberDesc M = members[blockIdx.x];
+    if (M.count == 0) return;
+    double mx = 0.0;
+    for (int i = threadIdx.x; i < M.count; i += blockDim.x) {
+        const double v = leaf_max[M.first + i];
+        mx = v > mx ? v : mx;
+    }
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] = red[threadIdx.x] > red[threadIdx.x + s] ? red[threadIdx.x] : red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) dt[blockIdx.x] = M.cfl / red[0];
 }
 
 // Per leaf partial totals sum_cells vol * mean_v, fixed tree order.

@@ -9,12 +9,26 @@
 
 namespace dgk {
 
-// residual / fused stage.  variant (2-D FP64, fused stage without limiter):
-// 0 = one lane per (cell, variable) in row slabs, 1 = one thread per cell.
-// fp32: residual arithmetic in FP32 (out_mode OUT_RES32 or OUT_RK).
+// Launch shape of the stage kernel.  variant (2-D FP64, fused stage without
+// limiter, no work list): 0 = one lane per (cell, variable) in row slabs,
+// 1 = one thread per cell.  rows: layers of the last axis per workgroup of
+// the thread-per-cell kernel (0 = the largest that fits its thread budget);
+// grid: workgroups of a persistent launch (0 = one per work item).
+struct StageShape {
+    int variant = 1;
+    int rows = 0;
+    int grid = 0;
+};
+
+// residual / fused stage.  fp32: residual arithmetic in FP32 (out_mode
+// OUT_RES32 or OUT_RK).
 template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, int variant, bool fp32,
-                        hipStream_t s);
+hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, bool fp32,
+                        const StageShape &shape, hipStream_t s);
+// rows the thread-per-cell stage kernel accepts for block size N: divisors
+// of N whose slab fits the kernel's thread budget, largest first
+template <int D, int P>
+int stage_rows_options(int N, int *rows, int max_options);
 // guard fill: one thread per guard cell of the listed faces
 template <int D, int P>
 hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s);

@@ -15,7 +15,7 @@ import torch
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgamr.so")
 
-OK, EINVAL, EUNSUPPORTED, EBALANCE, EHIP, ENONPHYSICAL, ESTATE = 0, -1, -2, -3, -4, -5, -6
+OK, EINVAL, EUNSUPPORTED, EBALANCE, EHIP, ENONPHYSICAL, ESTATE, EFULL = 0, -1, -2, -3, -4, -5, -6, -7
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 FP64, FP32_MFMA = 0, 1
 HANG_PAPER, HANG_CONSERVATIVE = 0, 1
@@ -29,6 +29,9 @@ EXPORTS = [
     "dgamr_fill_guardcells", "dgamr_dg_residual", "dgamr_rk_stage", "dgamr_compute_dt",
     "dgamr_step", "dgamr_run", "dgamr_conserved_totals", "dgamr_limit_positivity", "dgamr_indicator",
     "dgamr_project_ic", "dgamr_check_state", "dgamr_set_tuning", "dgamr_profile_enable", "dgamr_profile_read",
+    "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
+    "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_autotune",
+    "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture", "dgamr_graph_profile",
     "dgamr_last_error",
 ]
 
@@ -80,6 +83,23 @@ def lib():
         L.dgamr_set_tuning.argtypes = [vp, ctypes.c_int, ctypes.c_long]
         L.dgamr_profile_enable.argtypes = [vp, ctypes.c_int]
         L.dgamr_profile_read.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
+        i32, i32p = ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)
+        L.dgamr_pool_create.argtypes = [ctypes.POINTER(ForestDesc), ctypes.c_int64, i32, ctypes.POINTER(vp)]
+        L.dgamr_pool_destroy.argtypes = [vp]
+        L.dgamr_pool_bytes.argtypes = [vp, sz, sz]
+        L.dgamr_pool_admit.argtypes = [vp, vp, ctypes.c_double, i32p, i64p, vp]
+        L.dgamr_pool_release.argtypes = [vp, i32, vp]
+        L.dgamr_pool_step.argtypes = [vp, vp, vp, vp]
+        L.dgamr_pool_dt.argtypes = [vp, vp, ctypes.POINTER(vp)]
+        L.dgamr_pool_stats.argtypes = [vp, i64p, i32p]
+        L.dgamr_pool_set_shape.argtypes = [vp, i32, i32]
+        L.dgamr_pool_autotune.argtypes = [vp, vp, vp, vp, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
+        L.dgamr_pools_capture.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32,
+                                          ctypes.POINTER(vp)]
+        L.dgamr_graph_launch.argtypes = [vp, vp]
+        L.dgamr_graph_destroy.argtypes = [vp]
+        L.dgamr_run_capture.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.POINTER(vp)]
+        L.dgamr_graph_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
         L.dgamr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name != "dgamr_last_error":
@@ -214,6 +234,14 @@ class Forest:
         """nsteps SSP-RK3 steps in place, three launches per step."""
         _check(lib().dgamr_run(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
 
+    def capture_run(self, u, work, dt_dev, nsteps, cfl=0.1, profile=False):
+        """nsteps steps of run() captured into a HIP graph (RunGraph); each
+        launch advances u by nsteps steps."""
+        h = ctypes.c_void_p()
+        _check(lib().dgamr_run_capture(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), 1 if profile else 0,
+                                       ctypes.byref(h)))
+        return RunGraph(h, keep=(self, u, work, dt_dev))
+
     def conserved_totals(self, u, work, stream=None):
         t = torch.zeros(self.nv, dtype=torch.float64, device=u.device)
         _check(lib().dgamr_conserved_totals(self.h, _ptr(u), _ptr(t), _ptr(work), _stream(stream)))
@@ -252,3 +280,119 @@ class Forest:
         ms, n = ctypes.c_double(), ctypes.c_int64()
         _check(lib().dgamr_profile_read(self.h, ctypes.byref(ms), ctypes.byref(n)))
         return ms.value, n.value
+
+
+class Pool:
+    """Arena of leaf slots for many forests of one class (``dgamr_pool``),
+    stepped together; the state arena and work buffer are owned here as
+    torch tensors."""
+
+    def __init__(self, dim, degree, n_cell, capacity_leaves, max_members, gamma=1.4, precision=FP64,
+                 hanging=HANG_PAPER, limiter=LIMITER_NONE, device="cuda"):
+        d = ForestDesc()
+        d.dim, d.degree, d.n_cell, d.max_level, d.gamma = dim, degree, n_cell, 1, gamma
+        for a in range(3):
+            d.roots[a], d.lo[a], d.hi[a], d.bc[a] = 1, 0.0, 1.0, BC_PERIODIC
+        d.precision, d.hanging, d.limiter = precision, hanging, limiter
+        self.desc = d
+        self.dim, self.degree, self.N = dim, degree, n_cell
+        self.nv = dim + 2
+        self.nb = {2: [1, 3, 6, 10], 3: [1, 4, 10, 20]}[dim][degree]
+        self.ncell = n_cell ** dim
+        self.capacity, self.max_members = capacity_leaves, max_members
+        h = ctypes.c_void_p()
+        _check(lib().dgamr_pool_create(ctypes.byref(d), capacity_leaves, max_members, ctypes.byref(h)))
+        self.h = h
+        sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(lib().dgamr_pool_bytes(self.h, ctypes.byref(sb), ctypes.byref(wb)))
+        self.state_bytes, self.work_bytes = sb.value, wb.value
+        self.u = torch.zeros((capacity_leaves, self.nv, self.nb, self.ncell), dtype=torch.float64, device=device)
+        self.work = torch.zeros(wb.value // 8, dtype=torch.float64, device=device)
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            try:
+                torch.cuda.synchronize()
+            except Exception:
+                pass
+            _lib.dgamr_pool_destroy(self.h)
+            self.h = None
+
+    def leaf_bytes(self) -> int:
+        return 8 * self.nv * self.nb * self.ncell
+
+    def admit(self, forest: Forest, cfl: float, stream=None):
+        """Admit a forest; returns (member id, first slot).  Raises
+        DgamrError with code EFULL when it does not fit."""
+        m, first = ctypes.c_int32(), ctypes.c_int64()
+        _check(lib().dgamr_pool_admit(self.h, forest.h, cfl, ctypes.byref(m), ctypes.byref(first),
+                                      _stream(stream)))
+        return m.value, first.value
+
+    def release(self, member: int, stream=None):
+        _check(lib().dgamr_pool_release(self.h, member, _stream(stream)))
+
+    def view(self, first: int, n_leaves: int):
+        """The member's state: a view of the arena at its slot range."""
+        return self.u[first:first + n_leaves]
+
+    def step(self, stream=None):
+        _check(lib().dgamr_pool_step(self.h, _ptr(self.u), _ptr(self.work), _stream(stream)))
+
+    def dt(self):
+        """Per-member dt of the last step (device tensor view)."""
+        p = ctypes.c_void_p()
+        _check(lib().dgamr_pool_dt(self.h, _ptr(self.work), ctypes.byref(p)))
+        off = (p.value - self.work.data_ptr()) // 8
+        return self.work[off:off + self.max_members]
+
+    def stats(self):
+        n, m = ctypes.c_int64(), ctypes.c_int32()
+        _check(lib().dgamr_pool_stats(self.h, ctypes.byref(n), ctypes.byref(m)))
+        return n.value, m.value
+
+    def set_shape(self, rows=0, grid=0):
+        _check(lib().dgamr_pool_set_shape(self.h, rows, grid))
+
+    def autotune(self, stream=None):
+        """Returns (rows, grid, best stage-launch microseconds)."""
+        r, g, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().dgamr_pool_autotune(self.h, _ptr(self.u), _ptr(self.work), _stream(stream), ctypes.byref(r),
+                                         ctypes.byref(g), ctypes.byref(us)))
+        return r.value, g.value, us.value
+
+
+class RunGraph:
+    """A captured HIP graph (``dgamr_graph``); keeps what it references
+    alive."""
+
+    def __init__(self, h, keep=()):
+        self.h = h
+        self.keep = keep
+
+    def launch(self, stream=None):
+        _check(lib().dgamr_graph_launch(self.h, _stream(stream)))
+
+    def profile(self):
+        """(summed stage-kernel milliseconds, launches) of the last launch."""
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check(lib().dgamr_graph_profile(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.dgamr_graph_destroy(self.h)
+            self.h = None
+
+
+class Graph(RunGraph):
+    """HIP graph of nsteps steps of several pools (``dgamr_pools_capture``)."""
+
+    def __init__(self, pools, nsteps: int):
+        n = len(pools)
+        hp = (ctypes.c_void_p * n)(*[p.h for p in pools])
+        up = (ctypes.c_void_p * n)(*[p.u.data_ptr() for p in pools])
+        wp = (ctypes.c_void_p * n)(*[p.work.data_ptr() for p in pools])
+        h = ctypes.c_void_p()
+        _check(lib().dgamr_pools_capture(hp, up, wp, n, nsteps, ctypes.byref(h)))
+        super().__init__(h, keep=list(pools))  # keep the pools alive while the graph exists

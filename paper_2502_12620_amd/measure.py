@@ -6,7 +6,15 @@
     python -m paper_2502_12620_amd.measure sweep [--steps 10]
         the roofline sweep: uniform 2-D and 3-D vortex forests large enough
         to live in HBM (above the 256 MB last-level cache), FP64 stage kernel
-        timed with HIP events around each launch.
+        timed with HIP events around each launch;
+    python -m paper_2502_12620_amd.measure batch [--forests 512]
+        the batched workload: independent 2-D forests in one pool per degree,
+        autotuned, one HIP graph per batch of steps; batch wall time p50/p99
+        and DOF-stage/s against the same forests solved one after another;
+    python -m paper_2502_12620_amd.measure serve [--requests 100]
+        the served workload: a Poisson stream of 2-D/3-D solves through the
+        continuous-batching request loop; latency p50/p99 and DOF-stage/s
+        against plain sequential solves of the same requests.
 
 Each prints JSON lines.
 """
@@ -101,6 +109,126 @@ def cmd_copy(args):
                       "GBs_read_plus_write": 2 * n * 8 / ms / 1e6}), flush=True)
 
 
+def _pct(xs, q):
+    xs = sorted(xs)
+    if not xs:
+        return float("nan")
+    k = (len(xs) - 1) * q / 100.0
+    lo, hi = int(math.floor(k)), int(math.ceil(k))
+    return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
+
+
+def _forest(w, precision=G.FP64):
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, precision=precision)
+    z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
+    for rule in w.initial_refinement:
+        z = f.adapt(rule(w, f.keys()), z)
+    return f
+
+
+def cmd_batch(args):
+    ws = W.batched_forests(args.forests, seed=2502)
+    steps = ws[0].steps
+    prec = G.FP32_MFMA if args.precision == "fp32" else G.FP64
+    groups = {}
+    for w in ws:
+        groups.setdefault(w.degree, []).append((w, _forest(w, prec)))
+    pools, members = [], []
+    t_setup = time.perf_counter()
+    for p in sorted(groups):
+        lst = groups[p]
+        pool = G.Pool(2, p, 16, sum(f.n_leaves for _, f in lst), len(lst), precision=prec)
+        for w, f in lst:
+            mid, first = pool.admit(f, w.cfl)
+            f.project_ic(G.IC_VORTEX, w.ic_params, u=pool.view(first, f.n_leaves))
+            members.append((w, f, pool, first))
+        pools.append(pool)
+    torch.cuda.synchronize()
+    tune = [pool.autotune() for pool in pools]
+    # the autotuner left the arenas untouched; restart from the initial state
+    graph = G.Graph(pools, nsteps=steps)
+    setup_s = time.perf_counter() - t_setup
+    dofs = sum(w.dofs(f.n_leaves) for w, f in ((w, f) for w, f, _, _ in members))
+    leaves = sum(f.n_leaves for _, f, _, _ in members)
+    # one replay from the initial state: results against the plain path
+    graph.launch()
+    torch.cuda.synchronize()
+    # plain FP64 path: every forest alone, one after another (dgamr_run)
+    seq_times, max_rel = [], 0.0
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for w, f, pool, first in members:
+        u = f.project_ic(G.IC_VORTEX, w.ic_params)
+        work, dt = f.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+        f.run(u, work, dt, 1, w.cfl)  # warm-up of this forest's path
+        u = f.project_ic(G.IC_VORTEX, w.ic_params)
+        torch.cuda.synchronize()
+        e0.record()
+        f.run(u, work, dt, steps, w.cfl)
+        e1.record()
+        torch.cuda.synchronize()
+        seq_times.append(e0.elapsed_time(e1) / 1e3)
+        got = pool.view(first, f.n_leaves)
+        max_rel = max(max_rel, float((got - u).abs().max() / u.abs().max()))
+    seq_total = sum(seq_times)
+    # timed replays (the state keeps advancing: each replay is `steps` more steps)
+    times = []
+    for _ in range(args.repeats):
+        e0.record()
+        graph.launch()
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1) / 1e3)
+    med = _pct(times, 50)
+    out = {"workload": f"batched_{args.forests}_forests_2d", "forests": len(ws), "leaves": leaves, "dofs": dofs,
+           "precision": args.precision, "steps_per_batch": steps, "repeats": args.repeats,
+           "batch_wall_s_p50": med, "batch_wall_s_p99": _pct(times, 99), "batch_wall_s_min": min(times),
+           "dof_stage_per_s": dofs * 3 * steps / med,
+           "sequential_plain_s": seq_total, "sequential_dof_stage_per_s": dofs * 3 * steps / seq_total,
+           "speedup_vs_sequential": seq_total / med,
+           "max_rel_diff_vs_plain_path": max_rel,
+           "autotune": {f"p{p}": {"rows": r, "grid": g, "stage_us": us} for p, (r, g, us) in zip(sorted(groups), tune)},
+           "setup_s": setup_s}
+    print(json.dumps(out), flush=True)
+
+
+def cmd_serve(args):
+    from .serve import Request, Server
+
+    reqs = [Request(i, t, w) for i, (t, w) in enumerate(W.served_requests(args.requests, seed=12620, rate=args.rate))]
+    classes = sorted({(r.workload.dim, r.workload.degree, r.workload.n_cell) for r in reqs})
+    srv = Server(classes, hbm_budget=args.budget_gb * 1e9, max_members=256, tune=args.tune)
+    done = srv.run(reqs)
+    lat = [r.done - r.arrival for r in done]
+    work = sum(r.dofs * 3 * r.workload.steps for r in done)
+    out = {"workload": f"served_{args.requests}_requests", "requests": len(done), "rate_per_s": args.rate,
+           "hbm_budget_GB": args.budget_gb, "makespan_s": srv.makespan, "ticks": srv.ticks,
+           "latency_s_p50": _pct(lat, 50), "latency_s_p99": _pct(lat, 99),
+           "dof_stage_per_s": work / srv.makespan}
+    # plain sequential FP64: each request solved alone in arrival order; its
+    # queue is replayed from the measured service times
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    service = {}
+    for r in sorted(done, key=lambda r: r.arrival):
+        w = r.workload
+        f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
+        u = f.project_ic(w.ic_kind, w.ic_params)
+        work_buf, dt = f.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        f.run(u, work_buf, dt, w.steps, w.cfl)
+        torch.cuda.synchronize()
+        service[r.rid] = time.perf_counter() - t0
+        del f, u, work_buf
+    clock, seq_lat = 0.0, []
+    for r in sorted(done, key=lambda r: r.arrival):
+        start = max(clock, r.arrival)
+        clock = start + service[r.rid]
+        seq_lat.append(clock - r.arrival)
+    out.update({"sequential_makespan_s": clock, "sequential_latency_s_p50": _pct(seq_lat, 50),
+                "sequential_latency_s_p99": _pct(seq_lat, 99), "sequential_dof_stage_per_s": work / clock})
+    print(json.dumps(out), flush=True)
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="cmd", required=True)
@@ -112,9 +240,18 @@ def main(argv=None):
     c = sub.add_parser("copy")
     c.add_argument("--mb", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
+    b = sub.add_parser("batch")
+    b.add_argument("--forests", type=int, default=512)
+    b.add_argument("--repeats", type=int, default=20)
+    b.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    v = sub.add_parser("serve")
+    v.add_argument("--requests", type=int, default=100)
+    v.add_argument("--rate", type=float, default=200.0)
+    v.add_argument("--budget-gb", type=float, default=96.0)
+    v.add_argument("--tune", action="store_true")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    {"sweep": cmd_sweep, "copy": cmd_copy}[args.cmd](args)
+    {"sweep": cmd_sweep, "copy": cmd_copy, "batch": cmd_batch, "serve": cmd_serve}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -1,0 +1,64 @@
+"""The continuous-batching request loop: requests of several classes arrive
+over time, are admitted as pool slots free up (the HBM budget here is too
+small to hold them all at once), and every result equals the same request
+solved alone (bitwise: the pool runs the same kernels as a single forest
+with the thread-per-cell stage kernel)."""
+import numpy as np
+import pytest
+
+from paper_2502_12620_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _requests():
+    rng = np.random.default_rng(7)
+    out = []
+    t = 0.0
+    for i in range(14):
+        t += float(rng.exponential(0.002))
+        dim = 2 if i % 3 else 3
+        p = int(rng.integers(1, 4))
+        steps = int(rng.integers(2, 7))
+        if dim == 2:
+            roots = (int(rng.integers(1, 4)), int(rng.integers(1, 4)))
+            L = (2.5 * roots[0], 2.5 * roots[1])
+            w = W.Workload(f"r{i}", 2, p, 8, roots, (0.0, 0.0), L, (W.PERIODIC,) * 2, 1, W.IC_VORTEX,
+                           [3.0, L[0] / 2, L[1] / 2, 1.0, 1.0, L[0], L[1]], steps, cfl=0.05 + 0.05 * (i % 3))
+        else:
+            roots = (int(rng.integers(1, 3)), 2, 1)
+            L = (1.25 * roots[0], 2.5, 1.25)
+            w = W.Workload(f"r{i}", 3, p, 4, roots, (0.0,) * 3, L, (W.PERIODIC,) * 3, 1, W.IC_VORTEX,
+                           [3.0, L[0] / 2, L[1] / 2, 1.0, 1.0, L[0], L[1]], steps)
+        out.append((t, w))
+    return out
+
+
+def _alone(w):
+    from paper_2502_12620_amd import dgamr as G
+
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
+    f.set_tuning(G.TUNE_STAGE_VARIANT, 1)
+    u = f.project_ic(w.ic_kind, w.ic_params)
+    work, dt = f.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(w.steps):
+        f.step(u, work, dt, w.cfl)
+    torch.cuda.synchronize()
+    return u.cpu().numpy()
+
+
+def test_served_results_equal_solo_solves():
+    from paper_2502_12620_amd.serve import Request, Server
+
+    reqs = [Request(i, t, w) for i, (t, w) in enumerate(_requests())]
+    classes = sorted({(r.workload.dim, r.workload.degree, r.workload.n_cell) for r in reqs})
+    # about 2.5 MB and two members per class: requests queue for slots
+    srv = Server(classes, hbm_budget=2.5e6 * len(classes), max_members=2, keep_results=True)
+    done = srv.run(reqs)
+    assert len(done) == len(reqs)
+    assert srv.full_waits > 0, "no request had to wait for a slot"
+    for r in done:
+        assert r.done >= r.admitted >= r.arrival
+        got = r.result.cpu().numpy()
+        assert np.array_equal(got, _alone(r.workload)), f"request {r.rid} differs from its solo solve"
