@@ -158,11 +158,10 @@ int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, do
  * nsteps steps from its current contents, with the CFL time step of the
  * first step computed inside the graph and every later one folded into the
  * previous step's last stage; results equal dgamr_run's.  The graph holds
- * the pointers u, work and dt_dev.  With profile != 0 every stage launch is
- * bracketed by graph-owned events (dgamr_graph_profile reads them after a
- * launch).  Launching after a refinement of f fails with DGAMR_ESTATE. */
+ * the pointers u, work and dt_dev.  The profiling hook is not recorded into
+ * the graph.  Launching after a refinement of f fails with DGAMR_ESTATE. */
 int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev,
-                      int profile, dgamr_graph **out);
+                      dgamr_graph **out);
 
 /* Conserved totals T_v = sum over cells |cell| * mean_v (FP64), written to
  * totals_dev[n_var]; a fixed-order reduction. */
@@ -267,9 +266,6 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
 int dgamr_pools_capture(dgamr_pool *const *pools, double *const *u_arenas, void *const *works, int32_t npools,
                         int32_t nsteps, dgamr_graph **out);
 int dgamr_graph_launch(dgamr_graph *g, hipStream_t stream);
-/* Summed stage-kernel milliseconds and launch count of the last launch of
- * a graph captured with profiling (waits for it). */
-int dgamr_graph_profile(dgamr_graph *g, double *stage_ms, int64_t *stage_launches);
 int dgamr_graph_destroy(dgamr_graph *g);
 
 const char *dgamr_last_error(void);

@@ -79,9 +79,6 @@ struct dgamr_forest {
     long var_split_max_cells = 131072; // auto: lane per (cell, var) up to this many cells
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
-    // while a run is captured into a graph, stage-launch event pairs go to
-    // the graph instead of ev_rec
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> *capture_events = nullptr;
     long version = 0;        // bumped by every topology change
     explicit dgamr_forest(const dgamr_forest_desc &d) : topo(d) {}
 };
@@ -93,15 +90,10 @@ struct dgamr_graph {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     std::vector<std::pair<const long *, long>> versions;
-    std::vector<std::pair<hipEvent_t, hipEvent_t>> events; // stage-launch brackets, if profiled
     ~dgamr_graph()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
-        for (auto &pr : events) {
-            (void)hipEventDestroy(pr.first);
-            (void)hipEventDestroy(pr.second);
-        }
     }
 };
 

@@ -364,15 +364,9 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         }
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (f->prof) {
-            if (f->capture_events) { // events owned by the graph being captured
-                HIP_TRY(hipEventCreate(&e0));
-                HIP_TRY(hipEventCreate(&e1));
-                f->capture_events->emplace_back(e0, e1);
-            } else {
-                CHECK(take_event(f, e0));
-                CHECK(take_event(f, e1));
-                f->ev_rec.emplace_back(e0, e1);
-            }
+            CHECK(take_event(f, e0));
+            CHECK(take_event(f, e1));
+            f->ev_rec.emplace_back(e0, e1);
             HIP_TRY(hipEventRecord(e0, stream));
         }
         CHECK(launch_stage(f, a, guard3 ? dgk::GUARD_TRACE : dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
@@ -417,7 +411,7 @@ int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, do
     return DGAMR_OK;
 }
 
-int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev, int profile,
+int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev,
                       dgamr_graph **out)
 {
     GUARD_API({
@@ -435,8 +429,7 @@ int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *
         HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
         auto *g = new dgamr_graph;
         const bool prof_was = f->prof;
-        f->prof = profile != 0;
-        f->capture_events = &g->events;
+        f->prof = false; // no event records inside a graph
         int rc = DGAMR_OK;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = fail(DGAMR_EHIP, "hipStreamBeginCapture failed");
@@ -460,7 +453,6 @@ int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *
             if (rc == DGAMR_OK && hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0) != hipSuccess)
                 rc = fail(DGAMR_EHIP, "hipGraphInstantiate failed");
         }
-        f->capture_events = nullptr;
         f->prof = prof_was;
         (void)hipStreamDestroy(s);
         if (rc != DGAMR_OK) {

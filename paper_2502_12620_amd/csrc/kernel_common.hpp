@@ -60,6 +60,45 @@ __device__ __forceinline__ int link_nbr(const FaceLink &L, int k)
     return k == 0 ? L.nbr[0] : (k == 1 ? L.nbr[1] : (k == 2 ? L.nbr[2] : L.nbr[3]));
 }
 
+// 1/x for the state's normal positive densities: the hardware reciprocal
+// estimate refined by Newton-Raphson steps r <- r + r (1 - x r), two in
+// FP64 (quadratic convergence takes the estimate to full precision), one in
+// FP32.  Within an ulp of the correctly rounded quotient, at half the
+// instructions of the IEEE division sequence.
+__device__ __forceinline__ double recip(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    double e = fma(-x, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-x, r, 1.0);
+    return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x)
+{
+    const float r = __builtin_amdgcn_rcpf(x);
+    return fmaf(r, fmaf(-x, r, 1.0f), r);
+}
+
+// sqrt(a) for a >= 0 (wave speeds): Goldschmidt's iteration from the
+// hardware reciprocal-square-root estimate y (s = a y, h = y/2,
+// r = 1/2 - s h, s <- s + s r, h <- h + h r, twice), then one Newton
+// correction s <- s + h (a - s^2); zero for a = 0.  FP32 uses the hardware
+// square root.
+__device__ __forceinline__ double sqrt_nn(double a)
+{
+    const double y = __builtin_amdgcn_rsq(a);
+    double s = a * y, h = 0.5 * y;
+    double r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    r = fma(-s, h, 0.5);
+    s = fma(s, r, s);
+    h = fma(h, r, h);
+    s = fma(fma(-s, s, a), h, s);
+    return a > 0.0 ? s : 0.0;
+}
+__device__ __forceinline__ float sqrt_nn(float a) { return __builtin_amdgcn_sqrtf(a > 0.0f ? a : 0.0f); }
+
 // Euler flux along axis A (Eq. 2 and its 3-D analogue; EOS Eq. 23), in the
 // arithmetic type T of the residual (FP64, or FP32 for the FP32 path).
 template <int D, int A, typename T = double>
@@ -98,13 +137,13 @@ __device__ __forceinline__ void rusanov(const T *UL, const T *UR, T gamma, T *Ph
 {
     constexpr int NV = D + 2;
     const T gm1 = gamma - T(1);
-    const T rl = T(1) / UL[0], rr = T(1) / UR[0];
+    const T rl = recip(UL[0]), rr = recip(UR[0]);
     const T pl = pressure_r<D, T>(UL, gm1, rl), pr = pressure_r<D, T>(UR, gm1, rr);
     const T ul = UL[1 + A] * rl, ur = UR[1 + A] * rr;
     // a pressure rounded below zero (FP32 traces of a near-vacuum state)
     // enters the wave speed as zero; exact arithmetic never takes this branch
     // on a state the positivity limiter has passed
-    const T cl = sqrt(gamma * (pl > T(0) ? pl : T(0)) * rl), cr = sqrt(gamma * (pr > T(0) ? pr : T(0)) * rr);
+    const T cl = sqrt_nn(gamma * pl * rl), cr = sqrt_nn(gamma * pr * rr);
     const T al = fabs(ul) + cl, ar = fabs(ur) + cr;
     const T alpha = al > ar ? al : ar;
     T FL[NV], FR[NV];

@@ -434,7 +434,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
             }
             U[v] = s;
         }
-        const T rinv = T(1) / U[0];
+        const T rinv = recip(U[0]);
         const T p = pressure_r<D, T>(U, gm1, rinv);
         static_for<0, D>([&](auto Ai) __attribute__((always_inline)) {
             constexpr int A = Ai;
@@ -621,11 +621,17 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
-                const long idx = base + v * sv + m * ncell;
-                const double un = a != 0.0 ? g.un[idx] : 0.0;
-                const double us = std::is_same<T, double>::value ? double(K[v][m]) : g.us[idx];
-                Kn[v][m] = a * un + b * (us + dt * double(R[v][m]));
+                const double us = std::is_same<T, double>::value ? double(K[v][m]) : g.us[base + v * sv + m * ncell];
+                Kn[v][m] = b * (us + dt * double(R[v][m]));
             }
+        // stages 2 and 3 add the RK base state; a uniform branch keeps its
+        // loads here, after the residual, instead of live through it
+        if (a != 0.0) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int m = 0; m < NB; ++m) Kn[v][m] = fma(a, g.un[base + v * sv + m * ncell], Kn[v][m]);
+        }
         if constexpr (LIM) limit_cell<D, P>(Kn, g.gamma);
 #pragma unroll
         for (int v = 0; v < NV; ++v)

@@ -54,10 +54,10 @@ __device__ __forceinline__ double rusanov_v(double tl, double tr, double gamma, 
     quad_state(tl, L);
     quad_state(tr, R);
     const double gm1 = gamma - 1.0;
-    const double rl = 1.0 / L[0], rr = 1.0 / R[0];
+    const double rl = recip(L[0]), rr = recip(R[0]);
     const double pl = pressure_r<2>(L, gm1, rl), pr = pressure_r<2>(R, gm1, rr);
     const double ul = L[1 + A] * rl, ur = R[1 + A] * rr;
-    const double al = fabs(ul) + sqrt(gamma * pl * rl), ar = fabs(ur) + sqrt(gamma * pr * rr);
+    const double al = fabs(ul) + sqrt_nn(gamma * pl * rl), ar = fabs(ur) + sqrt_nn(gamma * pr * rr);
     const double alpha = al > ar ? al : ar;
     const double fl = flux_v<A>(tl, ul, pl, isM, isE), fr = flux_v<A>(tr, ur, pr, isM, isE);
     return 0.5 * ((fl + fr) - alpha * (tr - tl));
@@ -209,8 +209,13 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
         R[m] = 0.0;
     }
     if constexpr (OM == OUT_RK) {
+        if (g.rk_a != 0.0) { // uniform: stages 2 and 3
 #pragma unroll
-        for (int m = 0; m < NB; ++m) Un[m] = g.rk_a != 0.0 ? g.un[idx0 + m * ncell] : 0.0;
+            for (int m = 0; m < NB; ++m) Un[m] = g.un[idx0 + m * ncell];
+        } else {
+#pragma unroll
+            for (int m = 0; m < NB; ++m) Un[m] = 0.0;
+        }
     }
     const FaceLink Lxm = g.links[leaf * 4 + 0], Lxp = g.links[leaf * 4 + 1];
     const FaceLink Lym = g.links[leaf * 4 + 2], Lyp = g.links[leaf * 4 + 3];
@@ -251,7 +256,7 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
         }
         double U[4];
         quad_state(s, U);
-        const double rinv = 1.0 / U[0];
+        const double rinv = recip(U[0]);
         const double p = pressure_r<2>(U, gm1, rinv);
         const double fx = scale[0] * flux_v<0>(s, U[1] * rinv, p, isMx, isE);
         const double fy = scale[1] * flux_v<1>(s, U[2] * rinv, p, isMy, isE);

@@ -493,23 +493,6 @@ int dgamr_graph_launch(dgamr_graph *g, hipStream_t stream)
     return DGAMR_OK;
 }
 
-int dgamr_graph_profile(dgamr_graph *g, double *stage_ms, int64_t *stage_launches)
-{
-    CHECK(check_ptr(g, "graph"));
-    CHECK(check_ptr(stage_ms, "stage_ms"));
-    CHECK(check_ptr(stage_launches, "stage_launches"));
-    double total = 0.0;
-    for (auto &pr : g->events) {
-        HIP_TRY(hipEventSynchronize(pr.second));
-        float ms = 0.0f;
-        HIP_TRY(hipEventElapsedTime(&ms, pr.first, pr.second));
-        total += ms;
-    }
-    *stage_ms = total;
-    *stage_launches = int64_t(g->events.size());
-    return DGAMR_OK;
-}
-
 int dgamr_graph_destroy(dgamr_graph *g)
 {
     delete g;

@@ -31,7 +31,7 @@ EXPORTS = [
     "dgamr_project_ic", "dgamr_check_state", "dgamr_set_tuning", "dgamr_profile_enable", "dgamr_profile_read",
     "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
     "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_autotune",
-    "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture", "dgamr_graph_profile",
+    "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture",
     "dgamr_last_error",
 ]
 
@@ -98,8 +98,7 @@ def lib():
                                           ctypes.POINTER(vp)]
         L.dgamr_graph_launch.argtypes = [vp, vp]
         L.dgamr_graph_destroy.argtypes = [vp]
-        L.dgamr_run_capture.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, ctypes.c_int, ctypes.POINTER(vp)]
-        L.dgamr_graph_profile.argtypes = [vp, ctypes.POINTER(ctypes.c_double), i64p]
+        L.dgamr_run_capture.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, ctypes.POINTER(vp)]
         L.dgamr_last_error.restype = ctypes.c_char_p
         for name in EXPORTS:
             if name != "dgamr_last_error":
@@ -234,12 +233,11 @@ class Forest:
         """nsteps SSP-RK3 steps in place, three launches per step."""
         _check(lib().dgamr_run(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
 
-    def capture_run(self, u, work, dt_dev, nsteps, cfl=0.1, profile=False):
+    def capture_run(self, u, work, dt_dev, nsteps, cfl=0.1):
         """nsteps steps of run() captured into a HIP graph (RunGraph); each
         launch advances u by nsteps steps."""
         h = ctypes.c_void_p()
-        _check(lib().dgamr_run_capture(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), 1 if profile else 0,
-                                       ctypes.byref(h)))
+        _check(lib().dgamr_run_capture(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), ctypes.byref(h)))
         return RunGraph(h, keep=(self, u, work, dt_dev))
 
     def conserved_totals(self, u, work, stream=None):
@@ -372,12 +370,6 @@ class RunGraph:
 
     def launch(self, stream=None):
         _check(lib().dgamr_graph_launch(self.h, _stream(stream)))
-
-    def profile(self):
-        """(summed stage-kernel milliseconds, launches) of the last launch."""
-        ms, n = ctypes.c_double(), ctypes.c_int64()
-        _check(lib().dgamr_graph_profile(self.h, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

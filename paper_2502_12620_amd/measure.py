@@ -11,6 +11,9 @@
         the batched workload: independent 2-D forests in one pool per degree,
         autotuned, one HIP graph per batch of steps; batch wall time p50/p99
         and DOF-stage/s against the same forests solved one after another;
+    python -m paper_2502_12620_amd.measure sedov
+        the 3-D blast workload end to end (limiter, regrid every 10 steps)
+        with FP64 and with FP32 residuals, and their L1 / L2 difference;
     python -m paper_2502_12620_amd.measure serve [--requests 100]
         the served workload: a Poisson stream of 2-D/3-D solves through the
         continuous-batching request loop; latency p50/p99 and DOF-stage/s
@@ -191,6 +194,59 @@ def cmd_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def _sedov_gpu(w, precision):
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, precision=precision,
+                 limiter=G.LIMITER_POSITIVITY)
+    z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
+    for rule in w.initial_refinement:
+        z = f.adapt(rule(w, f.keys()), z)
+    u = f.project_ic(G.IC_SEDOV, w.ic_params)
+    work, dt = f.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    t0 = f.conserved_totals(u, work).cpu().numpy()
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    dof_stages, regrid_s = 0, 0.0
+    for step in range(w.steps):
+        if step and step % w.regrid_every == 0:
+            r0 = time.perf_counter()
+            eta = f.indicator(u, work).cpu().numpy()
+            flags = ((eta > w.refine_above).astype("int8") - (eta < w.coarsen_below).astype("int8"))
+            u = f.adapt(flags, u)
+            work = f.new_work()
+            torch.cuda.synchronize()
+            regrid_s += time.perf_counter() - r0
+        f.step(u, work, dt, w.cfl)
+        dof_stages += 3 * w.dofs(f.n_leaves)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - start
+    bad = f.check_state(u, work)
+    tot = f.conserved_totals(u, work).cpu().numpy()
+    return f, u.cpu().numpy(), {"wall_s": el, "regrid_s": regrid_s, "dof_stage_per_s": dof_stages / el,
+                                "final_leaves": f.n_leaves, "nonphysical_cells": bad,
+                                "rel_mass_drift": float(abs(tot[0] - t0[0]) / abs(t0[0]))}
+
+
+def cmd_sedov(args):
+    w = W.sedov_c3()
+    out = {"workload": w.name, "steps": w.steps}
+    res = {}
+    for name, prec in (("fp64", G.FP64), ("fp32", G.FP32_MFMA)):
+        f, u, r = _sedov_gpu(w, prec)
+        res[name] = (f.keys(), u)
+        out[name] = r
+    import numpy as np
+
+    (k64, u64), (k32, u32) = res["fp64"], res["fp32"]
+    if np.array_equal(k64, k32):
+        d = u32[:, 0] - u64[:, 0]
+        out["fp32_vs_fp64"] = {"rel_l1_density": float(np.abs(d).sum() / np.abs(u64[:, 0]).sum()),
+                               "rel_l2_density": float(np.linalg.norm(d) / np.linalg.norm(u64[:, 0])),
+                               "rel_max_all": float(np.abs(u32 - u64).max() / np.abs(u64).max())}
+    else:
+        out["fp32_vs_fp64"] = "the regrids produced different forests"
+    print(json.dumps(out), flush=True)
+
+
 def cmd_serve(args):
     from .serve import Request, Server
 
@@ -244,6 +300,7 @@ def main(argv=None):
     b.add_argument("--forests", type=int, default=512)
     b.add_argument("--repeats", type=int, default=20)
     b.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
+    sub.add_parser("sedov")
     v = sub.add_parser("serve")
     v.add_argument("--requests", type=int, default=100)
     v.add_argument("--rate", type=float, default=200.0)
@@ -251,7 +308,7 @@ def main(argv=None):
     v.add_argument("--tune", action="store_true")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    {"sweep": cmd_sweep, "copy": cmd_copy, "batch": cmd_batch, "serve": cmd_serve}[args.cmd](args)
+    {"sweep": cmd_sweep, "copy": cmd_copy, "batch": cmd_batch, "serve": cmd_serve, "sedov": cmd_sedov}[args.cmd](args)
 
 
 if __name__ == "__main__":

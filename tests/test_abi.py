@@ -74,3 +74,21 @@ def test_null_arguments_are_rejected():
     assert L.dgamr_num_leaves(None, None) == G.EINVAL
     assert L.dgamr_step(None, ctypes.c_double(0.1), None, None, None, None) == G.EINVAL
     assert b"null" in L.dgamr_last_error()
+
+
+def test_pool_and_graph_arguments_are_checked_before_any_device_call():
+    G, L = _lib()
+    h = ctypes.c_void_p()
+    assert L.dgamr_pool_create(None, 16, 4, ctypes.byref(h)) == G.EINVAL
+    d = _desc(G)
+    assert L.dgamr_pool_create(ctypes.byref(d), 0, 4, ctypes.byref(h)) == G.EINVAL
+    assert L.dgamr_pool_create(ctypes.byref(d), 16, 0, ctypes.byref(h)) == G.EINVAL
+    assert L.dgamr_pool_create(ctypes.byref(_desc(G, n_cell=7)), 16, 4, ctypes.byref(h)) == G.EINVAL
+    assert not h.value
+    assert L.dgamr_pool_step(None, None, None, None) == G.EINVAL
+    assert L.dgamr_pool_admit(None, None, ctypes.c_double(0.1), None, None, None) == G.EINVAL
+    assert L.dgamr_pool_release(None, 0, None) == G.EINVAL
+    assert L.dgamr_graph_launch(None, None) == G.EINVAL
+    assert L.dgamr_run_capture(None, ctypes.c_double(0.1), 1, None, None, None, None) == G.EINVAL
+    assert L.dgamr_pool_destroy(None) == G.OK
+    assert L.dgamr_graph_destroy(None) == G.OK

@@ -308,3 +308,19 @@ def test_nonphysical_state_is_reported():
     u[0, 3, 0, 5] = -1.0  # negative energy planted on the host
     ud = _cuda(u)
     assert gpu.check_state(ud, gpu.new_work()) == 1
+
+
+def test_sedov_full_size_steps():
+    """The 3-D blast workload at full size (176 leaves of 8^3 cells, degree 2,
+    limiter) for 3 steps against the oracle."""
+    w = W.sedov_c3()
+    orc, gpu = make_pair(w, limiter=True)
+    assert orc.n_leaves == 176
+    u = orc.project_ic(O.IC_SEDOV, w.ic_params)
+    ud = gpu.project_ic(W.IC_SEDOV, w.ic_params)
+    work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        dref = orc.step(u, w.cfl, limiter=True)
+        gpu.step(ud, work, dt, w.cfl)
+        assert abs(_host(dt)[0] - dref) <= 1e-13 * dref
+    assert rel_diff(_host(ud), u).max() <= 1e-11

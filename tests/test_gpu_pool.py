@@ -1,7 +1,7 @@
 """GPU tests of pools (many forests stepped together by the same stage
 kernels): every member's result equals the same forest stepped alone
-(bitwise: a member's arithmetic does not depend on the other members or on
-the launch shape), members admitted and released between steps
+(bitwise: a member's arithmetic does not depend on the other members; a
+different slab height changes it only at rounding level), members admitted and released between steps
 (continuous batching), HIP-graph replay against eager steps, the
 autotuner, and agreement with the oracle."""
 import numpy as np
@@ -168,11 +168,18 @@ def test_autotune_keeps_results():
     _admit_all(tuned, members)
     rows, grid, us = tuned.autotune()
     assert rows in (8, 4, 2, 1) and grid >= 0 and us > 0
-    for shape in [(rows, grid), (2, 0), (8, 256)]:
+    # a persistent grid walks the same items: bitwise the same result
+    tuned.set_shape(8, 4)
+    tuned.step()
+    ref.step()
+    assert torch.equal(tuned.u, ref.u), "a persistent grid changes the result"
+    # another slab height computes slab-edge faces from memory instead of
+    # LDS: the same arithmetic up to rounding
+    for shape in [(rows, grid), (2, 0), (1, 256)]:
         tuned.set_shape(*shape)
         tuned.step()
         ref.step()
-        assert torch.equal(tuned.u, ref.u), f"shape {shape} changes the result"
+        assert rel_diff(_host(tuned.u), _host(ref.u)).max() <= 1e-14, f"shape {shape}"
 
 
 @pytest.mark.parametrize("precision,limiter", [(0, False), (1, False), (0, True)])
@@ -204,7 +211,7 @@ def test_run_capture_replays_equal_run(dim):
     u_e = u_g.clone()
     work_g, work_e = f.new_work(), f.new_work()
     dt_g, dt_e = (torch.zeros(1, dtype=torch.float64, device="cuda") for _ in range(2))
-    graph = f.capture_run(u_g, work_g, dt_g, 3, 0.1, profile=True)
+    graph = f.capture_run(u_g, work_g, dt_g, 3, 0.1)
     scratch = torch.rand(1 << 18, device="cuda")
     for rep in range(3):
         graph.launch()
@@ -213,8 +220,6 @@ def test_run_capture_replays_equal_run(dim):
         torch.cuda.synchronize()
         assert torch.equal(u_g, u_e), f"replay {rep} differs from dgamr_run"
         assert torch.equal(dt_g, dt_e)
-        ms, n = graph.profile()
-        assert n == 9 and ms > 0.0
     f.adapt(np.zeros(f.n_leaves, np.int8), u_g)  # a (trivial) refinement invalidates the graph
     with pytest.raises(G.DgamrError) as e:
         graph.launch()
