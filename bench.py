@@ -11,8 +11,10 @@ Prints one JSON line: DOF-stage updates/s over exactly --steps timed steps
 (inputs resident in HBM), the roofline of the dominant kernel (the fused
 stage kernel, timed with HIP events around each of its launches in an
 eager pass of the same steps right after the timed graph launch), the
-same run with FP32 residual arithmetic (FP64 state), the oracle's rate on
-the host cores for a bounded sample of the same workload, and the L1 / L2
+same run with FP32 residual arithmetic (FP64 state), the batched
+workload's batch wall time p50/p99 (512 forests, 20 steps per batch, one HIP
+graph per batch) against the same forests solved one by one, the oracle's
+rate on the host cores for a bounded sample of the same workload, and the L1 / L2
 density difference and mass drift of both GPU runs against the oracle after
 the same number of steps.
 """
@@ -162,6 +164,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-residual run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 512-forest run")
+    ap.add_argument("--batched-repeats", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the whole forest lives on one "
@@ -215,6 +219,14 @@ def main():
             "kernel": "k_stage<float> (fused residual + RK stage, one thread per cell)",
             "avg_launch_us": r32["avg_launch_s"] * 1e6,
             "achieved_GBs": ab["bytes_per_launch"] / r32["avg_launch_s"] / 1e9}
+    if not args.no_batched:
+        from paper_2502_12620_amd.measure import batched_run
+
+        b = batched_run(512, args.batched_repeats)
+        out["batched"] = {k: b[k] for k in ("workload", "forests", "leaves", "dofs", "steps_per_batch", "repeats",
+                                            "batch_wall_s_p50", "batch_wall_s_p99", "dof_stage_per_s",
+                                            "sequential_dof_stage_per_s", "speedup_vs_sequential",
+                                            "max_rel_diff_vs_plain_path")}
     if not args.no_cpu:
         cpu, u_ref, tot_ref, tot0 = cpu_baseline(w, args.warmup + args.steps, args.cpu_budget)
         out["cpu_baseline"] = cpu

@@ -20,7 +20,8 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
 BC_PERIODIC, BC_OUTFLOW = 0, 1
 HANG_PAPER, HANG_CONSERVATIVE = 0, 1
-IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE = 0, 1, 2, 3
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE = 0, 1, 2, 3, 4
+EQ_EULER, EQ_ADVECTION = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -62,6 +63,9 @@ def lib():
         L.orc_create.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ip, dp, dp, ip,
                                  ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.orc_destroy.argtypes = [vp]
+        L.orc_set_advection.argtypes = [vp, dp]
+        L.orc_upwind.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
+        L.orc_upwind.restype = ctypes.c_double
         L.orc_num_leaves.argtypes = [vp]
         L.orc_leaf_keys.argtypes = [vp, ip]
         L.orc_state_len.restype = ctypes.c_long
@@ -151,6 +155,11 @@ def rusanov(dim: int, gamma: float, um, up, axis: int, sign: int) -> np.ndarray:
     return f
 
 
+def upwind(vel, um: float, up: float, axis: int, sign: int) -> float:
+    v = np.ascontiguousarray(list(vel) + [0.0] * (3 - len(vel)), dtype=np.float64)
+    return lib().orc_upwind(_dp(v), um, up, axis, sign)
+
+
 def rk_combine(stage: int, dt: float, un, us, r) -> np.ndarray:
     un, us, r = (np.ascontiguousarray(a, dtype=np.float64) for a in (un, us, r))
     out = np.zeros_like(un)
@@ -167,7 +176,7 @@ class Forest:
     """A forest of block trees with its DG state layout (see oracle.h)."""
 
     def __init__(self, dim, p, n_cell, roots, lo, hi, bc, max_level, gamma=1.4,
-                 hanging=HANG_PAPER):
+                 hanging=HANG_PAPER, equation=EQ_EULER, velocity=(1.0, 1.0, 1.0)):
         roots = np.array(list(roots) + [1] * (3 - len(roots)), dtype=np.int32)
         lo = np.array(list(lo) + [0.0] * (3 - len(lo)), dtype=np.float64)
         hi = np.array(list(hi) + [1.0] * (3 - len(hi)), dtype=np.float64)
@@ -180,6 +189,11 @@ class Forest:
                                     max_level, gamma, hanging)
         if not self.ptr:
             raise ValueError("oracle: invalid forest description")
+        self.equation = equation
+        if equation == EQ_ADVECTION:
+            self.velocity = np.array(list(velocity) + [0.0] * (3 - len(velocity)), dtype=np.float64)
+            lib().orc_set_advection(self.ptr, _dp(self.velocity))
+            self.nv = 1
 
     def __del__(self):
         if getattr(self, "ptr", None):

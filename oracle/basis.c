@@ -233,3 +233,12 @@ void orc_rusanov(int dim, double gamma, const double *um, const double *up,
     for (int v = 0; v < nv; ++v)
         fhat[v] = 0.5 * ((double)sign * (fm[v] + fp[v]) - alpha * (up[v] - um[v]));
 }
+
+/* Sec. 5.1: F(u) = vel u.  The Rusanov flux with alpha = |vel . n| for the
+ * outward normal n = sign*e_axis is the upwind flux:
+ * Fhat = 1/2 [ vn (u- + u+) - |vn| (u+ - u-) ],  vn = sign*vel_axis. */
+double orc_upwind(const double *vel, double um, double up, int axis, int sign)
+{
+    double vn = (double)sign * vel[axis];
+    return 0.5 * (vn * (um + up) - fabs(vn) * (up - um));
+}

@@ -296,6 +296,7 @@ orc_forest *orc_create(int dim, int p, int n_cell, const int *roots, const doubl
     f->N = n_cell;
     f->nb = orc_num_modes(dim, p);
     f->nv = dim + 2;
+    f->equation = ORC_EQ_EULER;
     f->q = p + 1;
     f->max_level = max_level;
     f->gamma = gamma;
@@ -317,6 +318,13 @@ orc_forest *orc_create(int dim, int p, int n_cell, const int *roots, const doubl
     }
     orc_build_topology(f);
     return f;
+}
+
+void orc_set_advection(orc_forest *f, const double *vel)
+{
+    f->equation = ORC_EQ_ADVECTION;
+    f->nv = 1;
+    for (int a = 0; a < 3; ++a) f->vel[a] = a < f->dim ? vel[a] : 0.0;
 }
 
 void orc_destroy(orc_forest *f)

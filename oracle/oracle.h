@@ -39,7 +39,10 @@ extern "C" {
 
 enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
 enum { ORC_HANG_PAPER = 0, ORC_HANG_CONSERVATIVE = 1 };
-enum { ORC_IC_VORTEX = 0, ORC_IC_SEDOV = 1, ORC_IC_UNIFORM = 2, ORC_IC_XWAVE = 3 };
+enum { ORC_IC_VORTEX = 0, ORC_IC_SEDOV = 1, ORC_IC_UNIFORM = 2, ORC_IC_XWAVE = 3, ORC_IC_COSINE = 4 };
+/* conservation law solved: the Euler equations (Sec. 2) or the linear
+ * scalar convection equation of Sec. 5.1 */
+enum { ORC_EQ_EULER = 0, ORC_EQ_ADVECTION = 1 };
 
 typedef struct orc_forest orc_forest;
 
@@ -64,6 +67,12 @@ void orc_rusanov(int dim, double gamma, const double *um, const double *up,
 orc_forest *orc_create(int dim, int p, int n_cell, const int *roots,
                        const double *lo, const double *hi, const int *bc,
                        int max_level, double gamma, int hanging);
+/* Switch a freshly created forest (before any other call) to the scalar
+ * convection equation u_t + vel . grad u = 0 (one variable). */
+void orc_set_advection(orc_forest *f, const double *vel);
+/* Upwind (Rusanov with alpha = |vel . n|) flux of the scalar convection
+ * equation for the outward normal sign*e_axis. */
+double orc_upwind(const double *vel, double um, double up, int axis, int sign);
 void orc_destroy(orc_forest *f);
 int orc_num_leaves(const orc_forest *f);
 void orc_leaf_keys(const orc_forest *f, int *keys /* n x 5 */);

@@ -47,6 +47,8 @@ struct orc_forest {
     int max_level;
     double gamma;
     int hanging;
+    int equation;     /* ORC_EQ_EULER or ORC_EQ_ADVECTION */
+    double vel[3];    /* advection velocity */
     long unit;        /* global units per root edge = N * 2^(max_level-1) */
     int nleaves;
     orc_key *leaf;

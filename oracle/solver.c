@@ -136,6 +136,21 @@ static double wrap_half(double d, double period)
     return d;
 }
 
+/* Physical flux along axis a: Euler (Eq. 2, 23) or scalar convection
+ * (Sec. 5.1, F = vel u). */
+static void phys_flux(const orc_forest *f, const double *u, int a, double *fl)
+{
+    if (f->equation == ORC_EQ_ADVECTION) fl[0] = f->vel[a] * u[0];
+    else orc_euler_flux(f->dim, f->gamma, u, a, fl);
+}
+
+/* Numerical flux for the outward normal side*e_axis (Eq. 5). */
+static void num_flux(const orc_forest *f, const double *um, const double *up, int axis, int side, double *fh)
+{
+    if (f->equation == ORC_EQ_ADVECTION) fh[0] = orc_upwind(f->vel, um[0], up[0], axis, side);
+    else orc_rusanov(f->dim, f->gamma, um, up, axis, side, fh);
+}
+
 /* Analytic states used as initial conditions and exact solutions.
  *  VORTEX  params: eps, xc, yc, u_inf, v_inf, period_x, period_y
  *          isentropic vortex with mean (rho,u,v,p) = (1,u_inf,v_inf,1),
@@ -146,13 +161,22 @@ static double wrap_half(double d, double period)
  *  UNIFORM params: rho, u, v, w, p
  *  XWAVE   params: amplitude, u, period_x
  *          rho = 1 + A sin(2 pi (x - u t)/Lx), velocity (u,0,0), p = 1:
- *          an exact entropy wave. */
+ *          an exact entropy wave.
+ *  COSINE  (scalar convection, Sec. 5.1) params: k, period_x, period_y,
+ *          period_z; u = prod_a [cos(2 pi k (x_a - vel_a t)/L_a) - 1]. */
 static void analytic_state(const orc_forest *f, int kind, const double *prm, double t,
                            const double *x, double *u)
 {
     const double pi = 3.14159265358979323846;
     double g = f->gamma;
     double vel[3] = {0, 0, 0};
+    if (kind == ORC_IC_COSINE) {
+        double prod = 1.0;
+        for (int a = 0; a < f->dim; ++a)
+            prod *= cos(2.0 * pi * prm[0] * (x[a] - f->vel[a] * t) / prm[1 + a]) - 1.0;
+        u[0] = prod;
+        return;
+    }
     if (kind == ORC_IC_VORTEX) {
         double eps = prm[0];
         double dx = wrap_half(x[0] - prm[1] - prm[3] * t, prm[5]);
@@ -365,8 +389,8 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
                 double uq[5];
                 eval_with(f, K, (long)f->nb * nc, nc, vphi + iq * nb, uq);
                 for (int a = 0; a < d; ++a) {
-                    double fl[5];
-                    orc_euler_flux(d, f->gamma, uq, a, fl);
+                    double fl[5] = {0, 0, 0, 0, 0};
+                    phys_flux(f, uq, a, fl);
                     for (int m = 0; m < f->nb; ++m) {
                         double dp = vdphi[(iq * d + a) * nb + m] * 2.0 / h[a];
                         for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] += vw[iq] * J * fl[v] * dp;
@@ -419,7 +443,7 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
                             double um[5], up[5], fh[5];
                             eval_poly(f, K, (long)f->nb * nc, nc, xo, um);
                             eval_poly(f, Kf, (long)f->nb * nc, nc, xf, up);
-                            orc_rusanov(d, f->gamma, um, up, axis, side, fh);
+                            num_flux(f, um, up, axis, side, fh);
                             for (int m = 0; m < f->nb; ++m) {
                                 double ph = orc_phi(d, f->exps + 3 * m, xo);
                                 for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] -= fw[iq] * Jff * fh[v] * ph;
@@ -444,7 +468,7 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
                     double um[5], up[5], fh[5];
                     eval_with(f, K, (long)f->nb * nc, nc, po, um);
                     eval_with(f, Kn, nsv, nsm, fnbr + (face * nfq + iq) * nb, up);
-                    orc_rusanov(d, f->gamma, um, up, axis, side, fh);
+                    num_flux(f, um, up, axis, side, fh);
                     for (int m = 0; m < f->nb; ++m) {
                         double ph = po[m];
                         for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] -= fw[iq] * Jf * fh[v] * ph;
@@ -491,6 +515,12 @@ double orc_max_rate(const orc_forest *f, const double *u)
     for (int i = 0; i < f->nleaves; ++i) {
         long lo[3], size;
         orc_leaf_box(f, &f->leaf[i], lo, &size);
+        if (f->equation == ORC_EQ_ADVECTION) { /* sum_a |vel_a| / h_a */
+            double rate = 0.0;
+            for (int a = 0; a < d; ++a) rate += fabs(f->vel[a]) / ((size / f->N) * unit_len(f, a));
+            if (rate > mx) mx = rate;
+            continue;
+        }
         for (int c = 0; c < nc; ++c) {
             double s[5];
             for (int v = 0; v < f->nv; ++v) s[v] = u[sidx(f, i, v, 0, c)];
@@ -534,6 +564,7 @@ void orc_totals(const orc_forest *f, const double *u, double *totals)
  *      theta2.  Cell means are unchanged. */
 void orc_limit_positivity(const orc_forest *f, double *u)
 {
+    if (f->equation != ORC_EQ_EULER) return; /* density and pressure only exist for Euler */
     int d = f->dim, nc = orc_ncell(f), q = f->q, nv = f->nv;
     double gx[8], gw[8];
     orc_gauss_legendre(q, gx, gw);
@@ -642,7 +673,9 @@ void orc_indicator(const orc_forest *f, const double *u, double *eta)
                 if (r > mx) mx = r;
                 if (r < mn) mn = r;
             }
-        eta[i] = mx / mn;
+        /* Euler: density ratio over the block and its face guards; scalar
+         * convection (Sec. 5.1): the largest cell average there */
+        eta[i] = f->equation == ORC_EQ_ADVECTION ? mx : mx / mn;
     }
     free(g);
 }

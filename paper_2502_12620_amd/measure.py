@@ -130,9 +130,16 @@ def _forest(w, precision=G.FP64):
 
 
 def cmd_batch(args):
-    ws = W.batched_forests(args.forests, seed=2502)
+    print(json.dumps(batched_run(args.forests, args.repeats, args.precision)), flush=True)
+
+
+def batched_run(forests: int = 512, repeats: int = 20, precision: str = "fp64") -> dict:
+    """The batched workload: pools per degree, autotuned, one HIP graph of a
+    batch (20 steps of every forest); batch wall times over `repeats`
+    replays, and the same forests solved one after another (dgamr_run)."""
+    ws = W.batched_forests(forests, seed=2502)
     steps = ws[0].steps
-    prec = G.FP32_MFMA if args.precision == "fp32" else G.FP64
+    prec = G.FP32_MFMA if precision == "fp32" else G.FP64
     groups = {}
     for w in ws:
         groups.setdefault(w.degree, []).append((w, _forest(w, prec)))
@@ -175,15 +182,15 @@ def cmd_batch(args):
     seq_total = sum(seq_times)
     # timed replays (the state keeps advancing: each replay is `steps` more steps)
     times = []
-    for _ in range(args.repeats):
+    for _ in range(repeats):
         e0.record()
         graph.launch()
         e1.record()
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1) / 1e3)
     med = _pct(times, 50)
-    out = {"workload": f"batched_{args.forests}_forests_2d", "forests": len(ws), "leaves": leaves, "dofs": dofs,
-           "precision": args.precision, "steps_per_batch": steps, "repeats": args.repeats,
+    out = {"workload": f"batched_{forests}_forests_2d", "forests": len(ws), "leaves": leaves, "dofs": dofs,
+           "precision": precision, "steps_per_batch": steps, "repeats": repeats,
            "batch_wall_s_p50": med, "batch_wall_s_p99": _pct(times, 99), "batch_wall_s_min": min(times),
            "dof_stage_per_s": dofs * 3 * steps / med,
            "sequential_plain_s": seq_total, "sequential_dof_stage_per_s": dofs * 3 * steps / seq_total,
@@ -191,7 +198,7 @@ def cmd_batch(args):
            "max_rel_diff_vs_plain_path": max_rel,
            "autotune": {f"p{p}": {"rows": r, "grid": g, "stage_us": us} for p, (r, g, us) in zip(sorted(groups), tune)},
            "setup_s": setup_s}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def _sedov_gpu(w, precision):
@@ -208,6 +215,7 @@ def _sedov_gpu(w, precision):
     dof_stages, regrid_s = 0, 0.0
     for step in range(w.steps):
         if step and step % w.regrid_every == 0:
+            torch.cuda.synchronize()
             r0 = time.perf_counter()
             eta = f.indicator(u, work).cpu().numpy()
             flags = ((eta > w.refine_above).astype("int8") - (eta < w.coarsen_below).astype("int8"))
