@@ -61,7 +61,12 @@ enum { DGAMR_BC_PERIODIC = 0, DGAMR_BC_OUTFLOW = 1 };
 enum { DGAMR_FP64 = 0, DGAMR_FP32_MFMA = 1 };
 enum { DGAMR_HANG_PAPER = 0, DGAMR_HANG_CONSERVATIVE = 1 };
 enum { DGAMR_LIMITER_NONE = 0, DGAMR_LIMITER_POSITIVITY = 1 };
-enum { DGAMR_IC_VORTEX = 0, DGAMR_IC_SEDOV = 1, DGAMR_IC_UNIFORM = 2, DGAMR_IC_XWAVE = 3 };
+enum { DGAMR_IC_VORTEX = 0, DGAMR_IC_SEDOV = 1, DGAMR_IC_UNIFORM = 2, DGAMR_IC_XWAVE = 3, DGAMR_IC_COSINE = 4 };
+/* Conservation law: the Euler equations (Sec. 2, Eq. 1-5, 23; d+2
+ * variables) or the linear scalar convection equation u_t + vel . grad u = 0
+ * of Sec. 5.1 (one variable; Rusanov flux with alpha = |vel . n|, i.e.
+ * upwind). */
+enum { DGAMR_EQ_EULER = 0, DGAMR_EQ_ADVECTION = 1 };
 
 typedef struct {
     int dim;          /* 2 or 3 */
@@ -77,6 +82,8 @@ typedef struct {
     int hanging;      /* DGAMR_HANG_PAPER (guard-cell fluxes, Sec. 3.5) or
                          DGAMR_HANG_CONSERVATIVE (coarse side lifts the fine-side flux) */
     int limiter;      /* DGAMR_LIMITER_* applied after each stage by dgamr_step */
+    int equation;     /* DGAMR_EQ_*; scalar convection requires FP64 and no limiter */
+    double velocity[3]; /* convection velocity (DGAMR_EQ_ADVECTION) */
 } dgamr_forest_desc;
 
 typedef struct dgamr_forest dgamr_forest;
@@ -172,13 +179,16 @@ int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev,
  * applied in place. */
 int dgamr_limit_positivity(dgamr_forest *f, double *u, hipStream_t stream);
 
-/* Block indicator: max/min density cell mean over the block's cells and
- * face-guard cells, per leaf (FP64, device). */
+/* Block indicator per leaf (FP64, device): Euler, max/min density cell mean
+ * over the block's cells and face-guard cells; scalar convection, the
+ * largest cell mean there (Sec. 5.1 refines on the cell average). */
 int dgamr_indicator(dgamr_forest *f, const double *u, double *eta_dev, void *work,
                     hipStream_t stream);
 
 /* L2 projection of an analytic state (DGAMR_IC_*, parameters as the test
- * workloads define them) with p+3 Gauss points per axis. */
+ * workloads define them) with p+3 Gauss points per axis.  DGAMR_IC_COSINE
+ * (scalar convection only): params k, L_x, L_y, L_z; the state is
+ * prod_a [cos(2 pi k (x_a - vel_a t)/L_a) - 1] with the forest's velocity. */
 int dgamr_project_ic(dgamr_forest *f, int kind, const double *params /* 8 */, double t,
                      double *u, hipStream_t stream);
 

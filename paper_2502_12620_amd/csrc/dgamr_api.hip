@@ -31,7 +31,7 @@ int nfc_of(const dgamr_forest *f)
     return f->topo.dim() == 2 ? n : n * n;
 }
 int nb_of(const dgamr_forest *f) { return dgk::num_modes(f->topo.dim(), f->topo.desc().degree); }
-int nv_of(const dgamr_forest *f) { return f->topo.dim() + 2; }
+int nv_of(const dgamr_forest *f) { return f->topo.nv(); }
 size_t state_elems(const dgamr_forest *f) { return size_t(f->topo.n()) * nv_of(f) * nb_of(f) * ncell_of(f); }
 size_t guard_elems(const dgamr_forest *f)
 {
@@ -87,7 +87,7 @@ int launch_fill(dgamr_forest *f, const double *u, double *guard, bool traces, hi
     dgk::FillArgs a{u, guard, f->d_links, nullptr, f->topo.n() * nf, f->topo.desc().n_cell, traces ? 1 : 0};
     if (a.nfaces == 0) return DGAMR_OK;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_fill<D, P>(a, nfc_of(f), s)));
+        HIP_TRY((dgk::launch_fill<D, P>(a, nfc_of(f), s, nv_of(f))));
         return DGAMR_OK;
     });
 }
@@ -106,18 +106,21 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     a.geo = f->d_geo;
     a.links = f->d_links;
     a.conservative = f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE;
+    for (int k = 0; k < 3; ++k) a.vel[k] = f->topo.desc().velocity[k];
     if (a.nleaves == 0) return DGAMR_OK;
     const bool fp32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
+    const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
     dgk::StageShape sh;
     sh.variant = stage_variant(f);
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, fp32, sh, s)));
+        HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, fp32, sh, s, eq)));
         return DGAMR_OK;
     });
 }
 
 int launch_limit(dgamr_forest *f, double *u, hipStream_t s)
 {
+    if (f->topo.advection()) return fail(DGAMR_EINVAL, "the positivity limiter is for the Euler equations");
     long total = long(f->topo.n()) * ncell_of(f);
     if (total == 0) return DGAMR_OK;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
@@ -132,7 +135,11 @@ int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, cons
     if (n == 0) return fail(DGAMR_EINVAL, "empty forest");
     int ncell = ncell_of(f), block = 1;
     while (block < ncell && block < 256) block <<= 1; // power of two for the tree reduction
-    if (f->topo.dim() == 2)
+    const double *vel = f->topo.desc().velocity;
+    if (f->topo.advection())
+        hipLaunchKernelGGL(dgk::k_rate_adv, dim3((n + 255) / 256), dim3(256), 0, s, f->d_geo, n, vel[0], vel[1],
+                           vel[2], f->topo.dim(), w.leafmax);
+    else if (f->topo.dim() == 2)
         hipLaunchKernelGGL(dgk::k_rate<2>, dim3(n), dim3(block), 0, s, u, f->d_geo, f->topo.desc().n_cell, nb_of(f),
                            f->topo.desc().gamma, w.leafmax, nullptr);
     else
@@ -266,7 +273,7 @@ int dgamr_apply_refinement(dgamr_forest *f, const double *u_old, double *u_new, 
         HIP_TRY(hipMemcpyAsync(d_inh, inh.data(), sizeof(Inherit) * n, hipMemcpyHostToDevice, stream));
         long total = long(n) * ncell_of(f);
         rc = dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-            HIP_TRY((dgk::launch_inherit<D, P>(u_old, u_new, d_inh, f->topo.desc().n_cell, total, stream)));
+            HIP_TRY((dgk::launch_inherit<D, P>(u_old, u_new, d_inh, f->topo.desc().n_cell, total, stream, nv_of(f))));
             return DGAMR_OK;
         });
         HIP_TRY(hipStreamSynchronize(stream));
@@ -357,7 +364,7 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         a.rate_out = s == 2 ? rate_out : nullptr;
         // 3-D reads the far side of every block face as traces from the
         // guard buffer; 2-D computes it inline
-        const bool guard3 = f->topo.dim() == 3;
+        const bool guard3 = f->topo.dim() == 3 && !f->topo.advection();
         if (guard3) {
             a.guard = w.guard;
             CHECK(launch_fill(f, us, w.guard, true, stream));
@@ -476,7 +483,15 @@ int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev,
     if (n == 0) return fail(DGAMR_EINVAL, "empty forest");
     int bp = 1;
     while (bp < block) bp <<= 1; // power of two for the tree reduction
-    if (f->topo.dim() == 2) {
+    if (f->topo.advection()) {
+        if (f->topo.dim() == 2)
+            hipLaunchKernelGGL((dgk::k_totals_leaf<2, 1>), dim3(n), dim3(bp), 0, stream, u, f->d_geo,
+                               f->topo.desc().n_cell, nb_of(f), w.part);
+        else
+            hipLaunchKernelGGL((dgk::k_totals_leaf<3, 1>), dim3(n), dim3(bp), 0, stream, u, f->d_geo,
+                               f->topo.desc().n_cell, nb_of(f), w.part);
+        hipLaunchKernelGGL(dgk::k_totals_final<1>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
+    } else if (f->topo.dim() == 2) {
         hipLaunchKernelGGL(dgk::k_totals_leaf<2>, dim3(n), dim3(bp), 0, stream, u, f->d_geo, f->topo.desc().n_cell,
                            nb_of(f), w.part);
         hipLaunchKernelGGL(dgk::k_totals_final<4>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
@@ -506,7 +521,13 @@ int dgamr_indicator(dgamr_forest *f, const double *u, double *eta_dev, void *wor
     CHECK(launch_fill(f, u, w.guard, false, stream));
     int n = f->topo.n();
     if (n == 0) return DGAMR_OK;
-    if (f->topo.dim() == 2)
+    if (f->topo.advection() && f->topo.dim() == 2)
+        hipLaunchKernelGGL((dgk::k_indicator_leaf<2, 1>), dim3(n), dim3(256), 0, stream, u, w.guard,
+                           f->topo.desc().n_cell, nb_of(f), eta_dev);
+    else if (f->topo.advection())
+        hipLaunchKernelGGL((dgk::k_indicator_leaf<3, 1>), dim3(n), dim3(256), 0, stream, u, w.guard,
+                           f->topo.desc().n_cell, nb_of(f), eta_dev);
+    else if (f->topo.dim() == 2)
         hipLaunchKernelGGL(dgk::k_indicator_leaf<2>, dim3(n), dim3(256), 0, stream, u, w.guard, f->topo.desc().n_cell,
                            nb_of(f), eta_dev);
     else
@@ -521,17 +542,22 @@ int dgamr_project_ic(dgamr_forest *f, int kind, const double *params, double t, 
     CHECK(check_ptr(f, "forest"));
     CHECK(check_ptr(params, "params"));
     CHECK(check_ptr(u, "u"));
-    if (kind < DGAMR_IC_VORTEX || kind > DGAMR_IC_XWAVE) return fail(DGAMR_EINVAL, "unknown initial condition");
+    if (kind < DGAMR_IC_VORTEX || kind > DGAMR_IC_COSINE) return fail(DGAMR_EINVAL, "unknown initial condition");
+    if ((kind == DGAMR_IC_COSINE) != f->topo.advection())
+        return fail(DGAMR_EINVAL, "DGAMR_IC_COSINE is the scalar convection state, the others are Euler states");
     dgk::IcParams prm;
     std::memcpy(prm.p, params, sizeof(prm.p));
     const auto &d = f->topo.desc();
+    if (kind == DGAMR_IC_COSINE)
+        for (int a = 0; a < 3; ++a) prm.p[4 + a] = d.velocity[a]; // translation of the exact solution
     double hmin[3];
     for (int a = 0; a < 3; ++a)
         hmin[a] = (d.hi[a] - d.lo[a]) / (double(d.roots[a]) * d.n_cell * double(1 << (d.max_level - 1)));
     long total = long(f->topo.n()) * ncell_of(f);
     if (total == 0) return DGAMR_OK;
     return dispatch(f->topo.dim(), d.degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_project_ic<D, P>(u, f->d_geo, d.n_cell, total, kind, prm, t, d.gamma, hmin, stream)));
+        HIP_TRY((dgk::launch_project_ic<D, P>(u, f->d_geo, d.n_cell, total, kind, prm, t, d.gamma, hmin, stream,
+                                              nv_of(f))));
         return DGAMR_OK;
     });
 }
@@ -548,7 +574,13 @@ int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work
     long total = long(f->topo.n()) * ncell_of(f);
     if (total > 0) {
         dim3 grid(unsigned((total + 255) / 256)), block(256);
-        if (f->topo.dim() == 2)
+        if (f->topo.advection() && f->topo.dim() == 2)
+            hipLaunchKernelGGL((dgk::k_check<2, 1>), grid, block, 0, stream, u, f->topo.desc().n_cell, nb_of(f), total,
+                               f->topo.desc().gamma, cnt);
+        else if (f->topo.advection())
+            hipLaunchKernelGGL((dgk::k_check<3, 1>), grid, block, 0, stream, u, f->topo.desc().n_cell, nb_of(f), total,
+                               f->topo.desc().gamma, cnt);
+        else if (f->topo.dim() == 2)
             hipLaunchKernelGGL(dgk::k_check<2>, grid, block, 0, stream, u, f->topo.desc().n_cell, nb_of(f), total,
                                f->topo.desc().gamma, cnt);
         else

@@ -1,6 +1,8 @@
 // Host-side forest topology; see forest.hpp.
 #include "forest.hpp"
 
+#include <cmath>
+
 #include <algorithm>
 #include <numeric>
 
@@ -44,6 +46,13 @@ int Forest::validate(const dgamr_forest_desc &d, std::string &err)
     if (d.precision != DGAMR_FP64 && d.precision != DGAMR_FP32_MFMA) { err = "bad precision"; return DGAMR_EINVAL; }
     if (d.hanging != DGAMR_HANG_PAPER && d.hanging != DGAMR_HANG_CONSERVATIVE) { err = "bad hanging mode"; return DGAMR_EINVAL; }
     if (d.limiter != DGAMR_LIMITER_NONE && d.limiter != DGAMR_LIMITER_POSITIVITY) { err = "bad limiter"; return DGAMR_EINVAL; }
+    if (d.equation != DGAMR_EQ_EULER && d.equation != DGAMR_EQ_ADVECTION) { err = "bad equation"; return DGAMR_EINVAL; }
+    if (d.equation == DGAMR_EQ_ADVECTION) {
+        if (d.limiter != DGAMR_LIMITER_NONE) { err = "the positivity limiter is for the Euler equations"; return DGAMR_EINVAL; }
+        if (d.precision != DGAMR_FP64) { err = "scalar convection is built in FP64 only"; return DGAMR_EUNSUPPORTED; }
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(d.velocity[a])) { err = "velocity must be finite"; return DGAMR_EINVAL; }
+    }
     return DGAMR_OK;
 }
 

@@ -50,7 +50,7 @@ int stage_rows_options(int N, int *rows, int max_options)
     return n;
 }
 
-template <int D, int P, typename T>
+template <int D, int P, typename T, int EQ = EQ_EULER>
 hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const StageShape &sh, hipStream_t s)
 {
     // slab of `rows` layers along the last axis within the thread budget
@@ -68,6 +68,18 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     // the fused 3-D stage reads every block face as traces from the guard
     // buffer (the step runs the fill kernel first); the fused 2-D stage
     // takes the far side inline
+    if constexpr (EQ == EQ_ADVECTION) {
+        // one variable: the far side is always taken inline
+        if (gm == GUARD_INLINE && om == OUT_RK) {
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, false, T, EQ>), grid, block, lds, s, a, rows);
+            return hipGetLastError();
+        }
+        if (gm == GUARD_BUFFER && om == OUT_RES64) {
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false, T, EQ>), grid, block, lds, s, a, rows);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     constexpr int GMRK = D == 3 ? GUARD_TRACE : GUARD_INLINE;
     if (gm == GMRK && om == OUT_RK) {
         if (lim) hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T>), grid, block, lds, s, a, rows);
@@ -89,9 +101,11 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
 }
 
 template <int D, int P>
-hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32, const StageShape &sh, hipStream_t s)
+hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32, const StageShape &sh, hipStream_t s,
+                        int eq)
 {
     if (a.nleaves == 0) return hipSuccess;
+    if (eq == EQ_ADVECTION) return fp32 ? hipErrorInvalidValue : launch_stage_cell<D, P, double, EQ_ADVECTION>(a, gm, om, lim, sh, s);
     if (fp32) return launch_stage_cell<D, P, float>(a, gm, om, lim, sh, s);
     if constexpr (D == 2) {
         // one lane per (cell, variable) unless the caller asks for one
@@ -102,10 +116,12 @@ hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32,
 }
 
 template <int D, int P>
-hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s)
+hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s, int nv)
 {
     const long threads = long(a.nfaces) * nfc;
-    hipLaunchKernelGGL((k_fill<D, P>), dim3(unsigned((threads + 255) / 256)), dim3(256), 0, s, a);
+    const dim3 grid(unsigned((threads + 255) / 256)), block(256);
+    if (nv == 1) hipLaunchKernelGGL((k_fill<D, P, 1>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_fill<D, P>), grid, block, 0, s, a);
     return hipGetLastError();
 }
 
@@ -118,27 +134,35 @@ hipError_t launch_limit(double *u, int N, long total, double gamma, hipStream_t 
 
 template <int D, int P>
 hipError_t launch_project_ic(double *u, const LeafGeo *geo, int N, long total, int kind, const IcParams &prm,
-                             double t, double gamma, const double *hmin, hipStream_t s)
+                             double t, double gamma, const double *hmin, hipStream_t s, int nv)
 {
-    hipLaunchKernelGGL((k_project_ic<D, P>), dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, u, geo, N, total,
-                       kind, prm, t, gamma, hmin[0], hmin[1], hmin[2]);
+    const dim3 grid(unsigned((total + 255) / 256)), block(256);
+    if (nv == 1)
+        hipLaunchKernelGGL((k_project_ic<D, P, 1>), grid, block, 0, s, u, geo, N, total, kind, prm, t, gamma, hmin[0],
+                           hmin[1], hmin[2]);
+    else
+        hipLaunchKernelGGL((k_project_ic<D, P>), grid, block, 0, s, u, geo, N, total, kind, prm, t, gamma, hmin[0],
+                           hmin[1], hmin[2]);
     return hipGetLastError();
 }
 
 template <int D, int P>
-hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, int N, long total, hipStream_t s)
+hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, int N, long total, hipStream_t s,
+                          int nv)
 {
-    hipLaunchKernelGGL((k_inherit<D, P>), dim3(unsigned((total + 255) / 256)), dim3(256), 0, s, uold, unew, inh, N,
-                       total);
+    const dim3 grid(unsigned((total + 255) / 256)), block(256);
+    if (nv == 1) hipLaunchKernelGGL((k_inherit<D, P, 1>), grid, block, 0, s, uold, unew, inh, N, total);
+    else hipLaunchKernelGGL((k_inherit<D, P>), grid, block, 0, s, uold, unew, inh, N, total);
     return hipGetLastError();
 }
 
-template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, bool, const StageShape &, hipStream_t);
+template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, bool, const StageShape &, hipStream_t,
+                                             int);
 template int stage_rows_options<DG_D, DG_P>(int, int *, int);
-template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t);
+template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t, int);
 template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStream_t);
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,
-                                                   double, const double *, hipStream_t);
-template hipError_t launch_inherit<DG_D, DG_P>(const double *, double *, const Inherit *, int, long, hipStream_t);
+                                                   double, const double *, hipStream_t, int);
+template hipError_t launch_inherit<DG_D, DG_P>(const double *, double *, const Inherit *, int, long, hipStream_t, int);
 
 } // namespace dgk

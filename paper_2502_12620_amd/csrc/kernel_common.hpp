@@ -164,6 +164,12 @@ enum GuardMode : int {
 };
 enum OutMode : int { OUT_RES64 = 0, OUT_RES32 = 1, OUT_RK = 2 };
 
+// conservation law: the Euler equations (Sec. 2) or the linear scalar
+// convection equation u_t + vel . grad u = 0 (Sec. 5.1)
+enum Equation : int { EQ_EULER = 0, EQ_ADVECTION = 1 };
+template <int D, int EQ>
+constexpr int nvar() { return EQ == EQ_ADVECTION ? 1 : D + 2; }
+
 struct StageArgs {
     const double *us;     // stage input (read-only during the stage)
     const double *un;     // RK base state (OUT_RK)
@@ -175,6 +181,7 @@ struct StageArgs {
     const double *dt;     // device dt (OUT_RK), per member when leaf_member is set
     double rk_a, rk_b;
     double gamma;
+    double vel[3];        // advection velocity (EQ_ADVECTION)
     int nleaves, N;       // work items: leaves listed in work (or all leaves)
     const int *work;      // leaf indices to process (null: 0 .. nleaves-1)
     const int *leaf_member; // member forest of each leaf (indexes dt), or null
@@ -193,6 +200,20 @@ struct StageArgs {
     double *dt_out;
     unsigned long long *rate_out;
 };
+
+// Numerical flux in the +e_A direction between the left state UL and the
+// right state UR: Rusanov for Euler (Eq. 5); for scalar convection the same
+// formula with alpha = |vel_A| is the upwind flux.
+template <int D, int A, int EQ, typename T, class Args>
+__device__ __forceinline__ void num_flux(const Args &g, const T *UL, const T *UR, T gamma, T *Phi)
+{
+    if constexpr (EQ == EQ_ADVECTION) {
+        const T a = T(g.vel[A]);
+        Phi[0] = T(0.5) * (a * (UL[0] + UR[0]) - fabs(a) * (UR[0] - UL[0]));
+    } else {
+        rusanov<D, A, T>(UL, UR, gamma, Phi);
+    }
+}
 
 struct FillArgs {
     const double *u;

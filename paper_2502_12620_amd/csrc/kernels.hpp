@@ -73,11 +73,12 @@ __device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, lo
 // flux over the 2^(d-1) fine sub-faces at the fine Gauss points, with the
 // fine cells' own traces, and lifts it with its own basis evaluated at the
 // mapped points (tangential xi = (xi_fine + sigma)/2).
-template <int D, int P, int A, typename T>
-__device__ __forceinline__ void mortar_lift(const StageArgs &g, const T (&K)[D + 2][Tab<D, P>::NB],
-                                            T (&R)[D + 2][Tab<D, P>::NB], int side, const FaceLink L, int t, T scale)
+template <int D, int P, int A, int EQ, typename T>
+__device__ __forceinline__ void mortar_lift(const StageArgs &g, const T (&K)[nvar<D, EQ>()][Tab<D, P>::NB],
+                                            T (&R)[nvar<D, EQ>()][Tab<D, P>::NB], int side, const FaceLink L, int t,
+                                            T scale)
 {
-    constexpr int NV = D + 2, NB = Tab<D, P>::NB, Q = P + 1, NF = Tab<D, P>::NF;
+    constexpr int NV = nvar<D, EQ>(), NB = Tab<D, P>::NB, Q = P + 1, NF = Tab<D, P>::NF;
     constexpr int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2; // tangential axes, lower first
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N;
     const long sv = long(NB) * ncell;
@@ -117,8 +118,8 @@ __device__ __forceinline__ void mortar_lift(const StageArgs &g, const T (&K)[D +
                 }
                 Uc[v] = side > 0 ? ec + oc : ec - oc;
             }
-            if (side > 0) rusanov<D, A, T>(Uc, Uf, T(g.gamma), Phi);
-            else rusanov<D, A, T>(Uf, Uc, T(g.gamma), Phi);
+            if (side > 0) num_flux<D, A, EQ, T>(g, Uc, Uf, T(g.gamma), Phi);
+            else num_flux<D, A, EQ, T>(g, Uf, Uc, T(g.gamma), Phi);
             // +face: -int Phi phi ; -face: +int Phi phi with phi(-1) = (-1)^{m_A} phi(+1)
 #pragma unroll
             for (int v = 0; v < NV; ++v) {
@@ -178,11 +179,11 @@ __device__ __forceinline__ void split_any(int child, const T *k, T *gk)
 //    coarser neighbour cell (Eq. 16), the combine of the 2^d finer cells
 //    (Eq. 17), or at an outflow boundary the mirror image, whose trace is
 //    the own trace.
-template <int D, int P, int A, int GM, int FCH, typename T>
-__device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[D + 2][Tab<D, P>::NB], int leaf, int side,
-                                           int t, const FaceLink &L, int f0, T (&Tr)[FCH][D + 2])
+template <int D, int P, int A, int GM, int FCH, int NV, typename T>
+__device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[NV][Tab<D, P>::NB], int leaf, int side,
+                                           int t, const FaceLink &L, int f0, T (&Tr)[FCH][NV])
 {
-    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    constexpr int NB = Tab<D, P>::NB;
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
     const long sv = long(NB) * ncell;
     const int face = 2 * A + (side > 0);
@@ -388,10 +389,10 @@ constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
 // rate stay FP64).
 // One work item: slab `item` of the leaf list (all leaves, or the listed
 // ones), for the thread's cell.
-template <int D, int P, int GM, int OM, bool LIM, typename T>
+template <int D, int P, int GM, int OM, bool LIM, typename T, int EQ>
 __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int item, int total)
 {
-    constexpr int NV = D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
+    constexpr int NV = nvar<D, EQ>(), NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
     constexpr int FCH = face_chunk<D, P>();
     extern __shared__ double lds_d[];
     T *lds = reinterpret_cast<T *>(lds_d);
@@ -434,12 +435,16 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
             }
             U[v] = s;
         }
-        const T rinv = recip(U[0]);
-        const T p = pressure_r<D, T>(U, gm1, rinv);
+        T rinv = T(0), p = T(0);
+        if constexpr (EQ == EQ_EULER) {
+            rinv = recip(U[0]);
+            p = pressure_r<D, T>(U, gm1, rinv);
+        }
         static_for<0, D>([&](auto Ai) __attribute__((always_inline)) {
             constexpr int A = Ai;
             T F[NV];
-            euler_flux<D, A, T>(U, U[1 + A] * rinv, p, F);
+            if constexpr (EQ == EQ_ADVECTION) F[0] = T(g.vel[A]) * U[0];
+            else euler_flux<D, A, T>(U, U[1 + A] * rinv, p, F);
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] *= scale[A];
 #pragma unroll
@@ -473,8 +478,8 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
         const FaceLink Lp = g.links[leaf * 2 * D + 2 * A + 1];
         const bool mort_m = g.conservative && ia == 0 && Lm.type == dgamr::LINK_FINE;
         const bool mort_p = g.conservative && ia == N - 1 && Lp.type == dgamr::LINK_FINE;
-        if (mort_m) mortar_lift<D, P, A, T>(g, K, R, -1, Lm, t, sc);
-        if (mort_p) mortar_lift<D, P, A, T>(g, K, R, +1, Lp, t, sc);
+        if (mort_m) mortar_lift<D, P, A, EQ, T>(g, K, R, -1, Lm, t, sc);
+        if (mort_p) mortar_lift<D, P, A, EQ, T>(g, K, R, +1, Lp, t, sc);
         auto face_chunk_body = [&](auto cv) __attribute__((always_inline)) {
             const int f0 = int(cv) * FCH;
             // own traces of this chunk: + side to LDS, - side kept
@@ -498,7 +503,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                     T TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * nslab + lc - stride];
-                    rusanov<D, A, T>(TL, Tm[fi], gamma, Fm[fi]);
+                    num_flux<D, A, EQ, T>(g, TL, Tm[fi], gamma, Fm[fi]);
                 }
             } else if (ia > 0) { // slab edge inside the leaf: the layer below
 #pragma unroll
@@ -510,13 +515,13 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         trace_eo_mem<D, P, T>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
-                    rusanov<D, A, T>(TL, Tm[fi], gamma, Fm[fi]);
+                    num_flux<D, A, EQ, T>(g, TL, Tm[fi], gamma, Fm[fi]);
                 }
             } else if (!mort_m) {
                 T TL[FCH][NV];
-                far_traces<D, P, A, GM, FCH, T>(g, K, leaf, -1, t, Lm, f0, TL);
+                far_traces<D, P, A, GM, FCH, NV, T>(g, K, leaf, -1, t, Lm, f0, TL);
 #pragma unroll
-                for (int fi = 0; fi < FCH; ++fi) rusanov<D, A, T>(TL[fi], Tm[fi], gamma, Fm[fi]);
+                for (int fi = 0; fi < FCH; ++fi) num_flux<D, A, EQ, T>(g, TL[fi], Tm[fi], gamma, Fm[fi]);
             } else {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi)
@@ -547,11 +552,11 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         trace_eo_mem<D, P, T>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
                         TR[v] = e - o;
                     }
-                    rusanov<D, A, T>(TL, TR, gamma, Fp[fi]);
+                    num_flux<D, A, EQ, T>(g, TL, TR, gamma, Fp[fi]);
                 }
             } else if (!mort_p) {
                 T TR[FCH][NV];
-                far_traces<D, P, A, GM, FCH, T>(g, K, leaf, +1, t, Lp, f0, TR);
+                far_traces<D, P, A, GM, FCH, NV, T>(g, K, leaf, +1, t, Lp, f0, TR);
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
                     T TL[NV];
@@ -561,7 +566,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         trace_eo<D, P, T>(K[v], A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
-                    rusanov<D, A, T>(TL, TR[fi], gamma, Fp[fi]);
+                    num_flux<D, A, EQ, T>(g, TL, TR[fi], gamma, Fp[fi]);
                 }
             } else {
 #pragma unroll
@@ -632,21 +637,26 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
                 for (int m = 0; m < NB; ++m) Kn[v][m] = fma(a, g.un[base + v * sv + m * ncell], Kn[v][m]);
         }
-        if constexpr (LIM) limit_cell<D, P>(Kn, g.gamma);
+        if constexpr (LIM && EQ == EQ_EULER) limit_cell<D, P>(Kn, g.gamma);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = Kn[v][m];
         if (g.rate_out) {
             // CFL rate of the new state from its cell mean, folded over the block
-            double U[NV];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) U[v] = Kn[v][0];
-            const double rinv = 1.0 / U[0];
-            const double cs = sqrt(g.gamma * pressure_r<D>(U, g.gamma - 1.0, rinv) * rinv);
             double rate = 0.0;
+            if constexpr (EQ == EQ_ADVECTION) {
 #pragma unroll
-            for (int a2 = 0; a2 < D; ++a2) rate += (fabs(U[1 + a2] * rinv) + cs) / g.geo[leaf].h[a2];
+                for (int a2 = 0; a2 < D; ++a2) rate += fabs(g.vel[a2]) / g.geo[leaf].h[a2];
+            } else {
+                double U[NV];
+#pragma unroll
+                for (int v = 0; v < NV; ++v) U[v] = Kn[v][0];
+                const double rinv = 1.0 / U[0];
+                const double cs = sqrt(g.gamma * pressure_r<D>(U, g.gamma - 1.0, rinv) * rinv);
+#pragma unroll
+                for (int a2 = 0; a2 < D; ++a2) rate += (fabs(U[1 + a2] * rinv) + cs) / g.geo[leaf].h[a2];
+            }
             __syncthreads();
             lds_d[lc] = rate;
             __syncthreads();
@@ -667,21 +677,22 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 // walks the items with a stride of the grid size.  With a grid that is a
 // multiple of the XCD count every item a workgroup takes maps to the same
 // XCD's leaf range.
-template <int D, int P, int GM, int OM, bool LIM, typename T = double>
+template <int D, int P, int GM, int OM, bool LIM, typename T = double, int EQ = EQ_EULER>
 __global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, int rows)
 {
     const int total = g.nleaves * (g.N / rows);
-    for (int item = blockIdx.x; item < total; item += gridDim.x) stage_item<D, P, GM, OM, LIM, T>(g, rows, item, total);
+    for (int item = blockIdx.x; item < total; item += gridDim.x)
+        stage_item<D, P, GM, OM, LIM, T, EQ>(g, rows, item, total);
 }
 
 // ------------------------------------------------------------------ guard fill
 // One thread per guard cell (leaf, face, t): Eq. 15 copy, Eq. 16 split of the
 // coarser neighbour cell, Eq. 17 combine of the 2^d finer cells, outflow
 // mirror K_m (-1)^{m_axis}; written as coefficients or as face traces.
-template <int D, int P>
+template <int D, int P, int NV = D + 2>
 __global__ __launch_bounds__(256) void k_fill(FillArgs g)
 {
-    constexpr int NV = D + 2, NB = Tab<D, P>::NB, NF = Tab<D, P>::NF;
+    constexpr int NB = Tab<D, P>::NB, NF = Tab<D, P>::NF;
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
     const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= long(g.nfaces) * nfc) return;

@@ -37,6 +37,8 @@ __global__ __launch_bounds__(256) void k_limit(double *u, int N, long ncell_tota
 //  UNIFORM rho, u, v, w, p
 //  XWAVE   amplitude, u, period_x: rho = 1 + A sin(2 pi (x - u t)/Lx),
 //          velocity (u,0,0), p = 1
+//  COSINE  (scalar convection, Sec. 5.1) k, period_x, period_y, period_z,
+//          vel_x, vel_y, vel_z: u = prod_a [cos(2 pi k (x_a - vel_a t)/L_a) - 1]
 __device__ __forceinline__ double wrap_half(double d, double period)
 {
     if (period <= 0.0) return d;
@@ -51,6 +53,12 @@ __device__ void analytic(int kind, const IcParams &P, double t, double gamma, co
 {
     const double pi = 3.14159265358979323846;
     double vel[3] = {0.0, 0.0, 0.0}, rho = 1.0, p = 1.0;
+    if (kind == DGAMR_IC_COSINE) {
+        double prod = 1.0;
+        for (int a = 0; a < D; ++a) prod *= cos(2.0 * pi * P.p[0] * (x[a] - P.p[4 + a] * t) / P.p[1 + a]) - 1.0;
+        U[0] = prod;
+        return;
+    }
     if (kind == DGAMR_IC_VORTEX) {
         double eps = P.p[0];
         double dx = wrap_half(x[0] - P.p[1] - P.p[3] * t, P.p[5]);
@@ -102,12 +110,12 @@ template <int P>
 inline constexpr IcTab<P> kIcTab{};
 
 // K_m = (1/M_m) int phi_m U0 dV with p+3 Gauss points per axis
-template <int D, int P>
+template <int D, int P, int NV = D + 2>
 __global__ __launch_bounds__(256) void k_project_ic(double *u, const LeafGeo *geo, int N, long ncell_total, int kind,
                                                     IcParams prm, double t, double gamma, double hmin0, double hmin1,
                                                     double hmin2)
 {
-    constexpr int NV = D + 2, NB = Tab<D, P>::NB, QI = P + 3;
+    constexpr int NB = Tab<D, P>::NB, QI = P + 3;
     const int ncell = D == 2 ? N * N : N * N * N;
     const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= ncell_total) return;
@@ -131,7 +139,7 @@ __global__ __launch_bounds__(256) void k_project_ic(double *u, const LeafGeo *ge
             w *= kIcTab<P>.w[qi[a]];
             x[a] = G.lo[a] + (ijk[a] + 0.5 * (kIcTab<P>.x[qi[a]] + 1.0)) * G.h[a];
         }
-        double U[NV];
+        double U[D + 2];
         analytic<D>(kind, prm, t, gamma, x, hmin, U);
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
@@ -153,11 +161,11 @@ __global__ __launch_bounds__(256) void k_project_ic(double *u, const LeafGeo *ge
 // Eq. 11-14 on a refinement switch: copy, split (child cells of a refined
 // leaf from the parent cells) or combine (cells of a coarsened parent from
 // its 2^d children's cells).
-template <int D, int P>
+template <int D, int P, int NV = D + 2>
 __global__ __launch_bounds__(256) void k_inherit(const double *uold, double *unew, const Inherit *inh, int N,
                                                  long ncell_total)
 {
-    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    constexpr int NB = Tab<D, P>::NB;
     const int ncell = D == 2 ? N * N : N * N * N;
     const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= ncell_total) return;

@@ -117,10 +117,9 @@ static __global__ __launch_bounds__(256) void k_dt_members(const double *leaf_ma
 }
 
 // Per leaf partial totals sum_cells vol * mean_v, fixed tree order.
-template <int D>
+template <int D, int NV = D + 2>
 __global__ __launch_bounds__(256) void k_totals_leaf(const double *u, const LeafGeo *geo, int N, int nb, double *part)
 {
-    constexpr int NV = D + 2;
     __shared__ double red[NV][256];
     const int leaf = blockIdx.x, ncell = D == 2 ? N * N : N * N * N;
     const long sv = long(nb) * ncell, base = long(leaf) * NV * sv;
@@ -158,12 +157,12 @@ __global__ __launch_bounds__(256) void k_totals_final(const double *part, int n,
         for (int v = 0; v < NV; ++v) tot[v] = red[v][0];
 }
 
-// counts cells with a non-finite coefficient or non-positive mean density / pressure
-template <int D>
+// counts cells with a non-finite coefficient or (Euler) a non-positive mean
+// density or pressure
+template <int D, int NV = D + 2>
 __global__ __launch_bounds__(256) void k_check(const double *u, int N, int nb, long ncell_total, double gamma,
                                                unsigned long long *bad)
 {
-    constexpr int NV = D + 2;
     const int ncell = D == 2 ? N * N : N * N * N;
     long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= ncell_total) return;
@@ -173,18 +172,20 @@ __global__ __launch_bounds__(256) void k_check(const double *u, int N, int nb, l
     bool ok = true;
     for (int v = 0; v < NV; ++v)
         for (int m = 0; m < nb; ++m) ok = ok && isfinite(u[base + v * sv + m * ncell]);
-    double U[NV];
-    for (int v = 0; v < NV; ++v) U[v] = u[base + v * sv];
-    ok = ok && U[0] > 0.0 && pressure<D>(U, gamma - 1.0) > 0.0;
+    if constexpr (NV == D + 2) {
+        double U[NV];
+        for (int v = 0; v < NV; ++v) U[v] = u[base + v * sv];
+        ok = ok && U[0] > 0.0 && pressure<D>(U, gamma - 1.0) > 0.0;
+    }
     if (!ok) atomicAdd(bad, 1ULL);
 }
 
 // ------------------------------------------------------------------ indicator
-// eta = max / min density mean over the block's cells and face-guard cells
-template <int D>
+// Euler: eta = max / min density mean over the block's cells and face-guard
+// cells; scalar convection (Sec. 5.1): the largest cell mean there
+template <int D, int NV = D + 2>
 __global__ __launch_bounds__(256) void k_indicator_leaf(const double *u, const double *guard, int N, int nb, double *eta)
 {
-    constexpr int NV = D + 2;
     __shared__ double smax[256], smin[256];
     const int leaf = blockIdx.x, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
     const long sv = long(nb) * ncell, base = long(leaf) * NV * sv;
@@ -210,7 +211,20 @@ __global__ __launch_bounds__(256) void k_indicator_leaf(const double *u, const d
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) eta[leaf] = smax[0] / smin[0];
+    if (threadIdx.x == 0) eta[leaf] = NV == 1 ? smax[0] : smax[0] / smin[0];
+}
+
+// Scalar convection: per leaf sum_a |vel_a| / h_a (the CFL rate does not
+// depend on the state); one thread per leaf (or listed leaf).
+static __global__ __launch_bounds__(256) void k_rate_adv(const LeafGeo *geo, int n, double v0, double v1, double v2,
+                                                         int dim, double *leaf_max)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double v[3] = {v0, v1, v2};
+    double rate = 0.0;
+    for (int a = 0; a < dim; ++a) rate += fabs(v[a]) / geo[i].h[a];
+    leaf_max[i] = rate;
 }
 
 } // namespace dgk

@@ -24,21 +24,21 @@ struct StageShape {
 // OUT_RES32 or OUT_RK).
 template <int D, int P>
 hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool limiter, bool fp32,
-                        const StageShape &shape, hipStream_t s);
+                        const StageShape &shape, hipStream_t s, int equation = EQ_EULER);
 // rows the thread-per-cell stage kernel accepts for block size N: divisors
 // of N whose slab fits the kernel's thread budget, largest first
 template <int D, int P>
 int stage_rows_options(int N, int *rows, int max_options);
 // guard fill: one thread per guard cell of the listed faces
 template <int D, int P>
-hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s);
+hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s, int nv = D + 2);
 template <int D, int P>
 hipError_t launch_limit(double *u, int N, long ncell_total, double gamma, hipStream_t s);
 template <int D, int P>
 hipError_t launch_project_ic(double *u, const LeafGeo *geo, int N, long ncell_total, int kind, const IcParams &prm,
-                             double t, double gamma, const double *hmin, hipStream_t s);
+                             double t, double gamma, const double *hmin, hipStream_t s, int nv = D + 2);
 template <int D, int P>
 hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, int N, long ncell_total,
-                          hipStream_t s);
+                          hipStream_t s, int nv = D + 2);
 
 } // namespace dgk

@@ -192,6 +192,7 @@ int dgamr_pool_create(const dgamr_forest_desc *cls, int64_t capacity_leaves, int
         std::string err;
         int rc = dgamr::Forest::validate(d, err);
         if (rc != DGAMR_OK) return fail(rc, err);
+        if (cls->equation != DGAMR_EQ_EULER) return fail(DGAMR_EUNSUPPORTED, "pools hold Euler forests");
         auto *p = new dgamr_pool;
         p->cls = *cls;
         p->dim = cls->dim;

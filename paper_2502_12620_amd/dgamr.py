@@ -20,7 +20,8 @@ BC_PERIODIC, BC_OUTFLOW = 0, 1
 FP64, FP32_MFMA = 0, 1
 HANG_PAPER, HANG_CONSERVATIVE = 0, 1
 LIMITER_NONE, LIMITER_POSITIVITY = 0, 1
-IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE = 0, 1, 2, 3
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE = 0, 1, 2, 3, 4
+EQ_EULER, EQ_ADVECTION = 0, 1
 TUNE_STAGE_VARIANT, TUNE_VAR_SPLIT_MAX_CELLS = 0, 1
 
 EXPORTS = [
@@ -48,6 +49,7 @@ class ForestDesc(ctypes.Structure):
         ("roots", ctypes.c_int * 3), ("lo", ctypes.c_double * 3), ("hi", ctypes.c_double * 3),
         ("bc", ctypes.c_int * 3), ("max_level", ctypes.c_int), ("gamma", ctypes.c_double),
         ("precision", ctypes.c_int), ("hanging", ctypes.c_int), ("limiter", ctypes.c_int),
+        ("equation", ctypes.c_int), ("velocity", ctypes.c_double * 3),
     ]
 
 
@@ -127,7 +129,8 @@ class Forest:
     """A device-resident forest of DG blocks (``dgamr_forest``)."""
 
     def __init__(self, dim, degree, n_cell, roots, lo, hi, bc, max_level, gamma=1.4,
-                 precision=FP64, hanging=HANG_PAPER, limiter=LIMITER_NONE):
+                 precision=FP64, hanging=HANG_PAPER, limiter=LIMITER_NONE, equation=EQ_EULER,
+                 velocity=(1.0, 1.0, 1.0)):
         d = ForestDesc()
         d.dim, d.degree, d.n_cell = dim, degree, n_cell
         roots, lo, hi, bc = (list(x) for x in (roots, lo, hi, bc))
@@ -138,9 +141,13 @@ class Forest:
             d.bc[a] = bc[a] if a < dim else BC_PERIODIC
         d.max_level, d.gamma = max_level, gamma
         d.precision, d.hanging, d.limiter = precision, hanging, limiter
+        d.equation = equation
+        for a in range(3):
+            d.velocity[a] = velocity[a] if a < len(velocity) else 0.0
         self.desc = d
         self.dim, self.degree, self.N = dim, degree, n_cell
-        self.nv = dim + 2
+        self.equation = equation
+        self.nv = 1 if equation == EQ_ADVECTION else dim + 2
         self.nb = {2: [1, 3, 6, 10], 3: [1, 4, 10, 20]}[dim][degree]
         self.precision = precision
         h = ctypes.c_void_p()

@@ -11,10 +11,14 @@
         the batched workload: independent 2-D forests in one pool per degree,
         autotuned, one HIP graph per batch of steps; batch wall time p50/p99
         and DOF-stage/s against the same forests solved one after another;
+    python -m paper_2502_12620_amd.measure convection [--dim 2 --degree 2 --n-cell 8]
+        the scalar convection workload (Sec. 5.1) with indicator-driven
+        regrids to t_end: DOF-stage/s and the L2 distance to the projected
+        exact solution;
     python -m paper_2502_12620_amd.measure sedov
         the 3-D blast workload end to end (limiter, regrid every 10 steps)
         with FP64 and with FP32 residuals, and their L1 / L2 difference;
-    python -m paper_2502_12620_amd.measure serve [--requests 100]
+    python -m paper_2502_12620_amd.measure serve [--requests 40]
         the served workload: a Poisson stream of 2-D/3-D solves through the
         continuous-batching request loop; latency p50/p99 and DOF-stage/s
         against plain sequential solves of the same requests.
@@ -255,13 +259,95 @@ def cmd_sedov(args):
     print(json.dumps(out), flush=True)
 
 
+def _ref_mass(dim, degree):
+    """Reference-cell mass of each basis mode, prod_a 2/(2 m_a + 1), graded
+    mode order (total degree |m| ascending, then m_x, m_y descending)."""
+    out = []
+    for s in range(degree + 1):
+        for mx in range(s, -1, -1):
+            if dim == 2:
+                out.append((2 / (2 * mx + 1)) * (2 / (2 * (s - mx) + 1)))
+            else:
+                for my in range(s - mx, -1, -1):
+                    out.append((2 / (2 * mx + 1)) * (2 / (2 * my + 1)) * (2 / (2 * (s - mx - my) + 1)))
+    return out
+
+
+def cmd_convection(args):
+    """The scalar convection workload of Sec. 5.1 on the GPU: regrids by the
+    block indicator, SSP-RK3 to t_end (last step shortened to land on it),
+    DOF-stage/s, and the L2 distance between the solution and the L2
+    projection of the exact (translated) solution on the final forest."""
+    w = W.convection_2d(degree=args.degree, n_cell=args.n_cell) if args.dim == 2 else \
+        W.convection_3d(degree=args.degree, n_cell=args.n_cell)
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma,
+                 equation=G.EQ_ADVECTION, velocity=w.velocity[:w.dim])
+    z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
+    for rule in w.initial_refinement:
+        z = f.adapt(rule(w, f.keys()), z)
+    u = f.project_ic(G.IC_COSINE, w.ic_params)
+    work, dt = f.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    t, steps, dof_stages, regrids = 0.0, 0, 0, 0
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    while t < w.t_end - 1e-14:
+        if w.regrid_every and steps % w.regrid_every == 0:
+            eta = f.indicator(u, work).cpu().numpy()
+            flags = W.regrid_flags(w, f.keys(), eta)
+            if (flags != 0).any():
+                u = f.adapt(flags, u)
+                work = f.new_work()
+                regrids += 1
+        f.compute_dt(w.cfl, u, dt, work)
+        h = float(dt.item())
+        if t + h > w.t_end:
+            dt.fill_(w.t_end - t)
+            h = w.t_end - t
+        f.step(u, work, dt, cfl=0.0)
+        t += h
+        steps += 1
+        dof_stages += 3 * w.dofs(f.n_leaves)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - start
+    ex = f.project_ic(G.IC_COSINE, w.ic_params, t=w.t_end)
+    vol = torch.tensor([g for g in _leaf_volumes(f, w)], dtype=torch.float64, device="cuda")
+    mass = torch.tensor(_ref_mass(w.dim, w.degree), dtype=torch.float64, device="cuda")
+    d2 = ((u - ex) ** 2 * mass[None, None, :, None]).sum(dim=(1, 2, 3))
+    l2 = float(torch.sqrt((d2 * vol / 2 ** w.dim).sum()))
+    out = {"workload": w.name, "degree": w.degree, "n_cell": w.n_cell, "t_end": w.t_end, "steps": steps,
+           "regrids": regrids, "final_leaves": f.n_leaves, "wall_s": el, "dof_stage_per_s": dof_stages / el,
+           "l2_to_projected_exact": l2}
+    print(json.dumps(out), flush=True)
+
+
+def _leaf_volumes(f, w):
+    """Cell volume of every leaf, from the keys (level) and the root box."""
+    keys = f.keys()
+    root = [(w.hi[a] - w.lo[a]) / w.roots[a] for a in range(w.dim)]
+    out = []
+    for k in keys:
+        v = 1.0
+        for a in range(w.dim):
+            v *= root[a] / 2 ** (int(k[1]) - 1) / w.n_cell
+        out.append(v)
+    return out
+
+
 def cmd_serve(args):
     from .serve import Request, Server
 
     reqs = [Request(i, t, w) for i, (t, w) in enumerate(W.served_requests(args.requests, seed=12620, rate=args.rate))]
     classes = sorted({(r.workload.dim, r.workload.degree, r.workload.n_cell) for r in reqs})
     srv = Server(classes, hbm_budget=args.budget_gb * 1e9, max_members=256, tune=args.tune)
-    done = srv.run(reqs)
+    total_work = sum(r.workload.dofs(math.prod(r.workload.roots)) * 3 * r.workload.steps for r in reqs)
+    print(json.dumps({"progress": "serving", "requests": len(reqs), "dof_stage_total": total_work}), flush=True)
+
+    def progress(r):
+        n = sum(1 for q in reqs if q.done >= 0)
+        if n % 5 == 0 or n == len(reqs):
+            print(json.dumps({"progress": "served", "done": n, "t_s": round(r.done, 3)}), flush=True)
+
+    done = srv.run(reqs, on_done=progress)
     lat = [r.done - r.arrival for r in done]
     work = sum(r.dofs * 3 * r.workload.steps for r in done)
     out = {"workload": f"served_{args.requests}_requests", "requests": len(done), "rate_per_s": args.rate,
@@ -283,6 +369,8 @@ def cmd_serve(args):
         torch.cuda.synchronize()
         service[r.rid] = time.perf_counter() - t0
         del f, u, work_buf
+        if len(service) % 5 == 0:
+            print(json.dumps({"progress": "sequential", "done": len(service)}), flush=True)
     clock, seq_lat = 0.0, []
     for r in sorted(done, key=lambda r: r.arrival):
         start = max(clock, r.arrival)
@@ -309,14 +397,19 @@ def main(argv=None):
     b.add_argument("--repeats", type=int, default=20)
     b.add_argument("--precision", choices=["fp64", "fp32"], default="fp64")
     sub.add_parser("sedov")
+    c2 = sub.add_parser("convection")
+    c2.add_argument("--dim", type=int, default=2)
+    c2.add_argument("--degree", type=int, default=2)
+    c2.add_argument("--n-cell", type=int, default=8)
     v = sub.add_parser("serve")
-    v.add_argument("--requests", type=int, default=100)
+    v.add_argument("--requests", type=int, default=40)
     v.add_argument("--rate", type=float, default=200.0)
     v.add_argument("--budget-gb", type=float, default=96.0)
     v.add_argument("--tune", action="store_true")
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    {"sweep": cmd_sweep, "copy": cmd_copy, "batch": cmd_batch, "serve": cmd_serve, "sedov": cmd_sedov}[args.cmd](args)
+    {"sweep": cmd_sweep, "copy": cmd_copy, "batch": cmd_batch, "serve": cmd_serve, "sedov": cmd_sedov,
+     "convection": cmd_convection}[args.cmd](args)
 
 
 if __name__ == "__main__":

@@ -102,9 +102,10 @@ class Server:
         c.members[mid] = _Member(req, f, mid, first, f.n_leaves, w.steps)
         return True
 
-    def run(self, requests, clock=time.perf_counter):
+    def run(self, requests, clock=time.perf_counter, on_done=None):
         """Serve the requests (sorted by arrival) until all are done; returns
-        them with admitted / done times (seconds after the start)."""
+        them with admitted / done times (seconds after the start).  on_done,
+        if given, is called with each finished request."""
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         total = len(pending)
         finished = []
@@ -157,6 +158,8 @@ class Server:
                         m.req.done = now
                         finished.append(m.req)
                         del c.members[mid]
+                        if on_done is not None:
+                            on_done(m.req)
             if self.keep:
                 for c in active:
                     c.stream.synchronize()

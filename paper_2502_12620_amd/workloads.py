@@ -14,7 +14,8 @@ from dataclasses import dataclass, field
 import numpy as np
 
 PERIODIC, OUTFLOW = 0, 1
-IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE = 0, 1, 2, 3
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE = 0, 1, 2, 3, 4
+EQ_EULER, EQ_ADVECTION = 0, 1
 
 
 @dataclass
@@ -39,6 +40,10 @@ class Workload:
     coarsen_below: float = 1.01
     # list of refinement passes; each pass maps leaf keys -> flags
     initial_refinement: list = field(default_factory=list)
+    equation: int = EQ_EULER
+    velocity: tuple = (1.0, 1.0, 1.0)
+    t_end: float = 0.0
+    min_level: int = 1
 
     def desc(self) -> dict:
         return dict(dim=self.dim, degree=self.degree, n_cell=self.n_cell, roots=self.roots, lo=self.lo,
@@ -60,7 +65,8 @@ class Workload:
 
     def dofs(self, n_leaves) -> int:
         nb = math.comb(self.degree + self.dim, self.dim)
-        return n_leaves * (self.dim + 2) * nb * self.n_cell ** self.dim
+        nv = 1 if self.equation == EQ_ADVECTION else self.dim + 2
+        return n_leaves * nv * nb * self.n_cell ** self.dim
 
 
 def refine_roots_near(centre, radius):
@@ -72,6 +78,11 @@ def refine_roots_near(centre, radius):
             fl.append(1 if np.hypot(*(c - np.asarray(centre))) <= radius else 0)
         return np.array(fl, dtype=np.int8)
     return rule
+
+
+def refine_all(w: Workload, keys):
+    """Flags +1 for every leaf."""
+    return np.ones(len(keys), dtype=np.int8)
 
 
 def refine_touching(point, level=None):
@@ -112,6 +123,40 @@ def sedov_c3() -> Workload:
                     (OUTFLOW, OUTFLOW, OUTFLOW), 3, IC_SEDOV, [1e-5, 1e3, 0.5, 0.5, 0.5], 100,
                     limiter=True, regrid_every=10,
                     initial_refinement=[refine_touching(c), refine_touching(c, level=2)])
+
+
+def convection_2d(degree: int = 2, n_cell: int = 8) -> Workload:
+    """Linear scalar convection (Sec. 5.1, first root set): one square root
+    block on the periodic [0,1]^2, velocity (1,1), u0 = [cos(2 pi x) - 1]
+    [cos(2 pi y) - 1], refinement levels 3..5 driven by the block's largest
+    cell average (refine above 3.0, coarsen below 1.0) every 10 steps,
+    SSP-RK3 at CFL 0.1 to t = 1.  Degree and block size are not given in
+    the paper; degree 2 with 8x8-cell blocks here."""
+    w = Workload("f1_convection2d", 2, degree, n_cell, (1, 1), (0.0, 0.0), (1.0, 1.0), (PERIODIC, PERIODIC), 5,
+                 IC_COSINE, [1.0, 1.0, 1.0, 1.0], 0, regrid_every=10, refine_above=3.0, coarsen_below=1.0,
+                 initial_refinement=[refine_all, refine_all])
+    w.equation, w.velocity, w.t_end, w.min_level = EQ_ADVECTION, (1.0, 1.0, 0.0), 1.0, 3
+    return w
+
+
+def convection_3d(degree: int = 1, n_cell: int = 4) -> Workload:
+    """Linear scalar convection in 3-D (Sec. 5.1): one root block on the
+    periodic [0,1]^3 refined to level 4, u0 = prod [cos(4 pi x_a) - 1],
+    velocity (1,1,1), to t = 0.25."""
+    w = Workload("f1_convection3d", 3, degree, n_cell, (1, 1, 1), (0.0,) * 3, (1.0,) * 3, (PERIODIC,) * 3, 4,
+                 IC_COSINE, [2.0, 1.0, 1.0, 1.0], 0, initial_refinement=[refine_all, refine_all, refine_all])
+    w.equation, w.velocity, w.t_end, w.min_level = EQ_ADVECTION, (1.0, 1.0, 1.0), 0.25, 4
+    return w
+
+
+def regrid_flags(w: Workload, keys, eta):
+    """Refinement flags of the convection workloads from the block
+    indicator: +1 above refine_above, -1 below coarsen_below, never below
+    the minimum level."""
+    flags = np.where(eta > w.refine_above, 1, np.where(eta < w.coarsen_below, -1, 0)).astype(np.int8)
+    levels = np.asarray(keys)[:, 1]
+    flags[(flags < 0) & (levels <= w.min_level)] = 0
+    return flags
 
 
 def roofline_2d(k: int, degree: int) -> Workload:
