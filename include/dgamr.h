@@ -202,8 +202,11 @@ int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work
  *     0 one lane per (cell, variable) in row slabs (latency-bound small
  *     forests), 1 one thread per cell (throughput on large forests);
  *   DGAMR_TUNE_VAR_SPLIT_MAX_CELLS: the automatic choice uses variant 0 up
- *     to this many cells (default 131072). */
-enum { DGAMR_TUNE_STAGE_VARIANT = 0, DGAMR_TUNE_VAR_SPLIT_MAX_CELLS = 1 };
+ *     to this many cells (default 131072);
+ *   DGAMR_TUNE_SLAB_ROWS: layers of the block's last axis per stage
+ *     workgroup (0 automatic, else a divisor of n_cell within the kernel's
+ *     thread budget; a launch that does not fit fails with DGAMR_EHIP). */
+enum { DGAMR_TUNE_STAGE_VARIANT = 0, DGAMR_TUNE_VAR_SPLIT_MAX_CELLS = 1, DGAMR_TUNE_SLAB_ROWS = 2 };
 int dgamr_set_tuning(dgamr_forest *f, int knob, long value);
 
 /* Measurement hook: while enabled, every launch of the fused stage kernel

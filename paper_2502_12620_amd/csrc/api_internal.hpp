@@ -77,6 +77,7 @@ struct dgamr_forest {
     bool prof = false;       // bracket stage launches with events
     int stage_variant = -1;  // 2-D stage kernel: -1 auto, 0 lane per (cell, var), 1 thread per cell
     long var_split_max_cells = 131072; // auto: lane per (cell, var) up to this many cells
+    int slab_rows = 0;       // layers of the last axis per stage workgroup, 0 = automatic
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
     long version = 0;        // bumped by every topology change

@@ -112,6 +112,7 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
     dgk::StageShape sh;
     sh.variant = stage_variant(f);
+    sh.rows = f->slab_rows;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
         HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, fp32, sh, s, eq)));
         return DGAMR_OK;
@@ -604,6 +605,11 @@ int dgamr_set_tuning(dgamr_forest *f, int knob, long value)
     } else if (knob == DGAMR_TUNE_VAR_SPLIT_MAX_CELLS) {
         if (value < 0) return fail(DGAMR_EINVAL, "cell count must be >= 0");
         f->var_split_max_cells = value;
+    } else if (knob == DGAMR_TUNE_SLAB_ROWS) {
+        const int N = f->topo.desc().n_cell;
+        if (value < 0 || value > N || (value > 0 && N % value != 0))
+            return fail(DGAMR_EINVAL, "slab rows must be 0 or a divisor of n_cell");
+        f->slab_rows = int(value);
     } else {
         return fail(DGAMR_EINVAL, "unknown tuning knob");
     }

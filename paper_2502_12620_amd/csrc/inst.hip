@@ -17,11 +17,16 @@ namespace dgk {
 // 2-D without the limiter: one lane per (cell, variable), a slab of rows
 // per workgroup, with enough slabs to give every compute unit work.
 template <int P>
-hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s)
+hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s, int rows_req)
 {
     int rows = a.N;
-    while (rows * a.N * 4 > 512) rows /= 2;
-    while (rows % 2 == 0 && rows > 1 && long(a.nleaves) * (a.N / rows) < 256) rows /= 2;
+    if (rows_req > 0) {
+        if (a.N % rows_req != 0 || rows_req * a.N * 4 > 512) return hipErrorInvalidValue;
+        rows = rows_req;
+    } else {
+        while (rows * a.N * 4 > 512) rows /= 2;
+        while (rows % 2 == 0 && rows > 1 && long(a.nleaves) * (a.N / rows) < 256) rows /= 2;
+    }
     const int slabs = a.N / rows;
     const size_t lds = sizeof(double) * (P + 1) * rows * a.N * 4;
     const dim3 grid(unsigned(a.nleaves * slabs)), block(rows * a.N * 4);
@@ -110,7 +115,7 @@ hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32,
     if constexpr (D == 2) {
         // one lane per (cell, variable) unless the caller asks for one
         // thread per cell (variant 1), needs the limiter or a work list
-        if (!lim && !a.work && (sh.variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s);
+        if (!lim && !a.work && (sh.variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s, sh.rows);
     }
     return launch_stage_cell<D, P, double>(a, gm, om, lim, sh, s);
 }

@@ -22,7 +22,7 @@ HANG_PAPER, HANG_CONSERVATIVE = 0, 1
 LIMITER_NONE, LIMITER_POSITIVITY = 0, 1
 IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE = 0, 1, 2, 3, 4
 EQ_EULER, EQ_ADVECTION = 0, 1
-TUNE_STAGE_VARIANT, TUNE_VAR_SPLIT_MAX_CELLS = 0, 1
+TUNE_STAGE_VARIANT, TUNE_VAR_SPLIT_MAX_CELLS, TUNE_SLAB_ROWS = 0, 1, 2
 
 EXPORTS = [
     "dgamr_create_forest", "dgamr_destroy_forest", "dgamr_num_leaves", "dgamr_leaf_keys",

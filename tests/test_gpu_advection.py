@@ -93,7 +93,10 @@ def test_project_totals_indicator_run(dim):
     assert rel_diff(_host(ud), u).max() <= TOL
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
     np.testing.assert_allclose(_host(gpu.conserved_totals(ud, work)), orc.totals(u), rtol=1e-14, atol=1e-16)
-    np.testing.assert_allclose(_host(gpu.indicator(ud, work)), orc.indicator(u), rtol=1e-15)
+    # the indicator's maximum may come from a face-guard cell, which the two
+    # sides compute by different exact operators (mat-vec vs quadrature):
+    # the guard-cell tolerance of 1e-13 applies
+    np.testing.assert_allclose(_host(gpu.indicator(ud, work)), orc.indicator(u), rtol=1e-13)
     assert gpu.check_state(ud, work) == 0
     t0 = orc.totals(u)
     for _ in range(6):
