@@ -39,19 +39,19 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s, in
     return hipGetLastError();
 }
 
-template <int D, int P>
+template <int D, int P, typename T>
 bool rows_ok(int N, int rows)
 {
     const int layer = D == 2 ? N : N * N;
-    return rows >= 1 && N % rows == 0 && rows * layer <= stage_threads<D, P>();
+    return rows >= 1 && N % rows == 0 && rows * layer <= stage_threads<D, P, T>();
 }
 
 template <int D, int P>
-int stage_rows_options(int N, int *rows, int max_options)
+int stage_rows_options(int N, int *rows, int max_options, bool fp32)
 {
     int n = 0;
     for (int r = N; r >= 1 && n < max_options; --r)
-        if (rows_ok<D, P>(N, r)) rows[n++] = r;
+        if (fp32 ? rows_ok<D, P, float>(N, r) : rows_ok<D, P, double>(N, r)) rows[n++] = r;
     return n;
 }
 
@@ -63,42 +63,52 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     int rows = sh.rows;
     if (rows == 0) {
         rows = a.N;
-        while (rows % 2 == 0 && rows * layer > stage_threads<D, P>()) rows /= 2;
+        while (rows % 2 == 0 && rows * layer > stage_threads<D, P, T>()) rows /= 2;
     }
-    if (!rows_ok<D, P>(a.N, rows)) return hipErrorInvalidValue;
+    if (!rows_ok<D, P, T>(a.N, rows)) return hipErrorInvalidValue;
     const int nslab = rows * layer;
     const long items = long(a.nleaves) * (a.N / rows);
     const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * nslab;
-    const dim3 grid(unsigned(sh.grid > 0 && sh.grid < items ? sh.grid : items)), block(nslab);
+    const bool persist = sh.grid > 0 && sh.grid < items;
+    // the persistent shape applies to the fused Euler stage (pools); every
+    // other launch takes one workgroup per item
+    const dim3 grid(unsigned(persist ? sh.grid : items)), block(nslab);
+    const dim3 grid_all = dim3(unsigned(items));
     // the fused 3-D stage reads every block face as traces from the guard
     // buffer (the step runs the fill kernel first); the fused 2-D stage
     // takes the far side inline
     if constexpr (EQ == EQ_ADVECTION) {
         // one variable: the far side is always taken inline
         if (gm == GUARD_INLINE && om == OUT_RK) {
-            hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, false, T, EQ>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_INLINE, OUT_RK, false, T, EQ>), grid_all, block, lds, s, a, rows);
             return hipGetLastError();
         }
         if (gm == GUARD_BUFFER && om == OUT_RES64) {
-            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false, T, EQ>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false, T, EQ>), grid_all, block, lds, s, a, rows);
             return hipGetLastError();
         }
         return hipErrorInvalidValue;
     }
     constexpr int GMRK = D == 3 ? GUARD_TRACE : GUARD_INLINE;
     if (gm == GMRK && om == OUT_RK) {
-        if (lim) hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T>), grid, block, lds, s, a, rows);
-        else hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T>), grid, block, lds, s, a, rows);
+        if (persist && lim)
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T, EQ_EULER, true>), grid, block, lds, s, a, rows);
+        else if (persist)
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T, EQ_EULER, true>), grid, block, lds, s, a, rows);
+        else if (lim)
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T>), grid, block, lds, s, a, rows);
+        else
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T>), grid, block, lds, s, a, rows);
         return hipGetLastError();
     }
     if constexpr (std::is_same<T, float>::value) {
         if (gm == GUARD_BUFFER && om == OUT_RES32) {
-            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false, T>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false, T>), grid_all, block, lds, s, a, rows);
             return hipGetLastError();
         }
     } else if constexpr (D == 3) { // the 2-D FP64 residual runs one lane per (cell, variable)
         if (gm == GUARD_BUFFER && om == OUT_RES64) {
-            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false, T>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false, T>), grid_all, block, lds, s, a, rows);
             return hipGetLastError();
         }
     }
@@ -163,7 +173,7 @@ hipError_t launch_inherit(const double *uold, double *unew, const Inherit *inh, 
 
 template hipError_t launch_stage<DG_D, DG_P>(const StageArgs &, int, int, bool, bool, const StageShape &, hipStream_t,
                                              int);
-template int stage_rows_options<DG_D, DG_P>(int, int *, int);
+template int stage_rows_options<DG_D, DG_P>(int, int *, int, bool);
 template hipError_t launch_fill<DG_D, DG_P>(const FillArgs &, int, hipStream_t, int);
 template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStream_t);
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,

@@ -379,9 +379,10 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 // 256 cells, so a thread may keep its cell's state and residual in up to
 // 512 registers); faces on a slab edge inside the leaf read the adjacent
 // layer straight from the stage input.
-// threads per workgroup: 3-D degree <= 1 keeps whole 512-cell leaves (its
+// threads per workgroup: 3-D degree <= 1 keeps whole 512-cell leaves (the
 // state fits 256 registers); every other case uses slabs of <= 256 cells
-template <int D, int P>
+// (3-D degree 2 in FP32 at 512 threads spills ~600 bytes per lane)
+template <int D, int P, typename T = double>
 constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
 
 // T is the arithmetic type of the residual: double, or float for the FP32
@@ -622,13 +623,25 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
         const double a = g.rk_a, b = g.rk_b;
         // FP64 update; the FP32 path re-reads U_s at full precision
         double Kn[NV][NB];
+        if constexpr (std::is_same<T, double>::value) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m) {
-                const double us = std::is_same<T, double>::value ? double(K[v][m]) : g.us[base + v * sv + m * ncell];
-                Kn[v][m] = b * (us + dt * double(R[v][m]));
-            }
+                for (int m = 0; m < NB; ++m) Kn[v][m] = b * (K[v][m] + dt * R[v][m]);
+        } else if (b != 0.0) {
+            // FP32 path: U_s again at full precision; inside a (uniform)
+            // branch so that its loads are issued here, not held in
+            // registers through the residual
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int m = 0; m < NB; ++m) Kn[v][m] = b * (g.us[base + v * sv + m * ncell] + dt * double(R[v][m]));
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int m = 0; m < NB; ++m) Kn[v][m] = 0.0;
+        }
         // stages 2 and 3 add the RK base state; a uniform branch keeps its
         // loads here, after the residual, instead of live through it
         if (a != 0.0) {
@@ -672,17 +685,21 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
     }
 }
 
-// The stage kernel: one workgroup per (leaf, slab) work item, or, with a
-// grid smaller than the item count (a persistent launch), each workgroup
-// walks the items with a stride of the grid size.  With a grid that is a
+// The stage kernel: one workgroup per (leaf, slab) work item, or (PERSIST,
+// a grid smaller than the item count) each workgroup walks the items with
+// a stride of the grid size.  With a grid that is a
 // multiple of the XCD count every item a workgroup takes maps to the same
 // XCD's leaf range.
-template <int D, int P, int GM, int OM, bool LIM, typename T = double, int EQ = EQ_EULER>
-__global__ __launch_bounds__((stage_threads<D, P>())) void k_stage(StageArgs g, int rows)
+template <int D, int P, int GM, int OM, bool LIM, typename T = double, int EQ = EQ_EULER, bool PERSIST = false>
+__global__ __launch_bounds__((stage_threads<D, P, T>())) void k_stage(StageArgs g, int rows)
 {
     const int total = g.nleaves * (g.N / rows);
-    for (int item = blockIdx.x; item < total; item += gridDim.x)
-        stage_item<D, P, GM, OM, LIM, T, EQ>(g, rows, item, total);
+    if constexpr (PERSIST) {
+        for (int item = blockIdx.x; item < total; item += gridDim.x)
+            stage_item<D, P, GM, OM, LIM, T, EQ>(g, rows, item, total);
+    } else { // one item per workgroup: no loop to hold values across items
+        stage_item<D, P, GM, OM, LIM, T, EQ>(g, rows, blockIdx.x, total);
+    }
 }
 
 // ------------------------------------------------------------------ guard fill

@@ -28,7 +28,7 @@ hipError_t launch_stage(const StageArgs &a, int guard_mode, int out_mode, bool l
 // rows the thread-per-cell stage kernel accepts for block size N: divisors
 // of N whose slab fits the kernel's thread budget, largest first
 template <int D, int P>
-int stage_rows_options(int N, int *rows, int max_options);
+int stage_rows_options(int N, int *rows, int max_options, bool fp32);
 // guard fill: one thread per guard cell of the listed faces
 template <int D, int P>
 hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s, int nv = D + 2);

@@ -371,7 +371,7 @@ int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid)
     if (rows > 0) {
         int opts[16];
         int n = dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
-            return dgk::stage_rows_options<D, P>(p->N, opts, 16);
+            return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32_MFMA);
         });
         if (std::find(opts, opts + n, rows) == opts + n) return fail(DGAMR_EINVAL, "rows not allowed for this class");
     }
@@ -390,7 +390,7 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
         if (p->nwork == 0) return fail(DGAMR_ESTATE, "pool has no members to tune on");
         int opts[16];
         const int nopt = dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
-            return dgk::stage_rows_options<D, P>(p->N, opts, 16);
+            return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32_MFMA);
         });
         PoolWork w = carve(p, work);
         CHECK(pool_dt(p, u_arena, w, stream));
