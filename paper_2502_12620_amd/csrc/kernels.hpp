@@ -384,6 +384,10 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 // (3-D degree 2 in FP32 at 512 threads spills ~600 bytes per lane)
 template <int D, int P, typename T = double>
 constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
+// waves per SIMD the register budget is cut for (2-D degree 2 in FP64
+// spills 44 bytes per lane to run two waves per SIMD instead of one)
+template <int D, int P, typename T = double>
+constexpr int stage_min_waves() { return (D == 2 && P == 2 && sizeof(T) == 8) ? 2 : 1; }
 
 // T is the arithmetic type of the residual: double, or float for the FP32
 // path (state read as FP64 and rounded; the stage update, limiter and CFL
@@ -691,7 +695,8 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 // multiple of the XCD count every item a workgroup takes maps to the same
 // XCD's leaf range.
 template <int D, int P, int GM, int OM, bool LIM, typename T = double, int EQ = EQ_EULER, bool PERSIST = false>
-__global__ __launch_bounds__((stage_threads<D, P, T>())) void k_stage(StageArgs g, int rows)
+__global__ __launch_bounds__((stage_threads<D, P, T>()), (stage_min_waves<D, P, T>())) void k_stage(StageArgs g,
+                                                                                                     int rows)
 {
     const int total = g.nleaves * (g.N / rows);
     if constexpr (PERSIST) {
