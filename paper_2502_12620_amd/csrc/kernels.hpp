@@ -384,10 +384,19 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 // (3-D degree 2 in FP32 at 512 threads spills ~600 bytes per lane)
 template <int D, int P, typename T = double>
 constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
-// waves per SIMD the register budget is cut for (2-D degree 2 in FP64
-// spills 44 bytes per lane to run two waves per SIMD instead of one)
+// waves per SIMD the register budget is cut for, chosen by measurement on
+// large forests: 2-D degree 1 in FP32 fits 128 registers (four waves);
+// 2-D degree 2 in FP64 spills 44 bytes per lane to run two waves per SIMD
+// instead of one (-20% time); 2-D degree 3 in FP32 runs two waves with 212
+// bytes of spills (-18%), while in FP64 (536 bytes) that is slower
 template <int D, int P, typename T = double>
-constexpr int stage_min_waves() { return (D == 2 && P == 2 && sizeof(T) == 8) ? 2 : 1; }
+constexpr int stage_min_waves()
+{
+    if (D != 2) return 1;
+    if (P == 1) return sizeof(T) == 4 ? 4 : 1;
+    if (P == 2) return 2;
+    return P == 3 && sizeof(T) == 4 ? 2 : 1;
+}
 
 // T is the arithmetic type of the residual: double, or float for the FP32
 // path (state read as FP64 and rounded; the stage update, limiter and CFL

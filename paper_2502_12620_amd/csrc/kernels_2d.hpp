@@ -344,12 +344,10 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
     });
 
     // ---- output (this lane's variable)
+    static_assert(OM == OUT_RES64 || OM == OUT_RK, "the FP32 residual runs one thread per cell");
     if constexpr (OM == OUT_RES64) {
 #pragma unroll
         for (int m = 0; m < NB; ++m) g.out64[idx0 + m * ncell] = R[m];
-    } else if constexpr (OM == OUT_RES32) {
-#pragma unroll
-        for (int m = 0; m < NB; ++m) g.out32[idx0 + m * ncell] = float(R[m]);
     } else {
         double dt;
         if (g.rate_in) {
