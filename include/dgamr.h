@@ -261,16 +261,20 @@ int dgamr_pool_step(dgamr_pool *p, double *u_arena, void *work, hipStream_t stre
 int dgamr_pool_dt(const dgamr_pool *p, void *work, double **dt_dev);
 /* Leaves in use and active members (host). */
 int dgamr_pool_stats(const dgamr_pool *p, int64_t *leaves_used, int32_t *members);
-/* Launch shape of the pool's stage kernel: rows = layers of the block's last
- * axis per workgroup (0 = largest allowed), grid = workgroups of a
- * persistent launch (0 = one per work item). */
+/* Launch shape of the pool's stage kernel (the thread-per-cell kernel):
+ * rows = layers of the block's last axis per workgroup (0 = largest
+ * allowed), grid = workgroups of a persistent launch (0 = one per work
+ * item). */
 int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid);
 /* Autotuner: times the stage kernel on the pool's current members for every
- * allowed (rows, grid) pair and keeps the fastest; writes the choice and its
- * average launch time in microseconds.  Synchronous; the state arena is
- * read, the work buffer overwritten. */
-int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream, int32_t *rows,
-                        int32_t *grid, double *best_us);
+ * allowed (rows, grid) pair of the thread-per-cell kernel and, for 2-D FP64
+ * classes without the limiter, every slab height of the lane-per-(cell,
+ * variable) kernel, and keeps the fastest; writes the choice (variant 1
+ * thread per cell, 0 lane per variable; rows; grid) and its average launch
+ * time in microseconds (any output pointer may be null).  Synchronous; the state
+ * arena is read, the work buffer overwritten. */
+int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream, int32_t *variant,
+                        int32_t *rows, int32_t *grid, double *best_us);
 
 /* HIP graph of nsteps steps of several pools (in the given order per step),
  * captured once and replayed with dgamr_graph_launch.  A graph holds the

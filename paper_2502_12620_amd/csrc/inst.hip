@@ -124,8 +124,8 @@ hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32,
     if (fp32) return launch_stage_cell<D, P, float>(a, gm, om, lim, sh, s);
     if constexpr (D == 2) {
         // one lane per (cell, variable) unless the caller asks for one
-        // thread per cell (variant 1), needs the limiter or a work list
-        if (!lim && !a.work && (sh.variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s, sh.rows);
+        // thread per cell (variant 1) or needs the limiter
+        if (!lim && (sh.variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s, sh.rows);
     }
     return launch_stage_cell<D, P, double>(a, gm, om, lim, sh, s);
 }

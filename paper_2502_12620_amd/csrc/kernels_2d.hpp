@@ -187,7 +187,8 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
     const int N = g.N, ncell = N * N;
     const int slabs = N / rows;
     const int wg = xcd_leaf(blockIdx.x, g.nleaves * slabs);
-    const int leaf = wg / slabs, j0 = (wg % slabs) * rows;
+    const int li = wg / slabs, j0 = (wg % slabs) * rows;
+    const int leaf = g.work ? g.work[li] : li; // listed leaves of a pool, or all
     const int lane = threadIdx.x, v = lane & 3;
     const int lc = lane >> 2;             // cell inside the slab
     const int i = lc % N, j = j0 + lc / N;
@@ -354,7 +355,7 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
             dt = g.cfl / __longlong_as_double((long long)*g.rate_in);
             if (blockIdx.x == 0 && threadIdx.x == 0) *g.dt_out = dt;
         } else {
-            dt = *g.dt;
+            dt = g.dt[g.leaf_member ? g.leaf_member[leaf] : 0];
         }
         if (g.rate_clear && blockIdx.x == 0 && threadIdx.x == 0) *g.rate_clear = 0ULL;
         const double a = g.rk_a, b = g.rk_b;

@@ -375,13 +375,14 @@ int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid)
         });
         if (std::find(opts, opts + n, rows) == opts + n) return fail(DGAMR_EINVAL, "rows not allowed for this class");
     }
+    p->shape.variant = 1; // the thread-per-cell kernel
     p->shape.rows = rows;
     p->shape.grid = grid;
     return DGAMR_OK;
 }
 
-int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream, int32_t *rows, int32_t *grid,
-                        double *best_us)
+int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream, int32_t *variant,
+                        int32_t *rows, int32_t *grid, double *best_us)
 {
     GUARD_API({
         CHECK(check_ptr(p, "pool"));
@@ -392,6 +393,9 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
         const int nopt = dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
             return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32_MFMA);
         });
+        // 2-D FP64 without the limiter also has the lane-per-(cell, variable)
+        // kernel: slabs of r rows with 4 r N <= 512 lanes
+        const bool try_lanes = p->dim == 2 && p->cls.precision == DGAMR_FP64 && p->cls.limiter == DGAMR_LIMITER_NONE;
         PoolWork w = carve(p, work);
         CHECK(pool_dt(p, u_arena, w, stream));
         hipEvent_t e0, e1;
@@ -401,17 +405,26 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
         dgk::StageShape best_sh = p->shape;
         const int reps = 3;
         int rc = DGAMR_OK;
-        // candidates: every allowed slab height, one workgroup per item or
-        // a persistent grid of 1, 2 or 4 workgroups per compute unit
-        for (int oi = 0; oi < nopt && rc == DGAMR_OK; ++oi) {
+        // candidates: the thread-per-cell kernel at every allowed slab
+        // height, one workgroup per item or a persistent grid of 1, 2 or 4
+        // workgroups per compute unit; the lane-per-variable kernel at every
+        // slab height it allows
+        struct Cand { int variant, rows, grid; };
+        std::vector<Cand> cands;
+        for (int oi = 0; oi < nopt; ++oi) {
             const long items = long(p->nwork) * (p->N / opts[oi]);
-            const int grids[4] = {0, 256, 512, 1024};
-            for (int gi = 0; gi < 4 && rc == DGAMR_OK; ++gi) {
-                if (grids[gi] && grids[gi] >= items) continue;
+            for (int gsz : {0, 256, 512, 1024})
+                if (gsz == 0 || gsz < items) cands.push_back({1, opts[oi], gsz});
+        }
+        if (try_lanes)
+            for (int r = p->N; r >= 1; --r)
+                if (p->N % r == 0 && 4 * r * p->N <= 512) cands.push_back({0, r, 0});
+        for (size_t ci = 0; ci < cands.size() && rc == DGAMR_OK; ++ci) {
+            {
                 dgk::StageShape sh;
-                sh.variant = 1;
-                sh.rows = opts[oi];
-                sh.grid = grids[gi];
+                sh.variant = cands[ci].variant;
+                sh.rows = cands[ci].rows;
+                sh.grid = cands[ci].grid;
                 rc = pool_stage(p, 0, u_arena, u_arena, w.u1, w, sh, stream); // warm-up
                 if (rc != DGAMR_OK) break;
                 if (hipEventRecord(e0, stream) != hipSuccess) { rc = fail(DGAMR_EHIP, "event record"); break; }
@@ -435,6 +448,7 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
         (void)hipEventDestroy(e1);
         if (rc != DGAMR_OK) return rc;
         p->shape = best_sh;
+        if (variant) *variant = best_sh.variant;
         if (rows) *rows = best_sh.rows;
         if (grid) *grid = best_sh.grid;
         if (best_us) *best_us = best;

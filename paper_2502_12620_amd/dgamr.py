@@ -95,7 +95,7 @@ def lib():
         L.dgamr_pool_dt.argtypes = [vp, vp, ctypes.POINTER(vp)]
         L.dgamr_pool_stats.argtypes = [vp, i64p, i32p]
         L.dgamr_pool_set_shape.argtypes = [vp, i32, i32]
-        L.dgamr_pool_autotune.argtypes = [vp, vp, vp, vp, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
+        L.dgamr_pool_autotune.argtypes = [vp, vp, vp, vp, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
         L.dgamr_pools_capture.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32,
                                           ctypes.POINTER(vp)]
         L.dgamr_graph_launch.argtypes = [vp, vp]
@@ -360,11 +360,12 @@ class Pool:
         _check(lib().dgamr_pool_set_shape(self.h, rows, grid))
 
     def autotune(self, stream=None):
-        """Returns (rows, grid, best stage-launch microseconds)."""
-        r, g, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
-        _check(lib().dgamr_pool_autotune(self.h, _ptr(self.u), _ptr(self.work), _stream(stream), ctypes.byref(r),
-                                         ctypes.byref(g), ctypes.byref(us)))
-        return r.value, g.value, us.value
+        """Returns (variant, rows, grid, best stage-launch microseconds);
+        variant 1 = one thread per cell, 0 = one lane per (cell, variable)."""
+        v, r, g, us = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_double()
+        _check(lib().dgamr_pool_autotune(self.h, _ptr(self.u), _ptr(self.work), _stream(stream), ctypes.byref(v),
+                                         ctypes.byref(r), ctypes.byref(g), ctypes.byref(us)))
+        return v.value, r.value, g.value, us.value
 
 
 class RunGraph:

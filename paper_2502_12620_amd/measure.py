@@ -200,7 +200,8 @@ def batched_run(forests: int = 512, repeats: int = 20, precision: str = "fp64") 
            "sequential_plain_s": seq_total, "sequential_dof_stage_per_s": dofs * 3 * steps / seq_total,
            "speedup_vs_sequential": seq_total / med,
            "max_rel_diff_vs_plain_path": max_rel,
-           "autotune": {f"p{p}": {"rows": r, "grid": g, "stage_us": us} for p, (r, g, us) in zip(sorted(groups), tune)},
+           "autotune": {f"p{p}": {"variant": v, "rows": r, "grid": g, "stage_us": us}
+                        for p, (v, r, g, us) in zip(sorted(groups), tune)},
            "setup_s": setup_s}
     return out
 

@@ -166,8 +166,8 @@ def test_autotune_keeps_results():
     _admit_all(ref, members)
     tuned = G.Pool(2, 2, 8, capacity_leaves=64, max_members=8)
     _admit_all(tuned, members)
-    rows, grid, us = tuned.autotune()
-    assert rows in (8, 4, 2, 1) and grid >= 0 and us > 0
+    variant, rows, grid, us = tuned.autotune()
+    assert variant in (0, 1) and rows in (8, 4, 2, 1) and grid >= 0 and us > 0
     # a persistent grid walks the same items: bitwise the same result
     tuned.set_shape(8, 4)
     tuned.step()
@@ -180,6 +180,11 @@ def test_autotune_keeps_results():
         tuned.step()
         ref.step()
         assert rel_diff(_host(tuned.u), _host(ref.u)).max() <= 1e-14, f"shape {shape}"
+    # the autotuner's own choice (which may be the lane-per-variable kernel)
+    tuned.autotune()
+    tuned.step()
+    ref.step()
+    assert rel_diff(_host(tuned.u), _host(ref.u)).max() <= 1e-13
 
 
 @pytest.mark.parametrize("precision,limiter", [(0, False), (1, False), (0, True)])
