@@ -198,11 +198,14 @@ int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work
 
 /* Kernel tuning (for the autotuner and measurements; results do not
  * depend on it beyond floating-point rounding):
- *   DGAMR_TUNE_STAGE_VARIANT: 2-D stage kernel, -1 automatic (default),
- *     0 one lane per (cell, variable) in row slabs (latency-bound small
- *     forests), 1 one thread per cell (throughput on large forests);
- *   DGAMR_TUNE_VAR_SPLIT_MAX_CELLS: the automatic choice uses variant 0 up
- *     to this many cells (default 131072);
+ *   DGAMR_TUNE_STAGE_VARIANT: stage kernel, -1 automatic (default),
+ *     0 one lane per (cell, variable), 1 one thread per cell.  2-D: variant
+ *     0 in row slabs for latency-bound small forests, 1 for throughput on
+ *     large forests.  3-D (fused FP64 stage without the limiter or mortar
+ *     faces; other forests always run variant 1): variant 0 in slabs of
+ *     layers, automatic at degree 3;
+ *   DGAMR_TUNE_VAR_SPLIT_MAX_CELLS: the automatic 2-D choice uses variant 0
+ *     up to this many cells (default 131072);
  *   DGAMR_TUNE_SLAB_ROWS: layers of the block's last axis per stage
  *     workgroup (0 automatic, else a divisor of n_cell within the kernel's
  *     thread budget; a launch that does not fit fails with DGAMR_EHIP). */
@@ -266,10 +269,16 @@ int dgamr_pool_stats(const dgamr_pool *p, int64_t *leaves_used, int32_t *members
  * allowed), grid = workgroups of a persistent launch (0 = one per work
  * item). */
 int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid);
+/* Launch shape of the pool's stage kernel (the lane-per-(cell, variable)
+ * kernel, for FP64 classes without the limiter and, in 3-D, without mortar
+ * faces): rows = rows of cells (2-D, 4 rows N <= 512) or whole layers (3-D,
+ * at least two unless the whole block, at most 144 cells) per workgroup,
+ * 0 = the kernel's own choice.  DGAMR_EINVAL for other classes or rows. */
+int dgamr_pool_set_lanes(dgamr_pool *p, int32_t rows);
 /* Autotuner: times the stage kernel on the pool's current members for every
- * allowed (rows, grid) pair of the thread-per-cell kernel and, for 2-D FP64
- * classes without the limiter, every slab height of the lane-per-(cell,
- * variable) kernel, and keeps the fastest; writes the choice (variant 1
+ * allowed (rows, grid) pair of the thread-per-cell kernel and, for the
+ * classes dgamr_pool_set_lanes accepts, every slab height of the
+ * lane-per-(cell, variable) kernel, and keeps the fastest; writes the choice (variant 1
  * thread per cell, 0 lane per variable; rows; grid) and its average launch
  * time in microseconds (any output pointer may be null).  Synchronous; the state
  * arena is read, the work buffer overwritten. */

@@ -95,6 +95,9 @@ int launch_fill(dgamr_forest *f, const double *u, double *guard, bool traces, hi
 int stage_variant(const dgamr_forest *f)
 {
     if (f->stage_variant >= 0) return f->stage_variant;
+    // 3-D: one lane per (cell, variable) at degree 3, where one thread per
+    // cell runs out of registers; one thread per cell below (measured)
+    if (f->topo.dim() == 3) return f->topo.desc().degree >= 3 ? 0 : 1;
     return long(f->topo.n()) * ncell_of(f) <= f->var_split_max_cells ? 0 : 1;
 }
 

@@ -2,6 +2,7 @@
 // launchers; compiled once per pair with -DDG_D=<dim> -DDG_P=<degree>.
 #include "kernels.hpp"
 #include "kernels_2d.hpp"
+#include "kernels_3d.hpp"
 #include "kernels_aux.hpp"
 #include "launch.hpp"
 
@@ -36,6 +37,35 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s, in
         hipLaunchKernelGGL((k_stage2v<P, GUARD_INLINE, OUT_RK>), grid, block, lds, s, a, rows);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// 3-D fused FP64 stage with one lane per (cell, variable)
+inline int rows_3v(int N)
+{
+    for (int r = N; r >= 1; --r)
+        if (rows_ok_3v(N, r)) return r;
+    return 0;
+}
+
+template <int P>
+hipError_t launch_stage_3v(const StageArgs &a, hipStream_t s, int rows_req)
+{
+    const int N = a.N, layer = N * N;
+    int rows = rows_req;
+    if (rows > 0) {
+        if (!rows_ok_3v(N, rows)) return hipErrorInvalidValue;
+    } else {
+        rows = rows_3v(N);
+        if (rows == 0) return hipErrorInvalidValue;
+        // small forests: thinner slabs until every compute unit has work
+        while (rows % 2 == 0 && rows_ok_3v(N, rows / 2) && long(a.nleaves) * (N / rows) < 256) rows /= 2;
+    }
+    const int nslab = rows * layer;
+    const int waves = (nslab + kCells3v - 1) / kCells3v;
+    const size_t lds = sizeof(double) * size_t(face_chunk_3v<P>()) * nslab * 5;
+    const dim3 grid(unsigned(long(a.nleaves) * (N / rows))), block(64 * waves);
+    hipLaunchKernelGGL((k_stage3v<P>), grid, block, lds, s, a, rows);
     return hipGetLastError();
 }
 
@@ -126,6 +156,12 @@ hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32,
         // one lane per (cell, variable) unless the caller asks for one
         // thread per cell (variant 1) or needs the limiter
         if (!lim && (sh.variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s, sh.rows);
+    } else {
+        // the fused stage with traces of the leaf faces, without the limiter
+        // or mortar faces, when asked for (variant 0) and a layer fits
+        if (sh.variant == 0 && !lim && om == OUT_RK && gm == GUARD_TRACE && !a.conservative && rows_3v(a.N) > 0 &&
+            (sh.rows == 0 || rows_ok_3v(a.N, sh.rows)))
+            return launch_stage_3v<P>(a, s, sh.rows);
     }
     return launch_stage_cell<D, P, double>(a, gm, om, lim, sh, s);
 }

@@ -35,6 +35,12 @@ constexpr int face_chunk() { return D == 2 ? (P == 3 ? 2 : Tab<D, P>::NF) : 1; }
 template <int D, int P>
 constexpr bool unroll_points() { return D == 2; }
 
+// Whether to apply table entry c taken at a point of such a loop: unrolled,
+// c is an immediate and its structural zeros drop out; in a loop, c is a
+// runtime value and a multiply by zero costs less than a branch on it.
+template <int D, int P>
+__device__ __forceinline__ bool use_entry(double c) { return !unroll_points<D, P>() || c != 0.0; }
+
 // even / odd parts (in the normal mode index) of the trace of K at face
 // point f of axis a: the trace at xi_a = +1 is e + o, at xi_a = -1 it is e - o.
 template <int D, int P, typename T>
@@ -45,7 +51,7 @@ __device__ __forceinline__ void trace_eo(const T *K, int a, int f, T &e, T &o)
 #pragma unroll
     for (int m = 0; m < Tab<D, P>::NB; ++m) {
         const double c = kTab<D, P>.phi_f[a][f][m];
-        if (c != 0.0) {
+        if (use_entry<D, P>(c)) {
             if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(T(c), K[m], e);
             else o = fma(T(c), K[m], o);
         }
@@ -61,7 +67,7 @@ __device__ __forceinline__ void trace_eo_mem(const double *__restrict__ coef, lo
 #pragma unroll
     for (int m = 0; m < Tab<D, P>::NB; ++m) {
         const double c = kTab<D, P>.phi_f[a][f][m];
-        if (c != 0.0) {
+        if (use_entry<D, P>(c)) {
             const T k = T(coef[m * sm]);
             if (kTab<D, P>.e[m][a] % 2 == 0) e = fma(T(c), k, e);
             else o = fma(T(c), k, o);
@@ -424,13 +430,18 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
     const T scale[3] = {T(g.geo[leaf].scale[0]), T(g.geo[leaf].scale[1]), T(g.geo[leaf].scale[2])};
     const long sv = long(NB) * ncell;
     const long base = long(leaf) * NV * sv + cell;
+    // (v, m) plane of this leaf in array X: a workgroup-uniform address, so
+    // the per-lane part of every state access is the one 32-bit cell offset
+    const long lbase = long(leaf) * NV * sv;
+    const unsigned uc = unsigned(cell);
+    auto plane = [&](auto *X, int v, int m) __attribute__((always_inline)) { return X + (lbase + v * sv + long(m) * ncell); };
 
     T K[NV][NB], R[NV][NB];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
-            K[v][m] = T(g.us[base + v * sv + m * ncell]);
+            K[v][m] = T(plane(g.us, v, m)[uc]);
             R[v][m] = T(0);
         }
 
@@ -445,7 +456,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
                 const double c = kTab<D, P>.phi_v[q][m];
-                if (c != 0.0) s = fma(T(c), K[v][m], s);
+                if (use_entry<D, P>(c)) s = fma(T(c), K[v][m], s);
             }
             U[v] = s;
         }
@@ -464,7 +475,8 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
             for (int m = 0; m < NB; ++m) {
                 const double c = kTab<D, P>.dproj[A][q][m];
-                if (c != 0.0) {
+                // a mode of degree 0 along A has no derivative along A
+                if (kTab<D, P>.e[m][A] != 0 && use_entry<D, P>(c)) {
 #pragma unroll
                     for (int v = 0; v < NV; ++v) R[v][m] = fma(T(c), F[v], R[v][m]);
                 }
@@ -599,7 +611,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
                     for (int m = 0; m < NB; ++m) {
                         const double c = kTab<D, P>.lift_f[A][F][m];
-                        if (c != 0.0) R[v][m] = fma(T(c), (kTab<D, P>.e[m][A] % 2 == 0) ? even : odd, R[v][m]);
+                        if (use_entry<D, P>(c)) R[v][m] = fma(T(c), (kTab<D, P>.e[m][A] % 2 == 0) ? even : odd, R[v][m]);
                     }
                 }
             }
@@ -617,12 +629,12 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = double(R[v][m]);
+            for (int m = 0; m < NB; ++m) plane(g.out64, v, m)[uc] = double(R[v][m]);
     } else if constexpr (OM == OUT_RES32) {
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m) g.out32[base + v * sv + m * ncell] = float(R[v][m]);
+            for (int m = 0; m < NB; ++m) plane(g.out32, v, m)[uc] = float(R[v][m]);
     } else {
         double dt;
         if (g.rate_in) {
@@ -648,7 +660,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int m = 0; m < NB; ++m) Kn[v][m] = b * (g.us[base + v * sv + m * ncell] + dt * double(R[v][m]));
+                for (int m = 0; m < NB; ++m) Kn[v][m] = b * (plane(g.us, v, m)[uc] + dt * double(R[v][m]));
         } else {
 #pragma unroll
             for (int v = 0; v < NV; ++v)
@@ -661,13 +673,13 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
             for (int v = 0; v < NV; ++v)
 #pragma unroll
-                for (int m = 0; m < NB; ++m) Kn[v][m] = fma(a, g.un[base + v * sv + m * ncell], Kn[v][m]);
+                for (int m = 0; m < NB; ++m) Kn[v][m] = fma(a, plane(g.un, v, m)[uc], Kn[v][m]);
         }
         if constexpr (LIM && EQ == EQ_EULER) limit_cell<D, P>(Kn, g.gamma);
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m) g.out64[base + v * sv + m * ncell] = Kn[v][m];
+            for (int m = 0; m < NB; ++m) plane(g.out64, v, m)[uc] = Kn[v][m];
         if (g.rate_out) {
             // CFL rate of the new state from its cell mean, folded over the block
             double rate = 0.0;

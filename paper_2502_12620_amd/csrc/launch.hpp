@@ -9,16 +9,28 @@
 
 namespace dgk {
 
-// Launch shape of the stage kernel.  variant (2-D FP64, fused stage without
-// limiter, no work list): 0 = one lane per (cell, variable) in row slabs,
-// 1 = one thread per cell.  rows: layers of the last axis per workgroup of
-// the thread-per-cell kernel (0 = the largest that fits its thread budget);
-// grid: workgroups of a persistent launch (0 = one per work item).
+// Launch shape of the stage kernel.  variant (FP64 without the limiter;
+// 2-D any output, 3-D the fused stage without mortar faces): 0 = one lane
+// per (cell, variable) in slabs of rows (2-D) or layers (3-D), 1 = one
+// thread per cell.  rows: layers of the last axis per workgroup (0 = the
+// kernel's own choice); grid: workgroups of a persistent launch of the
+// thread-per-cell kernel (0 = one per work item).
 struct StageShape {
     int variant = 1;
     int rows = 0;
     int grid = 0;
 };
+
+// 3-D lane-per-(cell, variable) kernel: 12 cells per wave, at most 12 waves
+// per workgroup; a slab is whole layers, at least two of them (so that only
+// z faces can be slab edges and a cell has at most one) unless it is the
+// whole leaf
+constexpr int kCells3v = 12;
+constexpr int kThreads3v = 768;
+inline bool rows_ok_3v(int N, int rows)
+{
+    return rows >= 1 && N % rows == 0 && (rows >= 2 || rows == N) && rows * N * N <= kCells3v * (kThreads3v / 64);
+}
 
 // residual / fused stage.  fp32: residual arithmetic in FP32 (out_mode
 // OUT_RES32 or OUT_RK).

@@ -381,6 +381,29 @@ int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid)
     return DGAMR_OK;
 }
 
+// classes the lane-per-(cell, variable) kernel takes, and its slab heights
+static bool lanes_class(const dgamr_pool *p)
+{
+    return p->cls.precision == DGAMR_FP64 && p->cls.limiter == DGAMR_LIMITER_NONE &&
+           (p->dim == 2 || p->cls.hanging != DGAMR_HANG_CONSERVATIVE);
+}
+
+static bool lanes_rows_ok(const dgamr_pool *p, int r)
+{
+    return p->dim == 2 ? (r >= 1 && p->N % r == 0 && 4 * r * p->N <= 512) : dgk::rows_ok_3v(p->N, r);
+}
+
+int dgamr_pool_set_lanes(dgamr_pool *p, int32_t rows)
+{
+    CHECK(check_ptr(p, "pool"));
+    if (!lanes_class(p)) return fail(DGAMR_EINVAL, "the lane kernel takes FP64 classes without the limiter (3-D: without mortar faces)");
+    if (rows < 0 || (rows > 0 && !lanes_rows_ok(p, rows))) return fail(DGAMR_EINVAL, "rows not allowed for the lane kernel");
+    p->shape.variant = 0;
+    p->shape.rows = rows;
+    p->shape.grid = 0;
+    return DGAMR_OK;
+}
+
 int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream, int32_t *variant,
                         int32_t *rows, int32_t *grid, double *best_us)
 {
@@ -393,9 +416,10 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
         const int nopt = dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
             return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32_MFMA);
         });
-        // 2-D FP64 without the limiter also has the lane-per-(cell, variable)
-        // kernel: slabs of r rows with 4 r N <= 512 lanes
-        const bool try_lanes = p->dim == 2 && p->cls.precision == DGAMR_FP64 && p->cls.limiter == DGAMR_LIMITER_NONE;
+        // FP64 without the limiter (3-D: and without mortar faces) also has
+        // the lane-per-(cell, variable) kernel: 2-D slabs of r rows with
+        // 4 r N <= 512 lanes, 3-D slabs of r layers as rows_ok_3v allows
+        const bool try_lanes = lanes_class(p);
         PoolWork w = carve(p, work);
         CHECK(pool_dt(p, u_arena, w, stream));
         hipEvent_t e0, e1;
@@ -418,7 +442,7 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
         }
         if (try_lanes)
             for (int r = p->N; r >= 1; --r)
-                if (p->N % r == 0 && 4 * r * p->N <= 512) cands.push_back({0, r, 0});
+                if (lanes_rows_ok(p, r)) cands.push_back({0, r, 0});
         for (size_t ci = 0; ci < cands.size() && rc == DGAMR_OK; ++ci) {
             {
                 dgk::StageShape sh;

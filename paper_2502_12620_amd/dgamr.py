@@ -31,7 +31,7 @@ EXPORTS = [
     "dgamr_step", "dgamr_run", "dgamr_conserved_totals", "dgamr_limit_positivity", "dgamr_indicator",
     "dgamr_project_ic", "dgamr_check_state", "dgamr_set_tuning", "dgamr_profile_enable", "dgamr_profile_read",
     "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
-    "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_autotune",
+    "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_set_lanes", "dgamr_pool_autotune",
     "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture",
     "dgamr_last_error",
 ]
@@ -95,6 +95,7 @@ def lib():
         L.dgamr_pool_dt.argtypes = [vp, vp, ctypes.POINTER(vp)]
         L.dgamr_pool_stats.argtypes = [vp, i64p, i32p]
         L.dgamr_pool_set_shape.argtypes = [vp, i32, i32]
+        L.dgamr_pool_set_lanes.argtypes = [vp, i32]
         L.dgamr_pool_autotune.argtypes = [vp, vp, vp, vp, i32p, i32p, i32p, ctypes.POINTER(ctypes.c_double)]
         L.dgamr_pools_capture.argtypes = [ctypes.POINTER(vp), ctypes.POINTER(vp), ctypes.POINTER(vp), i32, i32,
                                           ctypes.POINTER(vp)]
@@ -358,6 +359,10 @@ class Pool:
 
     def set_shape(self, rows=0, grid=0):
         _check(lib().dgamr_pool_set_shape(self.h, rows, grid))
+
+    def set_lanes(self, rows=0):
+        """The lane-per-(cell, variable) stage kernel with slabs of `rows`."""
+        _check(lib().dgamr_pool_set_lanes(self.h, rows))
 
     def autotune(self, stream=None):
         """Returns (variant, rows, grid, best stage-launch microseconds);

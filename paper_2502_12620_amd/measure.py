@@ -88,12 +88,12 @@ def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1):
 def cmd_sweep(args):
     cases = [W.roofline_2d(k, p) for k in (32, 64, 128) for p in (1, 2)]
     cases += [W.roofline_2d(64, 3)]
-    cases += [W.roofline_3d(16, p) for p in (1, 2)]
+    cases += [W.roofline_3d(16, p) for p in (1, 2)] + [W.roofline_3d(8, 3)]
     for w in cases:
         if args.only and w.name not in args.only.split(","):
             continue
         prec = G.FP32_MFMA if args.precision == "fp32" else G.FP64
-        variants = [0, 1] if (w.dim == 2 and args.variants and prec == G.FP64) else [-1]
+        variants = [0, 1] if (args.variants and prec == G.FP64) else [-1]
         for var in variants:
             print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var)), flush=True)
 
@@ -388,7 +388,7 @@ def main(argv=None):
     s = sub.add_parser("sweep")
     s.add_argument("--steps", type=int, default=10)
     s.add_argument("--only", default="", help="comma-separated workload names")
-    s.add_argument("--variants", action="store_true", help="2-D: time both stage kernels")
+    s.add_argument("--variants", action="store_true", help="FP64: time both stage kernels (lane per cell and variable; thread per cell)")
     s.add_argument("--precision", choices=["fp64", "fp32"], default="fp64", help="residual arithmetic")
     c = sub.add_parser("copy")
     c.add_argument("--mb", type=int, default=1024)

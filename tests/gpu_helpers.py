@@ -33,6 +33,18 @@ def rel_diff(got, ref):
     return np.array(out)
 
 
+def rel_diff_floored(got, ref, floor=1e-6):
+    """rel_diff with each variable's scale floored at floor x the largest
+    coefficient (for variables that are zero up to rounding, such as the z
+    momentum of an extruded vortex)."""
+    big = np.abs(ref).max()
+    out = []
+    for v in range(ref.shape[1]):
+        scale = max(np.abs(ref[:, v]).max(), floor * big)
+        out.append(np.abs(got[:, v] - ref[:, v]).max() / (scale if scale > 0 else 1.0))
+    return np.array(out)
+
+
 def small_c2(n_cell=4):
     """The two-level vortex forest of the 2-D AMR workload at a smaller block
     size, for runs the oracle finishes in seconds."""

@@ -86,6 +86,7 @@ def test_pool_and_graph_arguments_are_checked_before_any_device_call():
     assert L.dgamr_pool_create(ctypes.byref(_desc(G, n_cell=7)), 16, 4, ctypes.byref(h)) == G.EINVAL
     assert not h.value
     assert L.dgamr_pool_step(None, None, None, None) == G.EINVAL
+    assert L.dgamr_pool_set_lanes(None, 0) == G.EINVAL
     assert L.dgamr_pool_admit(None, None, ctypes.c_double(0.1), None, None, None) == G.EINVAL
     assert L.dgamr_pool_release(None, 0, None) == G.EINVAL
     assert L.dgamr_graph_launch(None, None) == G.EINVAL

@@ -9,7 +9,7 @@ import pytest
 
 import oracle as O
 from paper_2502_12620_amd import workloads as W
-from tests.gpu_helpers import make_pair, rel_diff
+from tests.gpu_helpers import make_pair, rel_diff, rel_diff_floored
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -200,6 +200,37 @@ def test_pool_3d_members(precision, limiter):
     for (w, cfl), (f, mid, first) in zip(members, adm):
         got = _host(pool.view(first, f.n_leaves))
         assert np.array_equal(got, _solo(w, cfl, 3, precision=precision, limiter=limiter))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_pool_3d_lane_kernel(p):
+    """3-D members stepped by the lane-per-(cell, variable) kernel over the
+    pool's work list with per-member dt agree with their solo runs (thread
+    per cell) to rounding; the autotuner's choice agrees too."""
+    G = _G()
+    members = [(_vortex("a3", 3, p, 4, (2, 2, 1), 2.0, 3.0, (2.0, 2.0), levels=2, refine_tree0=True), 0.1),
+               (_vortex("b3", 3, p, 4, (1, 2, 2), 2.5, 2.0, (1.0, 2.0)), 0.15)]
+    for rows in (2, 4, 0):
+        pool = G.Pool(3, p, 4, capacity_leaves=64, max_members=4)
+        adm = _admit_all(pool, members)
+        pool.set_lanes(rows)
+        for _ in range(3):
+            pool.step()
+        for (w, cfl), (f, mid, first) in zip(members, adm):
+            got = _host(pool.view(first, f.n_leaves))
+            assert rel_diff_floored(got, _solo(w, cfl, 3), floor=1e-2).max() <= 1e-13, f"rows {rows}, member {w.name}"
+    with pytest.raises(G.DgamrError):
+        pool.set_lanes(1)  # a one-layer slab of a 4-layer block
+    ref = G.Pool(3, p, 4, capacity_leaves=64, max_members=4)
+    _admit_all(ref, members)
+    tuned = G.Pool(3, p, 4, capacity_leaves=64, max_members=4)
+    _admit_all(tuned, members)
+    variant, rows, grid, us = tuned.autotune()
+    assert variant in (0, 1) and us > 0
+    for _ in range(2):
+        tuned.step()
+        ref.step()
+    assert rel_diff_floored(_host(tuned.u), _host(ref.u), floor=1e-2).max() <= 1e-13
 
 
 @pytest.mark.parametrize("dim", [2, 3])
