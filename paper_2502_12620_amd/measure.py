@@ -53,9 +53,10 @@ def stage_bytes_per_dof(dim: int, n_cell: int) -> float:
     return (16.0 + 24.0 + 24.0) / 3.0 + face
 
 
-def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1):
+def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1, rows=0):
     f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, precision=precision)
     f.set_tuning(G.TUNE_STAGE_VARIANT, variant)
+    f.set_tuning(G.TUNE_SLAB_ROWS, rows)
     u = f.project_ic(G.IC_VORTEX, w.ic_params)
     work = f.new_work()
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -78,6 +79,7 @@ def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1):
     del f, u, work
     torch.cuda.empty_cache()
     return {"workload": w.name, "precision": "fp32" if precision == G.FP32_MFMA else "fp64", "variant": variant,
+            "rows": rows,
             "dim": w.dim, "degree": w.degree, "leaves": n, "dofs": dof,
             "state_MB": dof * 8 / 1e6, "steps": steps, "dof_stage_per_s": dof * 3 * steps / el,
             "stage_kernel_us": avg * 1e6, "algorithmic_bytes_per_dof": bpd, "achieved_GBs": gbs,
@@ -95,7 +97,8 @@ def cmd_sweep(args):
         prec = G.FP32_MFMA if args.precision == "fp32" else G.FP64
         variants = [0, 1] if (args.variants and prec == G.FP64) else [-1]
         for var in variants:
-            print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var)), flush=True)
+            for rows in [int(r) for r in args.rows.split(",")]:
+                print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var, rows=rows)), flush=True)
 
 
 def cmd_copy(args):
@@ -390,6 +393,7 @@ def main(argv=None):
     s.add_argument("--only", default="", help="comma-separated workload names")
     s.add_argument("--variants", action="store_true", help="FP64: time both stage kernels (lane per cell and variable; thread per cell)")
     s.add_argument("--precision", choices=["fp64", "fp32"], default="fp64", help="residual arithmetic")
+    s.add_argument("--rows", default="0", help="comma-separated slab heights to time (0: the kernel's own)")
     c = sub.add_parser("copy")
     c.add_argument("--mb", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
