@@ -73,7 +73,9 @@ template <int D, int P, typename T>
 bool rows_ok(int N, int rows)
 {
     const int layer = D == 2 ? N : N * N;
-    return rows >= 1 && N % rows == 0 && rows * layer <= stage_threads<D, P, T>();
+    // 3-D: at least two layers unless the whole leaf (a cell has at most one
+    // slab edge)
+    return rows >= 1 && N % rows == 0 && (D == 2 || rows >= 2 || rows == N) && rows * layer <= stage_threads<D, P, T>();
 }
 
 template <int D, int P>
@@ -93,7 +95,7 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     int rows = sh.rows;
     if (rows == 0) {
         rows = a.N;
-        while (rows % 2 == 0 && rows * layer > stage_threads<D, P, T>()) rows /= 2;
+        while (rows % 2 == 0 && rows * layer > stage_default_cells<D, P, T>()) rows /= 2;
     }
     if (!rows_ok<D, P, T>(a.N, rows)) return hipErrorInvalidValue;
     const int nslab = rows * layer;

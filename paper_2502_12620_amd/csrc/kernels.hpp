@@ -390,15 +390,24 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 // (3-D degree 2 in FP32 at 512 threads spills ~600 bytes per lane)
 template <int D, int P, typename T = double>
 constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
+// default slab (cells per workgroup) when the caller does not choose one:
+// the whole budget, except 3-D degree <= 1 and 2-D degree 2, where
+// 128-cell slabs let several workgroups share a compute unit and hide each
+// other's barriers (measured on 8^3 blocks at degree 1: 512-cell slabs
+// 671 us, 256: 582 us, 128: 564 us; 16^2 blocks at degree 2: 256-cell
+// slabs 184 us, 128: 171 us)
+template <int D, int P, typename T = double>
+constexpr int stage_default_cells() { return ((D == 3 && P <= 1) || (D == 2 && P == 2)) ? 128 : stage_threads<D, P, T>(); }
 // waves per SIMD the register budget is cut for, chosen by measurement on
 // large forests: 2-D degree 1 in FP32 fits 128 registers (four waves);
 // 2-D degree 2 in FP64 spills 44 bytes per lane to run two waves per SIMD
 // instead of one (-20% time); 2-D degree 3 in FP32 runs two waves with 212
-// bytes of spills (-18%), while in FP64 (536 bytes) that is slower
+// bytes of spills (-18%), while in FP64 (536 bytes) that is slower; 3-D
+// degree 1 in FP32 fits 164 registers (three waves)
 template <int D, int P, typename T = double>
 constexpr int stage_min_waves()
 {
-    if (D != 2) return 1;
+    if (D != 2) return D == 3 && P == 1 && sizeof(T) == 4 ? 3 : 1;
     if (P == 1) return sizeof(T) == 4 ? 4 : 1;
     if (P == 2) return 2;
     return P == 3 && sizeof(T) == 4 ? 2 : 1;
@@ -506,6 +515,32 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
         const bool mort_p = g.conservative && ia == N - 1 && Lp.type == dgamr::LINK_FINE;
         if (mort_m) mortar_lift<D, P, A, EQ, T>(g, K, R, -1, Lm, t, sc);
         if (mort_p) mortar_lift<D, P, A, EQ, T>(g, K, R, +1, Lp, t, sc);
+        // A slab edge inside the leaf (only along the last axis).  In 3-D,
+        // slabs of at least two layers (or the whole leaf) give a cell at
+        // most one, whose neighbour's coefficients are read once here: read
+        // per face point, the compiler hoists both sides' loads out of the
+        // point loop and holds them (3-D degree 1: 255 registers and a
+        // spill -> 213; FP32 245 -> 165).  In 2-D (unrolled points) the
+        // per-point reads spill less.
+        constexpr bool EDGE_REGS = D == 3 && A == D - 1;
+        const bool edge_m = A == D - 1 && !in_m && ia > 0;
+        const bool edge_p = A == D - 1 && !in_p && ia < N - 1;
+        constexpr int NBE = EDGE_REGS ? NB : 1;
+        T nb[NV][NBE];
+        if constexpr (EDGE_REGS) {
+            if (edge_m || edge_p) {
+                const double *nk = g.us + base + (edge_m ? -stride : stride);
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int m = 0; m < NB; ++m) nb[v][m] = T(nk[v * sv + m * ncell]);
+            } else {
+#pragma unroll
+                for (int v = 0; v < NV; ++v)
+#pragma unroll
+                    for (int m = 0; m < NB; ++m) nb[v][m] = T(0);
+            }
+        }
         auto face_chunk_body = [&](auto cv) __attribute__((always_inline)) {
             const int f0 = int(cv) * FCH;
             // own traces of this chunk: + side to LDS, - side kept
@@ -531,14 +566,15 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                     for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * nslab + lc - stride];
                     num_flux<D, A, EQ, T>(g, TL, Tm[fi], gamma, Fm[fi]);
                 }
-            } else if (ia > 0) { // slab edge inside the leaf: the layer below
+            } else if (edge_m) { // slab edge inside the leaf: the layer below
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
                     T TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         T e, o;
-                        trace_eo_mem<D, P, T>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
+                        if constexpr (EDGE_REGS) trace_eo<D, P, T>(nb[v], A, f0 + fi, e, o);
+                        else trace_eo_mem<D, P, T>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
                     num_flux<D, A, EQ, T>(g, TL, Tm[fi], gamma, Fm[fi]);
@@ -566,7 +602,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                 for (int fi = 0; fi < FCH; ++fi)
 #pragma unroll
                     for (int v = 0; v < NV; ++v) Fp[fi][v] = lds[(v * FCH + fi) * nslab + lc + stride];
-            } else if (ia < N - 1) { // slab edge inside the leaf: the layer above
+            } else if (edge_p) { // slab edge inside the leaf: the layer above
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi) {
                     T TL[NV], TR[NV];
@@ -575,7 +611,8 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         T e, o;
                         trace_eo<D, P, T>(K[v], A, f0 + fi, e, o);
                         TL[v] = e + o;
-                        trace_eo_mem<D, P, T>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
+                        if constexpr (EDGE_REGS) trace_eo<D, P, T>(nb[v], A, f0 + fi, e, o);
+                        else trace_eo_mem<D, P, T>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
                         TR[v] = e - o;
                     }
                     num_flux<D, A, EQ, T>(g, TL, TR, gamma, Fp[fi]);

@@ -171,6 +171,18 @@ int pool_step(dgamr_pool *p, double *u, void *work, hipStream_t s)
 
 extern "C" {
 
+// classes the lane-per-(cell, variable) kernel takes, and its slab heights
+static bool lanes_class(const dgamr_pool *p)
+{
+    return p->cls.precision == DGAMR_FP64 && p->cls.limiter == DGAMR_LIMITER_NONE &&
+           (p->dim == 2 || p->cls.hanging != DGAMR_HANG_CONSERVATIVE);
+}
+
+static bool lanes_rows_ok(const dgamr_pool *p, int r)
+{
+    return p->dim == 2 ? (r >= 1 && p->N % r == 0 && 4 * r * p->N <= 512) : dgk::rows_ok_3v(p->N, r);
+}
+
 int dgamr_pool_create(const dgamr_forest_desc *cls, int64_t capacity_leaves, int32_t max_members, dgamr_pool **out)
 {
     GUARD_API({
@@ -203,6 +215,9 @@ int dgamr_pool_create(const dgamr_forest_desc *cls, int64_t capacity_leaves, int
         p->ncell = cls->dim == 2 ? p->N * p->N : p->N * p->N * p->N;
         p->nfc = cls->dim == 2 ? p->N : p->N * p->N;
         p->cap = capacity_leaves;
+        // default stage kernel as for a single forest of the class: one lane
+        // per (cell, variable) in 3-D at degree 3, one thread per cell else
+        if (p->dim == 3 && p->degree >= 3 && lanes_class(p)) p->shape.variant = 0;
         p->maxm = max_members;
         p->used.assign(size_t(capacity_leaves), 0);
         auto cleanup = [&](int code, const char *what) {
@@ -379,18 +394,6 @@ int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid)
     p->shape.rows = rows;
     p->shape.grid = grid;
     return DGAMR_OK;
-}
-
-// classes the lane-per-(cell, variable) kernel takes, and its slab heights
-static bool lanes_class(const dgamr_pool *p)
-{
-    return p->cls.precision == DGAMR_FP64 && p->cls.limiter == DGAMR_LIMITER_NONE &&
-           (p->dim == 2 || p->cls.hanging != DGAMR_HANG_CONSERVATIVE);
-}
-
-static bool lanes_rows_ok(const dgamr_pool *p, int r)
-{
-    return p->dim == 2 ? (r >= 1 && p->N % r == 0 && 4 * r * p->N <= 512) : dgk::rows_ok_3v(p->N, r);
 }
 
 int dgamr_pool_set_lanes(dgamr_pool *p, int32_t rows)
