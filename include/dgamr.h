@@ -241,7 +241,10 @@ int dgamr_profile_read(dgamr_forest *f, double *stage_ms, int64_t *stage_launche
  * dgamr_pool_bytes for the capacity).  Admit and release enqueue table
  * uploads on the given stream; steps on the same stream see them in order.
  * A released member's slots keep their contents until the next admission.
- * Pools are not thread-safe.
+ * Pools are not thread-safe.  The stage kernel is chosen as for a single
+ * forest of the class (3-D degree 3: one lane per (cell, variable); else
+ * one thread per cell) until dgamr_pool_set_shape, dgamr_pool_set_lanes or
+ * dgamr_pool_autotune changes it.
  * --------------------------------------------------------------------- */
 typedef struct dgamr_pool dgamr_pool;
 

@@ -231,11 +231,13 @@ def test_run_folds_the_cfl_step_into_the_stages(hanging):
 
 @pytest.mark.parametrize("p", [1, 2, 3])
 @pytest.mark.parametrize("hanging", [0, 1])
-def test_2d_stage_variants_agree_with_the_oracle(p, hanging):
+@pytest.mark.parametrize("N", [6, 8, 16])
+def test_2d_stage_variants_agree_with_the_oracle(p, hanging, N):
     """Both 2-D stage kernels (one lane per cell and variable; one thread per
-    cell) on a three-level forest with ragged N, against the oracle."""
+    cell) on a three-level forest with ragged and full-size N, against the
+    oracle."""
     G = _hip()
-    w = _forest(2, p, 6, 3)
+    w = _forest(2, p, N, 3)
     orc, gpu = make_pair(w, hanging=hanging)
     u = _physical_state(orc, w, seed=20 + p)
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
