@@ -60,10 +60,8 @@ __device__ __forceinline__ double rusanov_5(double tl, double tr, int addr0, dou
 }
 
 // even / odd parts (in the normal mode index) of the trace at face point f
-// of axis A.  With an
-// unrolled point loop f is a constant and zero table entries drop out; in a
-// runtime loop (PRUNE false) a multiply by zero costs less than a branch.
-template <int P, int A, bool PRUNE>
+// of axis A (a constant after unrolling: zero table entries drop out)
+template <int P, int A>
 __device__ __forceinline__ void trace3(const double *K, int f, double &e, double &o)
 {
     e = 0.0;
@@ -71,7 +69,7 @@ __device__ __forceinline__ void trace3(const double *K, int f, double &e, double
 #pragma unroll
     for (int m = 0; m < Tab<3, P>::NB; ++m) {
         const double c = kTab<3, P>.phi_f[A][f][m];
-        if (!PRUNE || c != 0.0) {
+        if (c != 0.0) {
             if (kTab<3, P>.e[m][A] % 2 == 0) e = fma(c, K[m], e);
             else o = fma(c, K[m], o);
         }
@@ -84,10 +82,10 @@ __device__ __forceinline__ void trace3(const double *K, int f, double &e, double
 // constants of every quadrature point ahead and holds them in registers.
 #define DG_PIN(x) asm volatile("" : "+v"(x))
 
-// point loops unrolled (table entries as constants) up to this degree;
-// above it they are loops over the tables read with scalar loads
-template <int P>
-constexpr bool unroll_3v() { return P <= 2; }
+// The point loops are unrolled at every degree (table entries become
+// constants).  At degree 3 loops over the tables read with scalar loads
+// spill less (92 against 260 bytes per lane) but wait on a scalar load at
+// every point: 2.13 ms against 1.30 ms per stage on 8^3 roots of 8^3 cells.
 
 // grid: one workgroup per (leaf, slab of `rows` layers); block: 64 lanes per
 // 12 cells of the slab (rows * N * N <= 144 cells)
@@ -127,7 +125,6 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
     }
 
     // ---- volume integral
-    constexpr bool UNR = unroll_3v<P>();
     const double gm1 = g.gamma - 1.0;
     auto vol_point = [&](auto qv) __attribute__((always_inline)) {
         const int q = qv;
@@ -135,7 +132,7 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
             const double c = kTab<3, P>.phi_v[q][m];
-            if (!UNR || c != 0.0) s = fma(c, K[m], s);
+            if (c != 0.0) s = fma(c, K[m], s);
         }
         double U[5];
         cell_state5(s, addr0, U);
@@ -149,19 +146,14 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
             for (int m = 0; m < NB; ++m) {
                 const double c = kTab<3, P>.dproj[A][q][m];
                 // a mode of degree 0 along A has no derivative along A
-                if (kTab<3, P>.e[m][A] != 0 && (!UNR || c != 0.0)) R[m] = fma(c, F, R[m]);
+                if (kTab<3, P>.e[m][A] != 0 && c != 0.0) R[m] = fma(c, F, R[m]);
             }
         });
 #pragma unroll
         for (int m = 0; m < NB; ++m) DG_PIN(R[m]);
         __builtin_amdgcn_sched_barrier(0);
     };
-    if constexpr (UNR) {
-        static_for<0, NQ>(vol_point);
-    } else {
-#pragma unroll 1
-        for (int q = 0; q < NQ; ++q) vol_point(q);
-    }
+    static_for<0, NQ>(vol_point);
 
     // ---- surface integrals, one axis at a time; LDS slot of (chunk point,
     // slab cell, variable)
@@ -198,7 +190,7 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
 #pragma unroll
             for (int fi = 0; fi < FCH; ++fi) {
                 double e, o;
-                trace3<P, A, UNR>(K, f0 + fi, e, o);
+                trace3<P, A>(K, f0 + fi, e, o);
                 if (live) lds[slot(fi, lc)] = e + o;
                 Tm[fi] = e - o;
             }
@@ -211,7 +203,7 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
                     tl = lds[slot(fi, lc - stride)];
                 } else if (edge_m) { // slab edge inside the leaf: the layer below
                     double e, o;
-                    trace3<P, A, UNR>(nb, f0 + fi, e, o);
+                    trace3<P, A>(nb, f0 + fi, e, o);
                     tl = e + o;
                 } else {
                     tl = gt_m[long(f0 + fi) * layer];
@@ -234,12 +226,12 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
                 for (int fi = 0; fi < FCH; ++fi) {
                     double e, o, tr;
                     if (edge_p) { // slab edge inside the leaf: the layer above
-                        trace3<P, A, UNR>(nb, f0 + fi, e, o);
+                        trace3<P, A>(nb, f0 + fi, e, o);
                         tr = e - o;
                     } else {
                         tr = gt_p[long(f0 + fi) * layer];
                     }
-                    trace3<P, A, UNR>(K, f0 + fi, e, o);
+                    trace3<P, A>(K, f0 + fi, e, o);
                     Fp[fi] = rusanov_5<A>(e + o, tr, addr0, g.gamma, isM, isE);
                     DG_PIN(Fp[fi]);
                     __builtin_amdgcn_sched_barrier(0);
@@ -253,19 +245,14 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
 #pragma unroll
                 for (int m = 0; m < NB; ++m) {
                     const double c = kTab<3, P>.lift_f[A][f0 + fi][m];
-                    if (!UNR || c != 0.0) R[m] = fma(c, (kTab<3, P>.e[m][A] % 2 == 0) ? even : odd, R[m]);
+                    if (c != 0.0) R[m] = fma(c, (kTab<3, P>.e[m][A] % 2 == 0) ? even : odd, R[m]);
                 }
             }
 #pragma unroll
             for (int m = 0; m < NB; ++m) DG_PIN(R[m]);
             __builtin_amdgcn_sched_barrier(0);
         };
-        if constexpr (UNR) {
-            static_for<0, NF / FCH>(chunk);
-        } else {
-#pragma unroll 1
-            for (int ci = 0; ci < NF / FCH; ++ci) chunk(ci);
-        }
+        static_for<0, NF / FCH>(chunk);
     });
 
     // ---- fused RK stage (FP64), as the thread-per-cell kernel rounds it
