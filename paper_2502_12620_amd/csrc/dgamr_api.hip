@@ -101,6 +101,23 @@ int stage_variant(const dgamr_forest *f)
     return long(f->topo.n()) * ncell_of(f) <= f->var_split_max_cells ? 0 : 1;
 }
 
+dgk::StageShape stage_shape(const dgamr_forest *f)
+{
+    dgk::StageShape sh;
+    sh.variant = stage_variant(f);
+    sh.rows = f->slab_rows;
+    return sh;
+}
+
+// the fused stage of this forest reads guard traces (the 3-D lane kernel)
+bool fused_reads_traces(const dgamr_forest *f)
+{
+    return dgk::stage_reads_traces(f->topo.dim(), stage_shape(f), f->topo.desc().limiter == DGAMR_LIMITER_POSITIVITY,
+                                   f->topo.desc().precision == DGAMR_FP32_MFMA,
+                                   f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE, f->topo.advection(),
+                                   f->topo.desc().n_cell);
+}
+
 int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t s, bool lim = false)
 {
     a.nleaves = f->topo.n();
@@ -113,9 +130,7 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     if (a.nleaves == 0) return DGAMR_OK;
     const bool fp32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
     const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
-    dgk::StageShape sh;
-    sh.variant = stage_variant(f);
-    sh.rows = f->slab_rows;
+    const dgk::StageShape sh = stage_shape(f);
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
         HIP_TRY((dgk::launch_stage<D, P>(a, gm, om, lim, fp32, sh, s, eq)));
         return DGAMR_OK;
@@ -342,8 +357,8 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
     return launch_dt(f, cfl, u, dt_dev, carve(f, work), stream);
 }
 
-// One SSP-RK3 step as three fused stage launches (guard traces computed
-// inline, limiter fused).  rate_in / rate_clear / rate_out select the CFL
+// One SSP-RK3 step as three fused stage launches (far side of block faces
+// inline, or from guard traces for the 3-D lane kernel; limiter fused).  rate_in / rate_clear / rate_out select the CFL
 // time step folded into the stages (see StageArgs).
 int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_dev,
              const unsigned long long *rate_in, unsigned long long *rate_clear, unsigned long long *rate_out,
@@ -366,9 +381,10 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         a.rate_clear = s == 0 ? rate_clear : nullptr;
         a.dt_out = dt_dev;
         a.rate_out = s == 2 ? rate_out : nullptr;
-        // 3-D reads the far side of every block face as traces from the
-        // guard buffer; 2-D computes it inline
-        const bool guard3 = f->topo.dim() == 3 && !f->topo.advection();
+        // the 3-D lane kernel reads the far side of every block face as
+        // traces from the guard buffer; the other stage kernels compute it
+        // inline
+        const bool guard3 = fused_reads_traces(f);
         if (guard3) {
             a.guard = w.guard;
             CHECK(launch_fill(f, us, w.guard, true, stream));

@@ -41,13 +41,6 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s, in
 }
 
 // 3-D fused FP64 stage with one lane per (cell, variable)
-inline int rows_3v(int N)
-{
-    for (int r = N; r >= 1; --r)
-        if (rows_ok_3v(N, r)) return r;
-    return 0;
-}
-
 template <int P>
 hipError_t launch_stage_3v(const StageArgs &a, hipStream_t s, int rows_req)
 {
@@ -106,9 +99,9 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     // other launch takes one workgroup per item
     const dim3 grid(unsigned(persist ? sh.grid : items)), block(nslab);
     const dim3 grid_all = dim3(unsigned(items));
-    // the fused 3-D stage reads every block face as traces from the guard
-    // buffer (the step runs the fill kernel first); the fused 2-D stage
-    // takes the far side inline
+    // the fused stage takes the far side of block faces inline (copy,
+    // split, combine, mirror of the neighbour cells); the residual entry
+    // point reads guard coefficients
     if constexpr (EQ == EQ_ADVECTION) {
         // one variable: the far side is always taken inline
         if (gm == GUARD_INLINE && om == OUT_RK) {
@@ -121,7 +114,7 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
         }
         return hipErrorInvalidValue;
     }
-    constexpr int GMRK = D == 3 ? GUARD_TRACE : GUARD_INLINE;
+    constexpr int GMRK = GUARD_INLINE; // the fused stage takes the far side inline
     if (gm == GMRK && om == OUT_RK) {
         if (persist && lim)
             hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T, EQ_EULER, true>), grid, block, lds, s, a, rows);
@@ -159,11 +152,12 @@ hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32,
         // thread per cell (variant 1) or needs the limiter
         if (!lim && (sh.variant == 0 || om != OUT_RK)) return launch_stage_2v<P>(a, gm, om, s, sh.rows);
     } else {
-        // the fused stage with traces of the leaf faces, without the limiter
-        // or mortar faces, when asked for (variant 0) and a layer fits
-        if (sh.variant == 0 && !lim && om == OUT_RK && gm == GUARD_TRACE && !a.conservative && rows_3v(a.N) > 0 &&
-            (sh.rows == 0 || rows_ok_3v(a.N, sh.rows)))
+        // the fused stage reading guard traces is the lane kernel (the
+        // caller filled the traces because stage_reads_traces holds)
+        if (gm == GUARD_TRACE && om == OUT_RK) {
+            if (!stage_reads_traces(3, sh, lim, false, a.conservative != 0, false, a.N)) return hipErrorInvalidValue;
             return launch_stage_3v<P>(a, s, sh.rows);
+        }
     }
     return launch_stage_cell<D, P, double>(a, gm, om, lim, sh, s);
 }

@@ -280,6 +280,83 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[NV][
     }
 }
 
+// Far-side polynomial of block face (A, side) for the cell with tangential
+// index t, per variable (its traces at the face are taken at -side):
+//  - guard-buffer mode: the stored guard cell;
+//  - inline mode: the same-level neighbour cell (Eq. 15), the split of the
+//    coarser neighbour cell (Eq. 16), the combine of the 2^d finer cells
+//    (Eq. 17), or at an outflow boundary the mirror image K_m (-1)^{m_A}.
+template <int D, int P, int A, int GM, int NV, typename T>
+__device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Tab<D, P>::NB], int leaf, int side,
+                                         int t, const FaceLink &L, T (&Kf)[NV][Tab<D, P>::NB])
+{
+    constexpr int NB = Tab<D, P>::NB;
+    const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
+    const long sv = long(NB) * ncell;
+    const int face = 2 * A + (side > 0);
+    const int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2;
+    if constexpr (GM == GUARD_BUFFER) {
+        const double *gk = g.guard + ((long(leaf) * 2 * D + face) * NV * NB) * nfc + t;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) Kf[v][m] = T(gk[(long(v) * NB + m) * nfc]);
+        return;
+    }
+    if (L.type == dgamr::LINK_BOUNDARY) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) Kf[v][m] = (kTab<D, P>.e[m][A] % 2) ? -K[v][m] : K[v][m];
+    } else if (L.type == dgamr::LINK_SAME) {
+        const int c = face_cell(A, side > 0 ? 0 : N - 1, t, N, D);
+        const double *nk = g.us + long(L.nbr[0]) * NV * sv + c;
+#pragma unroll
+        for (int v = 0; v < NV; ++v)
+#pragma unroll
+            for (int m = 0; m < NB; ++m) Kf[v][m] = T(nk[v * sv + m * ncell]);
+    } else if (L.type == dgamr::LINK_COARSE) {
+        const int t0 = t % N, t1 = t / N;
+        const int c0 = (L.off[0] * N + t0) / 2, c1 = D == 3 ? (L.off[1] * N + t1) / 2 : 0;
+        const int c = face_cell(A, side > 0 ? 0 : N - 1, c0 + N * c1, N, D);
+        const int child = ((side > 0 ? 0 : 1) << A) | ((t0 & 1) << TA) | (D == 3 ? ((t1 & 1) << TBX) : 0);
+        const double *ck = g.us + long(L.nbr[0]) * NV * sv + c;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            T kv[NB];
+#pragma unroll
+            for (int m = 0; m < NB; ++m) kv[m] = T(ck[v * sv + m * ncell]);
+            split_any<D, P, T>(child, kv, Kf[v]);
+        }
+    } else { // LINK_FINE
+        const int t0 = t % N, t1 = t / N;
+        const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
+        const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
+        const double *fk = g.us + long(link_nbr(L, h0 + 2 * h1)) * NV * sv;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+#pragma unroll
+            for (int m = 0; m < NB; ++m) Kf[v][m] = T(0);
+#pragma unroll
+            for (int ch = 0; ch < (1 << D); ++ch) {
+                const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
+                const int nidx = side > 0 ? bits[A] : N - 2 + bits[A];
+                const int fc = face_cell(A, nidx, (ft0 + bits[TA]) + N * (ft1 + (D == 3 ? bits[TBX] : 0)), N, D);
+                T kv[NB];
+#pragma unroll
+                for (int n = 0; n < NB; ++n) kv[n] = T(fk[v * sv + n * ncell + fc]);
+#pragma unroll
+                for (int m = 0; m < NB; ++m)
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) {
+                        const double cc = kTab<D, P>.comb[ch][m][n];
+                        if (cc != 0.0) Kf[v][m] = fma(T(cc), kv[n], Kf[v][m]);
+                    }
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ positivity limiter
 // Point set of the limiter: volume Gauss points, then the face Gauss
 // points of every face (basis values with the face side's sign).
@@ -515,25 +592,37 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
         const bool mort_p = g.conservative && ia == N - 1 && Lp.type == dgamr::LINK_FINE;
         if (mort_m) mortar_lift<D, P, A, EQ, T>(g, K, R, -1, Lm, t, sc);
         if (mort_p) mortar_lift<D, P, A, EQ, T>(g, K, R, +1, Lp, t, sc);
-        // A slab edge inside the leaf (only along the last axis).  In 3-D,
-        // slabs of at least two layers (or the whole leaf) give a cell at
-        // most one, whose neighbour's coefficients are read once here: read
-        // per face point, the compiler hoists both sides' loads out of the
-        // point loop and holds them (3-D degree 1: 255 registers and a
-        // spill -> 213; FP32 245 -> 165).  In 2-D (unrolled points) the
-        // per-point reads spill less.
-        constexpr bool EDGE_REGS = D == 3 && A == D - 1;
-        const bool edge_m = A == D - 1 && !in_m && ia > 0;
-        const bool edge_p = A == D - 1 && !in_p && ia < N - 1;
-        constexpr int NBE = EDGE_REGS ? NB : 1;
+        // In 3-D a cell has at most one side along A whose neighbour is not
+        // in the slab (slabs hold at least two layers or the whole leaf); the
+        // polynomial across it (the neighbour cell at a slab edge, or the
+        // far side of a block face: guard coefficients, or inline copy /
+        // split / combine / mirror) is built once here and its traces taken
+        // per face point.  Read per face point, the compiler hoists both
+        // sides' loads out of the point loop and holds them (3-D degree 1 with
+        // slab edges: 255 registers and a spill -> 213).  Mortar faces and
+        // block faces read as traces keep their own paths.  In 2-D
+        // (unrolled points) the per-point reads spill less.
+        constexpr bool FAR_REGS = D == 3;
+        const bool edge_m = FAR_REGS ? (!in_m && !mort_m && (ia > 0 || GM != GUARD_TRACE))
+                                     : (A == D - 1 && !in_m && ia > 0);
+        const bool edge_p = FAR_REGS ? (!in_p && !mort_p && (ia < N - 1 || GM != GUARD_TRACE))
+                                     : (A == D - 1 && !in_p && ia < N - 1);
+        constexpr int NBE = FAR_REGS ? NB : 1;
         T nb[NV][NBE];
-        if constexpr (EDGE_REGS) {
+        if constexpr (FAR_REGS) {
             if (edge_m || edge_p) {
-                const double *nk = g.us + base + (edge_m ? -stride : stride);
+                const int side = edge_m ? -1 : 1;
+                if (edge_m ? ia > 0 : ia < N - 1) { // slab edge: the neighbour cell
+                    const double *nk = g.us + base + side * stride;
 #pragma unroll
-                for (int v = 0; v < NV; ++v)
+                    for (int v = 0; v < NV; ++v)
 #pragma unroll
-                    for (int m = 0; m < NB; ++m) nb[v][m] = T(nk[v * sv + m * ncell]);
+                        for (int m = 0; m < NB; ++m) nb[v][m] = T(nk[v * sv + m * ncell]);
+                } else if (edge_m) { // (a link chosen at run time would go to scratch)
+                    far_poly<D, P, A, GM, NV, T>(g, K, leaf, -1, t, Lm, nb);
+                } else {
+                    far_poly<D, P, A, GM, NV, T>(g, K, leaf, +1, t, Lp, nb);
+                }
             } else {
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
@@ -573,7 +662,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         T e, o;
-                        if constexpr (EDGE_REGS) trace_eo<D, P, T>(nb[v], A, f0 + fi, e, o);
+                        if constexpr (FAR_REGS) trace_eo<D, P, T>(nb[v], A, f0 + fi, e, o);
                         else trace_eo_mem<D, P, T>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
@@ -611,7 +700,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         T e, o;
                         trace_eo<D, P, T>(K[v], A, f0 + fi, e, o);
                         TL[v] = e + o;
-                        if constexpr (EDGE_REGS) trace_eo<D, P, T>(nb[v], A, f0 + fi, e, o);
+                        if constexpr (FAR_REGS) trace_eo<D, P, T>(nb[v], A, f0 + fi, e, o);
                         else trace_eo_mem<D, P, T>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
                         TR[v] = e - o;
                     }

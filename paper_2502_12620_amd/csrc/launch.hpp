@@ -32,6 +32,25 @@ inline bool rows_ok_3v(int N, int rows)
     return rows >= 1 && N % rows == 0 && (rows >= 2 || rows == N) && rows * N * N <= kCells3v * (kThreads3v / 64);
 }
 
+// largest slab height the 3-D lane kernel takes for block size N (0: none)
+inline int rows_3v(int N)
+{
+    for (int r = N; r >= 1; --r)
+        if (rows_ok_3v(N, r)) return r;
+    return 0;
+}
+
+// Whether the fused stage of a 3-D Euler forest runs the lane kernel, which
+// reads the far side of block faces as traces written by the fill kernel
+// before the stage (the thread-per-cell kernel computes it inline): the
+// lane kernel is asked for (variant 0) and takes the case.
+inline bool stage_reads_traces(int dim, const StageShape &sh, bool limiter, bool fp32, bool conservative,
+                               bool advection, int N)
+{
+    return dim == 3 && !advection && !fp32 && !limiter && !conservative && sh.variant == 0 &&
+           (sh.rows == 0 ? rows_3v(N) > 0 : rows_ok_3v(N, sh.rows));
+}
+
 // residual / fused stage.  fp32: residual arithmetic in FP32 (out_mode
 // OUT_RES32 or OUT_RK).
 template <int D, int P>

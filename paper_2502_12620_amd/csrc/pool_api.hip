@@ -138,7 +138,8 @@ int pool_stage(dgamr_pool *p, int stage, const double *us, const double *un, dou
     const bool lim = p->cls.limiter == DGAMR_LIMITER_POSITIVITY;
     const bool fp32 = p->cls.precision == DGAMR_FP32_MFMA;
     int gm = dgk::GUARD_INLINE;
-    if (p->dim == 3) {
+    // the 3-D lane kernel reads guard traces of the listed leaves' faces
+    if (dgk::stage_reads_traces(p->dim, sh, lim, fp32, a.conservative != 0, false, p->N)) {
         gm = dgk::GUARD_TRACE;
         a.guard = w.guard;
         dgk::FillArgs fa{us, w.guard, p->d_links, p->d_work, p->nwork * 2 * p->dim, p->N, 1};

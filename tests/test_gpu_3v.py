@@ -52,7 +52,8 @@ def test_3d_lane_kernel_agrees_with_the_oracle(p, N, rows, bc):
         orc.step(u, 0.1)
     assert rel_diff(lane, u).max() <= TOL
     assert rel_diff(cell, u).max() <= TOL
-    assert rel_diff(lane, cell).max() <= 1e-13
+    # (floored: a variable that is zero up to rounding compares absolutely)
+    assert rel_diff_floored(lane, cell, floor=1e-2).max() <= 1e-13
 
 
 @pytest.mark.parametrize("case", ["conservative", "limiter", "fp32"])
