@@ -145,9 +145,11 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
 /* Sec. 4.3 step 2: one SSP-RK3 time step, in place on u: dt from the CFL
  * condition (cfl > 0) or taken from dt_dev (cfl <= 0), then per stage the
  * guard fill, the residual and the stage update (and the positivity limiter
- * when the forest asks for it).  The guard traces are computed inside the
- * stage kernel straight from the neighbours' cells (same values as
- * dgamr_fill_guardcells).  Asynchronous; captures into a HIP graph. */
+ * when the forest asks for it).  The far side of every block face is
+ * computed inside the stage kernel straight from the neighbours' cells (same
+ * values as dgamr_fill_guardcells); only the 3-D lane-per-(cell, variable)
+ * kernel reads guard traces that a fill kernel writes into the work buffer
+ * before each stage.  Asynchronous; captures into a HIP graph. */
 int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev,
                hipStream_t stream);
 
