@@ -114,3 +114,18 @@ def test_run_capture_replays_with_the_lane_kernel():
     for _ in range(6):
         orc.step(u, 0.1)
     assert rel_diff(_host(u_g), u).max() <= TOL
+
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("bc", [W.PERIODIC, W.OUTFLOW])
+def test_3d_thread_per_cell_conservative_mode_against_the_oracle(p, bc):
+    """The thread-per-cell kernel's inline far side with mortar faces
+    (conservative hanging mode, which the lane kernel does not take) on a
+    three-level forest, against the oracle."""
+    w = _forest(3, p, 4, 3, bc=bc)
+    orc, gpu = make_pair(w, hanging=1)
+    u = _physical_state(orc, w, seed=60 + p)
+    got = _steps(gpu, u, 1, 3)
+    for _ in range(3):
+        orc.step(u, 0.1)
+    assert rel_diff(got, u).max() <= TOL
