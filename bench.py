@@ -178,7 +178,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the whole forest lives on one "
-              "MI355X; sharding is described in DESIGN.md, not built)", file=sys.stderr)
+              "MI355X; sharding across GPUs is not built)", file=sys.stderr)
         sys.exit(2)
 
     import torch
