@@ -1,4 +1,4 @@
-"""Measurement helpers run on the GPU machine (not part of the solver path).
+"""Measurement helpers for an MI355X (not part of the solver path).
 
     python -m paper_2502_12620_amd.measure copy  [--mb 1024]
         a plain device-to-device copy of known size, the calibration kernel
