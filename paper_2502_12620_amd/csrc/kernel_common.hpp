@@ -170,6 +170,51 @@ enum Equation : int { EQ_EULER = 0, EQ_ADVECTION = 1 };
 template <int D, int EQ>
 constexpr int nvar() { return EQ == EQ_ADVECTION ? 1 : D + 2; }
 
+// max of two non-negative values in which a NaN wins
+__device__ __forceinline__ double nan_max(double a, double b) { return (b > a || b != b) ? b : a; }
+
+// *out = max(*out, bits of m) for a non-negative m (or a NaN).  The value
+// only grows, so a plain read that already holds at least m proves the
+// atomic unnecessary: after the first workgroups most skip it, which keeps
+// hundreds of same-address atomics off the memory system.
+__device__ __forceinline__ void atomic_max_bits(unsigned long long *out, double m)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(m);
+    if (__hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) atomicMax(out, b);
+}
+
+// Folds the workgroup's maximum of x (non-negative; a NaN wins) into *out
+// with an atomic max on the bit pattern.  A workgroup of whole waves takes
+// the maximum across each wave with lane exchanges and combines one value
+// per wave through LDS (two barriers); otherwise a tree over LDS (one
+// barrier per level).  Every thread of the workgroup calls it; lds holds at
+// least blockDim.x doubles and is free.
+__device__ __forceinline__ void block_max_to(double x, double *lds, unsigned long long *out)
+{
+    const int tid = int(threadIdx.x), n = int(blockDim.x);
+    if ((n & 63) == 0) {
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) x = nan_max(x, __shfl_xor(x, off));
+        __syncthreads();
+        if ((tid & 63) == 0) lds[tid >> 6] = x;
+        __syncthreads();
+        if (tid == 0) {
+            double m = lds[0];
+            for (int w = 1; w < (n >> 6); ++w) m = nan_max(m, lds[w]);
+            atomic_max_bits(out, m);
+        }
+    } else {
+        __syncthreads();
+        lds[tid] = x;
+        __syncthreads();
+        for (int s = 1; s < n; s <<= 1) {
+            if ((tid % (2 * s)) == 0 && tid + s < n) lds[tid] = nan_max(lds[tid], lds[tid + s]);
+            __syncthreads();
+        }
+        if (tid == 0) atomic_max_bits(out, lds[0]);
+    }
+}
+
 struct StageArgs {
     const double *us;     // stage input (read-only during the stage)
     const double *un;     // RK base state (OUT_RK)

@@ -821,17 +821,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 #pragma unroll
                 for (int a2 = 0; a2 < D; ++a2) rate += (fabs(U[1 + a2] * rinv) + cs) / g.geo[leaf].h[a2];
             }
-            __syncthreads();
-            lds_d[lc] = rate;
-            __syncthreads();
-            for (int s = 1; s < nslab; s <<= 1) {
-                if ((lc % (2 * s)) == 0 && lc + s < nslab) {
-                    const double o = lds_d[lc + s];
-                    lds_d[lc] = o > lds_d[lc] || o != o ? o : lds_d[lc];
-                }
-                __syncthreads();
-            }
-            if (lc == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds_d[0]));
+            block_max_to(rate, lds_d, g.rate_out);
         }
     }
 }

@@ -370,17 +370,7 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
             const double rinv = 1.0 / U[0];
             const double cs = sqrt(g.gamma * pressure_r<2>(U, gm1, rinv) * rinv);
             const double rate = (fabs(U[1] * rinv) + cs) / g.geo[leaf].h[0] + (fabs(U[2] * rinv) + cs) / g.geo[leaf].h[1];
-            __syncthreads();
-            if (v == 0) lds[lc] = rate;
-            __syncthreads();
-            for (int s = 1; s < nslab; s <<= 1) {
-                if (v == 0 && (lc % (2 * s)) == 0 && lc + s < nslab) {
-                    const double o = lds[lc + s];
-                    lds[lc] = o > lds[lc] || o != o ? o : lds[lc];
-                }
-                __syncthreads();
-            }
-            if (lane == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds[0]));
+            block_max_to(rate, lds, g.rate_out); // the four lanes of a cell hold the same rate
         }
     }
 }

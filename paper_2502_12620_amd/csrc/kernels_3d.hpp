@@ -284,17 +284,8 @@ __global__ __launch_bounds__(kThreads3v) void k_stage3v(StageArgs g, int rows)
         double rate = 0.0;
 #pragma unroll
         for (int a2 = 0; a2 < 3; ++a2) rate += (fabs(U[1 + a2] * rinv) + cs) / g.geo[leaf].h[a2];
-        __syncthreads();
-        if (live && v == 0) lds[lc] = rate;
-        __syncthreads();
-        for (int s = 1; s < nslab; s <<= 1) {
-            if (live && v == 0 && (lc % (2 * s)) == 0 && lc + s < nslab) {
-                const double o = lds[lc + s];
-                lds[lc] = o > lds[lc] || o != o ? o : lds[lc];
-            }
-            __syncthreads();
-        }
-        if (threadIdx.x == 0) atomicMax(g.rate_out, (unsigned long long)__double_as_longlong(lds[0]));
+        // every lane holds its cell's rate (unused lanes repeat a cell of the slab)
+        block_max_to(rate, lds, g.rate_out);
     }
 }
 
