@@ -334,26 +334,24 @@ __device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Ta
         const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
         const double *fk = g.us + long(link_nbr(L, h0 + 2 * h1)) * NV * sv;
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v) {
 #pragma unroll
             for (int m = 0; m < NB; ++m) Kf[v][m] = T(0);
-        // a loop over the children (hanging faces only), the table read
-        // with scalar loads: unrolled, the 2^d children's matrices made the
-        // code and its compile time several times larger
-#pragma unroll 1
-        for (int ch = 0; ch < (1 << D); ++ch) {
-            const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
-            const int nidx = side > 0 ? bits[A] : N - 2 + bits[A];
-            const int fc = face_cell(A, nidx, (ft0 + bits[TA]) + N * (ft1 + (D == 3 ? bits[TBX] : 0)), N, D);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
+            for (int ch = 0; ch < (1 << D); ++ch) {
+                const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
+                const int nidx = side > 0 ? bits[A] : N - 2 + bits[A];
+                const int fc = face_cell(A, nidx, (ft0 + bits[TA]) + N * (ft1 + (D == 3 ? bits[TBX] : 0)), N, D);
                 T kv[NB];
 #pragma unroll
                 for (int n = 0; n < NB; ++n) kv[n] = T(fk[v * sv + n * ncell + fc]);
 #pragma unroll
                 for (int m = 0; m < NB; ++m)
 #pragma unroll
-                    for (int n = 0; n < NB; ++n) Kf[v][m] = fma(T(kTab<D, P>.comb[ch][m][n]), kv[n], Kf[v][m]);
+                    for (int n = 0; n < NB; ++n) {
+                        const double cc = kTab<D, P>.comb[ch][m][n];
+                        if (cc != 0.0) Kf[v][m] = fma(T(cc), kv[n], Kf[v][m]);
+                    }
             }
         }
     }
