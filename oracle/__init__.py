@@ -18,10 +18,10 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = ["basis.c", "forest.c", "solver.c"]
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-BC_PERIODIC, BC_OUTFLOW = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_DIRICHLET = 0, 1, 2
 HANG_PAPER, HANG_CONSERVATIVE = 0, 1
-IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE = 0, 1, 2, 3, 4
-EQ_EULER, EQ_ADVECTION = 0, 1
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE, IC_EXP = 0, 1, 2, 3, 4, 5
+EQ_EULER, EQ_ADVECTION, EQ_DIFFUSION = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +64,10 @@ def lib():
                                  ctypes.c_int, ctypes.c_double, ctypes.c_int]
         L.orc_destroy.argtypes = [vp]
         L.orc_set_advection.argtypes = [vp, dp]
+        L.orc_set_diffusion.argtypes = [vp, ctypes.c_double, dp]
+        L.orc_set_time.argtypes = [vp, ctypes.c_double]
+        L.orc_get_time.argtypes = [vp]
+        L.orc_get_time.restype = ctypes.c_double
         L.orc_upwind.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
         L.orc_upwind.restype = ctypes.c_double
         L.orc_num_leaves.argtypes = [vp]
@@ -176,7 +180,8 @@ class Forest:
     """A forest of block trees with its DG state layout (see oracle.h)."""
 
     def __init__(self, dim, p, n_cell, roots, lo, hi, bc, max_level, gamma=1.4,
-                 hanging=HANG_PAPER, equation=EQ_EULER, velocity=(1.0, 1.0, 1.0)):
+                 hanging=HANG_PAPER, equation=EQ_EULER, velocity=(1.0, 1.0, 1.0), nu=1.0,
+                 avec=(-1.0, 1.0, 0.0)):
         roots = np.array(list(roots) + [1] * (3 - len(roots)), dtype=np.int32)
         lo = np.array(list(lo) + [0.0] * (3 - len(lo)), dtype=np.float64)
         hi = np.array(list(hi) + [1.0] * (3 - len(hi)), dtype=np.float64)
@@ -194,6 +199,11 @@ class Forest:
             self.velocity = np.array(list(velocity) + [0.0] * (3 - len(velocity)), dtype=np.float64)
             lib().orc_set_advection(self.ptr, _dp(self.velocity))
             self.nv = 1
+        elif equation == EQ_DIFFUSION:
+            self.nu = nu
+            self.avec = np.array(list(avec) + [0.0] * (3 - len(avec)), dtype=np.float64)[:3]
+            lib().orc_set_diffusion(self.ptr, nu, _dp(self.avec))
+            self.nv = 1
 
     def __del__(self):
         if getattr(self, "ptr", None):
@@ -203,6 +213,14 @@ class Forest:
     @property
     def n_leaves(self) -> int:
         return lib().orc_num_leaves(self.ptr)
+
+    @property
+    def time(self) -> float:
+        return lib().orc_get_time(self.ptr)
+
+    @time.setter
+    def time(self, t: float):
+        lib().orc_set_time(self.ptr, t)
 
     @property
     def ncell(self) -> int:

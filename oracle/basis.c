@@ -224,8 +224,11 @@ void orc_rusanov(int dim, double gamma, const double *um, const double *up,
     double fm[5], fp[5];
     orc_euler_flux(dim, gamma, um, axis, fm);
     orc_euler_flux(dim, gamma, up, axis, fp);
-    double cm = sqrt(gamma * orc_pressure(dim, gamma, um) / um[0]);
-    double cp = sqrt(gamma * orc_pressure(dim, gamma, up) / up[0]);
+    double am = gamma * orc_pressure(dim, gamma, um) / um[0];
+    double ap = gamma * orc_pressure(dim, gamma, up) / up[0];
+    /* a trace with gamma p / rho < 0 enters with zero sound speed */
+    double cm = sqrt(am > 0.0 ? am : 0.0);
+    double cp = sqrt(ap > 0.0 ? ap : 0.0);
     double lm = fabs(um[1 + axis] / um[0]) + cm;
     double lp = fabs(up[1 + axis] / up[0]) + cp;
     double alpha = lm > lp ? lm : lp;

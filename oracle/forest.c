@@ -327,6 +327,17 @@ void orc_set_advection(orc_forest *f, const double *vel)
     for (int a = 0; a < 3; ++a) f->vel[a] = a < f->dim ? vel[a] : 0.0;
 }
 
+void orc_set_diffusion(orc_forest *f, double nu, const double *avec)
+{
+    f->equation = ORC_EQ_DIFFUSION;
+    f->nv = 1;
+    f->nu = nu;
+    for (int a = 0; a < 3; ++a) f->avec[a] = a < f->dim ? avec[a] : 0.0;
+}
+
+void orc_set_time(orc_forest *f, double t) { f->time = f->stage_time = t; }
+double orc_get_time(const orc_forest *f) { return f->time; }
+
 void orc_destroy(orc_forest *f)
 {
     if (!f) return;

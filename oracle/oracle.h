@@ -37,12 +37,14 @@
 extern "C" {
 #endif
 
-enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1 };
+/* non-periodic faces: outflow (Euler, Sec. 5.3.1) or, for the diffusion
+ * equation, Dirichlet data from the exact solution (Sec. 5.2) */
+enum { ORC_BC_PERIODIC = 0, ORC_BC_OUTFLOW = 1, ORC_BC_DIRICHLET = 2 };
 enum { ORC_HANG_PAPER = 0, ORC_HANG_CONSERVATIVE = 1 };
-enum { ORC_IC_VORTEX = 0, ORC_IC_SEDOV = 1, ORC_IC_UNIFORM = 2, ORC_IC_XWAVE = 3, ORC_IC_COSINE = 4 };
-/* conservation law solved: the Euler equations (Sec. 2) or the linear
- * scalar convection equation of Sec. 5.1 */
-enum { ORC_EQ_EULER = 0, ORC_EQ_ADVECTION = 1 };
+enum { ORC_IC_VORTEX = 0, ORC_IC_SEDOV = 1, ORC_IC_UNIFORM = 2, ORC_IC_XWAVE = 3, ORC_IC_COSINE = 4, ORC_IC_EXP = 5 };
+/* equation solved: the Euler equations (Sec. 2), the linear scalar
+ * convection equation of Sec. 5.1 or the diffusion equation of Sec. 5.2 */
+enum { ORC_EQ_EULER = 0, ORC_EQ_ADVECTION = 1, ORC_EQ_DIFFUSION = 2 };
 
 typedef struct orc_forest orc_forest;
 
@@ -73,6 +75,16 @@ void orc_set_advection(orc_forest *f, const double *vel);
 /* Upwind (Rusanov with alpha = |vel . n|) flux of the scalar convection
  * equation for the outward normal sign*e_axis. */
 double orc_upwind(const double *vel, double um, double up, int axis, int sign);
+/* Switch a freshly created forest to the diffusion equation
+ * u_t = nu div grad u (Sec. 5.2, one variable) discretised with the
+ * symmetric interior-penalty DG method; every non-periodic face takes
+ * Dirichlet data from the exact solution exp(a . x + nu |a|^2 t)
+ * (a = avec[0..2]). */
+void orc_set_diffusion(orc_forest *f, double nu, const double *avec);
+/* time of the state (Dirichlet data of the diffusion equation); orc_step
+ * advances it by dt */
+void orc_set_time(orc_forest *f, double t);
+double orc_get_time(const orc_forest *f);
 void orc_destroy(orc_forest *f);
 int orc_num_leaves(const orc_forest *f);
 void orc_leaf_keys(const orc_forest *f, int *keys /* n x 5 */);

@@ -49,6 +49,10 @@ struct orc_forest {
     int hanging;
     int equation;     /* ORC_EQ_EULER or ORC_EQ_ADVECTION */
     double vel[3];    /* advection velocity */
+    double nu;        /* diffusion coefficient */
+    double avec[3];   /* exact diffusion solution exp(a . x + nu |a|^2 t) */
+    double time;      /* time of the state (Dirichlet data) */
+    double stage_time; /* time of the stage input the residual sees */
     long unit;        /* global units per root edge = N * 2^(max_level-1) */
     int nleaves;
     orc_key *leaf;

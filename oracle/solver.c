@@ -163,13 +163,25 @@ static void num_flux(const orc_forest *f, const double *um, const double *up, in
  *          rho = 1 + A sin(2 pi (x - u t)/Lx), velocity (u,0,0), p = 1:
  *          an exact entropy wave.
  *  COSINE  (scalar convection, Sec. 5.1) params: k, period_x, period_y,
- *          period_z; u = prod_a [cos(2 pi k (x_a - vel_a t)/L_a) - 1]. */
+ *          period_z; u = prod_a [cos(2 pi k (x_a - vel_a t)/L_a) - 1].
+ *  EXP     (diffusion, Sec. 5.2) u = exp(a . x + nu |a|^2 t) with the
+ *          forest's a and nu (params unused): an exact solution of
+ *          u_t = nu div grad u. */
 static void analytic_state(const orc_forest *f, int kind, const double *prm, double t,
                            const double *x, double *u)
 {
     const double pi = 3.14159265358979323846;
     double g = f->gamma;
     double vel[3] = {0, 0, 0};
+    if (kind == ORC_IC_EXP) {
+        double e = 0.0, a2 = 0.0;
+        for (int a = 0; a < f->dim; ++a) {
+            e += f->avec[a] * x[a];
+            a2 += f->avec[a] * f->avec[a];
+        }
+        u[0] = exp(e + f->nu * a2 * t);
+        return;
+    }
     if (kind == ORC_IC_COSINE) {
         double prod = 1.0;
         for (int a = 0; a < f->dim; ++a)
@@ -329,8 +341,14 @@ void orc_fill_guards(const orc_forest *f, const double *u, double *g)
  * cell at the block boundary (Sec. 3.3).  With the conservative hanging
  * mode, a coarse cell facing finer neighbours integrates instead over the
  * fine sub-faces, using the fine cells' own traces (mortar). */
+static void diffusion_residual(const orc_forest *f, const double *u, const double *g, double *r);
+
 void orc_residual(const orc_forest *f, const double *u, const double *g, double *r)
 {
+    if (f->equation == ORC_EQ_DIFFUSION) {
+        diffusion_residual(f, u, g, r);
+        return;
+    }
     int d = f->dim, nf = 2 * d, nfc = orc_nface_cells(f), nc = orc_ncell(f), q = f->q;
     double gx[8], gw[8];
     orc_gauss_legendre(q, gx, gw);
@@ -490,6 +508,157 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
     free(fnbr);
 }
 
+/* Diffusion equation u_t = nu div grad u (Sec. 5.2), symmetric interior
+ * penalty DG (the IPDG method the paper cites), per cell K and mode m:
+ *   M_m du_m/dt = nu [ - int_K grad u . grad phi_m dV
+ *       + sum_{faces f of K} int_f ( {grad u} . n phi_m
+ *                                   + 1/2 (u- - u+) grad phi_m . n
+ *                                   - sigma (u- - u+) phi_m ) dS ]
+ * with n the outward normal, u-/u+ the own and neighbour traces, {.} the
+ * mean of both sides and sigma = 2 (p+1)^2 / h_n (h_n the cell edge along
+ * n).  The neighbour is the adjacent cell inside the block or the guard
+ * cell (Sec. 3.5: a cell of the own size).  A non-periodic face is a
+ * Dirichlet face with data gD = the exact solution at the stage time:
+ *   int_f ( grad u- . n phi_m + (u- - gD) grad phi_m . n - sigma (u- - gD) phi_m ) dS. */
+static void diffusion_residual(const orc_forest *f, const double *u, const double *g, double *r)
+{
+    int d = f->dim, nf = 2 * d, nfc = orc_nface_cells(f), nc = orc_ncell(f), q = f->q, nb = f->nb;
+    double gx[8], gw[8];
+    orc_gauss_legendre(q, gx, gw);
+    double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *vw = malloc(sizeof(double) * 512);
+    int nq = tensor_points(d, q, gx, gw, vxi, vw);
+    double (*fxi)[3] = malloc(sizeof(double) * 3 * 64);
+    double *fw = malloc(sizeof(double) * 64);
+    int nfq = tensor_points(d - 1, q, gx, gw, fxi, fw);
+    /* reference derivatives at the volume points; values and normal
+     * derivatives at the face points seen from the own side (xi_a = side)
+     * and from the neighbour (xi_a = -side) */
+    double *vd = malloc(sizeof(double) * nq * d * nb);
+    double *fo = malloc(sizeof(double) * nf * nfq * nb), *fod = malloc(sizeof(double) * nf * nfq * nb);
+    double *fn_ = malloc(sizeof(double) * nf * nfq * nb), *fnd = malloc(sizeof(double) * nf * nfq * nb);
+    double (*fpt)[3] = malloc(sizeof(double) * 3 * nf * nfq);
+    for (int iq = 0; iq < nq; ++iq)
+        for (int a = 0; a < d; ++a)
+            for (int m = 0; m < nb; ++m) vd[(iq * d + a) * nb + m] = orc_dphi(d, f->exps + 3 * m, vxi[iq], a);
+    for (int face = 0; face < nf; ++face) {
+        int axis = face / 2, side = (face % 2) ? 1 : -1;
+        for (int iq = 0; iq < nfq; ++iq) {
+            double xo[3] = {0, 0, 0}, xn[3] = {0, 0, 0};
+            int n2 = 0;
+            for (int b = 0; b < d; ++b) {
+                if (b == axis) continue;
+                xo[b] = xn[b] = fxi[iq][n2++];
+            }
+            xo[axis] = side;
+            xn[axis] = -side;
+            for (int a = 0; a < 3; ++a) fpt[face * nfq + iq][a] = xo[a];
+            for (int m = 0; m < nb; ++m) {
+                long k = ((long)face * nfq + iq) * nb + m;
+                fo[k] = orc_phi(d, f->exps + 3 * m, xo);
+                fod[k] = orc_dphi(d, f->exps + 3 * m, xo, axis);
+                fn_[k] = orc_phi(d, f->exps + 3 * m, xn);
+                fnd[k] = orc_dphi(d, f->exps + 3 * m, xn, axis);
+            }
+        }
+    }
+    double sig0 = 2.0 * (f->p + 1) * (f->p + 1);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < f->nleaves; ++i) {
+        long lo[3], size;
+        orc_leaf_box(f, &f->leaf[i], lo, &size);
+        long hu = size / f->N;
+        double h[3] = {1, 1, 1};
+        for (int a = 0; a < d; ++a) h[a] = hu * unit_len(f, a);
+        double J = 1.0;
+        for (int a = 0; a < d; ++a) J *= 0.5 * h[a];
+        for (int c = 0; c < nc; ++c) {
+            int ijk[3];
+            orc_cell_ijk(f, c, ijk);
+            const double *K = u + sidx(f, i, 0, 0, c);
+            double acc[20];
+            memset(acc, 0, sizeof(acc));
+            /* volume: - int grad u . grad phi_m */
+            for (int iq = 0; iq < nq; ++iq) {
+                double gu[3] = {0, 0, 0};
+                for (int a = 0; a < d; ++a)
+                    for (int n = 0; n < nb; ++n) gu[a] += K[(long)n * nc] * vd[(iq * d + a) * nb + n] * 2.0 / h[a];
+                for (int m = 0; m < nb; ++m)
+                    for (int a = 0; a < d; ++a) acc[m] -= vw[iq] * J * gu[a] * vd[(iq * d + a) * nb + m] * 2.0 / h[a];
+            }
+            /* faces */
+            for (int face = 0; face < nf; ++face) {
+                int axis = face / 2, side = (face % 2) ? 1 : -1;
+                double Jf = 1.0;
+                for (int b = 0; b < d; ++b)
+                    if (b != axis) Jf *= 0.5 * h[b];
+                double sigma = sig0 / h[axis], s2 = 2.0 / h[axis];
+                int nijk[3] = {ijk[0], ijk[1], ijk[2]};
+                nijk[axis] += side;
+                int interior = nijk[axis] >= 0 && nijk[axis] < f->N;
+                const orc_face_nbr *fnb = &f->fn[i * nf + face];
+                int dirichlet = !interior && fnb->boundary;
+                int t = 0, mul = 1;
+                for (int b = 0; b < d; ++b) {
+                    if (b == axis) continue;
+                    t += ijk[b] * mul;
+                    mul *= f->N;
+                }
+                const double *Kn = NULL;
+                long nsm = 0;
+                if (interior) {
+                    Kn = u + sidx(f, i, 0, 0, orc_cell_index(f, nijk));
+                    nsm = nc;
+                } else if (!dirichlet) {
+                    Kn = g + gidx(f, i, face, 0, 0, t);
+                    nsm = nfc;
+                }
+                for (int iq = 0; iq < nfq; ++iq) {
+                    long k0 = ((long)face * nfq + iq) * nb;
+                    /* own trace and normal derivative d/dx_axis */
+                    double um = 0.0, gm = 0.0;
+                    for (int n = 0; n < nb; ++n) {
+                        um += K[(long)n * nc] * fo[k0 + n];
+                        gm += K[(long)n * nc] * fod[k0 + n] * s2;
+                    }
+                    double up = 0.0, gn = 0.0;
+                    if (dirichlet) {
+                        double x[3], ex[5];
+                        cell_point(f, i, c, fpt[face * nfq + iq], x);
+                        analytic_state(f, ORC_IC_EXP, NULL, f->stage_time, x, ex);
+                        up = ex[0];
+                    } else {
+                        for (int n = 0; n < nb; ++n) {
+                            up += Kn[(long)n * nsm] * fn_[k0 + n];
+                            gn += Kn[(long)n * nsm] * fnd[k0 + n] * s2;
+                        }
+                    }
+                    /* {grad u} . n; a Dirichlet face takes the own gradient */
+                    double flux_n = side * (dirichlet ? gm : 0.5 * (gm + gn));
+                    double jump = um - up;
+                    double wsym = dirichlet ? 1.0 : 0.5;
+                    for (int m = 0; m < nb; ++m) {
+                        double dn = side * fod[k0 + m] * s2;
+                        acc[m] += fw[iq] * Jf * (flux_n * fo[k0 + m] + wsym * jump * dn - sigma * jump * fo[k0 + m]);
+                    }
+                }
+            }
+            for (int m = 0; m < nb; ++m)
+                r[sidx(f, i, 0, m, c)] = f->nu * acc[m] / (J * orc_ref_mass(d, f->exps + 3 * m));
+        }
+    }
+    free(vxi);
+    free(vw);
+    free(fxi);
+    free(fw);
+    free(vd);
+    free(fo);
+    free(fod);
+    free(fn_);
+    free(fnd);
+    free(fpt);
+}
+
 /* ---------------------------------------------------------------- time stepping */
 
 /* Shu-Osher SSP-RK3 (Sec. 2, third order per Sec. 5.1):
@@ -515,6 +684,15 @@ double orc_max_rate(const orc_forest *f, const double *u)
     for (int i = 0; i < f->nleaves; ++i) {
         long lo[3], size;
         orc_leaf_box(f, &f->leaf[i], lo, &size);
+        if (f->equation == ORC_EQ_DIFFUSION) { /* nu sum_a 1 / h_a^2 */
+            double rate = 0.0;
+            for (int a = 0; a < d; ++a) {
+                double h = (size / f->N) * unit_len(f, a);
+                rate += f->nu / (h * h);
+            }
+            if (rate > mx) mx = rate;
+            continue;
+        }
         if (f->equation == ORC_EQ_ADVECTION) { /* sum_a |vel_a| / h_a */
             double rate = 0.0;
             for (int a = 0; a < d; ++a) rate += fabs(f->vel[a]) / ((size / f->N) * unit_len(f, a));
@@ -552,14 +730,38 @@ void orc_totals(const orc_forest *f, const double *u, double *totals)
     }
 }
 
+/* Gauss-Lobatto nodes on [-1,1] with L points (L = 2, 3, 4): the end
+ * points and the roots of P'_{L-1}, closed forms. */
+static int lobatto_nodes(int L, double *x)
+{
+    if (L == 2) { x[0] = -1.0; x[1] = 1.0; }
+    else if (L == 3) { x[0] = -1.0; x[1] = 0.0; x[2] = 1.0; }
+    else { x[0] = -1.0; x[1] = -1.0 / sqrt(5.0); x[2] = 1.0 / sqrt(5.0); x[3] = 1.0; L = 4; }
+    return L;
+}
+
 /* Positivity-preserving scaling limiter of Zhang and Shu (the paper's
  * references for the positivity limiter), written from the published
- * method.  For each cell, with eps = min(1e-13, mean rho, p(mean)) and the
- * point set S = volume Gauss points and face Gauss points of all faces:
+ * method.  The point set S is Zhang and Shu's for tensor cells: for every
+ * axis a, the points whose a-coordinate is a node of the L-point
+ * Gauss-Lobatto rule and whose other coordinates are nodes of the (p+1)-point
+ * Gauss rule, with L the smallest number of points such that the Lobatto
+ * rule is exact for degree p (2L - 3 >= p, L >= 2).  The cell mean is a
+ * convex combination of the values at S (their positivity is what the
+ * positivity of the next cell means needs); S contains the face Gauss
+ * points.  The volume Gauss points, where the volume integral evaluates the
+ * flux, are added to S.  For each cell, with eps = min(1e-13, mean rho,
+ * p(mean)):
  *   1. theta1 = min(1, (rho_mean - eps)/(rho_mean - min_S rho)); the
  *      non-mean density modes are scaled by theta1;
- *   2. for every point of S with p < eps, t solves p(Ubar + t(U - Ubar)) = eps
- *      (the root in [0,1) of a quadratic after multiplying by rho);
+ *   2. for every point of S with p(U) < eps, t = (pbar - eps)/(pbar - p(U)),
+ *      where the chord from (0, pbar) to (1, p(U)) reaches eps; pressure
+ *      is a concave function of the conserved variables where rho > 0, so
+ *      p(Ubar + t (U - Ubar)) >= eps there (the chord bound instead of the
+ *      exact root of the quadratic p(Ubar + t (U - Ubar)) = eps: the root
+ *      takes a square root of a discriminant that vanishes when the
+ *      pressure along the segment touches eps, where rounding of order
+ *      u becomes sqrt(u) in t; the chord is Lipschitz in the state);
  *      theta2 = min t (1 where p >= eps); all non-mean modes are scaled by
  *      theta2.  Cell means are unchanged. */
 void orc_limit_positivity(const orc_forest *f, double *u)
@@ -568,26 +770,42 @@ void orc_limit_positivity(const orc_forest *f, double *u)
     int d = f->dim, nc = orc_ncell(f), q = f->q, nv = f->nv;
     double gx[8], gw[8];
     orc_gauss_legendre(q, gx, gw);
-    double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
-    double *vw = malloc(sizeof(double) * 512);
-    int nq = tensor_points(d, q, gx, gw, vxi, vw);
-    double (*fxi)[3] = malloc(sizeof(double) * 3 * 64);
-    double *fw = malloc(sizeof(double) * 64);
-    int nfq = tensor_points(d - 1, q, gx, gw, fxi, fw);
-    int npts = nq + 2 * d * nfq;
+    int L = 2;
+    while (2 * L - 3 < f->p) ++L;
+    double lx[4];
+    L = lobatto_nodes(L, lx);
+    int nq = 1, nfq = 1;
+    for (int a = 0; a < d; ++a) nq *= q;
+    for (int a = 0; a < d - 1; ++a) nfq *= q;
+    int npts = nq + d * L * nfq;
     double (*pts)[3] = malloc(sizeof(double) * 3 * npts);
-    for (int k = 0; k < nq; ++k) memcpy(pts[k], vxi[k], sizeof(double) * 3);
-    int np = nq;
-    for (int face = 0; face < 2 * d; ++face) {
-        int axis = face / 2, side = (face % 2) ? 1 : -1;
-        for (int k = 0; k < nfq; ++k) {
-            int n = 0;
-            pts[np][0] = pts[np][1] = pts[np][2] = 0.0;
-            for (int b = 0; b < d; ++b)
-                pts[np][b] = (b == axis) ? side : fxi[k][n++];
-            ++np;
+    int np = 0;
+    /* volume Gauss points */
+    for (int k = 0; k < nq; ++k) {
+        int rem = k;
+        pts[np][0] = pts[np][1] = pts[np][2] = 0.0;
+        for (int a = 0; a < d; ++a) {
+            pts[np][a] = gx[rem % q];
+            rem /= q;
         }
+        ++np;
     }
+    /* Zhang-Shu points: Lobatto along axis a, Gauss along the others */
+    for (int a = 0; a < d; ++a)
+        for (int l = 0; l < L; ++l)
+            for (int k = 0; k < nfq; ++k) {
+                int rem = k;
+                pts[np][0] = pts[np][1] = pts[np][2] = 0.0;
+                for (int b = 0; b < d; ++b) {
+                    if (b == a) {
+                        pts[np][b] = lx[l];
+                    } else {
+                        pts[np][b] = gx[rem % q];
+                        rem /= q;
+                    }
+                }
+                ++np;
+            }
     double g = f->gamma;
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < f->nleaves; ++i)
@@ -619,37 +837,20 @@ void orc_limit_positivity(const orc_forest *f, double *u)
             for (int k = 0; k < npts; ++k) {
                 double uq[5];
                 eval_poly(f, K, sv, sm, pts[k], uq);
-                if (orc_pressure(d, g, uq) >= eps) continue;
-                double dr = uq[0] - mean[0], dE = uq[d + 1] - mean[d + 1];
-                double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
-                for (int a = 0; a < d; ++a) {
-                    double dm = uq[1 + a] - mean[1 + a];
-                    dm2 += dm * dm;
-                    mdm += mean[1 + a] * dm;
-                    m2 += mean[1 + a] * mean[1 + a];
-                }
-                double A = dr * dE - 0.5 * dm2;
-                double B = mean[0] * dE + mean[d + 1] * dr - mdm - eps * dr / (g - 1.0);
-                double C = mean[0] * mean[d + 1] - 0.5 * m2 - eps * mean[0] / (g - 1.0);
-                double t = 0.0;
-                if (C > 0.0) {
-                    double disc = B * B - 4.0 * A * C;
-                    if (disc < 0.0) disc = 0.0;
-                    double den = -B + sqrt(disc);
-                    t = (den > 0.0) ? 2.0 * C / den : 0.0;
-                    if (t > 1.0) t = 1.0;
-                    if (t < 0.0) t = 0.0;
-                }
+                double pq = orc_pressure(d, g, uq);
+                if (pq >= eps) continue;
+                /* p is concave in U where rho > 0, so along the segment
+                 * p(Ubar + t (U - Ubar)) >= (1 - t) pbar + t p(U): the
+                 * chord reaches eps at t = (pbar - eps) / (pbar - p(U)) */
+                double t = (pbar - eps) / (pbar - pq);
+                if (t > 1.0) t = 1.0;
+                if (t < 0.0) t = 0.0;
                 if (t < th2) th2 = t;
             }
             if (th2 < 1.0)
                 for (int v = 0; v < nv; ++v)
                     for (int m = 1; m < f->nb; ++m) K[v * sv + m * sm] *= th2;
         }
-    free(vxi);
-    free(vw);
-    free(fxi);
-    free(fw);
     free(pts);
 }
 
@@ -674,8 +875,9 @@ void orc_indicator(const orc_forest *f, const double *u, double *eta)
                 if (r < mn) mn = r;
             }
         /* Euler: density ratio over the block and its face guards; scalar
-         * convection (Sec. 5.1): the largest cell average there */
-        eta[i] = f->equation == ORC_EQ_ADVECTION ? mx : mx / mn;
+         * convection and diffusion (Sec. 5.1, 5.2): the largest cell
+         * average there */
+        eta[i] = f->equation == ORC_EQ_EULER ? mx / mn : mx;
     }
     free(g);
 }
@@ -690,13 +892,19 @@ double orc_step(const orc_forest *f, double cfl, double dt_fixed, int limiter, d
     double *g = malloc(sizeof(double) * orc_guard_len(f));
     memcpy(un, u, sizeof(double) * n);
     memcpy(us, u, sizeof(double) * n);
+    /* stage input times of SSP-RK3: t, t + dt, t + dt/2 (Dirichlet data) */
+    const double ct[3] = {0.0, 1.0, 0.5};
+    orc_forest *fm = (orc_forest *)f;
     for (int s = 0; s < 3; ++s) {
+        fm->stage_time = f->time + ct[s] * dt;
         orc_fill_guards(f, us, g);
         orc_residual(f, us, g, r);
         orc_rk_combine(n, s, dt, un, us, r, u);
         if (limiter) orc_limit_positivity(f, u);
         memcpy(us, u, sizeof(double) * n);
     }
+    fm->time += dt;
+    fm->stage_time = fm->time;
     free(un);
     free(us);
     free(r);

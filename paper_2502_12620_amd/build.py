@@ -13,8 +13,9 @@ OBJDIR = os.path.join(HERE, "_build")
 
 HIP_SOURCES = ["dgamr_api.hip", "pool_api.hip"]
 CXX_SOURCES = ["forest.cpp"]
-# degree-templated kernels: one translation unit per (dim, degree)
-INSTANCES = [(d, p) for d in (2, 3) for p in (0, 1, 2, 3)]
+# degree-templated kernels: one translation unit per (dim, degree, part);
+# the parts split the heavy kernels of one (dim, degree) pair (csrc/inst.hip)
+INSTANCES = [(d, p, part) for d in (2, 3) for p in (0, 1, 2, 3) for part in (0, 1, 2)]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fconstexpr-steps=200000000",
@@ -43,18 +44,19 @@ def build(verbose: bool = False) -> str:
     # existing objects of the others (a development shortcut; the default
     # compiles everything)
     only = [x for x in os.environ.get("DGAMR_BUILD_ONLY", "").split(",") if x]
-    for d, p in INSTANCES:
-        o = os.path.join(OBJDIR, f"inst_{d}_{p}.o")
-        if only and f"{d}_{p}" not in only and os.path.exists(o):
+    for d, p, part in INSTANCES:
+        o = os.path.join(OBJDIR, f"inst_{d}_{p}_{part}.o")
+        if only and f"{d}_{p}" not in only and f"{d}_{p}_{part}" not in only and os.path.exists(o):
             objs_keep.append(o)
             continue
-        jobs.append(["hipcc", *HIPFLAGS, f"-DDG_D={d}", f"-DDG_P={p}", "-c", os.path.join(CSRC, "inst.hip"), "-o", o])
+        jobs.append(["hipcc", *HIPFLAGS, f"-DDG_D={d}", f"-DDG_P={p}", f"-DDG_PART={part}", "-c",
+                     os.path.join(CSRC, "inst.hip"), "-o", o])
     for s in CXX_SOURCES:
         o = os.path.join(OBJDIR, s + ".o")
         jobs.append(["g++", "-O2", "-std=c++17", "-fPIC", "-Wall", "-D__HIP_PLATFORM_AMD__",
                      "-I/opt/rocm/include", "-c", os.path.join(CSRC, s), "-o", o])
     # longest first: the 3-D high-degree units dominate
-    jobs.sort(key=lambda j: ("DG_D=3" in " ".join(j), "DG_P=3" in " ".join(j)), reverse=True)
+    jobs.sort(key=lambda j: ("-DDG_D=3" in j, "-DDG_P=3" in j, "-DDG_P=2" in j), reverse=True)
     with ThreadPoolExecutor(max_workers=min(int(os.environ.get("MAX_JOBS", "8")), len(jobs))) as ex:
         logs = list(ex.map(_run, jobs))
     if verbose:

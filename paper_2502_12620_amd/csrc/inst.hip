@@ -1,5 +1,11 @@
 // One (dim, degree) instantiation of the degree-templated kernels and their
-// launchers; compiled once per pair with -DDG_D=<dim> -DDG_P=<degree>.
+// launchers; compiled once per pair with -DDG_D=<dim> -DDG_P=<degree> and
+// -DDG_PART=<part>, the heavy kernels split over parts so that the units
+// compile in parallel:
+//   part 0  the dispatcher launch_stage, the lane-per-(cell, variable)
+//           kernels, scalar convection, fill, limiter, projection, inheritance
+//   part 1  the thread-per-cell Euler stage kernels in FP64
+//   part 2  the thread-per-cell Euler stage kernels with FP32 arithmetic
 #include "kernels.hpp"
 #include "kernels_2d.hpp"
 #include "kernels_3d.hpp"
@@ -11,6 +17,9 @@
 #endif
 #ifndef DG_P
 #error "DG_P must be defined"
+#endif
+#ifndef DG_PART
+#error "DG_PART must be defined"
 #endif
 
 namespace dgk {
@@ -140,6 +149,13 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     return hipErrorInvalidValue;
 }
 
+#if DG_PART == 0
+// defined here, instantiated in parts 1 and 2
+extern template hipError_t launch_stage_cell<DG_D, DG_P, double, EQ_EULER>(const StageArgs &, int, int, bool,
+                                                                          const StageShape &, hipStream_t);
+extern template hipError_t launch_stage_cell<DG_D, DG_P, float, EQ_EULER>(const StageArgs &, int, int, bool,
+                                                                         const StageShape &, hipStream_t);
+
 template <int D, int P>
 hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32, const StageShape &sh, hipStream_t s,
                         int eq)
@@ -211,5 +227,12 @@ template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStr
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,
                                                    double, const double *, hipStream_t, int);
 template hipError_t launch_inherit<DG_D, DG_P>(const double *, double *, const Inherit *, int, long, hipStream_t, int);
+#elif DG_PART == 1
+template hipError_t launch_stage_cell<DG_D, DG_P, double, EQ_EULER>(const StageArgs &, int, int, bool,
+                                                                   const StageShape &, hipStream_t);
+#else
+template hipError_t launch_stage_cell<DG_D, DG_P, float, EQ_EULER>(const StageArgs &, int, int, bool,
+                                                                  const StageShape &, hipStream_t);
+#endif
 
 } // namespace dgk

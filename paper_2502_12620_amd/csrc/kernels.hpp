@@ -358,12 +358,27 @@ __device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Ta
 }
 
 // ------------------------------------------------------------------ positivity limiter
-// Point set of the limiter: volume Gauss points, then the face Gauss
-// points of every face (basis values with the face side's sign).
+// Gauss-Lobatto rule of Zhang and Shu's point set: the fewest points L
+// (L >= 2) whose rule is exact for degree P (2L - 3 >= P); its nodes are
+// -1, +1 and, for L = 3, 0.
+template <int P>
+constexpr int lobatto_points() { return P <= 1 ? 2 : 3; }
+
+// Interior Lobatto nodes that are not Gauss nodes of the (P+1)-point rule
+// (0 for L = 3 with an even number of Gauss points): 1 at degree 3, else 0.
+template <int P>
+constexpr int lobatto_extra() { return (lobatto_points<P>() == 3 && (P + 1) % 2 == 0) ? 1 : 0; }
+
+// Point set of the limiter: the volume Gauss points, then the face Gauss
+// points of every face (basis values with the face side's sign), then for
+// every axis a the points with xi_a = 0 and Gauss nodes on the other axes
+// when 0 is a Lobatto node but not a Gauss node.  Together these are
+// Zhang and Shu's points (Lobatto nodes along one axis, Gauss nodes along
+// the others, over all axes) plus the volume Gauss points.
 template <int D, int P>
 struct LimiterPoints {
     static constexpr int NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF, NB = Tab<D, P>::NB;
-    static constexpr int NPT = NQ + 2 * D * NF;
+    static constexpr int NPT = NQ + 2 * D * NF + lobatto_extra<P>() * D * NF;
     double phi[NPT][NB] = {};
     constexpr LimiterPoints()
     {
@@ -377,6 +392,11 @@ struct LimiterPoints {
                 for (int m = 0; m < NB; ++m)
                     phi[n][m] = kTab<D, P>.phi_f[a][f][m] * ((minus && kTab<D, P>.e[m][a] % 2) ? -1.0 : 1.0);
         }
+        if (lobatto_extra<P>())
+            for (int a = 0; a < D; ++a)
+                for (int f = 0; f < NF; ++f, ++n)
+                    for (int m = 0; m < NB; ++m) // the face point's tangential values times P_{m_a}(0)
+                        phi[n][m] = kTab<D, P>.phi_f[a][f][m] * leg(kTab<D, P>.e[m][a], 0.0);
     }
 };
 template <int D, int P>
@@ -385,9 +405,11 @@ inline constexpr LimiterPoints<D, P> kLimPts{};
 // Zhang-Shu scaling limiter (named in Sec. 5.3.2) on one cell, in place,
 // with eps = min(1e-13, mean rho, p(mean)):
 //   theta1 = min(1, (rho_mean - eps)/(rho_mean - min_S rho)) scales the
-//   non-mean density modes; then theta2 = min over S of the root t in
-//   [0,1) of p(Ubar + t(U - Ubar)) = eps (1 where p >= eps) scales all
-//   non-mean modes.  The cell mean is never changed.
+//   non-mean density modes; then theta2 = min over S of the chord bound
+//   t = (p(mean) - eps)/(p(mean) - p(U)) at the points with p(U) < eps
+//   (pressure is concave in the conserved variables where rho > 0, so the
+//   scaled state keeps p >= eps there) scales all non-mean modes.  The cell
+//   mean is never changed.
 template <int D, int P>
 __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 {
@@ -425,27 +447,10 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
             for (int m = 0; m < NB; ++m) s = fma(kLimPts<D, P>.phi[pt][m], K[v][m], s);
             U[v] = s;
         }
-        if (pressure<D>(U, gm1) < eps) {
-            const double dr = U[0] - mean[0], dE = U[D + 1] - mean[D + 1];
-            double dm2 = 0.0, mdm = 0.0, m2 = 0.0;
-#pragma unroll
-            for (int a = 0; a < D; ++a) {
-                const double dm = U[1 + a] - mean[1 + a];
-                dm2 += dm * dm;
-                mdm += mean[1 + a] * dm;
-                m2 += mean[1 + a] * mean[1 + a];
-            }
-            const double A = dr * dE - 0.5 * dm2;
-            const double B = mean[0] * dE + mean[D + 1] * dr - mdm - eps * dr / gm1;
-            const double C = mean[0] * mean[D + 1] - 0.5 * m2 - eps * mean[0] / gm1;
-            double tq = 0.0;
-            if (C > 0.0) {
-                double disc = B * B - 4.0 * A * C;
-                disc = disc < 0.0 ? 0.0 : disc;
-                const double den = -B + sqrt(disc);
-                tq = den > 0.0 ? 2.0 * C / den : 0.0;
-                tq = tq > 1.0 ? 1.0 : (tq < 0.0 ? 0.0 : tq);
-            }
+        const double pq = pressure<D>(U, gm1);
+        if (pq < eps) {
+            double tq = (pbar - eps) / (pbar - pq);
+            tq = tq > 1.0 ? 1.0 : (tq < 0.0 ? 0.0 : tq);
             th2 = tq < th2 ? tq : th2;
         }
     }

@@ -121,6 +121,26 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
+def check_buffer(t, name, dtype, numel, at_least=False, device_type="cuda"):
+    """Raise ValueError unless `t` is a contiguous torch tensor of `dtype`
+    with `numel` elements (at least `numel` when at_least) on the GPU.  The
+    C-ABI receives bare device pointers without sizes, so a stale or
+    mistyped buffer would be written past its end by the kernels; this is
+    the check that keeps it a Python error."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name}: expected a torch.Tensor, got {type(t).__name__}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: dtype {t.dtype}, expected {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: the tensor must be contiguous")
+    n = t.numel()
+    if (n < numel) if at_least else (n != numel):
+        raise ValueError(f"{name}: {n} elements, expected {'at least ' if at_least else ''}{numel} "
+                         "(sized for another forest, or for this forest before a refinement?)")
+    if t.device.type != device_type:
+        raise ValueError(f"{name}: on {t.device}, expected a {device_type} device tensor")
+
+
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
@@ -154,6 +174,7 @@ class Forest:
         h = ctypes.c_void_p()
         _check(lib().dgamr_create_forest(ctypes.byref(d), ctypes.byref(h)))
         self.h = h
+        self._planned = None
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:
@@ -201,16 +222,43 @@ class Forest:
     def new_work(self, device="cuda"):
         return torch.zeros(self.sizes()[3] // 8, dtype=torch.float64, device=device)
 
+    # ---- buffer checks (the C-ABI takes bare pointers)
+    def _state_elems(self):
+        return self.n_leaves * self.nv * self.nb * self.ncell
+
+    def _chk_state(self, t, name="u"):
+        check_buffer(t, name, torch.float64, self._state_elems())
+
+    def _chk_guard(self, t, name="guard"):
+        check_buffer(t, name, torch.float64, self.sizes()[1] // 8)
+
+    def _chk_res(self, t, name="r"):
+        dt = torch.float32 if self.precision == FP32_MFMA else torch.float64
+        check_buffer(t, name, dt, self._state_elems())
+
+    def _chk_work(self, t, name="work"):
+        check_buffer(t, name, torch.float64, (self.sizes()[3] + 7) // 8, at_least=True)
+
+    def _chk_dt(self, t, name="dt_dev"):
+        check_buffer(t, name, torch.float64, 1, at_least=True)
+
     # ---- C-ABI calls
     def set_refinement(self, flags) -> int:
         f = torch.as_tensor(flags, dtype=torch.int8).contiguous()
-        assert f.numel() == self.n_leaves
+        if f.numel() != self.n_leaves:
+            raise ValueError(f"flags: {f.numel()} entries for {self.n_leaves} leaves")
         n = ctypes.c_int64()
         _check(lib().dgamr_set_refinement(self.h, _ptr(f), ctypes.byref(n)))
+        self._planned = n.value
         return n.value
 
     def apply_refinement(self, u_old, u_new, stream=None):
         """u_new: caller-allocated state of the size set_refinement returned."""
+        self._chk_state(u_old, "u_old")
+        if self._planned is None:
+            raise ValueError("apply_refinement: no refinement plan pending (call set_refinement first)")
+        check_buffer(u_new, "u_new", torch.float64, self._planned * self.nv * self.nb * self.ncell)
+        self._planned = None
         _check(lib().dgamr_apply_refinement(self.h, _ptr(u_old), _ptr(u_new), _stream(stream)))
 
     def adapt(self, flags, u_old, stream=None):
@@ -221,42 +269,70 @@ class Forest:
         return u_new
 
     def fill_guardcells(self, u, guard, stream=None):
+        self._chk_state(u)
+        self._chk_guard(guard)
         _check(lib().dgamr_fill_guardcells(self.h, _ptr(u), _ptr(guard), _stream(stream)))
 
     def dg_residual(self, u, guard, r, stream=None):
+        self._chk_state(u)
+        self._chk_guard(guard)
+        self._chk_res(r)
         _check(lib().dgamr_dg_residual(self.h, _ptr(u), _ptr(guard), _ptr(r), _stream(stream)))
 
     def rk_stage(self, stage, dt_dev, u_n, u_s, r, u_next, stream=None):
+        self._chk_dt(dt_dev)
+        if stage > 0:
+            self._chk_state(u_n, "u_n")
+        self._chk_state(u_s, "u_s")
+        self._chk_res(r)
+        self._chk_state(u_next, "u_next")
         _check(lib().dgamr_rk_stage(self.h, stage, _ptr(dt_dev), _ptr(u_n), _ptr(u_s), _ptr(r), _ptr(u_next),
                                     _stream(stream)))
 
     def compute_dt(self, cfl, u, dt_dev, work, stream=None):
+        self._chk_state(u)
+        self._chk_dt(dt_dev)
+        self._chk_work(work)
         _check(lib().dgamr_compute_dt(self.h, cfl, _ptr(u), _ptr(dt_dev), _ptr(work), _stream(stream)))
 
     def step(self, u, work, dt_dev, cfl=0.1, stream=None):
         """One SSP-RK3 step in place; cfl <= 0 uses the dt already in dt_dev."""
+        self._chk_state(u)
+        self._chk_work(work)
+        self._chk_dt(dt_dev)
         _check(lib().dgamr_step(self.h, cfl, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
 
     def run(self, u, work, dt_dev, nsteps, cfl=0.1, stream=None):
         """nsteps SSP-RK3 steps in place, three launches per step."""
+        self._chk_state(u)
+        self._chk_work(work)
+        self._chk_dt(dt_dev)
         _check(lib().dgamr_run(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
 
     def capture_run(self, u, work, dt_dev, nsteps, cfl=0.1):
         """nsteps steps of run() captured into a HIP graph (RunGraph); each
         launch advances u by nsteps steps."""
+        self._chk_state(u)
+        self._chk_work(work)
+        self._chk_dt(dt_dev)
         h = ctypes.c_void_p()
         _check(lib().dgamr_run_capture(self.h, cfl, nsteps, _ptr(u), _ptr(work), _ptr(dt_dev), ctypes.byref(h)))
         return RunGraph(h, keep=(self, u, work, dt_dev))
 
     def conserved_totals(self, u, work, stream=None):
+        self._chk_state(u)
+        self._chk_work(work)
         t = torch.zeros(self.nv, dtype=torch.float64, device=u.device)
         _check(lib().dgamr_conserved_totals(self.h, _ptr(u), _ptr(t), _ptr(work), _stream(stream)))
         return t
 
     def limit_positivity(self, u, stream=None):
+        self._chk_state(u)
         _check(lib().dgamr_limit_positivity(self.h, _ptr(u), _stream(stream)))
 
     def indicator(self, u, work, stream=None):
+        self._chk_state(u)
+        self._chk_work(work)
         eta = torch.zeros(self.n_leaves, dtype=torch.float64, device=u.device)
         _check(lib().dgamr_indicator(self.h, _ptr(u), _ptr(eta), _ptr(work), _stream(stream)))
         return eta
@@ -264,11 +340,14 @@ class Forest:
     def project_ic(self, kind, params, t=0.0, u=None, stream=None):
         if u is None:
             u = self.new_state()
+        self._chk_state(u)
         prm = (ctypes.c_double * 8)(*(list(params) + [0.0] * (8 - len(params))))
         _check(lib().dgamr_project_ic(self.h, kind, prm, t, _ptr(u), _stream(stream)))
         return u
 
     def check_state(self, u, work, stream=None) -> int:
+        self._chk_state(u)
+        self._chk_work(work)
         bad = ctypes.c_int64()
         rc = lib().dgamr_check_state(self.h, _ptr(u), ctypes.byref(bad), _ptr(work), _stream(stream))
         if rc not in (OK, ENONPHYSICAL):

@@ -93,3 +93,25 @@ def test_pool_and_graph_arguments_are_checked_before_any_device_call():
     assert L.dgamr_run_capture(None, ctypes.c_double(0.1), 1, None, None, None, None) == G.EINVAL
     assert L.dgamr_pool_destroy(None) == G.OK
     assert L.dgamr_graph_destroy(None) == G.OK
+
+
+def test_binding_buffer_checks_on_the_host():
+    """The binding's buffer check (the C-ABI takes bare pointers) refuses a
+    wrong dtype, a non-contiguous view, a stale size and a host tensor, in
+    that order, before anything reaches the library."""
+    torch = pytest.importorskip("torch")
+    from paper_2502_12620_amd import dgamr as G
+
+    t = torch.zeros(12, dtype=torch.float64)
+    with pytest.raises(ValueError, match="dtype"):
+        G.check_buffer(t.float(), "u", torch.float64, 12)
+    with pytest.raises(ValueError, match="contiguous"):
+        G.check_buffer(torch.zeros(4, 6, dtype=torch.float64).t(), "u", torch.float64, 24)
+    with pytest.raises(ValueError, match="13"):
+        G.check_buffer(t, "u", torch.float64, 13)
+    with pytest.raises(ValueError, match="at least 20"):
+        G.check_buffer(t, "work", torch.float64, 20, at_least=True)
+    with pytest.raises(ValueError, match="device"):
+        G.check_buffer(t, "u", torch.float64, 12)
+    G.check_buffer(t, "u", torch.float64, 12, device_type="cpu")
+    G.check_buffer(t, "work", torch.float64, 8, at_least=True, device_type="cpu")
