@@ -153,6 +153,21 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
 int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev,
                hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * dgamr_step without the caller's work buffer.  The work area is a static
+ * device array of DGAMR_STATIC_WORK_BYTES (256 MiB) that the library holds
+ * on every GPU it runs on until the process ends; nothing is allocated or
+ * freed here, and no events are recorded.  Same launches and results as
+ * dgamr_step (cfl > 0: CFL time step; cfl <= 0: dt from dt_dev).  A forest
+ * whose work area (dgamr_state_bytes) exceeds the array fails with
+ * DGAMR_EUNSUPPORTED before anything is launched.  Every call on one GPU
+ * shares that GPU's array and leaves its contents behind: calls that
+ * overlap on one GPU (two streams, or two threads) race.  The forest's
+ * device must be current. */
+#define DGAMR_STATIC_WORK_BYTES (256u << 20)
+int dgamr_step_static(dgamr_forest *f, double cfl, double *u, double *dt_dev, hipStream_t stream);
+
 /* Sec. 4.3 step 2 repeated: nsteps SSP-RK3 steps in place on u, three
  * kernel launches per step.  With cfl > 0 the CFL time step of each step
  * after the first is folded into the previous step's last stage (its

@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdgamr.so")
 OBJDIR = os.path.join(HERE, "_build")
 
-HIP_SOURCES = ["dgamr_api.hip", "pool_api.hip"]
+HIP_SOURCES = ["dgamr_api.hip", "pool_api.hip", "static_api.hip"]
 CXX_SOURCES = ["forest.cpp"]
 # degree-templated kernels: one translation unit per (dim, degree, part);
 # the parts split the heavy kernels of one (dim, degree) pair (csrc/inst.hip)

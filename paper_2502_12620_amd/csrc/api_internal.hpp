@@ -84,6 +84,13 @@ struct dgamr_forest {
     explicit dgamr_forest(const dgamr_forest_desc &d) : topo(d) {}
 };
 
+namespace dgapi {
+// one dgamr_step with `work` as the work buffer (at least work_bytes_of(f)
+// bytes), recording no events
+int step_in_work(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev, hipStream_t stream);
+size_t work_bytes_of(const dgamr_forest *f);
+} // namespace dgapi
+
 // A captured HIP graph of steps (of one forest, or of several pools).  It
 // records the version counters of what it was captured from; launching it
 // after any of them changed is refused.

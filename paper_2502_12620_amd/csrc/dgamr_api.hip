@@ -414,6 +414,25 @@ int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_de
     return run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream);
 }
 
+} // extern "C"
+
+// dgamr_step with a work area the caller does not own (the static one of
+// dgamr_step_static): the same launches, no events recorded.
+int dgapi::step_in_work(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev, hipStream_t stream)
+{
+    Work w = carve(f, work);
+    if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
+    const bool prof_was = f->prof;
+    f->prof = false;
+    const int rc = run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream);
+    f->prof = prof_was;
+    return rc;
+}
+
+size_t dgapi::work_bytes_of(const dgamr_forest *f) { return work_elems(f) * sizeof(double); }
+
+extern "C" {
+
 int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, double *dt_dev, hipStream_t stream)
 {
     CHECK(check_ptr(f, "forest"));

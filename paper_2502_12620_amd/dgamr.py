@@ -33,7 +33,7 @@ EXPORTS = [
     "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
     "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_set_lanes", "dgamr_pool_autotune",
     "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture",
-    "dgamr_last_error",
+    "dgamr_step_static", "dgamr_last_error",
 ]
 
 
@@ -76,6 +76,7 @@ def lib():
         L.dgamr_rk_stage.argtypes = [vp, ctypes.c_int, vp, vp, vp, vp, vp, vp]
         L.dgamr_compute_dt.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
         L.dgamr_step.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
+        L.dgamr_step_static.argtypes = [vp, ctypes.c_double, vp, vp, vp]
         L.dgamr_run.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
         L.dgamr_conserved_totals.argtypes = [vp, vp, vp, vp, vp]
         L.dgamr_limit_positivity.argtypes = [vp, vp, vp]
@@ -301,6 +302,13 @@ class Forest:
         self._chk_work(work)
         self._chk_dt(dt_dev)
         _check(lib().dgamr_step(self.h, cfl, _ptr(u), _ptr(work), _ptr(dt_dev), _stream(stream)))
+
+    def step_static(self, u, dt_dev, cfl=0.1, stream=None):
+        """One SSP-RK3 step in place with the library's static work area
+        (dgamr_step_static: allocates nothing)."""
+        self._chk_state(u)
+        self._chk_dt(dt_dev)
+        _check(lib().dgamr_step_static(self.h, cfl, _ptr(u), _ptr(dt_dev), _stream(stream)))
 
     def run(self, u, work, dt_dev, nsteps, cfl=0.1, stream=None):
         """nsteps SSP-RK3 steps in place, three launches per step."""
