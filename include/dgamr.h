@@ -57,16 +57,21 @@ enum {
     DGAMR_EFULL = -7         /* a pool has no free slot range or member id */
 };
 
-enum { DGAMR_BC_PERIODIC = 0, DGAMR_BC_OUTFLOW = 1 };
+/* Non-periodic faces: outflow (Euler, Sec. 5.3.1) or Dirichlet data from the
+ * exact solution (diffusion only, Sec. 5.2). */
+enum { DGAMR_BC_PERIODIC = 0, DGAMR_BC_OUTFLOW = 1, DGAMR_BC_DIRICHLET = 2 };
 enum { DGAMR_FP64 = 0, DGAMR_FP32_MFMA = 1 };
 enum { DGAMR_HANG_PAPER = 0, DGAMR_HANG_CONSERVATIVE = 1 };
 enum { DGAMR_LIMITER_NONE = 0, DGAMR_LIMITER_POSITIVITY = 1 };
-enum { DGAMR_IC_VORTEX = 0, DGAMR_IC_SEDOV = 1, DGAMR_IC_UNIFORM = 2, DGAMR_IC_XWAVE = 3, DGAMR_IC_COSINE = 4 };
-/* Conservation law: the Euler equations (Sec. 2, Eq. 1-5, 23; d+2
- * variables) or the linear scalar convection equation u_t + vel . grad u = 0
- * of Sec. 5.1 (one variable; Rusanov flux with alpha = |vel . n|, i.e.
- * upwind). */
-enum { DGAMR_EQ_EULER = 0, DGAMR_EQ_ADVECTION = 1 };
+enum { DGAMR_IC_VORTEX = 0, DGAMR_IC_SEDOV = 1, DGAMR_IC_UNIFORM = 2, DGAMR_IC_XWAVE = 3, DGAMR_IC_COSINE = 4,
+       DGAMR_IC_EXP = 5 };
+/* Equation: the Euler equations (Sec. 2, Eq. 1-5, 23; d+2 variables), the
+ * linear scalar convection equation u_t + vel . grad u = 0 of Sec. 5.1 (one
+ * variable; Rusanov flux with alpha = |vel . n|, i.e. upwind), or the
+ * diffusion equation u_t = nu div grad u of Sec. 5.2 (one variable;
+ * symmetric interior-penalty DG with penalty 2 (p+1)^2 / h, Dirichlet data on
+ * non-periodic faces from the exact solution exp(a . x + nu |a|^2 t)). */
+enum { DGAMR_EQ_EULER = 0, DGAMR_EQ_ADVECTION = 1, DGAMR_EQ_DIFFUSION = 2 };
 
 typedef struct {
     int dim;          /* 2 or 3 */
@@ -82,8 +87,13 @@ typedef struct {
     int hanging;      /* DGAMR_HANG_PAPER (guard-cell fluxes, Sec. 3.5) or
                          DGAMR_HANG_CONSERVATIVE (coarse side lifts the fine-side flux) */
     int limiter;      /* DGAMR_LIMITER_* applied after each stage by dgamr_step */
-    int equation;     /* DGAMR_EQ_*; scalar convection requires FP64 and no limiter */
+    int equation;     /* DGAMR_EQ_*; scalar convection and diffusion require FP64
+                         and no limiter; diffusion degree >= 1, bc periodic or
+                         Dirichlet, paper hanging mode */
     double velocity[3]; /* convection velocity (DGAMR_EQ_ADVECTION) */
+    double diffusivity; /* nu (DGAMR_EQ_DIFFUSION), > 0 */
+    double exact_a[3];  /* a of the exact solution exp(a . x + nu |a|^2 t) that
+                           gives the Dirichlet data (DGAMR_EQ_DIFFUSION) */
 } dgamr_forest_desc;
 
 typedef struct dgamr_forest dgamr_forest;
@@ -138,9 +148,20 @@ int dgamr_rk_stage(dgamr_forest *f, int stage, const double *dt_dev, const doubl
                    const double *u_s, const void *r, double *u_next, hipStream_t stream);
 
 /* Sec. 4.3 step 2(a): dt = cfl / max over cells of sum_a (|u_a| + c)/h_a
- * from the cell means, written to device memory. */
+ * from the cell means, written to device memory.  Scalar convection: the
+ * same with |vel_a| for |u_a| + c; diffusion: dt = cfl / max over cells of
+ * nu sum_a 1/h_a^2 (a diffusive CFL number; explicit SSP-RK3 with the
+ * penalty above is stable for cfl up to about 0.04 / 0.01 / 0.004 at
+ * p = 1 / 2 / 3). */
 int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, void *work,
                      hipStream_t stream);
+
+/* Time of the state of a diffusion forest (the Dirichlet data of a stage is
+ * the exact solution at the stage's time: t, t + dt, t + dt/2).  dgamr_step
+ * and dgamr_run advance it by each step's dt; dgamr_dg_residual uses it.
+ * Host calls; other equations keep but do not use it. */
+int dgamr_set_time(dgamr_forest *f, double t);
+int dgamr_get_time(const dgamr_forest *f, double *t);
 
 /* Sec. 4.3 step 2: one SSP-RK3 time step, in place on u: dt from the CFL
  * condition (cfl > 0) or taken from dt_dev (cfl <= 0), then per stage the
@@ -149,7 +170,12 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
  * computed inside the stage kernel straight from the neighbours' cells (same
  * values as dgamr_fill_guardcells); only the 3-D lane-per-(cell, variable)
  * kernel reads guard traces that a fill kernel writes into the work buffer
- * before each stage.  Asynchronous; captures into a HIP graph. */
+ * before each stage.  Asynchronous; captures into a HIP graph.  Diffusion
+ * forests (cfl > 0 required; dt computed on the host from the forest's
+ * finest cells and written to dt_dev): per stage the guard fill of
+ * coefficients into the work buffer, then the interior-penalty residual and
+ * stage update with the Dirichlet data at the stage time; the forest's time
+ * advances by dt (so a graph replay would repeat the times: not captured). */
 int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev,
                hipStream_t stream);
 

@@ -81,6 +81,7 @@ struct dgamr_forest {
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
     long version = 0;        // bumped by every topology change
+    double time = 0.0;       // time of the state (Dirichlet data of a diffusion forest)
     explicit dgamr_forest(const dgamr_forest_desc &d) : topo(d) {}
 };
 

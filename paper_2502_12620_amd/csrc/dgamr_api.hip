@@ -2,6 +2,7 @@
 // refinement, and the launches of the HIP kernels.  See include/dgamr.h.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <exception>
@@ -139,7 +140,7 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
 
 int launch_limit(dgamr_forest *f, double *u, hipStream_t s)
 {
-    if (f->topo.advection()) return fail(DGAMR_EINVAL, "the positivity limiter is for the Euler equations");
+    if (f->topo.scalar()) return fail(DGAMR_EINVAL, "the positivity limiter is for the Euler equations");
     long total = long(f->topo.n()) * ncell_of(f);
     if (total == 0) return DGAMR_OK;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
@@ -178,6 +179,67 @@ int take_event(dgamr_forest *f, hipEvent_t &e)
         e = f->ev_free.back();
         f->ev_free.pop_back();
     }
+    return DGAMR_OK;
+}
+
+// Diffusion: dt = cfl / max over cells of nu sum_a 1/h_a^2 (the finest
+// cells), on the host.
+double diffusion_dt(const dgamr_forest *f, double cfl)
+{
+    const auto &d = f->topo.desc();
+    int lmax = 1;
+    for (const auto &k : f->topo.leaves()) lmax = k.level > lmax ? k.level : lmax;
+    double rate = 0.0;
+    for (int a = 0; a < f->topo.dim(); ++a) {
+        const double h = (d.hi[a] - d.lo[a]) / (double(d.roots[a]) * d.n_cell * double(1L << (lmax - 1)));
+        rate += d.diffusivity / (h * h);
+    }
+    return cfl / rate;
+}
+
+int launch_ipdg(dgamr_forest *f, const double *us, const double *un, const double *guard, double *out,
+                const double *dt_dev, double rk_a, double rk_b, double t, int om, hipStream_t s)
+{
+    const auto &d = f->topo.desc();
+    dgk::IpdgArgs a{};
+    a.us = us;
+    a.un = un;
+    a.guard = guard;
+    a.out = out;
+    a.geo = f->d_geo;
+    a.links = f->d_links;
+    a.dt = dt_dev;
+    a.rk_a = rk_a;
+    a.rk_b = rk_b;
+    a.nu = d.diffusivity;
+    for (int k = 0; k < 3; ++k) a.avec[k] = k < f->topo.dim() ? d.exact_a[k] : 0.0;
+    a.t = t;
+    a.ncell_total = long(f->topo.n()) * ncell_of(f);
+    a.N = d.n_cell;
+    return dispatch(f->topo.dim(), d.degree, [&](auto D, auto P) -> int {
+        HIP_TRY((dgk::launch_ipdg<D, P>(a, om, s)));
+        return DGAMR_OK;
+    });
+}
+
+// One SSP-RK3 step of a diffusion forest: dt from the host, per stage the
+// guard fill (coefficients) and the fused interior-penalty stage with the
+// Dirichlet data at the stage time (t, t + dt, t + dt/2).
+int step_diffusion(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_dev, hipStream_t s)
+{
+    if (!(cfl > 0.0)) return fail(DGAMR_EINVAL, "a diffusion step needs cfl > 0 (its time step is set on the host)");
+    const double dt = diffusion_dt(f, cfl);
+    hipLaunchKernelGGL(dgk::k_set_value, dim3(1), dim3(1), 0, s, dt_dev, dt);
+    HIP_TRY(hipGetLastError());
+    static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0}, C[3] = {0.0, 1.0, 0.5};
+    const double *us = u;
+    double *outs[3] = {w.u1, w.u2, u};
+    for (int st = 0; st < 3; ++st) {
+        CHECK(launch_fill(f, us, w.guard, false, s));
+        CHECK(launch_ipdg(f, us, u, w.guard, outs[st], dt_dev, A[st], B[st], f->time + C[st] * dt, dgk::OUT_RK, s));
+        us = outs[st];
+    }
+    f->time += dt;
     return DGAMR_OK;
 }
 
@@ -317,6 +379,9 @@ int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, voi
     CHECK(check_ptr(u, "u"));
     CHECK(check_ptr(guard, "guard"));
     CHECK(check_ptr(r, "r"));
+    if (f->topo.diffusion())
+        return launch_ipdg(f, u, nullptr, guard, static_cast<double *>(r), nullptr, 0.0, 1.0, f->time, dgk::OUT_RES64,
+                           stream);
     dgk::StageArgs a{};
     a.us = u;
     a.guard = guard;
@@ -354,6 +419,11 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
     CHECK(check_ptr(dt_dev, "dt_dev"));
     CHECK(check_ptr(work, "work"));
     if (!(cfl > 0.0)) return fail(DGAMR_EINVAL, "cfl must be positive");
+    if (f->topo.diffusion()) {
+        hipLaunchKernelGGL(dgk::k_set_value, dim3(1), dim3(1), 0, stream, dt_dev, diffusion_dt(f, cfl));
+        HIP_TRY(hipGetLastError());
+        return DGAMR_OK;
+    }
     return launch_dt(f, cfl, u, dt_dev, carve(f, work), stream);
 }
 
@@ -410,8 +480,25 @@ int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_de
     CHECK(check_ptr(work, "work"));
     CHECK(check_ptr(dt_dev, "dt_dev"));
     Work w = carve(f, work);
+    if (f->topo.diffusion()) return step_diffusion(f, cfl, u, w, dt_dev, stream);
     if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
     return run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream);
+}
+
+int dgamr_set_time(dgamr_forest *f, double t)
+{
+    CHECK(check_ptr(f, "forest"));
+    if (!std::isfinite(t)) return fail(DGAMR_EINVAL, "time must be finite");
+    f->time = t;
+    return DGAMR_OK;
+}
+
+int dgamr_get_time(const dgamr_forest *f, double *t)
+{
+    CHECK(check_ptr(f, "forest"));
+    CHECK(check_ptr(t, "t"));
+    *t = f->time;
+    return DGAMR_OK;
 }
 
 } // extern "C"
@@ -421,6 +508,7 @@ int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_de
 int dgapi::step_in_work(dgamr_forest *f, double cfl, double *u, void *work, double *dt_dev, hipStream_t stream)
 {
     Work w = carve(f, work);
+    if (f->topo.diffusion()) return step_diffusion(f, cfl, u, w, dt_dev, stream);
     if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
     const bool prof_was = f->prof;
     f->prof = false;
@@ -442,6 +530,10 @@ int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, do
     if (nsteps < 0) return fail(DGAMR_EINVAL, "nsteps must be >= 0");
     if (nsteps == 0) return DGAMR_OK;
     Work w = carve(f, work);
+    if (f->topo.diffusion()) {
+        for (int s = 0; s < nsteps; ++s) CHECK(step_diffusion(f, cfl, u, w, dt_dev, stream));
+        return DGAMR_OK;
+    }
     auto *slot = reinterpret_cast<unsigned long long *>(w.scal + 2);
     if (cfl <= 0.0) {
         for (int s = 0; s < nsteps; ++s) CHECK(run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream));
@@ -469,6 +561,8 @@ int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *
         *out = nullptr;
         if (!(cfl > 0.0)) return fail(DGAMR_EINVAL, "cfl must be positive");
         if (nsteps <= 0) return fail(DGAMR_EINVAL, "nsteps must be positive");
+        if (f->topo.diffusion())
+            return fail(DGAMR_EUNSUPPORTED, "diffusion steps take their stage times from the host: not captured");
         Work w = carve(f, work);
         auto *slot = reinterpret_cast<unsigned long long *>(w.scal + 2);
         hipStream_t s;
@@ -522,7 +616,7 @@ int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev,
     if (n == 0) return fail(DGAMR_EINVAL, "empty forest");
     int bp = 1;
     while (bp < block) bp <<= 1; // power of two for the tree reduction
-    if (f->topo.advection()) {
+    if (f->topo.scalar()) {
         if (f->topo.dim() == 2)
             hipLaunchKernelGGL((dgk::k_totals_leaf<2, 1>), dim3(n), dim3(bp), 0, stream, u, f->d_geo,
                                f->topo.desc().n_cell, nb_of(f), w.part);
@@ -560,10 +654,10 @@ int dgamr_indicator(dgamr_forest *f, const double *u, double *eta_dev, void *wor
     CHECK(launch_fill(f, u, w.guard, false, stream));
     int n = f->topo.n();
     if (n == 0) return DGAMR_OK;
-    if (f->topo.advection() && f->topo.dim() == 2)
+    if (f->topo.scalar() && f->topo.dim() == 2)
         hipLaunchKernelGGL((dgk::k_indicator_leaf<2, 1>), dim3(n), dim3(256), 0, stream, u, w.guard,
                            f->topo.desc().n_cell, nb_of(f), eta_dev);
-    else if (f->topo.advection())
+    else if (f->topo.scalar())
         hipLaunchKernelGGL((dgk::k_indicator_leaf<3, 1>), dim3(n), dim3(256), 0, stream, u, w.guard,
                            f->topo.desc().n_cell, nb_of(f), eta_dev);
     else if (f->topo.dim() == 2)
@@ -581,14 +675,19 @@ int dgamr_project_ic(dgamr_forest *f, int kind, const double *params, double t, 
     CHECK(check_ptr(f, "forest"));
     CHECK(check_ptr(params, "params"));
     CHECK(check_ptr(u, "u"));
-    if (kind < DGAMR_IC_VORTEX || kind > DGAMR_IC_COSINE) return fail(DGAMR_EINVAL, "unknown initial condition");
-    if ((kind == DGAMR_IC_COSINE) != f->topo.advection())
-        return fail(DGAMR_EINVAL, "DGAMR_IC_COSINE is the scalar convection state, the others are Euler states");
+    if (kind < DGAMR_IC_VORTEX || kind > DGAMR_IC_EXP) return fail(DGAMR_EINVAL, "unknown initial condition");
+    if ((kind == DGAMR_IC_COSINE) != f->topo.advection() || (kind == DGAMR_IC_EXP) != f->topo.diffusion())
+        return fail(DGAMR_EINVAL, "DGAMR_IC_COSINE is the scalar convection state, DGAMR_IC_EXP the diffusion "
+                                  "state, the others are Euler states");
     dgk::IcParams prm;
     std::memcpy(prm.p, params, sizeof(prm.p));
     const auto &d = f->topo.desc();
     if (kind == DGAMR_IC_COSINE)
         for (int a = 0; a < 3; ++a) prm.p[4 + a] = d.velocity[a]; // translation of the exact solution
+    if (kind == DGAMR_IC_EXP) { // the forest's exact solution
+        for (int a = 0; a < 3; ++a) prm.p[a] = d.exact_a[a];
+        prm.p[3] = d.diffusivity;
+    }
     double hmin[3];
     for (int a = 0; a < 3; ++a)
         hmin[a] = (d.hi[a] - d.lo[a]) / (double(d.roots[a]) * d.n_cell * double(1 << (d.max_level - 1)));
@@ -613,10 +712,10 @@ int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work
     long total = long(f->topo.n()) * ncell_of(f);
     if (total > 0) {
         dim3 grid(unsigned((total + 255) / 256)), block(256);
-        if (f->topo.advection() && f->topo.dim() == 2)
+        if (f->topo.scalar() && f->topo.dim() == 2)
             hipLaunchKernelGGL((dgk::k_check<2, 1>), grid, block, 0, stream, u, f->topo.desc().n_cell, nb_of(f), total,
                                f->topo.desc().gamma, cnt);
-        else if (f->topo.advection())
+        else if (f->topo.scalar())
             hipLaunchKernelGGL((dgk::k_check<3, 1>), grid, block, 0, stream, u, f->topo.desc().n_cell, nb_of(f), total,
                                f->topo.desc().gamma, cnt);
         else if (f->topo.dim() == 2)

@@ -38,7 +38,14 @@ int Forest::validate(const dgamr_forest_desc &d, std::string &err)
     for (int a = 0; a < d.dim; ++a) {
         if (d.roots[a] < 1) { err = "roots must be >= 1"; return DGAMR_EINVAL; }
         if (!(d.hi[a] > d.lo[a])) { err = "hi must exceed lo"; return DGAMR_EINVAL; }
-        if (d.bc[a] != DGAMR_BC_PERIODIC && d.bc[a] != DGAMR_BC_OUTFLOW) { err = "bad bc"; return DGAMR_EINVAL; }
+        if (d.bc[a] != DGAMR_BC_PERIODIC && d.bc[a] != DGAMR_BC_OUTFLOW && d.bc[a] != DGAMR_BC_DIRICHLET) {
+            err = "bad bc";
+            return DGAMR_EINVAL;
+        }
+        if ((d.bc[a] == DGAMR_BC_DIRICHLET) != (d.equation == DGAMR_EQ_DIFFUSION && d.bc[a] != DGAMR_BC_PERIODIC)) {
+            err = "Dirichlet faces belong to the diffusion equation, whose non-periodic faces are Dirichlet";
+            return DGAMR_EINVAL;
+        }
         ntree *= d.roots[a];
     }
     if (ntree >= (1L << 24)) { err = "too many roots"; return DGAMR_EUNSUPPORTED; }
@@ -46,7 +53,19 @@ int Forest::validate(const dgamr_forest_desc &d, std::string &err)
     if (d.precision != DGAMR_FP64 && d.precision != DGAMR_FP32_MFMA) { err = "bad precision"; return DGAMR_EINVAL; }
     if (d.hanging != DGAMR_HANG_PAPER && d.hanging != DGAMR_HANG_CONSERVATIVE) { err = "bad hanging mode"; return DGAMR_EINVAL; }
     if (d.limiter != DGAMR_LIMITER_NONE && d.limiter != DGAMR_LIMITER_POSITIVITY) { err = "bad limiter"; return DGAMR_EINVAL; }
-    if (d.equation != DGAMR_EQ_EULER && d.equation != DGAMR_EQ_ADVECTION) { err = "bad equation"; return DGAMR_EINVAL; }
+    if (d.equation != DGAMR_EQ_EULER && d.equation != DGAMR_EQ_ADVECTION && d.equation != DGAMR_EQ_DIFFUSION) {
+        err = "bad equation";
+        return DGAMR_EINVAL;
+    }
+    if (d.equation == DGAMR_EQ_DIFFUSION) {
+        if (d.limiter != DGAMR_LIMITER_NONE) { err = "the positivity limiter is for the Euler equations"; return DGAMR_EINVAL; }
+        if (d.precision != DGAMR_FP64) { err = "diffusion is built in FP64 only"; return DGAMR_EUNSUPPORTED; }
+        if (d.hanging != DGAMR_HANG_PAPER) { err = "diffusion takes hanging faces from guard cells only"; return DGAMR_EUNSUPPORTED; }
+        if (d.degree < 1) { err = "the interior-penalty method needs degree >= 1"; return DGAMR_EUNSUPPORTED; }
+        if (!(d.diffusivity > 0.0) || !std::isfinite(d.diffusivity)) { err = "diffusivity must be positive"; return DGAMR_EINVAL; }
+        for (int a = 0; a < 3; ++a)
+            if (!std::isfinite(d.exact_a[a])) { err = "exact_a must be finite"; return DGAMR_EINVAL; }
+    }
     if (d.equation == DGAMR_EQ_ADVECTION) {
         if (d.limiter != DGAMR_LIMITER_NONE) { err = "the positivity limiter is for the Euler equations"; return DGAMR_EINVAL; }
         if (d.precision != DGAMR_FP64) { err = "scalar convection is built in FP64 only"; return DGAMR_EUNSUPPORTED; }

@@ -60,9 +60,11 @@ class Forest {
     static int validate(const dgamr_forest_desc &d, std::string &err);
 
     int dim() const { return desc_.dim; }
-    // conserved variables per cell: d + 2 (Euler) or 1 (scalar convection)
-    int nv() const { return desc_.equation == DGAMR_EQ_ADVECTION ? 1 : desc_.dim + 2; }
+    // variables per cell: d + 2 (Euler) or 1 (scalar convection, diffusion)
+    int nv() const { return scalar() ? 1 : desc_.dim + 2; }
     bool advection() const { return desc_.equation == DGAMR_EQ_ADVECTION; }
+    bool diffusion() const { return desc_.equation == DGAMR_EQ_DIFFUSION; }
+    bool scalar() const { return desc_.equation != DGAMR_EQ_EULER; }
     int n() const { return static_cast<int>(leaves_.size()); }
     const std::vector<Key> &leaves() const { return leaves_; }
     const std::vector<FaceLink> &links() const { return links_; }

@@ -6,10 +6,12 @@
 //           kernels, scalar convection, fill, limiter, projection, inheritance
 //   part 1  the thread-per-cell Euler stage kernels in FP64
 //   part 2  the thread-per-cell Euler stage kernels with FP32 arithmetic
+//   part 3  the diffusion stage
 #include "kernels.hpp"
 #include "kernels_2d.hpp"
 #include "kernels_3d.hpp"
 #include "kernels_aux.hpp"
+#include "kernels_ipdg.hpp"
 #include "launch.hpp"
 
 #ifndef DG_D
@@ -227,6 +229,18 @@ template hipError_t launch_limit<DG_D, DG_P>(double *, int, long, double, hipStr
 template hipError_t launch_project_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,
                                                    double, const double *, hipStream_t, int);
 template hipError_t launch_inherit<DG_D, DG_P>(const double *, double *, const Inherit *, int, long, hipStream_t, int);
+#elif DG_PART == 3
+template <int D, int P>
+hipError_t launch_ipdg(const IpdgArgs &a, int om, hipStream_t s)
+{
+    if (a.ncell_total == 0) return hipSuccess;
+    const dim3 grid(unsigned((a.ncell_total + 255) / 256)), block(256);
+    if (om == OUT_RES64) hipLaunchKernelGGL((k_ipdg<D, P, OUT_RES64>), grid, block, 0, s, a);
+    else if (om == OUT_RK) hipLaunchKernelGGL((k_ipdg<D, P, OUT_RK>), grid, block, 0, s, a);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+template hipError_t launch_ipdg<DG_D, DG_P>(const IpdgArgs &, int, hipStream_t);
 #elif DG_PART == 1
 template hipError_t launch_stage_cell<DG_D, DG_P, double, EQ_EULER>(const StageArgs &, int, int, bool,
                                                                    const StageShape &, hipStream_t);

@@ -275,4 +275,22 @@ struct IcParams {
     double p[8];
 };
 
+// Diffusion stage (Sec. 5.2): interior-penalty residual, optionally fused
+// with the SSP-RK3 stage update.
+struct IpdgArgs {
+    const double *us;    // stage input (read-only)
+    const double *un;    // RK base state (OUT_RK)
+    const double *guard; // guard coefficients G[leaf][face][0][mode][t]
+    double *out;         // residual (OUT_RES64) or next state (OUT_RK)
+    const LeafGeo *geo;
+    const FaceLink *links;
+    const double *dt;    // device dt (OUT_RK)
+    double rk_a, rk_b;
+    double nu;
+    double avec[3];      // exact solution exp(a . x + nu |a|^2 t)
+    double t;            // time of the stage input (Dirichlet data)
+    long ncell_total;
+    int N;
+};
+
 } // namespace dgk

@@ -39,6 +39,7 @@ __global__ __launch_bounds__(256) void k_limit(double *u, int N, long ncell_tota
 //          velocity (u,0,0), p = 1
 //  COSINE  (scalar convection, Sec. 5.1) k, period_x, period_y, period_z,
 //          vel_x, vel_y, vel_z: u = prod_a [cos(2 pi k (x_a - vel_a t)/L_a) - 1]
+//  EXP     (diffusion, Sec. 5.2) a_x, a_y, a_z, nu: u = exp(a . x + nu |a|^2 t)
 __device__ __forceinline__ double wrap_half(double d, double period)
 {
     if (period <= 0.0) return d;
@@ -53,6 +54,15 @@ __device__ void analytic(int kind, const IcParams &P, double t, double gamma, co
 {
     const double pi = 3.14159265358979323846;
     double vel[3] = {0.0, 0.0, 0.0}, rho = 1.0, p = 1.0;
+    if (kind == DGAMR_IC_EXP) { // diffusion (Sec. 5.2): a = p[0..2], nu = p[3]
+        double e = 0.0, a2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            e += P.p[a] * x[a];
+            a2 += P.p[a] * P.p[a];
+        }
+        U[0] = exp(e + P.p[3] * a2 * t);
+        return;
+    }
     if (kind == DGAMR_IC_COSINE) {
         double prod = 1.0;
         for (int a = 0; a < D; ++a) prod *= cos(2.0 * pi * P.p[0] * (x[a] - P.p[4 + a] * t) / P.p[1 + a]) - 1.0;

@@ -227,4 +227,8 @@ static __global__ __launch_bounds__(256) void k_rate_adv(const LeafGeo *geo, int
     leaf_max[i] = rate;
 }
 
+// *p = v (one thread): a host-computed value put on the device in stream
+// order (the diffusion time step)
+static __global__ void k_set_value(double *p, double v) { *p = v; }
+
 } // namespace dgk

@@ -63,6 +63,9 @@ int stage_rows_options(int N, int *rows, int max_options, bool fp32);
 // guard fill: one thread per guard cell of the listed faces
 template <int D, int P>
 hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s, int nv = D + 2);
+// diffusion stage: one thread per cell; out_mode OUT_RES64 or OUT_RK
+template <int D, int P>
+hipError_t launch_ipdg(const IpdgArgs &a, int out_mode, hipStream_t s);
 template <int D, int P>
 hipError_t launch_limit(double *u, int N, long ncell_total, double gamma, hipStream_t s);
 template <int D, int P>

@@ -16,12 +16,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdgamr.so")
 
 OK, EINVAL, EUNSUPPORTED, EBALANCE, EHIP, ENONPHYSICAL, ESTATE, EFULL = 0, -1, -2, -3, -4, -5, -6, -7
-BC_PERIODIC, BC_OUTFLOW = 0, 1
+BC_PERIODIC, BC_OUTFLOW, BC_DIRICHLET = 0, 1, 2
 FP64, FP32_MFMA = 0, 1
 HANG_PAPER, HANG_CONSERVATIVE = 0, 1
 LIMITER_NONE, LIMITER_POSITIVITY = 0, 1
-IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE = 0, 1, 2, 3, 4
-EQ_EULER, EQ_ADVECTION = 0, 1
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE, IC_EXP = 0, 1, 2, 3, 4, 5
+EQ_EULER, EQ_ADVECTION, EQ_DIFFUSION = 0, 1, 2
 TUNE_STAGE_VARIANT, TUNE_VAR_SPLIT_MAX_CELLS, TUNE_SLAB_ROWS = 0, 1, 2
 
 EXPORTS = [
@@ -33,7 +33,7 @@ EXPORTS = [
     "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
     "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_set_lanes", "dgamr_pool_autotune",
     "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture",
-    "dgamr_step_static", "dgamr_last_error",
+    "dgamr_step_static", "dgamr_set_time", "dgamr_get_time", "dgamr_last_error",
 ]
 
 
@@ -50,6 +50,7 @@ class ForestDesc(ctypes.Structure):
         ("bc", ctypes.c_int * 3), ("max_level", ctypes.c_int), ("gamma", ctypes.c_double),
         ("precision", ctypes.c_int), ("hanging", ctypes.c_int), ("limiter", ctypes.c_int),
         ("equation", ctypes.c_int), ("velocity", ctypes.c_double * 3),
+        ("diffusivity", ctypes.c_double), ("exact_a", ctypes.c_double * 3),
     ]
 
 
@@ -77,6 +78,8 @@ def lib():
         L.dgamr_compute_dt.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
         L.dgamr_step.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
         L.dgamr_step_static.argtypes = [vp, ctypes.c_double, vp, vp, vp]
+        L.dgamr_set_time.argtypes = [vp, ctypes.c_double]
+        L.dgamr_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.dgamr_run.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
         L.dgamr_conserved_totals.argtypes = [vp, vp, vp, vp, vp]
         L.dgamr_limit_positivity.argtypes = [vp, vp, vp]
@@ -152,7 +155,7 @@ class Forest:
 
     def __init__(self, dim, degree, n_cell, roots, lo, hi, bc, max_level, gamma=1.4,
                  precision=FP64, hanging=HANG_PAPER, limiter=LIMITER_NONE, equation=EQ_EULER,
-                 velocity=(1.0, 1.0, 1.0)):
+                 velocity=(1.0, 1.0, 1.0), nu=1.0, exact_a=(-1.0, 1.0, 0.0)):
         d = ForestDesc()
         d.dim, d.degree, d.n_cell = dim, degree, n_cell
         roots, lo, hi, bc = (list(x) for x in (roots, lo, hi, bc))
@@ -166,10 +169,12 @@ class Forest:
         d.equation = equation
         for a in range(3):
             d.velocity[a] = velocity[a] if a < len(velocity) else 0.0
+            d.exact_a[a] = exact_a[a] if a < len(exact_a) else 0.0
+        d.diffusivity = nu
         self.desc = d
         self.dim, self.degree, self.N = dim, degree, n_cell
         self.equation = equation
-        self.nv = 1 if equation == EQ_ADVECTION else dim + 2
+        self.nv = 1 if equation in (EQ_ADVECTION, EQ_DIFFUSION) else dim + 2
         self.nb = {2: [1, 3, 6, 10], 3: [1, 4, 10, 20]}[dim][degree]
         self.precision = precision
         h = ctypes.c_void_p()
@@ -192,6 +197,17 @@ class Forest:
     @property
     def ncell(self) -> int:
         return self.N ** self.dim
+
+    @property
+    def time(self) -> float:
+        """Time of the state (the Dirichlet data of a diffusion forest)."""
+        t = ctypes.c_double()
+        _check(lib().dgamr_get_time(self.h, ctypes.byref(t)))
+        return t.value
+
+    @time.setter
+    def time(self, t: float):
+        _check(lib().dgamr_set_time(self.h, t))
 
     def keys(self):
         k = torch.zeros((self.n_leaves, 5), dtype=torch.int32)

@@ -15,6 +15,10 @@
         the scalar convection workload (Sec. 5.1) with indicator-driven
         regrids to t_end: DOF-stage/s and the L2 distance to the projected
         exact solution;
+    python -m paper_2502_12620_amd.measure diffusion [--degree 2]
+        the diffusion workload (Sec. 5.2) with indicator-driven regrids to
+        t = 0.2: DOF-stage/s and the L2 distance to the projected exact
+        solution;
     python -m paper_2502_12620_amd.measure sedov
         the 3-D blast workload end to end (limiter, regrid every 10 steps)
         with FP64 and with FP32 residuals, and their L1 / L2 difference;
@@ -324,6 +328,53 @@ def cmd_convection(args):
     print(json.dumps(out), flush=True)
 
 
+def cmd_diffusion(args):
+    """The diffusion workload of Sec. 5.2 on the GPU: regrids by the block
+    indicator every 10 steps, SSP-RK3 at the diffusive CFL number to
+    t_end (the last step shortened to land on it), DOF-stage/s, and the L2
+    distance between the solution and the L2 projection of the exact
+    solution on the final forest."""
+    w = W.diffusion_2d(degree=args.degree)
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma,
+                 equation=G.EQ_DIFFUSION, nu=w.nu, exact_a=w.exact_a)
+    z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
+    for rule in w.initial_refinement:
+        z = f.adapt(rule(w, f.keys()), z)
+    u = f.project_ic(G.IC_EXP, [])
+    f.time = 0.0
+    work, dt = f.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    steps, dof_stages, regrids = 0, 0, 0
+    torch.cuda.synchronize()
+    start = time.perf_counter()
+    while f.time < w.t_end - 1e-14:
+        if steps % w.regrid_every == 0:
+            eta = f.indicator(u, work).cpu().numpy()
+            flags = W.regrid_flags(w, f.keys(), eta)
+            if (flags != 0).any():
+                u = f.adapt(flags, u)
+                work = f.new_work()
+                regrids += 1
+        f.compute_dt(1.0, u, dt, work)  # dt per unit CFL number: dt is proportional to it
+        per_cfl = float(dt.item())
+        cfl = min(w.cfl, (w.t_end - f.time) / per_cfl)
+        f.step(u, work, dt, cfl=cfl)
+        steps += 1
+        dof_stages += 3 * w.dofs(f.n_leaves)
+        if steps % 20000 == 0:
+            print(json.dumps({"progress": "diffusion", "steps": steps, "t": f.time}), flush=True)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - start
+    ex = f.project_ic(G.IC_EXP, [], t=f.time)
+    vol = torch.tensor([g for g in _leaf_volumes(f, w)], dtype=torch.float64, device="cuda")
+    mass = torch.tensor(_ref_mass(w.dim, w.degree), dtype=torch.float64, device="cuda")
+    d2 = ((u - ex) ** 2 * mass[None, None, :, None]).sum(dim=(1, 2, 3))
+    l2 = float(torch.sqrt((d2 * vol / 2 ** w.dim).sum()))
+    out = {"workload": w.name, "degree": w.degree, "n_cell": w.n_cell, "t_end": f.time, "steps": steps,
+           "regrids": regrids, "final_leaves": f.n_leaves, "wall_s": el, "dof_stage_per_s": dof_stages / el,
+           "l2_to_projected_exact": l2}
+    print(json.dumps(out), flush=True)
+
+
 def _leaf_volumes(f, w):
     """Cell volume of every leaf, from the keys (level) and the root box."""
     keys = f.keys()
@@ -406,6 +457,8 @@ def main(argv=None):
     c2.add_argument("--dim", type=int, default=2)
     c2.add_argument("--degree", type=int, default=2)
     c2.add_argument("--n-cell", type=int, default=8)
+    df = sub.add_parser("diffusion")
+    df.add_argument("--degree", type=int, default=2)
     v = sub.add_parser("serve")
     v.add_argument("--requests", type=int, default=40)
     v.add_argument("--rate", type=float, default=200.0)
@@ -414,7 +467,7 @@ def main(argv=None):
     args = ap.parse_args(argv)
     torch.cuda.set_device(0)
     {"sweep": cmd_sweep, "copy": cmd_copy, "batch": cmd_batch, "serve": cmd_serve, "sedov": cmd_sedov,
-     "convection": cmd_convection}[args.cmd](args)
+     "convection": cmd_convection, "diffusion": cmd_diffusion}[args.cmd](args)
 
 
 if __name__ == "__main__":

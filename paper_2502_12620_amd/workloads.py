@@ -13,9 +13,9 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-PERIODIC, OUTFLOW = 0, 1
-IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE = 0, 1, 2, 3, 4
-EQ_EULER, EQ_ADVECTION = 0, 1
+PERIODIC, OUTFLOW, DIRICHLET = 0, 1, 2
+IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE, IC_EXP = 0, 1, 2, 3, 4, 5
+EQ_EULER, EQ_ADVECTION, EQ_DIFFUSION = 0, 1, 2
 
 
 @dataclass
@@ -44,6 +44,8 @@ class Workload:
     velocity: tuple = (1.0, 1.0, 1.0)
     t_end: float = 0.0
     min_level: int = 1
+    nu: float = 1.0
+    exact_a: tuple = (-1.0, 1.0, 0.0)
 
     def desc(self) -> dict:
         return dict(dim=self.dim, degree=self.degree, n_cell=self.n_cell, roots=self.roots, lo=self.lo,
@@ -65,7 +67,7 @@ class Workload:
 
     def dofs(self, n_leaves) -> int:
         nb = math.comb(self.degree + self.dim, self.dim)
-        nv = 1 if self.equation == EQ_ADVECTION else self.dim + 2
+        nv = 1 if self.equation in (EQ_ADVECTION, EQ_DIFFUSION) else self.dim + 2
         return n_leaves * nv * nb * self.n_cell ** self.dim
 
 
@@ -149,8 +151,23 @@ def convection_3d(degree: int = 1, n_cell: int = 4) -> Workload:
     return w
 
 
+def diffusion_2d(degree: int = 2, n_cell: int = 6) -> Workload:
+    """Diffusion (Sec. 5.2): u_t = div grad u on the unit square, one root
+    block, Dirichlet data and initial state from exp(-x + y + 2t), 6x6-cell
+    blocks, refinement levels 2..4 driven by the block's largest cell
+    average (refine above 3.0, coarsen below 1.0) every 10 steps, SSP-RK3 at
+    the diffusive CFL number 0.006 (dt = 0.006 h^2 / 2) to t = 0.2.  The
+    degree is not given in the paper; 2 here."""
+    w = Workload("f4_diffusion2d", 2, degree, n_cell, (1, 1), (0.0, 0.0), (1.0, 1.0), (DIRICHLET, DIRICHLET), 4,
+                 IC_EXP, [], 0, cfl=0.006, regrid_every=10, refine_above=3.0, coarsen_below=1.0,
+                 initial_refinement=[refine_all])
+    w.equation, w.t_end, w.min_level = EQ_DIFFUSION, 0.2, 2
+    w.nu, w.exact_a = 1.0, (-1.0, 1.0)
+    return w
+
+
 def regrid_flags(w: Workload, keys, eta):
-    """Refinement flags of the convection workloads from the block
+    """Refinement flags of the convection and diffusion workloads from the block
     indicator: +1 above refine_above, -1 below coarsen_below, never below
     the minimum level."""
     flags = np.where(eta > w.refine_above, 1, np.where(eta < w.coarsen_below, -1, 0)).astype(np.int8)
