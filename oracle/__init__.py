@@ -66,6 +66,8 @@ def lib():
         L.orc_set_advection.argtypes = [vp, dp]
         L.orc_set_diffusion.argtypes = [vp, ctypes.c_double, dp]
         L.orc_set_time.argtypes = [vp, ctypes.c_double]
+        L.orc_set_frames.argtypes = [vp, ip]
+        L.orc_set_frames.restype = ctypes.c_int
         L.orc_get_time.argtypes = [vp]
         L.orc_get_time.restype = ctypes.c_double
         L.orc_upwind.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
@@ -204,6 +206,12 @@ class Forest:
             self.avec = np.array(list(avec) + [0.0] * (3 - len(avec)), dtype=np.float64)[:3]
             lib().orc_set_diffusion(self.ptr, nu, _dp(self.avec))
             self.nv = 1
+
+    def set_frames(self, codes):
+        """Rotation code of each root's local frame (see oracle.h)."""
+        c = np.ascontiguousarray(codes, dtype=np.int32)
+        if lib().orc_set_frames(self.ptr, _ip(c)) != 0:
+            raise ValueError("oracle: frames refused")
 
     def __del__(self):
         if getattr(self, "ptr", None):

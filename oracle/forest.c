@@ -44,16 +44,88 @@ int orc_cell_index(const orc_forest *f, const int *ijk)
     return ijk[0] + f->N * (ijk[1] + (f->dim == 3 ? f->N * ijk[2] : 0));
 }
 
+/* Frames of the root blocks (Sec. 3.1: neighbouring roots may be rotated
+ * against each other; the relative rotation is what the guard fill of
+ * Sec. 3.5 has to undo).  A root's frame is a rotation Q of its local axes,
+ * global vector = Q local vector, Q a signed permutation matrix with
+ * determinant +1.  2-D: code k is k quarter turns counter-clockwise.  3-D:
+ * code k is the k-th such matrix when the permutations (pi(0), pi(1), pi(2))
+ * of the local axes are taken in lexicographic order and, for each, the
+ * signs of the local axes s_l (bit l of 0..7 set: s_l = -1) in increasing
+ * order, with Q[pi(l)][l] = s_l. */
+void orc_frame_matrix(const orc_forest *f, int tree, int Q[3][3])
+{
+    int code = f->frame ? f->frame[tree] : 0;
+    memset(Q, 0, sizeof(int) * 9);
+    if (f->dim == 2) {
+        static const int c[4] = {1, 0, -1, 0}, sn[4] = {0, 1, 0, -1};
+        Q[0][0] = c[code];
+        Q[0][1] = -sn[code];
+        Q[1][0] = sn[code];
+        Q[1][1] = c[code];
+        Q[2][2] = 1;
+        return;
+    }
+    static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int n = 0;
+    for (int pi = 0; pi < 6; ++pi)
+        for (int sg = 0; sg < 8; ++sg) {
+            int M[3][3];
+            memset(M, 0, sizeof(M));
+            for (int l = 0; l < 3; ++l) M[perms[pi][l]][l] = (sg >> l) & 1 ? -1 : 1;
+            int det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                      M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                      M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+            if (det != 1) continue;
+            if (n == code) {
+                memcpy(Q, M, sizeof(M));
+                return;
+            }
+            ++n;
+        }
+}
+
+/* lower corner and edge of a leaf in its root's local frame */
+void orc_leaf_lbox(const orc_forest *f, const orc_key *k, long *lo, long *size)
+{
+    long edge = f->unit / ipow2(k->level - 1);
+    for (int a = 0; a < 3; ++a) lo[a] = (a < f->dim) ? k->idx[a] * edge : 0;
+    *size = edge;
+}
+
+/* a local box [p, p + e) of root `tree` in global units: along global axis
+ * pi(l) the local interval of axis l, reversed when Q[pi(l)][l] = -1 */
+static void local_to_global(const orc_forest *f, int tree, const long *p, long e, long *g)
+{
+    int Q[3][3];
+    orc_frame_matrix(f, tree, Q);
+    int r[3];
+    r[0] = tree % f->roots[0];
+    r[1] = (tree / f->roots[0]) % f->roots[1];
+    r[2] = tree / (f->roots[0] * f->roots[1]);
+    for (int a = 0; a < 3; ++a) g[a] = 0;
+    for (int l = 0; l < f->dim; ++l)
+        for (int a = 0; a < f->dim; ++a) {
+            if (Q[a][l] == 1) g[a] = r[a] * f->unit + p[l];
+            if (Q[a][l] == -1) g[a] = r[a] * f->unit + f->unit - p[l] - e;
+        }
+}
+
 /* lower corner and edge (global units) of a leaf */
 void orc_leaf_box(const orc_forest *f, const orc_key *k, long *lo, long *size)
 {
-    long edge = f->unit / ipow2(k->level - 1);
-    int r[3];
-    r[0] = k->tree % f->roots[0];
-    r[1] = (k->tree / f->roots[0]) % f->roots[1];
-    r[2] = k->tree / (f->roots[0] * f->roots[1]);
-    for (int a = 0; a < 3; ++a) lo[a] = (a < f->dim) ? r[a] * f->unit + k->idx[a] * edge : 0;
-    *size = edge;
+    long l[3];
+    orc_leaf_lbox(f, k, l, size);
+    local_to_global(f, k->tree, l, *size, lo);
+}
+
+void orc_cell_gbox(const orc_forest *f, const orc_key *k, const int *ijk, long *lo)
+{
+    long l[3], size;
+    orc_leaf_lbox(f, k, l, &size);
+    long h = size / f->N;
+    for (int a = 0; a < f->dim; ++a) l[a] += ijk[a] * h;
+    local_to_global(f, k->tree, l, h, lo);
 }
 
 /* Morton code of the leaf's lower corner at the finest level: bit b of x
@@ -185,9 +257,22 @@ static void tangential_axes(int dim, int axis, int *ta)
         if (b != axis) ta[n++] = b;
 }
 
-/* Guard plan for guard cell t of face (axis, side) of leaf i: the guard
- * cell is the cell of this leaf's level just outside the face (Sec. 3.3);
- * it is covered by cells of the face neighbours. */
+/* global axis and side of the local face (axis, side) of a leaf of `tree` */
+static void global_face(const orc_forest *f, int tree, int axis, int side, int *gaxis, int *gside)
+{
+    int Q[3][3];
+    orc_frame_matrix(f, tree, Q);
+    for (int a = 0; a < f->dim; ++a)
+        if (Q[a][axis] != 0) {
+            *gaxis = a;
+            *gside = side * Q[a][axis];
+        }
+}
+
+/* Guard plan for guard cell t of the local face (axis, side) of leaf i: the
+ * guard cell is the cell of this leaf's level just outside the face
+ * (Sec. 3.3); it is covered by cells of the face neighbours.  Boxes are
+ * global; a neighbour in a root of another frame is found the same way. */
 static void build_guard_plan(const orc_forest *f, int i, int axis, int side, int t,
                              const orc_face_nbr *fn, orc_guard_plan *gp)
 {
@@ -201,8 +286,11 @@ static void build_guard_plan(const orc_forest *f, int i, int axis, int side, int
     ijk[ta[0]] = t % f->N;
     if (f->dim == 3) ijk[ta[1]] = t / f->N;
     long glo[3] = {0, 0, 0};
-    for (int a = 0; a < f->dim; ++a) glo[a] = lo[a] + ijk[a] * h;
-    glo[axis] += side * h;
+    orc_cell_gbox(f, &f->leaf[i], ijk, glo);
+    int gaxis = axis, gside = side;
+    global_face(f, f->leaf[i].tree, axis, side, &gaxis, &gside);
+    glo[gaxis] += gside * h;
+    axis = gaxis;
     gp->npiece = 0;
     gp->piece = NULL;
     if (fn->boundary) {
@@ -225,9 +313,10 @@ static void build_guard_plan(const orc_forest *f, int i, int axis, int side, int
             int cijk[3];
             orc_cell_ijk(f, c, cijk);
             long clo[3] = {0, 0, 0}, olo[3] = {0, 0, 0}, ohi[3] = {0, 0, 0};
+            orc_cell_gbox(f, &f->leaf[j], cijk, clo);
+            clo[axis] += shift;
             int ok = 1;
             for (int a = 0; a < f->dim; ++a) {
-                clo[a] = blo[a] + cijk[a] * bh;
                 olo[a] = clo[a] > glo[a] ? clo[a] : glo[a];
                 ohi[a] = (clo[a] + bh) < (glo[a] + h) ? (clo[a] + bh) : (glo[a] + h);
                 if (olo[a] >= ohi[a]) ok = 0;
@@ -244,10 +333,11 @@ static void build_guard_plan(const orc_forest *f, int i, int axis, int side, int
             pc->src_size = bh;
         }
     }
-    if (gp->npiece == 1 && fn->level_diff == 0)
+    int same_frame = (f->frame ? f->frame[f->leaf[fn->nb[0]].tree] : 0) == (f->frame ? f->frame[f->leaf[i].tree] : 0);
+    if (gp->npiece == 1 && fn->level_diff == 0 && same_frame)
         gp->kind = 0; /* Eq. 15: same level, rotation identity: copy */
     else
-        gp->kind = 1; /* Eq. 16-17: L2 projection (split or combine) */
+        gp->kind = 1; /* Eq. 15-17 with a rotation, or split / combine: L2 projection */
 }
 
 void orc_free_topology(orc_forest *f)
@@ -272,7 +362,9 @@ void orc_build_topology(orc_forest *f)
     for (int i = 0; i < f->nleaves; ++i)
         for (int face = 0; face < nf; ++face) {
             int axis = face / 2, side = (face % 2) ? 1 : -1;
-            find_face_nbrs(f, i, axis, side, &f->fn[i * nf + face]);
+            int gaxis = axis, gside = side;
+            global_face(f, f->leaf[i].tree, axis, side, &gaxis, &gside);
+            find_face_nbrs(f, i, gaxis, gside, &f->fn[i * nf + face]);
             if (abs(f->fn[i * nf + face].level_diff) > 1) {
                 fprintf(stderr, "oracle: 2:1 balance violated\n");
                 abort();
@@ -335,6 +427,28 @@ void orc_set_diffusion(orc_forest *f, double nu, const double *avec)
     for (int a = 0; a < 3; ++a) f->avec[a] = a < f->dim ? avec[a] : 0.0;
 }
 
+int orc_set_frames(orc_forest *f, const int *codes)
+{
+    int ntree = f->roots[0] * f->roots[1] * f->roots[2], ncode = f->dim == 2 ? 4 : 24;
+    int any = 0;
+    for (int t = 0; t < ntree; ++t) {
+        if (codes[t] < 0 || codes[t] >= ncode) return -1;
+        any |= codes[t] != 0;
+    }
+    /* a rotated root must map onto its own box: equal physical edges */
+    if (any)
+        for (int a = 1; a < f->dim; ++a)
+            if ((f->hi[a] - f->lo[a]) / f->roots[a] != (f->hi[0] - f->lo[0]) / f->roots[0]) return -1;
+    /* the mortar of the conservative mode and the convection velocity are
+     * written along the global axes */
+    if (any && (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_ADVECTION)) return -1;
+    free(f->frame);
+    f->frame = malloc(sizeof(int) * ntree);
+    memcpy(f->frame, codes, sizeof(int) * ntree);
+    orc_build_topology(f);
+    return 0;
+}
+
 void orc_set_time(orc_forest *f, double t) { f->time = f->stage_time = t; }
 double orc_get_time(const orc_forest *f) { return f->time; }
 
@@ -345,6 +459,7 @@ void orc_destroy(orc_forest *f)
     free(f->leaf);
     free(f->new_leaf);
     free(f->exps);
+    free(f->frame);
     free(f);
 }
 
@@ -488,7 +603,7 @@ static int key_eq(const orc_key *a, const orc_key *b)
  * an overlap box into a destination cell's coefficients (accumulating) */
 void orc_project_overlap(const orc_forest *f, const double *src, long src_stride,
                          const long *src_lo, long src_size, const long *dst_lo, long dst_size,
-                         const long *olo, const long *ohi, double *acc);
+                         const long *olo, const long *ohi, int (*Qs)[3], int (*Qd)[3], double *acc);
 
 /* Eq. 11-14: each new cell receives the L2 projection of the old piecewise
  * polynomial over its box; unchanged leaves are copied. */
@@ -510,12 +625,14 @@ void orc_apply_adapt(orc_forest *f, const double *u_old, double *u_new)
             continue;
         }
         memset(dst, 0, sizeof(double) * per_leaf);
+        /* inheritance stays inside one tree: boxes in its local frame */
         long lo[3], size;
-        orc_leaf_box(f, k, lo, &size);
+        orc_leaf_lbox(f, k, lo, &size);
         long h = size / f->N;
         for (int j = 0; j < old_n; ++j) {
+            if (old[j].tree != k->tree) continue;
             long blo[3], bsize;
-            orc_leaf_box(f, &old[j], blo, &bsize);
+            orc_leaf_lbox(f, &old[j], blo, &bsize);
             int ok = 1;
             for (int a = 0; a < f->dim; ++a)
                 if (!overlaps(lo[a], lo[a] + size, blo[a], blo[a] + bsize)) ok = 0;
@@ -540,7 +657,7 @@ void orc_apply_adapt(orc_forest *f, const double *u_old, double *u_new)
                     if (!ov) continue;
                     double acc[5 * 20];
                     memset(acc, 0, sizeof(acc));
-                    orc_project_overlap(f, u_old + j * per_leaf + sc, nc, slo, bh, clo, h, olo, ohi, acc);
+                    orc_project_overlap(f, u_old + j * per_leaf + sc, nc, slo, bh, clo, h, olo, ohi, NULL, NULL, acc);
                     for (int v = 0; v < nv; ++v)
                         for (int l = 0; l < nb; ++l) dst[((long)v * nb + l) * nc + c] += acc[v * nb + l];
                 }

@@ -81,6 +81,17 @@ double orc_upwind(const double *vel, double um, double up, int axis, int sign);
  * Dirichlet data from the exact solution exp(a . x + nu |a|^2 t)
  * (a = avec[0..2]). */
 void orc_set_diffusion(orc_forest *f, double nu, const double *avec);
+/* Frames of the root blocks (Sec. 3.1: neighbouring roots may be rotated
+ * against each other): codes[tree] is the rotation of the root's local axes,
+ * global vector = Q local vector; 2-D: code k = k quarter turns
+ * counter-clockwise; 3-D: code k = the k-th signed permutation matrix with
+ * determinant +1 (permutations of the local axes in lexicographic order,
+ * then the sign patterns of the local axes, bit l = axis l negative).  The
+ * leaf keys, cells, modes and momentum of a root are in its local frame.
+ * Requires equal root edges, the paper hanging mode and the Euler or
+ * diffusion equation; returns 0, or -1 (nothing changed).  Call before
+ * refining. */
+int orc_set_frames(orc_forest *f, const int *codes);
 /* time of the state (Dirichlet data of the diffusion equation); orc_step
  * advances it by dt */
 void orc_set_time(orc_forest *f, double t);

@@ -59,13 +59,22 @@ struct orc_forest {
     int *exps;        /* nb x 3 */
     orc_face_nbr *fn; /* nleaves x 2d */
     orc_guard_plan *gp; /* nleaves x 2d x N^(d-1) */
+    int *frame;       /* rotation code of each root's local frame (NULL: all 0) */
     /* adaptation plan */
     int new_n;
     orc_key *new_leaf;
 };
 
 /* geometry helpers shared by the oracle's own files */
+/* frame matrix of a root: global vector = Q * local vector */
+void orc_frame_matrix(const orc_forest *f, int tree, int Q[3][3]);
+/* global box (lower corner, edge) of a leaf, in global units */
 void orc_leaf_box(const orc_forest *f, const orc_key *k, long *lo, long *size);
+/* the same in the coordinates of the leaf's own root (local frame, the
+ * root's lower corner at 0) */
+void orc_leaf_lbox(const orc_forest *f, const orc_key *k, long *lo, long *size);
+/* global lower corner of the leaf's cell with local index ijk */
+void orc_cell_gbox(const orc_forest *f, const orc_key *k, const int *ijk, long *lo);
 long orc_domain_units(const orc_forest *f, int axis);
 void orc_build_topology(orc_forest *f);
 void orc_free_topology(orc_forest *f);

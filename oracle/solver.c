@@ -30,6 +30,30 @@ static double unit_len(const orc_forest *f, int a)
     return (f->hi[a] - f->lo[a]) / (double)orc_domain_units(f, a);
 }
 
+/* physical cell edge of leaf i along its local axis a (the global axis the
+ * root's frame maps it to) */
+static double local_h(const orc_forest *f, int i, int a)
+{
+    int Q[3][3];
+    orc_frame_matrix(f, f->leaf[i].tree, Q);
+    long lo[3], size;
+    orc_leaf_box(f, &f->leaf[i], lo, &size);
+    for (int g = 0; g < f->dim; ++g)
+        if (Q[g][a] != 0) return (size / f->N) * unit_len(f, g);
+    return 0.0;
+}
+
+/* the vector components (momentum) of a state: global = Q local, local =
+ * Q^T global; scalar equations have none */
+static void rotate_state(const orc_forest *f, int Q[3][3], int transpose, double *u)
+{
+    if (f->equation != ORC_EQ_EULER) return;
+    double m[3] = {0, 0, 0};
+    for (int a = 0; a < f->dim; ++a)
+        for (int b = 0; b < f->dim; ++b) m[a] += (transpose ? Q[b][a] : Q[a][b]) * u[1 + b];
+    for (int a = 0; a < f->dim; ++a) u[1 + a] = m[a];
+}
+
 static long sidx(const orc_forest *f, long leaf, int v, int m, int cell)
 {
     return ((leaf * f->nv + v) * f->nb + m) * (long)orc_ncell(f) + cell;
@@ -81,15 +105,20 @@ static int tensor_points(int dim, int q, const double *gx, const double *gw, dou
     return n;
 }
 
-/* L2 projection (Eq. 11-14 written for one overlap piece): accumulate into
- * acc[v*nb+l] the contribution (1/M_dst,l) int_{overlap} phi^dst_l u^src dV
- * for a source cell (lower corner src_lo, edge src_size) and a destination
- * cell (dst_lo, dst_size).  src points at coefficient (v=0,m=0) with modes
- * src_stride apart and variables nb*src_stride apart.  Gauss rule with p+1
- * points per axis on the overlap box (exact: degree <= 2p per axis). */
+/* L2 projection (Eq. 11-14 written for one overlap piece, with the rotation
+ * of Sec. 3.5): accumulate into acc[v*nb+l] the contribution
+ * (1/M_dst,l) int_{overlap} phi^dst_l u^src dV for a source cell (global
+ * lower corner src_lo, edge src_size) and a destination cell (dst_lo,
+ * dst_size).  Each cell's polynomial lives in its root's local frame: a
+ * point's reference coordinates in a cell are Q^T times those taken along
+ * the global axes of its box, and the source state's momentum is turned
+ * into the destination frame, Qd^T Qs m (Qs, Qd null: identity).  src
+ * points at coefficient (v=0,m=0) with modes src_stride apart and
+ * variables nb*src_stride apart.  Gauss rule with p+1 points per axis on
+ * the overlap box (exact: degree <= 2p per axis). */
 void orc_project_overlap(const orc_forest *f, const double *src, long src_stride,
                          const long *src_lo, long src_size, const long *dst_lo, long dst_size,
-                         const long *olo, const long *ohi, double *acc)
+                         const long *olo, const long *ohi, int (*Qs)[3], int (*Qd)[3], double *acc)
 {
     int q = f->p + 1;
     double gx[8], gw[8];
@@ -105,8 +134,24 @@ void orc_project_overlap(const orc_forest *f, const double *src, long src_stride
             xs[a] = 2.0 * (x - src_lo[a]) / (double)src_size - 1.0;
             xd[a] = 2.0 * (x - dst_lo[a]) / (double)dst_size - 1.0;
         }
+        if (Qs) { /* global-axis reference coordinates -> the cells' local ones */
+            double t[3] = {0, 0, 0}, r[3] = {0, 0, 0};
+            for (int a = 0; a < f->dim; ++a)
+                for (int b = 0; b < f->dim; ++b) {
+                    t[a] += Qs[b][a] * xs[b];
+                    r[a] += Qd[b][a] * xd[b];
+                }
+            for (int a = 0; a < f->dim; ++a) {
+                xs[a] = t[a];
+                xd[a] = r[a];
+            }
+        }
         double u[5];
         eval_poly(f, src, (long)f->nb * src_stride, src_stride, xs, u);
+        if (Qs) {
+            rotate_state(f, Qs, 0, u);
+            rotate_state(f, Qd, 1, u);
+        }
         for (int l = 0; l < f->nb; ++l) {
             double ph = orc_phi(f->dim, f->exps + 3 * l, xd);
             double c = frac * w[iq] * ph / orc_ref_mass(f->dim, f->exps + 3 * l);
@@ -218,19 +263,37 @@ static void analytic_state(const orc_forest *f, int kind, const double *prm, dou
     }
 }
 
-/* physical coordinates of reference point xi in cell c of leaf i */
+/* physical coordinates of the (local) reference point xi in cell c of
+ * leaf i */
 static void cell_point(const orc_forest *f, int i, int c, const double *xi, double *x)
 {
     long lo[3], size;
     orc_leaf_box(f, &f->leaf[i], lo, &size);
     long h = size / f->N;
-    int ijk[3];
+    int ijk[3], Q[3][3];
     orc_cell_ijk(f, c, ijk);
+    orc_cell_gbox(f, &f->leaf[i], ijk, lo);
+    orc_frame_matrix(f, f->leaf[i].tree, Q);
     for (int a = 0; a < 3; ++a) x[a] = 0.0;
     for (int a = 0; a < f->dim; ++a) {
-        double gl = lo[a] + ijk[a] * h + 0.5 * (xi[a] + 1.0) * h;
+        double xg = 0.0; /* reference coordinate along global axis a */
+        for (int b = 0; b < f->dim; ++b) xg += Q[a][b] * xi[b];
+        double gl = lo[a] + 0.5 * (xg + 1.0) * h;
         x[a] = f->lo[a] + gl * unit_len(f, a);
     }
+}
+
+/* the analytic state at the local reference point xi of cell c of leaf i,
+ * in the leaf's frame */
+static void analytic_local(const orc_forest *f, int i, int c, int kind, const double *params, double t,
+                           const double *xi, double *u)
+{
+    double x[3];
+    cell_point(f, i, c, xi, x);
+    analytic_state(f, kind, params, t, x, u);
+    int Q[3][3];
+    orc_frame_matrix(f, f->leaf[i].tree, Q);
+    rotate_state(f, Q, 1, u);
 }
 
 /* L2 projection of an analytic state with p+3 Gauss points per axis:
@@ -249,9 +312,8 @@ void orc_project_ic(const orc_forest *f, int kind, const double *params, double 
             double acc[5 * 20];
             memset(acc, 0, sizeof(acc));
             for (int iq = 0; iq < nq; ++iq) {
-                double x[3], s[5];
-                cell_point(f, i, c, xi[iq], x);
-                analytic_state(f, kind, params, t, x, s);
+                double s[5];
+                analytic_local(f, i, c, kind, params, t, xi[iq], s);
                 for (int l = 0; l < f->nb; ++l) {
                     double ph = orc_phi(f->dim, f->exps + 3 * l, xi[iq]);
                     for (int v = 0; v < f->nv; ++v) acc[v * f->nb + l] += w[iq] * ph * s[v];
@@ -309,22 +371,26 @@ void orc_fill_guards(const orc_forest *f, const double *u, double *g)
                         for (int m = 0; m < f->nb; ++m)
                             g[gidx(f, i, face, v, m, t)] = u[sidx(f, pc->leaf, v, m, pc->cell)];
                 } else {
-                    /* the guard cell box in the same (unwrapped) frame */
+                    /* the guard cell's global box (in the pieces' unwrapped
+                     * frame): the own cell's box moved across the face */
                     long lo[3], size;
                     orc_leaf_box(f, &f->leaf[i], lo, &size);
                     long h = size / f->N;
                     int c = face_cell(f, axis, side, t);
-                    int ijk[3];
+                    int ijk[3], Qd[3][3];
                     orc_cell_ijk(f, c, ijk);
                     long glo[3] = {0, 0, 0};
-                    for (int a = 0; a < f->dim; ++a) glo[a] = lo[a] + ijk[a] * h;
-                    glo[axis] += side * h;
+                    orc_cell_gbox(f, &f->leaf[i], ijk, glo);
+                    orc_frame_matrix(f, f->leaf[i].tree, Qd);
+                    for (int a = 0; a < f->dim; ++a) glo[a] += side * Qd[a][axis] * h;
                     double acc[5 * 20];
                     memset(acc, 0, sizeof(acc));
                     for (int k = 0; k < gp->npiece; ++k) {
                         const orc_piece *pc = &gp->piece[k];
+                        int Qs[3][3];
+                        orc_frame_matrix(f, f->leaf[pc->leaf].tree, Qs);
                         orc_project_overlap(f, u + sidx(f, pc->leaf, 0, 0, pc->cell), nc, pc->src_lo,
-                                            pc->src_size, glo, h, pc->lo, pc->hi, acc);
+                                            pc->src_size, glo, h, pc->lo, pc->hi, Qs, Qd, acc);
                     }
                     for (int v = 0; v < f->nv; ++v)
                         for (int m = 0; m < f->nb; ++m) g[gidx(f, i, face, v, m, t)] = acc[v * f->nb + m];
@@ -393,7 +459,7 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
         orc_leaf_box(f, &f->leaf[i], lo, &size);
         long hu = size / f->N;
         double h[3] = {1, 1, 1};
-        for (int a = 0; a < d; ++a) h[a] = hu * unit_len(f, a);
+        for (int a = 0; a < d; ++a) h[a] = local_h(f, i, a); /* local axes */
         double J = 1.0;
         for (int a = 0; a < d; ++a) J *= 0.5 * h[a];
         for (int c = 0; c < nc; ++c) {
@@ -567,9 +633,8 @@ static void diffusion_residual(const orc_forest *f, const double *u, const doubl
     for (int i = 0; i < f->nleaves; ++i) {
         long lo[3], size;
         orc_leaf_box(f, &f->leaf[i], lo, &size);
-        long hu = size / f->N;
         double h[3] = {1, 1, 1};
-        for (int a = 0; a < d; ++a) h[a] = hu * unit_len(f, a);
+        for (int a = 0; a < d; ++a) h[a] = local_h(f, i, a); /* local axes */
         double J = 1.0;
         for (int a = 0; a < d; ++a) J *= 0.5 * h[a];
         for (int c = 0; c < nc; ++c) {
@@ -704,7 +769,7 @@ double orc_max_rate(const orc_forest *f, const double *u)
             for (int v = 0; v < f->nv; ++v) s[v] = u[sidx(f, i, v, 0, c)];
             double cs = sqrt(f->gamma * orc_pressure(d, f->gamma, s) / s[0]);
             double rate = 0.0;
-            for (int a = 0; a < d; ++a) rate += (fabs(s[1 + a] / s[0]) + cs) / ((size / f->N) * unit_len(f, a));
+            for (int a = 0; a < d; ++a) rate += (fabs(s[1 + a] / s[0]) + cs) / local_h(f, i, a);
             if (rate > mx) mx = rate;
         }
     }
@@ -715,7 +780,8 @@ double orc_max_rate(const orc_forest *f, const double *u)
  * dt = CFL / max_cells sum_a (|u_a| + c) / h_a. */
 double orc_dt(const orc_forest *f, const double *u, double cfl) { return cfl / orc_max_rate(f, u); }
 
-/* T_v = sum over cells of |cell| * mean_v, leaf by leaf, cell by cell. */
+/* T_v = sum over cells of |cell| * mean_v, leaf by leaf, cell by cell (the
+ * momentum along the global axes). */
 void orc_totals(const orc_forest *f, const double *u, double *totals)
 {
     int nc = orc_ncell(f);
@@ -725,8 +791,14 @@ void orc_totals(const orc_forest *f, const double *u, double *totals)
         orc_leaf_box(f, &f->leaf[i], lo, &size);
         double vol = 1.0;
         for (int a = 0; a < f->dim; ++a) vol *= (size / f->N) * unit_len(f, a);
-        for (int c = 0; c < nc; ++c)
-            for (int v = 0; v < f->nv; ++v) totals[v] += vol * u[sidx(f, i, v, 0, c)];
+        int Q[3][3];
+        orc_frame_matrix(f, f->leaf[i].tree, Q);
+        for (int c = 0; c < nc; ++c) {
+            double m[5] = {0, 0, 0, 0, 0};
+            for (int v = 0; v < f->nv; ++v) m[v] = u[sidx(f, i, v, 0, c)];
+            rotate_state(f, Q, 0, m); /* momentum along the global axes */
+            for (int v = 0; v < f->nv; ++v) totals[v] += vol * m[v];
+        }
     }
 }
 
@@ -929,9 +1001,8 @@ void orc_errors(const orc_forest *f, const double *u, int kind, const double *pa
         for (int a = 0; a < f->dim; ++a) J *= 0.5 * (size / f->N) * unit_len(f, a);
         for (int c = 0; c < nc; ++c)
             for (int iq = 0; iq < nq; ++iq) {
-                double x[3], ex[5], uh[5];
-                cell_point(f, i, c, xi[iq], x);
-                analytic_state(f, kind, params, t, x, ex);
+                double ex[5], uh[5];
+                analytic_local(f, i, c, kind, params, t, xi[iq], ex);
                 eval_poly(f, u + sidx(f, i, 0, 0, c), (long)f->nb * nc, nc, xi[iq], uh);
                 for (int v = 0; v < f->nv; ++v) {
                     double e = uh[v] - ex[v];
