@@ -105,6 +105,25 @@ typedef struct dgamr_graph dgamr_graph;
  * tables and uploads them to the current device.  EINVAL on a bad
  * descriptor, EUNSUPPORTED outside the built limits. */
 int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out);
+
+/* Sec. 3.1, 3.5: root blocks whose local frames are rotated against each
+ * other.  codes[tree] (one per root, trees row-major) is the rotation of the
+ * root's local axes, global vector = Q local vector: 2-D, code k = k quarter
+ * turns counter-clockwise (0..3); 3-D, code k = the k-th signed permutation
+ * matrix of determinant +1 when the permutations of the local axes are
+ * taken in lexicographic order and then the sign patterns (bit l: local
+ * axis l negative), 0..23.  The leaf keys, cells, modes and momentum of a
+ * root are in its local frame.  A guard cell across roots of different
+ * frames is the copy, split or combine of the neighbour's cells in the
+ * neighbour's frame, then turned into the own frame (K_d = R^n S^i K_s,
+ * Eq. 15-17): a signed permutation of the modes (exact: total-degree
+ * Legendre spaces are closed under signed permutations of the axes) and of
+ * the momentum components.  The steps of such a forest run the fill, the
+ * residual over the guard buffer and the stage update as separate launches.
+ * Requires equal root edges, the unrefined forest (ESTATE otherwise), the
+ * paper hanging mode and the Euler or diffusion equation (EUNSUPPORTED);
+ * pools do not admit such forests. */
+int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes);
 int dgamr_destroy_forest(dgamr_forest *f);
 
 /* Host queries.  keys: n_leaves x 5 int32 (tree, level, i, j, k). */

@@ -73,6 +73,8 @@ struct dgamr_forest {
     int device = 0;
     dgamr::LeafGeo *d_geo = nullptr;
     dgamr::FaceLink *d_links = nullptr;
+    dgamr::RotPlan *d_plans = nullptr; // guard-cell plans of rotated faces
+    size_t plans_cap = 0;
     int cap = 0;             // leaves the device tables can hold
     bool prof = false;       // bracket stage launches with events
     int stage_variant = -1;  // 2-D stage kernel: -1 auto, 0 lane per (cell, var), 1 thread per cell

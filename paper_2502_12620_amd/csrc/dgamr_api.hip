@@ -77,6 +77,14 @@ int upload(dgamr_forest *f)
     std::vector<LeafGeo> geo = f->topo.geometry();
     HIP_TRY(hipMemcpy(f->d_geo, geo.data(), sizeof(LeafGeo) * n, hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy(f->d_links, f->topo.links().data(), sizeof(FaceLink) * size_t(n) * nf, hipMemcpyHostToDevice));
+    const auto &plans = f->topo.plans();
+    if (plans.size() > f->plans_cap) {
+        if (f->d_plans) HIP_TRY(hipFree(f->d_plans));
+        f->plans_cap = plans.size() + plans.size() / 2 + 16;
+        HIP_TRY(hipMalloc(&f->d_plans, sizeof(dgamr::RotPlan) * f->plans_cap));
+    }
+    if (!plans.empty())
+        HIP_TRY(hipMemcpy(f->d_plans, plans.data(), sizeof(dgamr::RotPlan) * plans.size(), hipMemcpyHostToDevice));
     return DGAMR_OK;
 }
 
@@ -85,7 +93,7 @@ int upload(dgamr_forest *f)
 int launch_fill(dgamr_forest *f, const double *u, double *guard, bool traces, hipStream_t s)
 {
     int nf = 2 * f->topo.dim();
-    dgk::FillArgs a{u, guard, f->d_links, nullptr, f->topo.n() * nf, f->topo.desc().n_cell, traces ? 1 : 0};
+    dgk::FillArgs a{u, guard, f->d_links, f->d_plans, nullptr, f->topo.n() * nf, f->topo.desc().n_cell, traces ? 1 : 0};
     if (a.nfaces == 0) return DGAMR_OK;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
         HIP_TRY((dgk::launch_fill<D, P>(a, nfc_of(f), s, nv_of(f))));
@@ -113,6 +121,7 @@ dgk::StageShape stage_shape(const dgamr_forest *f)
 // the fused stage of this forest reads guard traces (the 3-D lane kernel)
 bool fused_reads_traces(const dgamr_forest *f)
 {
+    if (f->topo.rotated()) return false;
     return dgk::stage_reads_traces(f->topo.dim(), stage_shape(f), f->topo.desc().limiter == DGAMR_LIMITER_POSITIVITY,
                                    f->topo.desc().precision == DGAMR_FP32_MFMA,
                                    f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE, f->topo.advection(),
@@ -285,6 +294,7 @@ int dgamr_destroy_forest(dgamr_forest *f)
     }
     (void)hipFree(f->d_geo);
     (void)hipFree(f->d_links);
+    (void)hipFree(f->d_plans);
     delete f;
     return DGAMR_OK;
 }
@@ -438,6 +448,29 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
     static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
     const double *us = u;
     double *outs[3] = {w.u1, w.u2, u};
+    if (f->topo.rotated()) {
+        // roots of different frames: the guard fill applies the rotation of
+        // each guard cell (Sec. 3.5) into the guard buffer, then the residual
+        // over guard coefficients, the stage update and the limiter, unfused
+        const bool r32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
+        for (int s = 0; s < 3; ++s) {
+            CHECK(launch_fill(f, us, w.guard, false, stream));
+            dgk::StageArgs a{};
+            a.us = us;
+            a.guard = w.guard;
+            a.out64 = r32 ? nullptr : w.res;
+            a.out32 = r32 ? reinterpret_cast<float *>(w.res) : nullptr;
+            CHECK(launch_stage(f, a, dgk::GUARD_BUFFER, r32 ? dgk::OUT_RES32 : dgk::OUT_RES64, stream));
+            dgk::RkArgs rk{u, us, w.res, outs[s], dt_dev, A[s], B[s], long(state_elems(f)), r32 ? 1 : 0};
+            long blocks = (rk.n + 255) / 256;
+            if (blocks > 65536) blocks = 65536;
+            hipLaunchKernelGGL(dgk::k_rk, dim3(unsigned(blocks)), dim3(256), 0, stream, rk);
+            HIP_TRY(hipGetLastError());
+            if (lim) CHECK(launch_limit(f, outs[s], stream));
+            us = outs[s];
+        }
+        return DGAMR_OK;
+    }
     for (int s = 0; s < 3; ++s) {
         dgk::StageArgs a{};
         a.us = us;
@@ -483,6 +516,19 @@ int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_de
     if (f->topo.diffusion()) return step_diffusion(f, cfl, u, w, dt_dev, stream);
     if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
     return run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream);
+}
+
+int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes)
+{
+    GUARD_API({
+        CHECK(check_ptr(f, "forest"));
+        CHECK(check_ptr(codes, "codes"));
+        std::string err;
+        int rc = f->topo.set_frames(codes, err);
+        if (rc != DGAMR_OK) return fail(rc, err);
+        f->version += 1;
+        return upload(f);
+    })
 }
 
 int dgamr_set_time(dgamr_forest *f, double t)
@@ -535,8 +581,11 @@ int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, do
         return DGAMR_OK;
     }
     auto *slot = reinterpret_cast<unsigned long long *>(w.scal + 2);
-    if (cfl <= 0.0) {
-        for (int s = 0; s < nsteps; ++s) CHECK(run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream));
+    if (cfl <= 0.0 || f->topo.rotated()) { // rotated frames: the unfused stages take dt per step
+        for (int s = 0; s < nsteps; ++s) {
+            if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
+            CHECK(run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream));
+        }
         return DGAMR_OK;
     }
     CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
@@ -584,6 +633,11 @@ int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *
             for (int st = 0; st < nsteps && rc == DGAMR_OK; ++st) {
                 const int rd = st & 1, wr = rd ^ 1;
                 const bool last = st == nsteps - 1;
+                if (f->topo.rotated()) { // unfused stages: the CFL reduction of every step
+                    if (st > 0) rc = launch_dt(f, cfl, u, dt_dev, w, s);
+                    if (rc == DGAMR_OK) rc = run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, s);
+                    continue;
+                }
                 rc = run_step(f, cfl, u, w, dt_dev, slot + rd, slot + wr, last ? nullptr : slot + wr, s);
             }
             hipGraph_t graph = nullptr;

@@ -12,6 +12,37 @@ namespace {
 constexpr int kMaxLevel = 12; // idx < 2048 per axis: 11 bits each in the packed key
 }
 
+void frame_matrix(int dim, int code, int Q[3][3])
+{
+    for (int g = 0; g < 3; ++g)
+        for (int l = 0; l < 3; ++l) Q[g][l] = 0;
+    if (dim == 2) {
+        static const int c[4] = {1, 0, -1, 0}, sn[4] = {0, 1, 0, -1};
+        Q[0][0] = c[code];
+        Q[0][1] = -sn[code];
+        Q[1][0] = sn[code];
+        Q[1][1] = c[code];
+        Q[2][2] = 1;
+        return;
+    }
+    static const int perms[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int n = 0;
+    for (int pi = 0; pi < 6; ++pi)
+        for (int sg = 0; sg < 8; ++sg) {
+            int M[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            for (int l = 0; l < 3; ++l) M[perms[pi][l]][l] = ((sg >> l) & 1) ? -1 : 1;
+            const int det = M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                            M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                            M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0]);
+            if (det != 1) continue;
+            if (n++ == code) {
+                for (int g = 0; g < 3; ++g)
+                    for (int l = 0; l < 3; ++l) Q[g][l] = M[g][l];
+                return;
+            }
+        }
+}
+
 Forest::Forest(const dgamr_forest_desc &d) : desc_(d)
 {
     for (int a = desc_.dim; a < 3; ++a) {
@@ -128,13 +159,67 @@ void Forest::sort_keys(std::vector<Key> &v) const
     });
 }
 
+int Forest::set_frames(const int32_t *codes, std::string &err)
+{
+    const int d = desc_.dim, ntree = desc_.roots[0] * desc_.roots[1] * desc_.roots[2];
+    if (n() != ntree) {
+        err = "root frames are set on the unrefined forest";
+        return DGAMR_ESTATE;
+    }
+    bool any = false;
+    for (int t = 0; t < ntree; ++t) {
+        if (codes[t] < 0 || codes[t] >= (d == 2 ? 4 : 24)) {
+            err = "frame codes are 0..3 (2-D) or 0..23 (3-D)";
+            return DGAMR_EINVAL;
+        }
+        any = any || codes[t] != 0;
+    }
+    if (any) {
+        for (int a = 1; a < d; ++a)
+            if ((desc_.hi[a] - desc_.lo[a]) / desc_.roots[a] != (desc_.hi[0] - desc_.lo[0]) / desc_.roots[0]) {
+                err = "rotated root frames need equal root edges";
+                return DGAMR_EINVAL;
+            }
+        if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.equation == DGAMR_EQ_ADVECTION) {
+            err = "rotated root frames are built for the paper hanging mode, Euler and diffusion";
+            return DGAMR_EUNSUPPORTED;
+        }
+    }
+    frame_.assign(codes, codes + ntree);
+    rotated_ = any;
+    return build_links(err);
+}
+
+// Position of a leaf-level index (at `span` leaves per root edge) moved
+// between a root's local frame and the global axes (relative to the root):
+// along global axis g = pi(l) the local index l, reversed when Q[g][l] = -1.
+static void local_to_root(const int Q[3][3], int d, int span, const int *loc, int *glob)
+{
+    for (int l = 0; l < d; ++l)
+        for (int g = 0; g < d; ++g) {
+            if (Q[g][l] == 1) glob[g] = loc[l];
+            if (Q[g][l] == -1) glob[g] = span - 1 - loc[l];
+        }
+}
+static void root_to_local(const int Q[3][3], int d, int span, const int *glob, int *loc)
+{
+    for (int l = 0; l < d; ++l)
+        for (int g = 0; g < d; ++g) {
+            if (Q[g][l] == 1) loc[l] = glob[g];
+            if (Q[g][l] == -1) loc[l] = span - 1 - glob[g];
+        }
+}
+
 int Forest::build_links(std::string &err)
 {
     const int d = desc_.dim, nf = 2 * d;
     links_.assign(size_t(n()) * nf, FaceLink{});
+    plans_.clear();
     for (int i = 0; i < n(); ++i) {
         const Key &k = leaves_[i];
         const int span = 1 << (k.level - 1);
+        int Q[3][3];
+        frame_matrix(d, frame_of(k.tree), Q);
         for (int face = 0; face < nf; ++face) {
             const int a = face / 2, s = (face % 2) ? 1 : -1;
             FaceLink &L = links_[size_t(i) * nf + face];
@@ -144,66 +229,239 @@ int Forest::build_links(std::string &err)
                 if (b != a) tang[nt++] = b;
             int nidx[3] = {k.idx[0], k.idx[1], k.idx[2]};
             int ntree = k.tree;
+            // the neighbour's face toward this leaf, in the neighbour's frame
+            int na = a, ns = -s;
             nidx[a] += s;
             if (nidx[a] < 0 || nidx[a] >= span) {
-                if (!neighbour_root(k.tree, a, s, ntree)) {
+                // across the root face: global axis and side of the local face
+                int ga = 0, gs = 0;
+                for (int g = 0; g < d; ++g)
+                    if (Q[g][a] != 0) {
+                        ga = g;
+                        gs = s * Q[g][a];
+                    }
+                if (!neighbour_root(k.tree, ga, gs, ntree)) {
                     L.type = LINK_BOUNDARY;
                     continue;
                 }
-                nidx[a] = s > 0 ? 0 : span - 1;
+                int glob[3] = {0, 0, 0}, Qn[3][3];
+                local_to_root(Q, d, span, k.idx, glob);
+                glob[ga] = gs > 0 ? 0 : span - 1;
+                frame_matrix(d, frame_of(ntree), Qn);
+                root_to_local(Qn, d, span, glob, nidx);
+                nidx[2] = d == 3 ? nidx[2] : 0;
+                for (int l = 0; l < d; ++l)
+                    if (Qn[ga][l] != 0) {
+                        na = l;
+                        ns = -gs * Qn[ga][l];
+                    }
             }
+            const bool rot = frame_of(ntree) != frame_of(k.tree);
             int j = find(ntree, k.level, nidx);
             if (j >= 0) {
                 L.type = LINK_SAME;
                 L.nbr[0] = j;
-                continue;
+            } else {
+                int pidx[3] = {nidx[0] >> 1, nidx[1] >> 1, nidx[2] >> 1};
+                j = find(ntree, k.level - 1, pidx);
+                if (j >= 0) {
+                    L.type = LINK_COARSE;
+                    L.nbr[0] = j;
+                    for (int q = 0; q < nt; ++q) L.off[q] = k.idx[tang[q]] & 1;
+                } else {
+                    // the 2^(d-1) children of the same-level position that touch
+                    // the face, ordered by this leaf's tangential axes (in the
+                    // neighbour's frame when the frames differ; rotated faces
+                    // take their sources from the guard-cell plans)
+                    int ntang[2] = {0, 0}, nnt = 0;
+                    for (int b = 0; b < d; ++b)
+                        if (b != na) ntang[nnt++] = b;
+                    bool ok = k.level < desc_.max_level;
+                    for (int c = 0; ok && c < (1 << (d - 1)); ++c) {
+                        int cidx[3] = {2 * nidx[0], 2 * nidx[1], 2 * nidx[2]};
+                        cidx[na] += (ns > 0) ? 1 : 0;
+                        for (int q = 0; q < nnt; ++q) cidx[ntang[q]] += (c >> q) & 1;
+                        int jj = find(ntree, k.level + 1, cidx);
+                        if (jj < 0) ok = false;
+                        L.nbr[c] = jj;
+                    }
+                    if (!ok) {
+                        err = "forest violates 2:1 face balance";
+                        return DGAMR_EBALANCE;
+                    }
+                    L.type = LINK_FINE;
+                }
             }
-            int pidx[3] = {nidx[0] >> 1, nidx[1] >> 1, nidx[2] >> 1};
-            j = find(ntree, k.level - 1, pidx);
-            if (j >= 0) {
-                L.type = LINK_COARSE;
-                L.nbr[0] = j;
-                for (int q = 0; q < nt; ++q) L.off[q] = k.idx[tang[q]] & 1;
-                continue;
+            L.rot = 0;
+            if (rot) {
+                L.rot = 1 + int(plans_.size());
+                if (!rot_plans(i, face, L)) {
+                    err = "a guard cell across rotated roots is not covered by its neighbours";
+                    return DGAMR_EBALANCE;
+                }
             }
-            bool ok = k.level < desc_.max_level;
-            for (int c = 0; ok && c < (1 << (d - 1)); ++c) {
-                int cidx[3] = {2 * nidx[0], 2 * nidx[1], 2 * nidx[2]};
-                cidx[a] += (s > 0) ? 0 : 1;
-                for (int q = 0; q < nt; ++q) cidx[tang[q]] += (c >> q) & 1;
-                int jj = find(ntree, k.level + 1, cidx);
-                if (jj < 0) ok = false;
-                L.nbr[c] = jj;
-            }
-            if (!ok) {
-                err = "forest violates 2:1 face balance";
-                return DGAMR_EBALANCE;
-            }
-            L.type = LINK_FINE;
         }
     }
     return DGAMR_OK;
 }
 
+// Guard-cell plans of the rotated face (leaf i, face): for each guard cell
+// t, its box in the neighbour root's local frame (finest-level units), the
+// neighbour cells that cover it, and the relative frame.
+bool Forest::rot_plans(int i, int face, const FaceLink &L)
+{
+    const int d = desc_.dim, N = desc_.n_cell;
+    const Key &k = leaves_[i];
+    const long unit = long(N) << (desc_.max_level - 1); // finest units per root edge
+    const long edge = unit >> (k.level - 1), h = edge / N;
+    const int a = face / 2, s = (face % 2) ? 1 : -1;
+    int Q[3][3];
+    frame_matrix(d, frame_of(k.tree), Q);
+    const int src = L.nbr[0];
+    int Qn[3][3];
+    frame_matrix(d, frame_of(leaves_[src].tree), Qn);
+    // m = Qn^T Q: source reference coordinates from destination ones
+    int m[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int lp = 0; lp < d; ++lp)
+        for (int l = 0; l < d; ++l)
+            for (int g = 0; g < d; ++g) m[lp][l] += Qn[g][lp] * Q[g][l];
+    int tang[2] = {0, 0}, nt = 0;
+    for (int b = 0; b < d; ++b)
+        if (b != a) tang[nt++] = b;
+    auto leaf_lbox = [&](int j, long *lo) {
+        const Key &q = leaves_[j];
+        const long e = unit >> (q.level - 1);
+        for (int b = 0; b < 3; ++b) lo[b] = b < d ? q.idx[b] * e : 0;
+        return e;
+    };
+    const int nfc = d == 2 ? N : N * N;
+    for (int t = 0; t < nfc; ++t) {
+        // guard cell box in this root's local frame
+        long lo[3] = {0, 0, 0};
+        leaf_lbox(i, lo);
+        int ijk[3] = {0, 0, 0};
+        ijk[a] = s > 0 ? N - 1 : 0;
+        ijk[tang[0]] = t % N;
+        if (d == 3) ijk[tang[1]] = t / N;
+        for (int b = 0; b < d; ++b) lo[b] += ijk[b] * h;
+        lo[a] += s * h;
+        // to the global axes relative to this root, then across into the
+        // neighbour root (the face's global axis shifts by one root edge)
+        long gl[3] = {0, 0, 0};
+        int ga = 0, gs = 0;
+        for (int l = 0; l < d; ++l)
+            for (int g = 0; g < d; ++g) {
+                if (Q[g][l] == 1) gl[g] = lo[l];
+                if (Q[g][l] == -1) gl[g] = unit - lo[l] - h;
+                if (l == a && Q[g][l] != 0) {
+                    ga = g;
+                    gs = s * Q[g][l];
+                }
+            }
+        gl[ga] += gs > 0 ? -unit : unit;
+        long nl[3] = {0, 0, 0}; // guard box in the neighbour's local frame
+        for (int l = 0; l < d; ++l)
+            for (int g = 0; g < d; ++g) {
+                if (Qn[g][l] == 1) nl[l] = gl[g];
+                if (Qn[g][l] == -1) nl[l] = unit - gl[g] - h;
+            }
+        RotPlan P{};
+        for (int lp = 0; lp < 3; ++lp)
+            for (int l = 0; l < 3; ++l) P.m[3 * lp + l] = (signed char)m[lp][l];
+        auto cell_of = [&](int j, const long *pt, long &ch) {
+            long blo[3];
+            const long e = leaf_lbox(j, blo), hc = e / N;
+            int c = 0, mul = 1;
+            for (int b = 0; b < d; ++b) {
+                c += int((pt[b] - blo[b]) / hc) * mul;
+                mul *= N;
+            }
+            ch = hc;
+            return c;
+        };
+        auto contains = [&](int j, const long *pt) {
+            long blo[3];
+            const long e = leaf_lbox(j, blo);
+            for (int b = 0; b < d; ++b)
+                if (pt[b] < blo[b] || pt[b] >= blo[b] + e) return false;
+            return true;
+        };
+        if (L.type != LINK_FINE && !contains(src, nl)) return false;
+        if (L.type == LINK_SAME) {
+            long hc;
+            P.type = PLAN_COPY;
+            P.leaf[0] = src;
+            P.cell[0] = cell_of(src, nl, hc);
+        } else if (L.type == LINK_COARSE) {
+            long hc;
+            P.type = PLAN_SPLIT;
+            P.leaf[0] = src;
+            P.cell[0] = cell_of(src, nl, hc);
+            long blo[3];
+            leaf_lbox(src, blo);
+            int child = 0;
+            for (int b = 0; b < d; ++b) child |= int(((nl[b] - blo[b]) % hc) / (hc / 2)) << b;
+            P.child = child;
+        } else {
+            P.type = PLAN_COMBINE;
+            for (int c = 0; c < (1 << d); ++c) {
+                long pt[3] = {0, 0, 0};
+                for (int b = 0; b < d; ++b) pt[b] = nl[b] + ((c >> b) & 1) * (h / 2);
+                int jf = -1;
+                for (int q = 0; q < (1 << (d - 1)); ++q)
+                    if (L.nbr[q] >= 0 && contains(L.nbr[q], pt)) jf = L.nbr[q];
+                if (jf < 0) return false;
+                long hc;
+                P.leaf[c] = jf;
+                P.cell[c] = cell_of(jf, pt, hc);
+            }
+        }
+        plans_.push_back(P);
+    }
+    return true;
+}
+
 std::vector<LeafGeo> Forest::geometry() const
 {
+    const int d = desc_.dim;
     std::vector<LeafGeo> g(n());
     for (int i = 0; i < n(); ++i) {
         const Key &k = leaves_[i];
         int r[3] = {k.tree % desc_.roots[0], (k.tree / desc_.roots[0]) % desc_.roots[1],
                     k.tree / (desc_.roots[0] * desc_.roots[1])};
+        int Q[3][3];
+        frame_matrix(d, frame_of(k.tree), Q);
         LeafGeo &G = g[i];
         G.vol = 1.0;
+        // local origin of the leaf: its local lower corner, mapped through the
+        // root's frame (the root box maps onto itself)
+        const int span = 1 << (k.level - 1);
         for (int a = 0; a < 3; ++a) {
-            double root = (desc_.hi[a] - desc_.lo[a]) / desc_.roots[a];
-            double edge = root / double(1 << (k.level - 1));
-            G.lo[a] = desc_.lo[a] + r[a] * root + k.idx[a] * edge;
-            G.h[a] = edge / desc_.n_cell;
-            G.scale[a] = 2.0 / G.h[a];
-            if (a < desc_.dim) G.vol *= G.h[a];
+            const double root = (desc_.hi[a] - desc_.lo[a]) / desc_.roots[a];
+            G.lo[a] = desc_.lo[a] + r[a] * root;
+        }
+        for (int l = 0; l < 3; ++l) {
+            const int ga = [&] {
+                for (int gg = 0; gg < d; ++gg)
+                    if (Q[gg][l] != 0) return gg;
+                return l;
+            }();
+            const double root = (desc_.hi[ga] - desc_.lo[ga]) / desc_.roots[ga];
+            const double edge = root / double(span);
+            G.h[l] = edge / desc_.n_cell;
+            G.scale[l] = 2.0 / G.h[l];
+            if (l < d) {
+                G.vol *= G.h[l];
+                // the local coordinate k.idx[l] * edge from the root's local
+                // origin, which sits at the root's far side when Q[ga][l] = -1
+                G.lo[ga] += Q[ga][l] > 0 ? k.idx[l] * edge : root - k.idx[l] * edge;
+            }
         }
         G.level = k.level;
         G.pad = 0;
+        for (int gg = 0; gg < 3; ++gg)
+            for (int l = 0; l < 3; ++l) G.q[3 * gg + l] = (signed char)Q[gg][l];
+        for (int x = 9; x < 12; ++x) G.q[x] = 0;
     }
     return g;
 }

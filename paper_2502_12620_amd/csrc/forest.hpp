@@ -21,27 +21,52 @@ struct Key {
 
 enum LinkType : int { LINK_SAME = 0, LINK_COARSE = 1, LINK_FINE = 2, LINK_BOUNDARY = 3 };
 
-// Neighbour relation across one face.  SAME/COARSE: nbr[0].  FINE: the
-// 2^(d-1) finer leaves, ordered by their tangential position (lower axis
-// bit fastest).  COARSE: off[k] is this leaf's half (0/1) along the k-th
-// tangential axis inside the coarse neighbour's face.
+// Neighbour relation across one face (in the leaf's local frame).
+// SAME/COARSE: nbr[0].  FINE: the 2^(d-1) finer leaves, ordered by their
+// tangential position (lower axis bit fastest).  COARSE: off[k] is this
+// leaf's half (0/1) along the k-th tangential axis inside the coarse
+// neighbour's face.  rot: 0 when the neighbour's root has the same frame;
+// else 1 + the index of this face's first guard-cell plan (RotPlan), and
+// nbr/off are not used by the kernels.
 struct FaceLink {
     int type;
     int nbr[4];
     int off[2];
-    int pad;
+    int rot;
 };
 static_assert(sizeof(FaceLink) == 32, "FaceLink is uploaded as 8 int32");
 
-// Per-leaf geometry uploaded to the device.
+// Per-leaf geometry uploaded to the device, along the leaf's local axes.
 struct LeafGeo {
     double scale[3]; // 2 / h_a
-    double lo[3];    // physical lower corner of the leaf
-    double h[3];     // cell edge per axis
+    double lo[3];    // physical position of the leaf's local origin corner
+    double h[3];     // cell edge per local axis
     double vol;      // cell volume
     int level;
     int pad;
+    signed char q[12]; // the root's frame Q (q[3 g + l]): global vector = Q local
 };
+
+// Guard cell across a face between roots of different frames (Sec. 3.5:
+// K_d = R^n K_s, R^n S^i K_s or R^n C(K_s...)): the source cells in the
+// neighbour's frame, the operator applied there, and the rotation into the
+// destination frame.  m[3 l' + l]: the source's reference coordinate l' is
+// m times the destination's coordinate l (a signed permutation); momentum
+// goes to the destination frame with its transpose.
+enum PlanType : int { PLAN_COPY = 0, PLAN_SPLIT = 1, PLAN_COMBINE = 2 };
+struct RotPlan {
+    int type;
+    int child;       // PLAN_SPLIT: position of the guard cell inside the source cell (source frame)
+    int leaf[8];     // COPY/SPLIT: [0]; COMBINE: fine cell of child position c (source frame)
+    int cell[8];
+    signed char m[12];
+};
+
+// frame matrix of a rotation code: 2-D quarter turns counter-clockwise;
+// 3-D the code-th signed permutation matrix of determinant +1 (the
+// permutations of the local axes in lexicographic order, then the sign
+// patterns, bit l = local axis l negative).  Q[g][l]: global = Q local.
+void frame_matrix(int dim, int code, int Q[3][3]);
 
 // Inheritance of one new leaf: copied, split from a parent or combined
 // from 2^d children of the old forest.
@@ -70,8 +95,13 @@ class Forest {
     const std::vector<FaceLink> &links() const { return links_; }
     const dgamr_forest_desc &desc() const { return desc_; }
 
-    // rebuilds links_; DGAMR_EBALANCE on a 2:1 violation
+    // rebuilds links_ (and the guard plans of rotated faces); DGAMR_EBALANCE
+    // on a 2:1 violation
     int build_links(std::string &err);
+    // rotation codes of the root frames (one per tree), before any refinement
+    int set_frames(const int32_t *codes, std::string &err);
+    bool rotated() const { return rotated_; }
+    const std::vector<RotPlan> &plans() const { return plans_; }
     std::vector<LeafGeo> geometry() const;
 
     // refinement planning and switching; see dgamr_set_refinement
@@ -94,6 +124,11 @@ class Forest {
     std::vector<Key> leaves_;
     std::unordered_map<uint64_t, int> index_;
     std::vector<FaceLink> links_;
+    std::vector<int> frame_;      // per tree (empty: all 0)
+    bool rotated_ = false;        // some root has a non-zero frame
+    std::vector<RotPlan> plans_;  // guard-cell plans of rotated faces
+    int frame_of(int tree) const { return frame_.empty() ? 0 : frame_[tree]; }
+    bool rot_plans(int i, int face, const FaceLink &L);
     std::vector<Key> planned_;
     std::vector<Inherit> planned_inh_;
     bool has_plan_ = false;

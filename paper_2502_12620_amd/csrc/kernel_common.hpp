@@ -15,6 +15,7 @@ namespace dgk {
 using dgamr::FaceLink;
 using dgamr::Inherit;
 using dgamr::LeafGeo;
+using dgamr::RotPlan;
 
 constexpr int kXcds = 8; // MI355X: 8 XCDs, workgroups dispatched round-robin
 
@@ -32,6 +33,20 @@ __device__ __forceinline__ void cell_ijk(int cell, int N, int D, int *ijk)
     ijk[0] = cell % N;
     ijk[1] = (cell / N) % N;
     ijk[2] = D == 3 ? cell / (N * N) : 0;
+}
+
+// physical position of the local point (ijk + (xi + 1)/2) h of a leaf:
+// its local origin plus the frame Q applied to the local offset
+template <int D>
+__device__ __forceinline__ void leaf_point(const LeafGeo &G, const int *ijk, const double *xi, double *x)
+{
+    for (int g = 0; g < 3; ++g) x[g] = g < D ? G.lo[g] : 0.0;
+#pragma unroll
+    for (int l = 0; l < D; ++l) {
+        const double off = (ijk[l] + 0.5 * (xi[l] + 1.0)) * G.h[l];
+#pragma unroll
+        for (int g = 0; g < D; ++g) x[g] += double(G.q[3 * g + l]) * off;
+    }
 }
 
 // tangential index t of a cell on the face normal to axis a (the lower of
@@ -264,6 +279,7 @@ struct FillArgs {
     const double *u;
     double *guard;
     const FaceLink *links;
+    const RotPlan *plans; // guard cells of faces between roots of different frames
     const int *work;   // leaves whose 2d faces are filled (null: all leaves)
     int nfaces;        // number of faces to fill (2d per listed leaf)
     int N;

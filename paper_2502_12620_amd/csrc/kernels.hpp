@@ -177,6 +177,35 @@ __device__ __forceinline__ void split_any(int child, const T *k, T *gk)
     }
 }
 
+// Adds the combine contribution of child CH (Eq. 13-14): gk += C_CH k.
+template <int D, int P, int CH>
+__device__ __forceinline__ void comb_coeffs(const double *k, double *gk)
+{
+    constexpr int NB = Tab<D, P>::NB;
+#pragma unroll
+    for (int m = 0; m < NB; ++m)
+#pragma unroll
+        for (int n = 0; n < NB; ++n) {
+            const double c = kTab<D, P>.comb[CH][m][n];
+            if (c != 0.0) gk[m] = fma(c, k[n], gk[m]);
+        }
+}
+
+template <int D, int P>
+__device__ __forceinline__ void comb_any(int child, const double *k, double *gk)
+{
+    switch (child) {
+    case 0: comb_coeffs<D, P, 0>(k, gk); break;
+    case 1: comb_coeffs<D, P, 1>(k, gk); break;
+    case 2: comb_coeffs<D, P, 2>(k, gk); break;
+    case 3: comb_coeffs<D, P, 3>(k, gk); break;
+    case 4: if constexpr (D == 3) comb_coeffs<D, P, 4>(k, gk); break;
+    case 5: if constexpr (D == 3) comb_coeffs<D, P, 5>(k, gk); break;
+    case 6: if constexpr (D == 3) comb_coeffs<D, P, 6>(k, gk); break;
+    default: if constexpr (D == 3) comb_coeffs<D, P, 7>(k, gk); break;
+    }
+}
+
 // Far-side traces of block face (A, side) at the FCH face points starting
 // at f0, for the cell with tangential index t (the far polynomial touches
 // the face with its -side side):
@@ -889,6 +918,66 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
             for (int m = 0; m < NB; ++m) out[(v * NB + m) * nfc] = gk[m];
         }
     };
+    if (L.rot > 0) {
+        // a neighbour root of another frame (Sec. 3.5): copy, split or combine
+        // in the source frame, then the rotation R^n into this leaf's frame
+        const RotPlan Rp = g.plans[L.rot - 1 + t];
+        double ks[NV][NB];
+        for (int v = 0; v < NV; ++v) {
+            double kv[NB];
+            if (Rp.type == dgamr::PLAN_COMBINE) {
+#pragma unroll
+                for (int m = 0; m < NB; ++m) kv[m] = 0.0;
+                for (int ch = 0; ch < (1 << D); ++ch) {
+                    const double *src = g.u + long(Rp.leaf[ch]) * NV * sv + long(v) * sv + Rp.cell[ch];
+                    double kf[NB];
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) kf[n] = src[long(n) * ncell];
+                    comb_any<D, P>(ch, kf, kv);
+                }
+            } else {
+                const double *src = g.u + long(Rp.leaf[0]) * NV * sv + long(v) * sv + Rp.cell[0];
+                double kc[NB];
+#pragma unroll
+                for (int n = 0; n < NB; ++n) kc[n] = src[long(n) * ncell];
+                if (Rp.type == dgamr::PLAN_SPLIT) split_any<D, P, double>(Rp.child, kc, kv);
+                else
+#pragma unroll
+                    for (int n = 0; n < NB; ++n) kv[n] = kc[n];
+            }
+            // modes: phi_n(m xi) = sign * phi_n'(xi), exponent l of n' = exponent
+            // l' of n where m[l'][l] != 0
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                int e2[3] = {0, 0, 0};
+                double sg = 1.0;
+                for (int lp = 0; lp < D; ++lp)
+                    for (int l = 0; l < D; ++l) {
+                        const int mm = Rp.m[3 * lp + l];
+                        if (mm != 0) {
+                            e2[l] = kTab<D, P>.e[n][lp];
+                            if (mm < 0 && (kTab<D, P>.e[n][lp] & 1)) sg = -sg;
+                        }
+                    }
+                int idx = 0;
+                for (int q = 0; q < NB; ++q)
+                    if (kTab<D, P>.e[q][0] == e2[0] && kTab<D, P>.e[q][1] == e2[1] && kTab<D, P>.e[q][2] == e2[2])
+                        idx = q;
+                ks[v][idx] = sg * kv[n];
+            }
+        }
+        if (NV == D + 2) { // momentum into this leaf's frame: m_dst[l] = sum_l' m[l'][l] m_src[l']
+#pragma unroll
+            for (int n = 0; n < NB; ++n) {
+                double mv[3] = {0.0, 0.0, 0.0};
+                for (int l = 0; l < D; ++l)
+                    for (int lp = 0; lp < D; ++lp) mv[l] += double(Rp.m[3 * lp + l]) * ks[1 + lp][n];
+                for (int l = 0; l < D; ++l) ks[1 + l][n] = mv[l];
+            }
+        }
+        for (int v = 0; v < NV; ++v) emit(v, ks[v]);
+        return;
+    }
     if (L.type == dgamr::LINK_SAME) {
         const int c = face_cell(a, side > 0 ? 0 : N - 1, t, N, D);
         const double *src = g.u + long(L.nbr[0]) * NV * sv + c;

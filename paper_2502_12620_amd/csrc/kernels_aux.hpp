@@ -144,13 +144,23 @@ __global__ __launch_bounds__(256) void k_project_ic(double *u, const LeafGeo *ge
 #pragma unroll 1
     for (int q = 0; q < NQI; ++q) {
         const int qi[3] = {q % QI, (q / QI) % QI, q / (QI * QI)};
-        double x[3] = {0, 0, 0}, w = 1.0;
+        double x[3] = {0, 0, 0}, xi[3] = {0, 0, 0}, w = 1.0;
         for (int a = 0; a < D; ++a) {
             w *= kIcTab<P>.w[qi[a]];
-            x[a] = G.lo[a] + (ijk[a] + 0.5 * (kIcTab<P>.x[qi[a]] + 1.0)) * G.h[a];
+            xi[a] = kIcTab<P>.x[qi[a]];
         }
+        leaf_point<D>(G, ijk, xi, x);
         double U[D + 2];
         analytic<D>(kind, prm, t, gamma, x, hmin, U);
+        if constexpr (NV == D + 2) { // momentum into the leaf's frame: Q^T m
+            double m[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int l = 0; l < D; ++l)
+#pragma unroll
+                for (int g2 = 0; g2 < D; ++g2) m[l] += double(G.q[3 * g2 + l]) * U[1 + g2];
+#pragma unroll
+            for (int l = 0; l < D; ++l) U[1 + l] = m[l];
+        }
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
             double ph = w;

@@ -154,16 +154,15 @@ __global__ __launch_bounds__(256) void k_ipdg(IpdgArgs g)
                 face_val_dn<D, P, A>(K, f, s, um, dm);
                 if (dirichlet) {
                     // physical face point
-                    double x[3] = {0.0, 0.0, 0.0};
+                    double x[3] = {0.0, 0.0, 0.0}, xi[3] = {0.0, 0.0, 0.0};
                     const int f0 = f % Q, f1 = f / Q;
                     int k = 0;
 #pragma unroll
                     for (int b = 0; b < D; ++b) {
-                        double xi;
-                        if (b == A) xi = double(s);
-                        else xi = gl_x(Q, k++ == 0 ? f0 : f1);
-                        x[b] = G.lo[b] + (ijk[b] + 0.5 * (xi + 1.0)) * G.h[b];
+                        if (b == A) xi[b] = double(s);
+                        else xi[b] = gl_x(Q, k++ == 0 ? f0 : f1);
                     }
+                    leaf_point<D>(G, ijk, xi, x);
                     double e = 0.0, a2 = 0.0;
 #pragma unroll
                     for (int b = 0; b < D; ++b) {

@@ -134,8 +134,17 @@ __global__ __launch_bounds__(256) void k_totals_leaf(const double *u, const Leaf
             for (int v = 0; v < NV; ++v) red[v][threadIdx.x] += red[v][threadIdx.x + st];
         __syncthreads();
     }
-    if (threadIdx.x == 0)
-        for (int v = 0; v < NV; ++v) part[long(leaf) * NV + v] = red[v][0] * geo[leaf].vol;
+    if (threadIdx.x == 0) {
+        double tv[NV];
+        for (int v = 0; v < NV; ++v) tv[v] = red[v][0] * geo[leaf].vol;
+        if constexpr (NV == D + 2) { // momentum along the global axes: Q m
+            double m[3] = {0.0, 0.0, 0.0};
+            for (int g = 0; g < D; ++g)
+                for (int l = 0; l < D; ++l) m[g] += double(geo[leaf].q[3 * g + l]) * tv[1 + l];
+            for (int g = 0; g < D; ++g) tv[1 + g] = m[g];
+        }
+        for (int v = 0; v < NV; ++v) part[long(leaf) * NV + v] = tv[v];
+    }
 }
 
 template <int NV>

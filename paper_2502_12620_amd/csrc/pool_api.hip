@@ -142,7 +142,7 @@ int pool_stage(dgamr_pool *p, int stage, const double *us, const double *un, dou
     if (dgk::stage_reads_traces(p->dim, sh, lim, fp32, a.conservative != 0, false, p->N)) {
         gm = dgk::GUARD_TRACE;
         a.guard = w.guard;
-        dgk::FillArgs fa{us, w.guard, p->d_links, p->d_work, p->nwork * 2 * p->dim, p->N, 1};
+        dgk::FillArgs fa{us, w.guard, p->d_links, nullptr, p->d_work, p->nwork * 2 * p->dim, p->N, 1};
         CHECK(dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
             HIP_TRY((dgk::launch_fill<D, P>(fa, p->nfc, s)));
             return DGAMR_OK;
@@ -288,6 +288,7 @@ int dgamr_pool_admit(dgamr_pool *p, const dgamr_forest *f, double cfl, int32_t *
         CHECK(check_ptr(member, "member"));
         CHECK(check_ptr(slot_first, "slot_first"));
         if (!same_class(p->cls, f->topo.desc())) return fail(DGAMR_EINVAL, "forest is not of the pool's class");
+        if (f->topo.rotated()) return fail(DGAMR_EUNSUPPORTED, "pools hold forests whose roots share one frame");
         if (!(cfl > 0.0)) return fail(DGAMR_EINVAL, "cfl must be positive");
         const int64_t n = f->topo.n();
         if (n == 0) return fail(DGAMR_EINVAL, "empty forest");

@@ -33,7 +33,7 @@ EXPORTS = [
     "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
     "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_set_lanes", "dgamr_pool_autotune",
     "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture",
-    "dgamr_step_static", "dgamr_set_time", "dgamr_get_time", "dgamr_last_error",
+    "dgamr_step_static", "dgamr_set_time", "dgamr_get_time", "dgamr_set_root_frames", "dgamr_last_error",
 ]
 
 
@@ -79,6 +79,7 @@ def lib():
         L.dgamr_step.argtypes = [vp, ctypes.c_double, vp, vp, vp, vp]
         L.dgamr_step_static.argtypes = [vp, ctypes.c_double, vp, vp, vp]
         L.dgamr_set_time.argtypes = [vp, ctypes.c_double]
+        L.dgamr_set_root_frames.argtypes = [vp, vp]
         L.dgamr_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.dgamr_run.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
         L.dgamr_conserved_totals.argtypes = [vp, vp, vp, vp, vp]
@@ -208,6 +209,13 @@ class Forest:
     @time.setter
     def time(self, t: float):
         _check(lib().dgamr_set_time(self.h, t))
+
+    def set_root_frames(self, codes):
+        """Rotation code of each root's local frame (dgamr_set_root_frames)."""
+        c = torch.as_tensor(list(codes), dtype=torch.int32).contiguous()
+        if c.numel() != self.desc.roots[0] * self.desc.roots[1] * self.desc.roots[2]:
+            raise ValueError("one frame code per root")
+        _check(lib().dgamr_set_root_frames(self.h, _ptr(c)))
 
     def keys(self):
         k = torch.zeros((self.n_leaves, 5), dtype=torch.int32)
