@@ -14,10 +14,14 @@ stage launches in it; an eager pass with events around every launch is
 reported beside it), the
 same run with FP32 residual arithmetic (FP64 state), the batched
 workload's batch wall time p50/p99 (512 forests, 20 steps per batch, one HIP
-graph per batch) against the same forests solved one by one, the oracle's
-rate on the host cores for a bounded sample of the same workload, and the L1 / L2
-density difference and mass drift of both GPU runs against the oracle after
-the same number of steps.
+graph per batch, the pools of the three degrees on parallel branches)
+against the same forests solved one by one, the stage kernels on forests far
+larger than the last-level cache (2-D 128 x 128 roots, 3-D 16^3 roots) against
+the HBM and arithmetic roofs, the oracle's rate on the host cores for a
+bounded sample of the same workload (all cores and one thread, plus samples
+of the 3-D blast and of a 64 x 64-root forest), and the L1 / L2 density
+difference and mass drift of both GPU runs against the oracle after the same
+number of steps.
 """
 from __future__ import annotations
 
@@ -72,16 +76,63 @@ def read_counter_traffic(workload_name: str):
     return float(m_bytes.group(1))
 
 
-def cpu_baseline(w, n_ref_steps: int, budget_s: float):
-    """The oracle (as it stands) on the host cores: whole SSP-RK3 steps of the
-    same workload from the same initial state.  Returns the rate over at least
-    budget_s seconds of steps, and the oracle state after n_ref_steps steps
-    (the reference for the accuracy of the GPU results)."""
-    import oracle as O
+def cpu_model() -> str:
+    """The host CPU's model name (lscpu), or the platform string."""
+    import platform
+    import subprocess
 
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.lower().startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except (OSError, subprocess.SubprocessError):
+        pass
+    return platform.processor() or platform.machine()
+
+
+def _oracle_forest(O, w):
     f = O.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
     for rule in w.initial_refinement:
         f.adapt(rule(w, f.keys()))
+    return f
+
+
+def _oracle_leg(O, w, ic, threads, budget_s, limiter=False, min_steps=1):
+    """Whole SSP-RK3 steps of the oracle on workload w from its initial
+    state at the given thread count, until budget_s has passed (at least
+    min_steps).  Regrids are not taken: the sample keeps the initial forest."""
+    O.set_threads(threads)
+    f = _oracle_forest(O, w)
+    u = f.project_ic(ic, w.ic_params)
+    dof = w.dofs(f.n_leaves)
+    start = time.perf_counter()
+    steps = 0
+    while True:
+        f.step(u, w.cfl, limiter=limiter)
+        steps += 1
+        el = time.perf_counter() - start
+        if steps >= min_steps and el > budget_s:
+            break
+    return {"value": dof * 3 * steps / el, "threads": O.threads(), "steps": steps, "seconds": el,
+            "leaves": f.n_leaves, "dofs": dof}
+
+
+def cpu_baseline(w, n_ref_steps: int, budget_s: float, legs: bool = True, full_legs: bool = False):
+    """The oracle (as it stands) on the host cores: whole SSP-RK3 steps of the
+    same workload from the same initial state, at every core the process may
+    use.  Returns the rate over at least budget_s seconds of steps, and the
+    oracle state after n_ref_steps steps (the reference for the accuracy of
+    the GPU results).  With legs: the same workload at one thread, and
+    bounded samples of the 3-D blast workload (all cores; one thread too
+    with full_legs) and of the 64 x 64-root uniform degree-2 forest (all
+    cores and one thread)."""
+    import oracle as O
+    from paper_2502_12620_amd import workloads as W
+
+    ncores = len(os.sched_getaffinity(0))
+    O.set_threads(ncores)
+    f = _oracle_forest(O, w)
     u = f.project_ic(O.IC_VORTEX, w.ic_params)
     t0 = f.totals(u)
     dof = w.dofs(f.n_leaves)
@@ -98,7 +149,25 @@ def cpu_baseline(w, n_ref_steps: int, budget_s: float):
             break
     out = {"value": dof * 3 * steps / el, "unit": "DOF-stage updates/s", "cores": O.threads(), "kind": "oracle",
            "sample": f"{steps} SSP-RK3 steps of {w.name} ({f.n_leaves} leaves, {dof} DOF) from the vortex "
-                     f"initial state, {el:.1f} s"}
+                     f"initial state, {el:.1f} s",
+           "cpu_model": cpu_model(), "cores_available": ncores}
+    if legs:
+        leg_budget = budget_s / 3.0
+        c3 = W.sedov_c3()
+        rs = W.roofline_2d(64, 2)
+        out["legs"] = {
+            f"{w.name}_1_thread": _oracle_leg(O, w, O.IC_VORTEX, 1, leg_budget),
+            f"{c3.name}_{ncores}_threads": _oracle_leg(O, c3, O.IC_SEDOV, ncores, leg_budget, limiter=True),
+            f"{rs.name}_{ncores}_threads": _oracle_leg(O, rs, O.IC_VORTEX, ncores, leg_budget),
+            f"{rs.name}_1_thread": _oracle_leg(O, rs, O.IC_VORTEX, 1, leg_budget),
+        }
+        if full_legs:
+            out["legs"][f"{c3.name}_1_thread"] = _oracle_leg(O, c3, O.IC_SEDOV, 1, leg_budget, limiter=True)
+        out["legs"]["note"] = ("DOF-stage updates/s of whole steps (at least one) from each workload's initial "
+                               "state; the blast with the limiter on, its initial 176-leaf forest, no regrid in "
+                               "the sample" + ("" if full_legs else "; its one-thread step (about 40 s) is timed "
+                                                                    "with --cpu-full only"))
+        O.set_threads(ncores)
     return out, ref[0], ref[1], t0
 
 
@@ -164,6 +233,32 @@ def time_path(G, w, precision, hang, steps, warmup):
             "eager_avg_launch_s": eager_ms / 1e3 / max(eager_launches, 1)}
 
 
+def roofline_sweep(steps: int) -> dict:
+    """The stage kernels on forests far larger than the last-level cache:
+    2-D 128 x 128 roots of 16 x 16 cells at degrees 1 and 2, 3-D 16^3 roots of
+    8^3 cells at degrees 1 and 2 (FP64), and the 3-D degree-2 forest with the
+    FP32 residual, its volume integral on the vector unit and on the matrix
+    cores.  Per case: the
+    average stage-kernel duration (HIP events around every stage launch of
+    `steps` eager steps), its algorithmic bytes, the fraction of the HBM
+    roof, and the estimated flop rate against the FP64 (or FP32) roof."""
+    from paper_2502_12620_amd import dgamr as G
+    from paper_2502_12620_amd import workloads as W
+    from paper_2502_12620_amd.measure import run_workload
+
+    cases = [(W.roofline_2d(128, 1), G.FP64, 0), (W.roofline_2d(128, 2), G.FP64, 0),
+             (W.roofline_3d(16, 1), G.FP64, 0), (W.roofline_3d(16, 2), G.FP64, 0),
+             (W.roofline_3d(16, 2), G.FP32, 0), (W.roofline_3d(16, 2), G.FP32, 1)]
+    out = {}
+    for w, prec, mf in cases:
+        r = run_workload(w, steps, warmup=2, precision=prec, mfma=mf)
+        key = w.name + ("_fp32" + ("_mfma" if mf else "") if prec == G.FP32 else "_fp64")
+        out[key] = {k: r[k] for k in ("leaves", "dofs", "state_MB", "stage_kernel_us", "algorithmic_bytes_per_dof",
+                                      "achieved_GBs", "hbm_frac", "est_TFLOPs", "fp64_frac", "fp32_frac",
+                                      "mfma_volume", "dof_stage_per_s") if k in r}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,9 +267,13 @@ def main():
     ap.add_argument("--hanging", choices=["paper", "conservative"], default="paper")
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-cpu-legs", action="store_true", help="time the oracle on the benchmark workload only")
+    ap.add_argument("--cpu-full", action="store_true", help="also time the oracle's 3-D blast step at one thread")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-residual run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 512-forest run")
     ap.add_argument("--batched-repeats", type=int, default=10)
+    ap.add_argument("--no-sweep", action="store_true", help="skip the large-forest stage-kernel roofline runs")
+    ap.add_argument("--sweep-steps", type=int, default=5)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (the whole forest lives on one "
@@ -193,7 +292,8 @@ def main():
     n = r64["f"].n_leaves
     ab = algorithmic_bytes_per_stage(w, n)
     dof = ab["dof"]
-    r32 = time_path(G, w, G.FP32_MFMA, hang, args.steps, args.warmup) if not args.no_fp32 else None
+    r32 = time_path(G, w, G.FP32, hang, args.steps, args.warmup) if not args.no_fp32 else None
+    sweep = roofline_sweep(args.sweep_steps) if not args.no_sweep else None
 
     value = dof * 3 * args.steps / r64["elapsed"]
     avg_s = r64["avg_launch_s"]
@@ -223,6 +323,8 @@ def main():
                      "algorithmic_bytes_per_launch": ab["bytes_per_launch"],
                      "algorithmic_bytes_per_dof": ab["bytes_per_dof"]},
     }
+    if sweep is not None:
+        out["roofline_sweep"] = sweep
     if r32 is not None:
         out["fp32_residual"] = {
             "value": dof * 3 * args.steps / r32["elapsed"], "unit": "DOF-stage updates/s",
@@ -237,9 +339,12 @@ def main():
         out["batched"] = {k: b[k] for k in ("workload", "forests", "leaves", "dofs", "steps_per_batch", "repeats",
                                             "batch_wall_s_p50", "batch_wall_s_p99", "dof_stage_per_s",
                                             "sequential_dof_stage_per_s", "speedup_vs_sequential",
-                                            "max_rel_diff_vs_plain_path")}
+                                            "max_rel_diff_vs_plain_path", "pools", "concurrent_branches",
+                                            "launches_per_step", "stage_launches_per_stage", "launch_note",
+                                            "per_pool", "batch_achieved_GBs", "batch_hbm_frac")}
     if not args.no_cpu:
-        cpu, u_ref, tot_ref, tot0 = cpu_baseline(w, args.warmup + args.steps, args.cpu_budget)
+        cpu, u_ref, tot_ref, tot0 = cpu_baseline(w, args.warmup + args.steps, args.cpu_budget,
+                                                 legs=not args.no_cpu_legs, full_legs=args.cpu_full)
         out["cpu_baseline"] = cpu
         out["accuracy_vs_oracle"] = {"steps": args.warmup + args.steps,
                                      "fp64": accuracy(r64["u"], r64["totals"], u_ref, tot_ref, tot0)}

@@ -27,7 +27,7 @@
  *               t indexes the N^(d-1) cells of the face, the lower of the
  *               remaining axes fastest
  *      residual R like U, FP64; FP32 when the forest precision is
- *               DGAMR_FP32_MFMA
+ *               DGAMR_FP32
  *      vars     (rho, rho u, rho v[, rho w], E), E = total energy per volume
  *      modes    total-degree Legendre products P_mx P_my [P_mz], |m| <= p,
  *               graded by |m|; inside one degree m_x descending, then m_y
@@ -60,7 +60,10 @@ enum {
 /* Non-periodic faces: outflow (Euler, Sec. 5.3.1) or Dirichlet data from the
  * exact solution (diffusion only, Sec. 5.2). */
 enum { DGAMR_BC_PERIODIC = 0, DGAMR_BC_OUTFLOW = 1, DGAMR_BC_DIRICHLET = 2 };
-enum { DGAMR_FP64 = 0, DGAMR_FP32_MFMA = 1 };
+/* Residual arithmetic: FP64, or FP32 (FP32 inputs and accumulation for the
+ * volume, face and lifting contractions; the state and the stage update stay
+ * FP64). */
+enum { DGAMR_FP64 = 0, DGAMR_FP32 = 1 };
 enum { DGAMR_HANG_PAPER = 0, DGAMR_HANG_CONSERVATIVE = 1 };
 enum { DGAMR_LIMITER_NONE = 0, DGAMR_LIMITER_POSITIVITY = 1 };
 enum { DGAMR_IC_VORTEX = 0, DGAMR_IC_SEDOV = 1, DGAMR_IC_UNIFORM = 2, DGAMR_IC_XWAVE = 3, DGAMR_IC_COSINE = 4,
@@ -83,7 +86,7 @@ typedef struct {
     int bc[3];        /* DGAMR_BC_* per axis */
     int max_level;    /* >= 1; roots are level 1 */
     double gamma;     /* ideal-gas ratio (Eq. 23) */
-    int precision;    /* DGAMR_FP64 or DGAMR_FP32_MFMA (residual contractions) */
+    int precision;    /* DGAMR_FP64 or DGAMR_FP32 (residual contractions) */
     int hanging;      /* DGAMR_HANG_PAPER (guard-cell fluxes, Sec. 3.5) or
                          DGAMR_HANG_CONSERVATIVE (coarse side lifts the fine-side flux) */
     int limiter;      /* DGAMR_LIMITER_* applied after each stage by dgamr_step */
@@ -156,7 +159,7 @@ int dgamr_fill_guardcells(dgamr_forest *f, const double *u, double *guard, hipSt
 
 /* Sec. 2, Eq. 3-5: R = M^-1 [ volume flux integral - surface integral of the
  * Rusanov flux ], neighbour traces from the block interior or the guard
- * buffer.  r is FP64, or FP32 for DGAMR_FP32_MFMA forests. */
+ * buffer.  r is FP64, or FP32 for DGAMR_FP32 forests. */
 int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, void *r,
                       hipStream_t stream);
 
@@ -270,8 +273,19 @@ int dgamr_check_state(dgamr_forest *f, const double *u, int64_t *bad, void *work
  *     up to this many cells (default 131072);
  *   DGAMR_TUNE_SLAB_ROWS: layers of the block's last axis per stage
  *     workgroup (0 automatic, else a divisor of n_cell within the kernel's
- *     thread budget; a launch that does not fit fails with DGAMR_EHIP). */
-enum { DGAMR_TUNE_STAGE_VARIANT = 0, DGAMR_TUNE_VAR_SPLIT_MAX_CELLS = 1, DGAMR_TUNE_SLAB_ROWS = 2 };
+ *     thread budget; a launch that does not fit fails with DGAMR_EHIP);
+ *   DGAMR_TUNE_MFMA: FP32 residual (DGAMR_FP32 forests): 1 contracts the
+ *     volume integral on the matrix cores (v_mfma_f32_16x16x4f32, FP32
+ *     accumulation: 16 cells x 16 quadrature points or modes per tile) at
+ *     degree 2 and 3 (3-D: degree 2) when a stage workgroup is whole waves
+ *     of cells; 0 (default) on the vector unit.  The traces, face fluxes and
+ *     lifting run on the vector unit either way.  With a few modes per cell
+ *     the tiles are mostly padding, and the matrix cores' FP32 rate is twice
+ *     the vector unit's (without packed FP32 instructions), so the vector
+ *     unit, which also skips the basis tables' structural zeros, is as fast
+ *     or faster on every measured forest. */
+enum { DGAMR_TUNE_STAGE_VARIANT = 0, DGAMR_TUNE_VAR_SPLIT_MAX_CELLS = 1, DGAMR_TUNE_SLAB_ROWS = 2,
+       DGAMR_TUNE_MFMA = 3 };
 int dgamr_set_tuning(dgamr_forest *f, int knob, long value);
 
 /* Measurement hook: while enabled, every launch of the fused stage kernel
@@ -350,14 +364,23 @@ int dgamr_pool_set_lanes(dgamr_pool *p, int32_t rows);
 int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t stream, int32_t *variant,
                         int32_t *rows, int32_t *grid, double *best_us);
 
-/* HIP graph of nsteps steps of several pools (in the given order per step),
- * captured once and replayed with dgamr_graph_launch.  A graph holds the
+/* HIP graph of nsteps steps of several pools, captured once and replayed
+ * with dgamr_graph_launch: one branch per pool holding its nsteps steps in
+ * order, the branches independent (pools share no memory), so the device
+ * runs the pools' launches concurrently.  A graph holds the
  * pools' work-list lengths at capture: launching it after an admit or
  * release on any of its pools fails with DGAMR_ESTATE. */
 int dgamr_pools_capture(dgamr_pool *const *pools, double *const *u_arenas, void *const *works, int32_t npools,
                         int32_t nsteps, dgamr_graph **out);
 int dgamr_graph_launch(dgamr_graph *g, hipStream_t stream);
 int dgamr_graph_destroy(dgamr_graph *g);
+
+/* Accuracy check of the device arithmetic the stage kernels use for the
+ * density reciprocal and the wave-speed square root (Newton-Raphson and
+ * Goldschmidt iterations from the hardware estimates): y[i] = 1/x[i]
+ * (fn 0) or sqrt(x[i]) (fn 1, 0 for x <= 0), n doubles in device memory,
+ * asynchronous on the stream. */
+int dgamr_math_probe(int fn, const double *x, double *y, int64_t n, hipStream_t stream);
 
 const char *dgamr_last_error(void);
 

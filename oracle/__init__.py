@@ -95,6 +95,7 @@ def lib():
         L.orc_step.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp]
         L.orc_errors.argtypes = [vp, dp, ctypes.c_int, dp, ctypes.c_double, dp, dp]
         L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -175,6 +176,10 @@ def rk_combine(stage: int, dt: float, un, us, r) -> np.ndarray:
 
 def threads() -> int:
     return lib().orc_threads()
+
+
+def set_threads(n: int):
+    lib().orc_set_threads(n)
 
 
 # ---------------------------------------------------------------- forest

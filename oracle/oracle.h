@@ -130,6 +130,8 @@ double orc_step(const orc_forest *f, double cfl, double dt_fixed,
 void orc_errors(const orc_forest *f, const double *u, int kind,
                 const double *params, double t, double *l1, double *l2);
 int orc_threads(void);
+/* OpenMP threads of the oracle's parallel loops (n > 0) */
+void orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -24,6 +24,15 @@ int orc_threads(void)
 #endif
 }
 
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* physical length of one global unit along an axis */
 static double unit_len(const orc_forest *f, int a)
 {

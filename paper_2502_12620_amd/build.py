@@ -15,7 +15,7 @@ HIP_SOURCES = ["dgamr_api.hip", "pool_api.hip", "static_api.hip"]
 CXX_SOURCES = ["forest.cpp"]
 # degree-templated kernels: one translation unit per (dim, degree, part);
 # the parts split the heavy kernels of one (dim, degree) pair (csrc/inst.hip)
-INSTANCES = [(d, p, part) for d in (2, 3) for p in (0, 1, 2, 3) for part in (0, 1, 2, 3)]
+INSTANCES = [(d, p, part) for d in (2, 3) for p in (0, 1, 2, 3) for part in (0, 1, 2, 3, 4)]
 
 HIPFLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-fconstexpr-steps=200000000",

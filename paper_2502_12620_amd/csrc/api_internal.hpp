@@ -80,6 +80,7 @@ struct dgamr_forest {
     int stage_variant = -1;  // 2-D stage kernel: -1 auto, 0 lane per (cell, var), 1 thread per cell
     long var_split_max_cells = 131072; // auto: lane per (cell, var) up to this many cells
     int slab_rows = 0;       // layers of the last axis per stage workgroup, 0 = automatic
+    int mfma = 0;            // FP32 residual: 1 = volume integral on the matrix cores where built
     std::vector<hipEvent_t> ev_free;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> ev_rec;
     long version = 0;        // bumped by every topology change

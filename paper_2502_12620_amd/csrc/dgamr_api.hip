@@ -115,6 +115,7 @@ dgk::StageShape stage_shape(const dgamr_forest *f)
     dgk::StageShape sh;
     sh.variant = stage_variant(f);
     sh.rows = f->slab_rows;
+    sh.mfma = f->mfma;
     return sh;
 }
 
@@ -123,7 +124,7 @@ bool fused_reads_traces(const dgamr_forest *f)
 {
     if (f->topo.rotated()) return false;
     return dgk::stage_reads_traces(f->topo.dim(), stage_shape(f), f->topo.desc().limiter == DGAMR_LIMITER_POSITIVITY,
-                                   f->topo.desc().precision == DGAMR_FP32_MFMA,
+                                   f->topo.desc().precision == DGAMR_FP32,
                                    f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE, f->topo.advection(),
                                    f->topo.desc().n_cell);
 }
@@ -138,7 +139,7 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     a.conservative = f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE;
     for (int k = 0; k < 3; ++k) a.vel[k] = f->topo.desc().velocity[k];
     if (a.nleaves == 0) return DGAMR_OK;
-    const bool fp32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
+    const bool fp32 = f->topo.desc().precision == DGAMR_FP32;
     const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
     const dgk::StageShape sh = stage_shape(f);
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
@@ -329,7 +330,7 @@ int dgamr_state_bytes(const dgamr_forest *f, size_t *u_bytes, size_t *guard_byte
     if (u_bytes) *u_bytes = state_elems(f) * sizeof(double);
     if (guard_bytes) *guard_bytes = guard_elems(f) * sizeof(double);
     if (residual_bytes)
-        *residual_bytes = state_elems(f) * (f->topo.desc().precision == DGAMR_FP32_MFMA ? sizeof(float) : sizeof(double));
+        *residual_bytes = state_elems(f) * (f->topo.desc().precision == DGAMR_FP32 ? sizeof(float) : sizeof(double));
     if (work_bytes) *work_bytes = work_elems(f) * sizeof(double);
     return DGAMR_OK;
 }
@@ -395,7 +396,7 @@ int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, voi
     dgk::StageArgs a{};
     a.us = u;
     a.guard = guard;
-    bool r32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
+    bool r32 = f->topo.desc().precision == DGAMR_FP32;
     a.out64 = r32 ? nullptr : static_cast<double *>(r);
     a.out32 = r32 ? static_cast<float *>(r) : nullptr;
     return launch_stage(f, a, dgk::GUARD_BUFFER, r32 ? dgk::OUT_RES32 : dgk::OUT_RES64, stream);
@@ -413,7 +414,7 @@ int dgamr_rk_stage(dgamr_forest *f, int stage, const double *dt_dev, const doubl
     if (stage > 0) CHECK(check_ptr(u_n, "u_n"));
     static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
     dgk::RkArgs a{u_n, u_s, r, u_next, dt_dev, A[stage], B[stage], long(state_elems(f)),
-                  f->topo.desc().precision == DGAMR_FP32_MFMA ? 1 : 0};
+                  f->topo.desc().precision == DGAMR_FP32 ? 1 : 0};
     if (a.n == 0) return DGAMR_OK;
     long blocks = (a.n + 255) / 256;
     if (blocks > 65536) blocks = 65536;
@@ -452,7 +453,7 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         // roots of different frames: the guard fill applies the rotation of
         // each guard cell (Sec. 3.5) into the guard buffer, then the residual
         // over guard coefficients, the stage update and the limiter, unfused
-        const bool r32 = f->topo.desc().precision == DGAMR_FP32_MFMA;
+        const bool r32 = f->topo.desc().precision == DGAMR_FP32;
         for (int s = 0; s < 3; ++s) {
             CHECK(launch_fill(f, us, w.guard, false, stream));
             dgk::StageArgs a{};
@@ -516,6 +517,18 @@ int dgamr_step(dgamr_forest *f, double cfl, double *u, void *work, double *dt_de
     if (f->topo.diffusion()) return step_diffusion(f, cfl, u, w, dt_dev, stream);
     if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
     return run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream);
+}
+
+int dgamr_math_probe(int fn, const double *x, double *y, int64_t n, hipStream_t stream)
+{
+    if (fn != 0 && fn != 1) return fail(DGAMR_EINVAL, "fn must be 0 (reciprocal) or 1 (square root)");
+    CHECK(check_ptr(x, "x"));
+    CHECK(check_ptr(y, "y"));
+    if (n < 0) return fail(DGAMR_EINVAL, "n must be >= 0");
+    if (n == 0) return DGAMR_OK;
+    hipLaunchKernelGGL(dgk::k_math_probe, dim3(unsigned((n + 255) / 256)), dim3(256), 0, stream, fn, x, y, long(n));
+    HIP_TRY(hipGetLastError());
+    return DGAMR_OK;
 }
 
 int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes)
@@ -796,6 +809,9 @@ int dgamr_set_tuning(dgamr_forest *f, int knob, long value)
     } else if (knob == DGAMR_TUNE_VAR_SPLIT_MAX_CELLS) {
         if (value < 0) return fail(DGAMR_EINVAL, "cell count must be >= 0");
         f->var_split_max_cells = value;
+    } else if (knob == DGAMR_TUNE_MFMA) {
+        if (value != 0 && value != 1) return fail(DGAMR_EINVAL, "mfma must be 0 or 1");
+        f->mfma = int(value);
     } else if (knob == DGAMR_TUNE_SLAB_ROWS) {
         const int N = f->topo.desc().n_cell;
         if (value < 0 || value > N || (value > 0 && N % value != 0))

@@ -81,7 +81,7 @@ int Forest::validate(const dgamr_forest_desc &d, std::string &err)
     }
     if (ntree >= (1L << 24)) { err = "too many roots"; return DGAMR_EUNSUPPORTED; }
     if (!(d.gamma > 1.0)) { err = "gamma must exceed 1"; return DGAMR_EINVAL; }
-    if (d.precision != DGAMR_FP64 && d.precision != DGAMR_FP32_MFMA) { err = "bad precision"; return DGAMR_EINVAL; }
+    if (d.precision != DGAMR_FP64 && d.precision != DGAMR_FP32) { err = "bad precision"; return DGAMR_EINVAL; }
     if (d.hanging != DGAMR_HANG_PAPER && d.hanging != DGAMR_HANG_CONSERVATIVE) { err = "bad hanging mode"; return DGAMR_EINVAL; }
     if (d.limiter != DGAMR_LIMITER_NONE && d.limiter != DGAMR_LIMITER_POSITIVITY) { err = "bad limiter"; return DGAMR_EINVAL; }
     if (d.equation != DGAMR_EQ_EULER && d.equation != DGAMR_EQ_ADVECTION && d.equation != DGAMR_EQ_DIFFUSION) {

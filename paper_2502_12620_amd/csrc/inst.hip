@@ -7,11 +7,14 @@
 //   part 1  the thread-per-cell Euler stage kernels in FP64
 //   part 2  the thread-per-cell Euler stage kernels with FP32 arithmetic
 //   part 3  the diffusion stage
+//   part 4  the thread-per-cell Euler stage kernels with FP32 arithmetic and
+//           the volume integral on the matrix cores (degree >= 2)
 #include "kernels.hpp"
 #include "kernels_2d.hpp"
 #include "kernels_3d.hpp"
 #include "kernels_aux.hpp"
 #include "kernels_ipdg.hpp"
+#include "kernels_mfma.hpp"
 #include "launch.hpp"
 
 #ifndef DG_D
@@ -91,7 +94,7 @@ int stage_rows_options(int N, int *rows, int max_options, bool fp32)
     return n;
 }
 
-template <int D, int P, typename T, int EQ = EQ_EULER>
+template <int D, int P, typename T, int EQ = EQ_EULER, bool MF = false>
 hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const StageShape &sh, hipStream_t s)
 {
     // slab of `rows` layers along the last axis within the thread budget
@@ -104,7 +107,14 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     if (!rows_ok<D, P, T>(a.N, rows)) return hipErrorInvalidValue;
     const int nslab = rows * layer;
     const long items = long(a.nleaves) * (a.N / rows);
-    const size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * nslab;
+    size_t lds = sizeof(double) * (D + 2) * face_chunk<D, P>() * nslab;
+    if constexpr (MF) {
+        // whole waves only; the volume phase's per-wave LDS regions alias the
+        // face exchange's buffer
+        if (nslab % 64 != 0) return hipErrorNotSupported;
+        const size_t mf = sizeof(float) * size_t(mfma_lds_floats<D, P>()) * (nslab / 64);
+        lds = mf > lds ? mf : lds;
+    }
     const bool persist = sh.grid > 0 && sh.grid < items;
     // the persistent shape applies to the fused Euler stage (pools); every
     // other launch takes one workgroup per item
@@ -128,18 +138,19 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     constexpr int GMRK = GUARD_INLINE; // the fused stage takes the far side inline
     if (gm == GMRK && om == OUT_RK) {
         if (persist && lim)
-            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T, EQ_EULER, true>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T, EQ_EULER, true, MF>), grid, block, lds, s, a, rows);
         else if (persist)
-            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T, EQ_EULER, true>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T, EQ_EULER, true, MF>), grid, block, lds, s, a, rows);
         else if (lim)
-            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, true, T, EQ_EULER, false, MF>), grid, block, lds, s, a, rows);
         else
-            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T>), grid, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T, EQ_EULER, false, MF>), grid, block, lds, s, a, rows);
         return hipGetLastError();
     }
     if constexpr (std::is_same<T, float>::value) {
         if (gm == GUARD_BUFFER && om == OUT_RES32) {
-            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false, T>), grid_all, block, lds, s, a, rows);
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES32, false, T, EQ_EULER, false, MF>), grid_all, block,
+                               lds, s, a, rows);
             return hipGetLastError();
         }
     } else if constexpr (D == 3) { // the 2-D FP64 residual runs one lane per (cell, variable)
@@ -157,6 +168,10 @@ extern template hipError_t launch_stage_cell<DG_D, DG_P, double, EQ_EULER>(const
                                                                           const StageShape &, hipStream_t);
 extern template hipError_t launch_stage_cell<DG_D, DG_P, float, EQ_EULER>(const StageArgs &, int, int, bool,
                                                                          const StageShape &, hipStream_t);
+#if DG_P >= 2 && !(DG_D == 3 && DG_P == 3)
+extern template hipError_t launch_stage_cell<DG_D, DG_P, float, EQ_EULER, true>(const StageArgs &, int, int, bool,
+                                                                               const StageShape &, hipStream_t);
+#endif
 
 template <int D, int P>
 hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32, const StageShape &sh, hipStream_t s,
@@ -164,7 +179,17 @@ hipError_t launch_stage(const StageArgs &a, int gm, int om, bool lim, bool fp32,
 {
     if (a.nleaves == 0) return hipSuccess;
     if (eq == EQ_ADVECTION) return fp32 ? hipErrorInvalidValue : launch_stage_cell<D, P, double, EQ_ADVECTION>(a, gm, om, lim, sh, s);
-    if (fp32) return launch_stage_cell<D, P, float>(a, gm, om, lim, sh, s);
+    if (fp32) {
+        if constexpr (mfma_volume<D, P>()) {
+            // the volume integral on the matrix cores where the slab is whole
+            // waves; otherwise (small blocks) on the vector unit
+            if (sh.mfma) {
+                const hipError_t e = launch_stage_cell<D, P, float, EQ_EULER, true>(a, gm, om, lim, sh, s);
+                if (e != hipErrorNotSupported) return e;
+            }
+        }
+        return launch_stage_cell<D, P, float>(a, gm, om, lim, sh, s);
+    }
     if constexpr (D == 2) {
         // one lane per (cell, variable) unless the caller asks for one
         // thread per cell (variant 1) or needs the limiter
@@ -244,9 +269,14 @@ template hipError_t launch_ipdg<DG_D, DG_P>(const IpdgArgs &, int, hipStream_t);
 #elif DG_PART == 1
 template hipError_t launch_stage_cell<DG_D, DG_P, double, EQ_EULER>(const StageArgs &, int, int, bool,
                                                                    const StageShape &, hipStream_t);
-#else
+#elif DG_PART == 2
 template hipError_t launch_stage_cell<DG_D, DG_P, float, EQ_EULER>(const StageArgs &, int, int, bool,
                                                                   const StageShape &, hipStream_t);
+#else
+#if DG_P >= 2 && !(DG_D == 3 && DG_P == 3)
+template hipError_t launch_stage_cell<DG_D, DG_P, float, EQ_EULER, true>(const StageArgs &, int, int, bool,
+                                                                        const StageShape &, hipStream_t);
+#endif
 #endif
 
 } // namespace dgk

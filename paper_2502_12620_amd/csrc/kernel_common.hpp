@@ -28,7 +28,7 @@ __device__ __forceinline__ int xcd_leaf(int bid, int n)
     return x * q + (x < r ? x : r) + slot;
 }
 
-__device__ __forceinline__ void cell_ijk(int cell, int N, int D, int *ijk)
+__host__ __device__ __forceinline__ void cell_ijk(int cell, int N, int D, int *ijk)
 {
     ijk[0] = cell % N;
     ijk[1] = (cell / N) % N;
@@ -51,14 +51,14 @@ __device__ __forceinline__ void leaf_point(const LeafGeo &G, const int *ijk, con
 
 // tangential index t of a cell on the face normal to axis a (the lower of
 // the remaining axes fastest)
-__device__ __forceinline__ int face_t(const int *ijk, int a, int N, int D)
+__host__ __device__ __forceinline__ int face_t(const int *ijk, int a, int N, int D)
 {
     if (D == 2) return a == 0 ? ijk[1] : ijk[0];
     return a == 0 ? ijk[1] + N * ijk[2] : (a == 1 ? ijk[0] + N * ijk[2] : ijk[0] + N * ijk[1]);
 }
 
 // cell index of (normal index n along a, tangential index t)
-__device__ __forceinline__ int face_cell(int a, int n, int t, int N, int D)
+__host__ __device__ __forceinline__ int face_cell(int a, int n, int t, int N, int D)
 {
     int t0 = t % N, t1 = t / N;
     int i, j, k;
@@ -70,9 +70,56 @@ __device__ __forceinline__ int face_cell(int a, int n, int t, int N, int D)
 
 // k-th neighbour of a face link, selected without indexing the struct (a
 // runtime index into a local copy would put it in scratch memory)
-__device__ __forceinline__ int link_nbr(const FaceLink &L, int k)
+__host__ __device__ __forceinline__ int link_nbr(const FaceLink &L, int k)
 {
     return k == 0 ? L.nbr[0] : (k == 1 ? L.nbr[1] : (k == 2 ? L.nbr[2] : L.nbr[3]));
+}
+
+// Where the guard cell at face point t of a block face comes from (Sec.
+// 3.5).  a: the face's axis; side: +1 for the face on the + side (the
+// neighbour lies along +a), -1 otherwise; t: the tangential index
+// (face_t).  The guard cell has this block's cell size and sits next to the
+// face on the neighbour's side.
+//
+// Neighbour of the same level (Eq. 15): its cell next to the face.
+__host__ __device__ __forceinline__ int same_cell(int a, int side, int t, int N, int D)
+{
+    return face_cell(a, side > 0 ? 0 : N - 1, t, N, D);
+}
+
+// Coarser neighbour (Eq. 16): the guard cell is child coarse_child() (bit b:
+// upper half along axis b) of the neighbour's cell coarse_cell(); off is the
+// link's position of this block on the coarse face, in block edges.
+__host__ __device__ __forceinline__ int coarse_cell(int a, int side, int t, const int *off, int N, int D)
+{
+    const int t0 = t % N, t1 = t / N;
+    const int c0 = (off[0] * N + t0) / 2, c1 = D == 3 ? (off[1] * N + t1) / 2 : 0;
+    return face_cell(a, side > 0 ? 0 : N - 1, c0 + N * c1, N, D);
+}
+__host__ __device__ __forceinline__ int coarse_child(int a, int side, int t, int N, int D)
+{
+    const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2; // tangential axes, lower first
+    const int t0 = t % N, t1 = t / N;
+    return ((side > 0 ? 0 : 1) << a) | ((t0 & 1) << ta) | (D == 3 ? ((t1 & 1) << tb) : 0);
+}
+
+// Finer neighbours (Eq. 17): the guard cell is covered by 2^d cells of one
+// of the 2^(d-1) finer blocks on the face: the link's neighbour slot
+// fine_block() (bit 0: upper half along the lower tangential axis, bit 1:
+// along the other), and in it the cell fine_cell() under child ch of the
+// guard cell (bit b of ch: upper half along axis b).
+__host__ __device__ __forceinline__ int fine_block(int t, int N, int D)
+{
+    const int t0 = t % N, t1 = t / N;
+    return (2 * t0) / N + (D == 3 ? 2 * ((2 * t1) / N) : 0);
+}
+__host__ __device__ __forceinline__ int fine_cell(int a, int side, int t, int ch, int N, int D)
+{
+    const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2;
+    const int t0 = t % N, t1 = t / N;
+    const int na = (ch >> a) & 1, n0 = (ch >> ta) & 1, n1 = D == 3 ? (ch >> tb) & 1 : 0;
+    const int f0 = (2 * t0) % N + n0, f1 = D == 3 ? (2 * t1) % N + n1 : 0;
+    return face_cell(a, side > 0 ? na : N - 2 + na, f0 + N * f1, N, D);
 }
 
 // 1/x for the state's normal positive densities: the hardware reciprocal

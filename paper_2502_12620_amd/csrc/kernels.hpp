@@ -88,18 +88,17 @@ __device__ __forceinline__ void mortar_lift(const StageArgs &g, const T (&K)[nva
     constexpr int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2; // tangential axes, lower first
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N;
     const long sv = long(NB) * ncell;
-    const int t0 = t % N, t1 = t / N;
-    const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
-    const int fleaf = link_nbr(L, h0 + 2 * h1);
-    const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
-    const int fn = side > 0 ? 0 : N - 1;
+    const int fleaf = link_nbr(L, fine_block(t, N, D));
+    // the fine cells touching the face: children with the half along A
+    // nearest to this block
+    const int near = (side > 0 ? 0 : 1) << A;
     const double sub = D == 2 ? 0.5 : 0.25; // fine face Jacobian / coarse face Jacobian
     // runs only on hanging faces: kept as loops (table values computed on
     // the fly) to keep the code small
 #pragma unroll 1
     for (int S = 0; S < (1 << (D - 1)); ++S) {
         const int s0 = S & 1, s1 = (S >> 1) & 1;
-        const int fcell = face_cell(A, fn, (ft0 + s0) + N * (ft1 + s1), N, D);
+        const int fcell = fine_cell(A, side, t, near | (s0 << TA) | (s1 << TBX), N, D);
         const double *fk = g.us + long(fleaf) * NV * sv + fcell;
 #pragma unroll 1
         for (int F = 0; F < NF; ++F) {
@@ -250,12 +249,11 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[NV][
         }
         return;
     }
-    const int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2;
     if (L.type == dgamr::LINK_BOUNDARY) {
 #pragma unroll
         for (int v = 0; v < NV; ++v) traces_of(K[v], v, side);
     } else if (L.type == dgamr::LINK_SAME) {
-        const int c = face_cell(A, side > 0 ? 0 : N - 1, t, N, D);
+        const int c = same_cell(A, side, t, N, D);
         const double *nk = g.us + long(L.nbr[0]) * NV * sv + c;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -265,10 +263,8 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[NV][
             traces_of(kv, v, -side);
         }
     } else if (L.type == dgamr::LINK_COARSE) {
-        const int t0 = t % N, t1 = t / N;
-        const int c0 = (L.off[0] * N + t0) / 2, c1 = D == 3 ? (L.off[1] * N + t1) / 2 : 0;
-        const int c = face_cell(A, side > 0 ? 0 : N - 1, c0 + N * c1, N, D);
-        const int child = ((side > 0 ? 0 : 1) << A) | ((t0 & 1) << TA) | (D == 3 ? ((t1 & 1) << TBX) : 0);
+        const int c = coarse_cell(A, side, t, L.off, N, D);
+        const int child = coarse_child(A, side, t, N, D);
         const double *ck = g.us + long(L.nbr[0]) * NV * sv + c;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -279,10 +275,7 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[NV][
             traces_of(gv, v, -side);
         }
     } else { // LINK_FINE
-        const int t0 = t % N, t1 = t / N;
-        const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
-        const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
-        const double *fk = g.us + long(link_nbr(L, h0 + 2 * h1)) * NV * sv;
+        const double *fk = g.us + long(link_nbr(L, fine_block(t, N, D))) * NV * sv;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             T gv[NB];
@@ -290,9 +283,7 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[NV][
             for (int m = 0; m < NB; ++m) gv[m] = T(0);
 #pragma unroll
             for (int ch = 0; ch < (1 << D); ++ch) {
-                const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
-                const int nidx = side > 0 ? bits[A] : N - 2 + bits[A];
-                const int fc = face_cell(A, nidx, (ft0 + bits[TA]) + N * (ft1 + (D == 3 ? bits[TBX] : 0)), N, D);
+                const int fc = fine_cell(A, side, t, ch, N, D);
                 T kv[NB];
 #pragma unroll
                 for (int n = 0; n < NB; ++n) kv[n] = T(fk[v * sv + n * ncell + fc]);
@@ -323,7 +314,6 @@ __device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Ta
     const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
     const long sv = long(NB) * ncell;
     const int face = 2 * A + (side > 0);
-    const int TA = A == 0 ? 1 : 0, TBX = A == 2 ? 1 : 2;
     if constexpr (GM == GUARD_BUFFER) {
         const double *gk = g.guard + ((long(leaf) * 2 * D + face) * NV * NB) * nfc + t;
 #pragma unroll
@@ -338,17 +328,15 @@ __device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Ta
 #pragma unroll
             for (int m = 0; m < NB; ++m) Kf[v][m] = (kTab<D, P>.e[m][A] % 2) ? -K[v][m] : K[v][m];
     } else if (L.type == dgamr::LINK_SAME) {
-        const int c = face_cell(A, side > 0 ? 0 : N - 1, t, N, D);
+        const int c = same_cell(A, side, t, N, D);
         const double *nk = g.us + long(L.nbr[0]) * NV * sv + c;
 #pragma unroll
         for (int v = 0; v < NV; ++v)
 #pragma unroll
             for (int m = 0; m < NB; ++m) Kf[v][m] = T(nk[v * sv + m * ncell]);
     } else if (L.type == dgamr::LINK_COARSE) {
-        const int t0 = t % N, t1 = t / N;
-        const int c0 = (L.off[0] * N + t0) / 2, c1 = D == 3 ? (L.off[1] * N + t1) / 2 : 0;
-        const int c = face_cell(A, side > 0 ? 0 : N - 1, c0 + N * c1, N, D);
-        const int child = ((side > 0 ? 0 : 1) << A) | ((t0 & 1) << TA) | (D == 3 ? ((t1 & 1) << TBX) : 0);
+        const int c = coarse_cell(A, side, t, L.off, N, D);
+        const int child = coarse_child(A, side, t, N, D);
         const double *ck = g.us + long(L.nbr[0]) * NV * sv + c;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -358,19 +346,14 @@ __device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Ta
             split_any<D, P, T>(child, kv, Kf[v]);
         }
     } else { // LINK_FINE
-        const int t0 = t % N, t1 = t / N;
-        const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
-        const int ft0 = (2 * t0) % N, ft1 = D == 3 ? (2 * t1) % N : 0;
-        const double *fk = g.us + long(link_nbr(L, h0 + 2 * h1)) * NV * sv;
+        const double *fk = g.us + long(link_nbr(L, fine_block(t, N, D))) * NV * sv;
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
 #pragma unroll
             for (int m = 0; m < NB; ++m) Kf[v][m] = T(0);
 #pragma unroll
             for (int ch = 0; ch < (1 << D); ++ch) {
-                const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
-                const int nidx = side > 0 ? bits[A] : N - 2 + bits[A];
-                const int fc = face_cell(A, nidx, (ft0 + bits[TA]) + N * (ft1 + (D == 3 ? bits[TBX] : 0)), N, D);
+                const int fc = fine_cell(A, side, t, ch, N, D);
                 T kv[NB];
 #pragma unroll
                 for (int n = 0; n < NB; ++n) kv[n] = T(fk[v * sv + n * ncell + fc]);
@@ -529,7 +512,15 @@ constexpr int stage_min_waves()
 // rate stay FP64).
 // One work item: slab `item` of the leaf list (all leaves, or the listed
 // ones), for the thread's cell.
-template <int D, int P, int GM, int OM, bool LIM, typename T, int EQ>
+template <int D, int P>
+__device__ __forceinline__ void volume_mfma(const float (&K)[D + 2][Tab<D, P>::NB], float (&R)[D + 2][Tab<D, P>::NB],
+                                            float *lds, const float *scale, float gm1);
+template <int D, int P>
+constexpr int mfma_lds_floats();
+
+// MF: the volume integral on the matrix cores (FP32 Euler, whole waves of
+// cells; kernels_mfma.hpp)
+template <int D, int P, int GM, int OM, bool LIM, typename T, int EQ, bool MF = false>
 __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int item, int total)
 {
     constexpr int NV = nvar<D, EQ>(), NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
@@ -603,7 +594,15 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
             }
         });
     };
-    if constexpr (unroll_points<D, P>()) {
+    if constexpr (MF) {
+        static_assert(std::is_same<T, float>::value && EQ == EQ_EULER, "matrix-core volume: FP32 Euler");
+        float *wave_lds = reinterpret_cast<float *>(lds_d) + (threadIdx.x >> 6) * mfma_lds_floats<D, P>();
+        // the per-wave regions alias the face exchange and the CFL fold of
+        // the previous work item of a persistent workgroup: every wave
+        // leaves them before any wave writes here
+        __syncthreads();
+        volume_mfma<D, P>(K, R, wave_lds, scale, gm1);
+    } else if constexpr (unroll_points<D, P>()) {
         static_for<0, NQ>(vol_point);
     } else {
 #pragma unroll 1
@@ -865,16 +864,17 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 // a stride of the grid size.  With a grid that is a
 // multiple of the XCD count every item a workgroup takes maps to the same
 // XCD's leaf range.
-template <int D, int P, int GM, int OM, bool LIM, typename T = double, int EQ = EQ_EULER, bool PERSIST = false>
+template <int D, int P, int GM, int OM, bool LIM, typename T = double, int EQ = EQ_EULER, bool PERSIST = false,
+          bool MF = false>
 __global__ __launch_bounds__((stage_threads<D, P, T>()), (stage_min_waves<D, P, T>())) void k_stage(StageArgs g,
                                                                                                      int rows)
 {
     const int total = g.nleaves * (g.N / rows);
     if constexpr (PERSIST) {
         for (int item = blockIdx.x; item < total; item += gridDim.x)
-            stage_item<D, P, GM, OM, LIM, T, EQ>(g, rows, item, total);
+            stage_item<D, P, GM, OM, LIM, T, EQ, MF>(g, rows, item, total);
     } else { // one item per workgroup: no loop to hold values across items
-        stage_item<D, P, GM, OM, LIM, T, EQ>(g, rows, blockIdx.x, total);
+        stage_item<D, P, GM, OM, LIM, T, EQ, MF>(g, rows, blockIdx.x, total);
     }
 }
 
@@ -895,7 +895,6 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
     const int a = face / 2, side = (face & 1) ? 1 : -1;
     const FaceLink L = g.links[lf];
     const long sv = long(NB) * ncell;
-    const int ta = a == 0 ? 1 : 0, tb = a == 2 ? 1 : 2;
     // one variable of the guard cell -> coefficients, or its values at the
     // face points (the guard cell touches the face with its -side side)
     auto emit = [&](int v, const double *gk) __attribute__((always_inline)) {
@@ -979,7 +978,7 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
         return;
     }
     if (L.type == dgamr::LINK_SAME) {
-        const int c = face_cell(a, side > 0 ? 0 : N - 1, t, N, D);
+        const int c = same_cell(a, side, t, N, D);
         const double *src = g.u + long(L.nbr[0]) * NV * sv + c;
         for (int v = 0; v < NV; ++v) {
             double gk[NB];
@@ -1004,11 +1003,8 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
     } else if (L.type == dgamr::LINK_COARSE) {
         // the guard cell (fine size) lies in one coarse cell; along a it is
         // the half nearest to this leaf
-        const int t0 = t % N, t1 = t / N;
-        const int c0 = (L.off[0] * N + t0) / 2, c1 = D == 3 ? (L.off[1] * N + t1) / 2 : 0;
-        const int b0 = t0 & 1, b1 = D == 3 ? (t1 & 1) : 0;
-        const int c = face_cell(a, side > 0 ? 0 : N - 1, c0 + N * c1, N, D);
-        const int child = ((side > 0 ? 0 : 1) << a) | (b0 << ta) | (D == 3 ? (b1 << tb) : 0);
+        const int c = coarse_cell(a, side, t, L.off, N, D);
+        const int child = coarse_child(a, side, t, N, D);
         const double *src = g.u + long(L.nbr[0]) * NV * sv + c;
         for (int v = 0; v < NV; ++v) {
             double ks[NB], gk[NB];
@@ -1018,21 +1014,14 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
             emit(v, gk);
         }
     } else { // LINK_FINE: 2^d fine cells, 2 along a and 2^(d-1) tangential
-        const int t0 = t % N, t1 = t / N;
-        const int h0 = (2 * t0) / N, h1 = D == 3 ? (2 * t1) / N : 0;
-        const int fleaf = link_nbr(L, h0 + 2 * h1);
-        const int f0 = (2 * t0) % N, f1 = D == 3 ? (2 * t1) % N : 0;
-        const double *base = g.u + long(fleaf) * NV * sv;
+        const double *base = g.u + long(link_nbr(L, fine_block(t, N, D))) * NV * sv;
         for (int v = 0; v < NV; ++v) {
             double acc[NB];
 #pragma unroll
             for (int m = 0; m < NB; ++m) acc[m] = 0.0;
 #pragma unroll
             for (int ch = 0; ch < (1 << D); ++ch) {
-                const int bits[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
-                const int na = bits[a], n0 = bits[ta], n1 = D == 3 ? bits[tb] : 0;
-                const int nidx = side > 0 ? na : N - 2 + na;
-                const int c = face_cell(a, nidx, (f0 + n0) + N * (f1 + n1), N, D);
+                const int c = fine_cell(a, side, t, ch, N, D);
                 double ks[NB];
 #pragma unroll
                 for (int n = 0; n < NB; ++n) ks[n] = base[v * sv + n * ncell + c];

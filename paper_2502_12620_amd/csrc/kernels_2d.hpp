@@ -93,28 +93,24 @@ __device__ __forceinline__ void far_coeffs_v(const StageArgs &g, const double *K
 #pragma unroll
         for (int m = 0; m < NB; ++m) kv[m] = (kTab<2, P>.e[m][A] % 2) ? -K[m] : K[m];
     } else if (L.type == dgamr::LINK_SAME) {
-        const int c = face_cell(A, side > 0 ? 0 : N - 1, t, N, 2);
+        const int c = same_cell(A, side, t, N, 2);
         const double *nk = g.us + long(L.nbr[0]) * NV * sv + v * sv + c;
 #pragma unroll
         for (int m = 0; m < NB; ++m) kv[m] = nk[m * ncell];
     } else if (L.type == dgamr::LINK_COARSE) {
-        const int c0 = (L.off[0] * N + t) / 2;
-        const int c = face_cell(A, side > 0 ? 0 : N - 1, c0, N, 2);
-        const int child = ((side > 0 ? 0 : 1) << A) | ((t & 1) << (1 - A));
+        const int c = coarse_cell(A, side, t, L.off, N, 2);
+        const int child = coarse_child(A, side, t, N, 2);
         const double *ck = g.us + long(L.nbr[0]) * NV * sv + v * sv + c;
         double kc[NB];
 #pragma unroll
         for (int m = 0; m < NB; ++m) kc[m] = ck[m * ncell];
         split_any<2, P>(child, kc, kv);
     } else { // LINK_FINE
-        const int h0 = (2 * t) / N, ft = (2 * t) % N;
-        const double *fk = g.us + long(link_nbr(L, h0)) * NV * sv + v * sv;
+        const double *fk = g.us + long(link_nbr(L, fine_block(t, N, 2))) * NV * sv + v * sv;
         double kf[4][NB];
 #pragma unroll
         for (int ch = 0; ch < 4; ++ch) {
-            const int ba = (ch >> A) & 1, bt = (ch >> (1 - A)) & 1;
-            const int nidx = side > 0 ? ba : N - 2 + ba;
-            const int fc = face_cell(A, nidx, ft + bt, N, 2);
+            const int fc = fine_cell(A, side, t, ch, N, 2);
 #pragma unroll
             for (int n = 0; n < NB; ++n) kf[ch][n] = fk[n * ncell + fc];
         }
@@ -144,12 +140,13 @@ __device__ __forceinline__ void mortar_lift_v(const StageArgs &g, const double *
     constexpr int TA = 1 - A;
     const int N = g.N, ncell = N * N;
     const long sv = long(NB) * ncell;
-    const int h0 = (2 * t) / N, ft = (2 * t) % N;
-    const int fn = side > 0 ? 0 : N - 1;
-    const double *fk0 = g.us + long(link_nbr(L, h0)) * NV * sv + v * sv;
+    const double *fk0 = g.us + long(link_nbr(L, fine_block(t, N, 2))) * NV * sv + v * sv;
+    // the fine cells touching the face: children with the half along A
+    // nearest to this block
+    const int near = (side > 0 ? 0 : 1) << A;
 #pragma unroll 1
     for (int S = 0; S < 2; ++S) {
-        const double *fk = fk0 + face_cell(A, fn, ft + S, N, 2);
+        const double *fk = fk0 + fine_cell(A, side, t, near | (S << TA), N, 2);
         double kf[NB];
 #pragma unroll
         for (int m = 0; m < NB; ++m) kf[m] = fk[m * ncell];

@@ -236,6 +236,15 @@ static __global__ __launch_bounds__(256) void k_rate_adv(const LeafGeo *geo, int
     leaf_max[i] = rate;
 }
 
+// y = recip(x) (fn 0) or sqrt_nn(x) (fn 1), the stage kernels' FP64
+// reciprocal and wave-speed square root, for their accuracy check
+static __global__ __launch_bounds__(256) void k_math_probe(int fn, const double *x, double *y, long n)
+{
+    const long i = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    y[i] = fn == 0 ? recip(x[i]) : sqrt_nn(x[i]);
+}
+
 // *p = v (one thread): a host-computed value put on the device in stream
 // order (the diffusion time step)
 static __global__ void k_set_value(double *p, double v) { *p = v; }

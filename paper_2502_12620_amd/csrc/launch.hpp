@@ -19,6 +19,7 @@ struct StageShape {
     int variant = 1;
     int rows = 0;
     int grid = 0;
+    int mfma = 0; // FP32 residual: 1 = the volume integral on the matrix cores where built
 };
 
 // 3-D lane-per-(cell, variable) kernel: 12 cells per wave, at most 12 waves

@@ -136,7 +136,7 @@ int pool_stage(dgamr_pool *p, int stage, const double *us, const double *un, dou
     a.links = p->d_links;
     a.conservative = p->cls.hanging == DGAMR_HANG_CONSERVATIVE;
     const bool lim = p->cls.limiter == DGAMR_LIMITER_POSITIVITY;
-    const bool fp32 = p->cls.precision == DGAMR_FP32_MFMA;
+    const bool fp32 = p->cls.precision == DGAMR_FP32;
     int gm = dgk::GUARD_INLINE;
     // the 3-D lane kernel reads guard traces of the listed leaves' faces
     if (dgk::stage_reads_traces(p->dim, sh, lim, fp32, a.conservative != 0, false, p->N)) {
@@ -388,7 +388,7 @@ int dgamr_pool_set_shape(dgamr_pool *p, int32_t rows, int32_t grid)
     if (rows > 0) {
         int opts[16];
         int n = dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
-            return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32_MFMA);
+            return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32);
         });
         if (std::find(opts, opts + n, rows) == opts + n) return fail(DGAMR_EINVAL, "rows not allowed for this class");
     }
@@ -419,7 +419,7 @@ int dgamr_pool_autotune(dgamr_pool *p, double *u_arena, void *work, hipStream_t 
         if (p->nwork == 0) return fail(DGAMR_ESTATE, "pool has no members to tune on");
         int opts[16];
         const int nopt = dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
-            return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32_MFMA);
+            return dgk::stage_rows_options<D, P>(p->N, opts, 16, p->cls.precision == DGAMR_FP32);
         });
         // FP64 without the limiter (3-D: and without mortar faces) also has
         // the lane-per-(cell, variable) kernel: 2-D slabs of r rows with
@@ -501,15 +501,32 @@ int dgamr_pools_capture(dgamr_pool *const *pools, double *const *u_arenas, void 
             CHECK(check_ptr(works[i], "work"));
             CHECK(wait_upload(pools[i]));
         }
+        // One branch per pool: the pools share no memory, so their steps
+        // run concurrently; each branch keeps its pool's steps in order.  The
+        // branches fork from and join into the capturing stream through
+        // events (no event nodes are left in the graph).
         hipStream_t s;
         HIP_TRY(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
-        auto *g = new dgamr_graph;
+        std::vector<hipStream_t> br(npools, nullptr);
+        std::vector<hipEvent_t> ev(npools + 1, nullptr);
         int rc = DGAMR_OK;
-        if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        for (int i = 0; i < npools && rc == DGAMR_OK; ++i)
+            if (hipStreamCreateWithFlags(&br[i], hipStreamNonBlocking) != hipSuccess) rc = fail(DGAMR_EHIP, "stream");
+        for (int i = 0; i <= npools && rc == DGAMR_OK; ++i)
+            if (hipEventCreateWithFlags(&ev[i], hipEventDisableTiming) != hipSuccess) rc = fail(DGAMR_EHIP, "event");
+        auto *g = new dgamr_graph;
+        if (rc != DGAMR_OK) {
+        } else if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
             rc = fail(DGAMR_EHIP, "hipStreamBeginCapture failed");
         } else {
-            for (int st = 0; st < nsteps && rc == DGAMR_OK; ++st)
-                for (int i = 0; i < npools && rc == DGAMR_OK; ++i) rc = pool_step(pools[i], u_arenas[i], works[i], s);
+            if (hipEventRecord(ev[npools], s) != hipSuccess) rc = fail(DGAMR_EHIP, "fork event");
+            for (int i = 0; i < npools && rc == DGAMR_OK; ++i) {
+                if (hipStreamWaitEvent(br[i], ev[npools], 0) != hipSuccess) rc = fail(DGAMR_EHIP, "fork wait");
+                for (int st = 0; st < nsteps && rc == DGAMR_OK; ++st)
+                    rc = pool_step(pools[i], u_arenas[i], works[i], br[i]);
+                if (rc == DGAMR_OK && hipEventRecord(ev[i], br[i]) != hipSuccess) rc = fail(DGAMR_EHIP, "join event");
+                if (rc == DGAMR_OK && hipStreamWaitEvent(s, ev[i], 0) != hipSuccess) rc = fail(DGAMR_EHIP, "join wait");
+            }
             hipGraph_t graph = nullptr;
             hipError_t e = hipStreamEndCapture(s, &graph);
             if (rc == DGAMR_OK && e != hipSuccess) rc = fail(DGAMR_EHIP, "hipStreamEndCapture failed");
@@ -518,6 +535,10 @@ int dgamr_pools_capture(dgamr_pool *const *pools, double *const *u_arenas, void 
                 rc = fail(DGAMR_EHIP, "hipGraphInstantiate failed");
         }
         (void)hipStreamDestroy(s);
+        for (auto b : br)
+            if (b) (void)hipStreamDestroy(b);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
         if (rc != DGAMR_OK) {
             dgamr_graph_destroy(g);
             return rc;

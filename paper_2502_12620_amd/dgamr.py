@@ -17,12 +17,12 @@ LIB_PATH = os.path.join(HERE, "libdgamr.so")
 
 OK, EINVAL, EUNSUPPORTED, EBALANCE, EHIP, ENONPHYSICAL, ESTATE, EFULL = 0, -1, -2, -3, -4, -5, -6, -7
 BC_PERIODIC, BC_OUTFLOW, BC_DIRICHLET = 0, 1, 2
-FP64, FP32_MFMA = 0, 1
+FP64, FP32 = 0, 1
 HANG_PAPER, HANG_CONSERVATIVE = 0, 1
 LIMITER_NONE, LIMITER_POSITIVITY = 0, 1
 IC_VORTEX, IC_SEDOV, IC_UNIFORM, IC_XWAVE, IC_COSINE, IC_EXP = 0, 1, 2, 3, 4, 5
 EQ_EULER, EQ_ADVECTION, EQ_DIFFUSION = 0, 1, 2
-TUNE_STAGE_VARIANT, TUNE_VAR_SPLIT_MAX_CELLS, TUNE_SLAB_ROWS = 0, 1, 2
+TUNE_STAGE_VARIANT, TUNE_VAR_SPLIT_MAX_CELLS, TUNE_SLAB_ROWS, TUNE_MFMA = 0, 1, 2, 3
 
 EXPORTS = [
     "dgamr_create_forest", "dgamr_destroy_forest", "dgamr_num_leaves", "dgamr_leaf_keys",
@@ -33,7 +33,8 @@ EXPORTS = [
     "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
     "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_set_lanes", "dgamr_pool_autotune",
     "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture",
-    "dgamr_step_static", "dgamr_set_time", "dgamr_get_time", "dgamr_set_root_frames", "dgamr_last_error",
+    "dgamr_step_static", "dgamr_set_time", "dgamr_get_time", "dgamr_set_root_frames", "dgamr_math_probe",
+    "dgamr_last_error",
 ]
 
 
@@ -80,6 +81,7 @@ def lib():
         L.dgamr_step_static.argtypes = [vp, ctypes.c_double, vp, vp, vp]
         L.dgamr_set_time.argtypes = [vp, ctypes.c_double]
         L.dgamr_set_root_frames.argtypes = [vp, vp]
+        L.dgamr_math_probe.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int64, vp]
         L.dgamr_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.dgamr_run.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
         L.dgamr_conserved_totals.argtypes = [vp, vp, vp, vp, vp]
@@ -149,6 +151,15 @@ def check_buffer(t, name, dtype, numel, at_least=False, device_type="cuda"):
 def _stream(stream=None):
     s = stream if stream is not None else torch.cuda.current_stream()
     return ctypes.c_void_p(s.cuda_stream)
+
+
+def math_probe(fn: int, x, stream=None):
+    """The stage kernels' FP64 reciprocal (fn 0) or square root (fn 1) of a
+    device tensor (dgamr_math_probe)."""
+    check_buffer(x, "x", torch.float64, x.numel())
+    y = torch.empty_like(x)
+    _check(lib().dgamr_math_probe(fn, _ptr(x), _ptr(y), x.numel(), _stream(stream)))
+    return y
 
 
 class Forest:
@@ -241,7 +252,7 @@ class Forest:
         return torch.zeros(self.guard_shape(), dtype=torch.float64, device=device)
 
     def new_residual(self, device="cuda"):
-        dt = torch.float32 if self.precision == FP32_MFMA else torch.float64
+        dt = torch.float32 if self.precision == FP32 else torch.float64
         return torch.zeros(self.state_shape(), dtype=dt, device=device)
 
     def new_work(self, device="cuda"):
@@ -258,7 +269,7 @@ class Forest:
         check_buffer(t, name, torch.float64, self.sizes()[1] // 8)
 
     def _chk_res(self, t, name="r"):
-        dt = torch.float32 if self.precision == FP32_MFMA else torch.float64
+        dt = torch.float32 if self.precision == FP32 else torch.float64
         check_buffer(t, name, dt, self._state_elems())
 
     def _chk_work(self, t, name="work"):

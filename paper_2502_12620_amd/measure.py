@@ -22,10 +22,11 @@
     python -m paper_2502_12620_amd.measure sedov
         the 3-D blast workload end to end (limiter, regrid every 10 steps)
         with FP64 and with FP32 residuals, and their L1 / L2 difference;
-    python -m paper_2502_12620_amd.measure serve [--requests 40]
+    python -m paper_2502_12620_amd.measure serve [--requests 40 --rates 200]
         the served workload: a Poisson stream of 2-D/3-D solves through the
-        continuous-batching request loop; latency p50/p99 and DOF-stage/s
-        against plain sequential solves of the same requests.
+        continuous-batching request loop, at one or more arrival rates;
+        latency p50/p99 and DOF-stage/s against plain sequential solves of
+        the same requests.
 
 Each prints JSON lines.
 """
@@ -44,6 +45,7 @@ from . import workloads as W
 
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
+FP32_PEAK_TFLOPS = 157.3  # dense FP32 on the matrix cores (and the vector unit's FMA rate)
 # estimated FP64 flops per DOF per stage (volume evaluate + flux + project,
 # face traces + Rusanov + lift), by (dim, degree)
 FLOP_PER_DOF = {(2, 1): 76, (2, 2): 120, (2, 3): 176, (3, 1): 207, (3, 2): 480, (3, 3): 945}
@@ -57,10 +59,11 @@ def stage_bytes_per_dof(dim: int, n_cell: int) -> float:
     return (16.0 + 24.0 + 24.0) / 3.0 + face
 
 
-def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1, rows=0):
+def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1, rows=0, mfma=0):
     f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, precision=precision)
     f.set_tuning(G.TUNE_STAGE_VARIANT, variant)
     f.set_tuning(G.TUNE_SLAB_ROWS, rows)
+    f.set_tuning(G.TUNE_MFMA, mfma)
     u = f.project_ic(G.IC_VORTEX, w.ic_params)
     work = f.new_work()
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -82,13 +85,25 @@ def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1, r
     bad = f.check_state(u, work)
     del f, u, work
     torch.cuda.empty_cache()
-    return {"workload": w.name, "precision": "fp32" if precision == G.FP32_MFMA else "fp64", "variant": variant,
-            "rows": rows,
+    fp32 = precision == G.FP32
+    out = {"workload": w.name, "precision": "fp32" if fp32 else "fp64", "variant": variant,
+            "rows": rows, "mfma_volume": bool(mfma and fp32 and mfma_volume(w.dim, w.degree)),
             "dim": w.dim, "degree": w.degree, "leaves": n, "dofs": dof,
             "state_MB": dof * 8 / 1e6, "steps": steps, "dof_stage_per_s": dof * 3 * steps / el,
             "stage_kernel_us": avg * 1e6, "algorithmic_bytes_per_dof": bpd, "achieved_GBs": gbs,
-            "hbm_frac": gbs / HBM_PEAK_GBS, "est_TFLOPs": flops, "fp64_frac": flops / FP64_PEAK_TFLOPS,
+            "hbm_frac": gbs / HBM_PEAK_GBS, "est_TFLOPs": flops,
             "nonphysical_cells": bad}
+    if fp32:
+        out["fp32_frac"] = flops / FP32_PEAK_TFLOPS
+    else:
+        out["fp64_frac"] = flops / FP64_PEAK_TFLOPS
+    return out
+
+
+def mfma_volume(dim: int, degree: int) -> bool:
+    """Whether the FP32 stage kernel's volume integral runs on the matrix
+    cores (degree >= 2, except 3-D degree 3)."""
+    return degree >= 2 and not (dim == 3 and degree == 3)
 
 
 def cmd_sweep(args):
@@ -98,11 +113,13 @@ def cmd_sweep(args):
     for w in cases:
         if args.only and w.name not in args.only.split(","):
             continue
-        prec = G.FP32_MFMA if args.precision == "fp32" else G.FP64
+        prec = G.FP32 if args.precision == "fp32" else G.FP64
         variants = [0, 1] if (args.variants and prec == G.FP64) else [-1]
         for var in variants:
             for rows in [int(r) for r in args.rows.split(",")]:
-                print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var, rows=rows)), flush=True)
+                for mf in [int(m) for m in args.mfma.split(",")]:
+                    print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var, rows=rows, mfma=mf)),
+                          flush=True)
 
 
 def cmd_copy(args):
@@ -150,7 +167,7 @@ def batched_run(forests: int = 512, repeats: int = 20, precision: str = "fp64") 
     replays, and the same forests solved one after another (dgamr_run)."""
     ws = W.batched_forests(forests, seed=2502)
     steps = ws[0].steps
-    prec = G.FP32_MFMA if precision == "fp32" else G.FP64
+    prec = G.FP32 if precision == "fp32" else G.FP64
     groups = {}
     for w in ws:
         groups.setdefault(w.degree, []).append((w, _forest(w, prec)))
@@ -200,7 +217,24 @@ def batched_run(forests: int = 512, repeats: int = 20, precision: str = "fp64") 
         torch.cuda.synchronize()
         times.append(e0.elapsed_time(e1) / 1e3)
     med = _pct(times, 50)
+    # per degree class: the pool's stage kernel timed alone by the autotuner,
+    # against the HBM roof; and the whole batch's stage traffic over the
+    # batch wall time (the pools run on parallel branches of the graph)
+    bpd = stage_bytes_per_dof(2, 16)
+    per_pool = {}
+    for p, (v, r, g, us) in zip(sorted(groups), tune):
+        pd = sum(w.dofs(f.n_leaves) for w, f in groups[p])
+        gbs = pd * bpd / (us * 1e-6) / 1e9
+        per_pool[f"p{p}"] = {"forests": len(groups[p]), "dofs": pd, "stage_us_alone": us, "achieved_GBs": gbs,
+                             "hbm_frac": gbs / HBM_PEAK_GBS}
+    batch_gbs = dofs * bpd * 3 * steps / med / 1e9
     out = {"workload": f"batched_{forests}_forests_2d", "forests": len(ws), "leaves": leaves, "dofs": dofs,
+           "pools": len(pools), "concurrent_branches": len(pools),
+           "launches_per_step": 5 * len(pools),
+           "stage_launches_per_stage": len(pools),
+           "launch_note": "per pool and step: two CFL reductions and three stage kernels; the pools' launches run "
+                          "on parallel branches of one HIP graph",
+           "per_pool": per_pool, "batch_achieved_GBs": batch_gbs, "batch_hbm_frac": batch_gbs / HBM_PEAK_GBS,
            "precision": precision, "steps_per_batch": steps, "repeats": repeats,
            "batch_wall_s_p50": med, "batch_wall_s_p99": _pct(times, 99), "batch_wall_s_min": min(times),
            "dof_stage_per_s": dofs * 3 * steps / med,
@@ -250,7 +284,7 @@ def cmd_sedov(args):
     w = W.sedov_c3()
     out = {"workload": w.name, "steps": w.steps}
     res = {}
-    for name, prec in (("fp64", G.FP64), ("fp32", G.FP32_MFMA)):
+    for name, prec in (("fp64", G.FP64), ("fp32", G.FP32)):
         f, u, r = _sedov_gpu(w, prec)
         res[name] = (f.keys(), u)
         out[name] = r
@@ -388,32 +422,11 @@ def _leaf_volumes(f, w):
     return out
 
 
-def cmd_serve(args):
-    from .serve import Request, Server
-
-    reqs = [Request(i, t, w) for i, (t, w) in enumerate(W.served_requests(args.requests, seed=12620, rate=args.rate))]
-    classes = sorted({(r.workload.dim, r.workload.degree, r.workload.n_cell) for r in reqs})
-    srv = Server(classes, hbm_budget=args.budget_gb * 1e9, max_members=256, tune=args.tune)
-    total_work = sum(r.workload.dofs(math.prod(r.workload.roots)) * 3 * r.workload.steps for r in reqs)
-    print(json.dumps({"progress": "serving", "requests": len(reqs), "dof_stage_total": total_work}), flush=True)
-
-    def progress(r):
-        n = sum(1 for q in reqs if q.done >= 0)
-        if n % 5 == 0 or n == len(reqs):
-            print(json.dumps({"progress": "served", "done": n, "t_s": round(r.done, 3)}), flush=True)
-
-    done = srv.run(reqs, on_done=progress)
-    lat = [r.done - r.arrival for r in done]
-    work = sum(r.dofs * 3 * r.workload.steps for r in done)
-    out = {"workload": f"served_{args.requests}_requests", "requests": len(done), "rate_per_s": args.rate,
-           "hbm_budget_GB": args.budget_gb, "makespan_s": srv.makespan, "ticks": srv.ticks,
-           "latency_s_p50": _pct(lat, 50), "latency_s_p99": _pct(lat, 99),
-           "dof_stage_per_s": work / srv.makespan}
-    # plain sequential FP64: each request solved alone in arrival order; its
-    # queue is replayed from the measured service times
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+def _sequential_service(reqs):
+    """Each request solved alone (plain FP64 path, dgamr_run): its service
+    time in seconds, by request id."""
     service = {}
-    for r in sorted(done, key=lambda r: r.arrival):
+    for r in reqs:
         w = r.workload
         f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
         u = f.project_ic(w.ic_kind, w.ic_params)
@@ -424,16 +437,57 @@ def cmd_serve(args):
         torch.cuda.synchronize()
         service[r.rid] = time.perf_counter() - t0
         del f, u, work_buf
-        if len(service) % 5 == 0:
+        if len(service) % 25 == 0:
             print(json.dumps({"progress": "sequential", "done": len(service)}), flush=True)
-    clock, seq_lat = 0.0, []
-    for r in sorted(done, key=lambda r: r.arrival):
-        start = max(clock, r.arrival)
-        clock = start + service[r.rid]
-        seq_lat.append(clock - r.arrival)
-    out.update({"sequential_makespan_s": clock, "sequential_latency_s_p50": _pct(seq_lat, 50),
-                "sequential_latency_s_p99": _pct(seq_lat, 99), "sequential_dof_stage_per_s": work / clock})
-    print(json.dumps(out), flush=True)
+    return service
+
+
+def cmd_serve(args):
+    """The served stream at each arrival rate: the same requests (seed
+    12620; the rate only scales the arrival times), served by the
+    continuous-batching loop, against the same requests solved one after
+    another in arrival order (queue replayed from measured service times)."""
+    from .serve import Request, Server
+
+    rates = [float(x) for x in args.rates.split(",")]
+    service = None
+    for rate in rates:
+        reqs = [Request(i, t, w) for i, (t, w) in enumerate(W.served_requests(args.requests, seed=12620, rate=rate))]
+        classes = sorted({(r.workload.dim, r.workload.degree, r.workload.n_cell) for r in reqs})
+        srv = Server(classes, hbm_budget=args.budget_gb * 1e9, max_members=256, tune=args.tune)
+        total_work = sum(r.workload.dofs(math.prod(r.workload.roots)) * 3 * r.workload.steps for r in reqs)
+        print(json.dumps({"progress": "serving", "rate_per_s": rate, "requests": len(reqs),
+                          "dof_stage_total": total_work}), flush=True)
+
+        def progress(r):
+            n = sum(1 for q in reqs if q.done >= 0)
+            if n % 25 == 0 or n == len(reqs):
+                print(json.dumps({"progress": "served", "done": n, "t_s": round(r.done, 3)}), flush=True)
+
+        done = srv.run(reqs, on_done=progress)
+        lat = [r.done - r.arrival for r in done]
+        wait = [r.admitted - r.arrival for r in done]
+        work = sum(r.dofs * 3 * r.workload.steps for r in done)
+        out = {"workload": f"served_{args.requests}_requests", "requests": len(done), "rate_per_s": rate,
+               "offered_dof_stage_per_s": work / max(r.arrival for r in done),
+               "hbm_budget_GB": args.budget_gb, "peak_pool_GB": srv.peak_bytes / 1e9, "makespan_s": srv.makespan,
+               "steps_enqueued": srv.steps_enqueued, "pool_rebuilds": srv.rebuilds, "members_moved": srv.moved,
+               "deferred_admissions": srv.full_waits,
+               "latency_s_p50": _pct(lat, 50), "latency_s_p99": _pct(lat, 99),
+               "queue_wait_s_p50": _pct(wait, 50), "queue_wait_s_p99": _pct(wait, 99),
+               "dof_stage_per_s": work / srv.makespan}
+        del srv
+        torch.cuda.empty_cache()
+        if service is None:
+            service = _sequential_service(sorted(done, key=lambda r: r.arrival))
+        clock, seq_lat = 0.0, []
+        for r in sorted(done, key=lambda r: r.arrival):
+            start = max(clock, r.arrival)
+            clock = start + service[r.rid]
+            seq_lat.append(clock - r.arrival)
+        out.update({"sequential_makespan_s": clock, "sequential_latency_s_p50": _pct(seq_lat, 50),
+                    "sequential_latency_s_p99": _pct(seq_lat, 99), "sequential_dof_stage_per_s": work / clock})
+        print(json.dumps(out), flush=True)
 
 
 def main(argv=None):
@@ -445,6 +499,7 @@ def main(argv=None):
     s.add_argument("--variants", action="store_true", help="FP64: time both stage kernels (lane per cell and variable; thread per cell)")
     s.add_argument("--precision", choices=["fp64", "fp32"], default="fp64", help="residual arithmetic")
     s.add_argument("--rows", default="0", help="comma-separated slab heights to time (0: the kernel's own)")
+    s.add_argument("--mfma", default="0", help="FP32: comma-separated 1 (volume integral on the matrix cores) / 0")
     c = sub.add_parser("copy")
     c.add_argument("--mb", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
@@ -461,7 +516,7 @@ def main(argv=None):
     df.add_argument("--degree", type=int, default=2)
     v = sub.add_parser("serve")
     v.add_argument("--requests", type=int, default=40)
-    v.add_argument("--rate", type=float, default=200.0)
+    v.add_argument("--rates", default="200", help="comma-separated arrival rates (requests/s)")
     v.add_argument("--budget-gb", type=float, default=96.0)
     v.add_argument("--tune", action="store_true")
     args = ap.parse_args(argv)

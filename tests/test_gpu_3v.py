@@ -64,7 +64,7 @@ def test_forests_it_does_not_take_run_the_thread_per_cell_kernel(case):
     G = _G()
     w = _forest(3, 1, 4, 2)
     orc, gpu = make_pair(w, hanging=1 if case == "conservative" else 0, limiter=case == "limiter",
-                         precision=G.FP32_MFMA if case == "fp32" else None)
+                         precision=G.FP32 if case == "fp32" else None)
     u = _physical_state(orc, w, seed=7)
     assert np.array_equal(_steps(gpu, u, 0, 2), _steps(gpu, u, 1, 2))
 

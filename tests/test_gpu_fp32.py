@@ -1,4 +1,4 @@
-"""GPU parity of the FP32 residual path (precision FP32_MFMA): residual
+"""GPU parity of the FP32 residual path (precision FP32): residual
 arithmetic in FP32, state, stage combination, limiter and totals in FP64.
 
 Tolerances.  The residual of one cell is a signed sum of at most
@@ -73,7 +73,7 @@ CASES32 = [(2, 1, 6, 3), (2, 2, 16, 2), (2, 3, 10, 3), (3, 1, 4, 3), (3, 2, 6, 2
 def test_fp32_residual_against_the_oracle(dim, p, N, levels, hanging):
     G = _G()
     w = _forest(dim, p, N, levels)
-    orc, gpu = make_pair(w, hanging=hanging, precision=G.FP32_MFMA)
+    orc, gpu = make_pair(w, hanging=hanging, precision=G.FP32)
     u = _physical_state(orc, w, seed=dim * 100 + p * 10 + N)
     r_ref = orc.residual(u)
     ud = _cuda(u)
@@ -96,7 +96,7 @@ def test_fp32_fused_step_matches_the_entry_points(dim, p):
     + rk_stage per stage; both FP32, so equal to FP32 rounding."""
     G = _G()
     w = _forest(dim, p, 6 if dim == 2 else 4, 3)
-    orc, gpu = make_pair(w, hanging=1, precision=G.FP32_MFMA)
+    orc, gpu = make_pair(w, hanging=1, precision=G.FP32)
     u = _physical_state(orc, w, seed=3)
     ud = _cuda(u)
     work = gpu.new_work()
@@ -127,7 +127,7 @@ def test_fp32_c2_full_size_200_steps(hanging):
     with FP32 residuals against the FP64 oracle."""
     G = _G()
     w = W.vortex_c2()
-    orc, gpu = make_pair(w, hanging=hanging, precision=G.FP32_MFMA)
+    orc, gpu = make_pair(w, hanging=hanging, precision=G.FP32)
     u = orc.project_ic(O.IC_VORTEX, w.ic_params)
     ud = _cuda(u)
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -149,7 +149,7 @@ def test_fp32_conservative_mode_conserves():
     cell-mean updates."""
     G = _G()
     w = small_c2(4)
-    orc, gpu = make_pair(w, hanging=1, precision=G.FP32_MFMA)
+    orc, gpu = make_pair(w, hanging=1, precision=G.FP32)
     u = orc.project_ic(O.IC_VORTEX, w.ic_params)
     ud = _cuda(u)
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -163,7 +163,7 @@ def test_fp32_conservative_mode_conserves():
 def test_fp32_free_stream_across_refinement():
     G = _G()
     w = _forest(2, 2, 8, 3)
-    orc, gpu = make_pair(w, hanging=0, precision=G.FP32_MFMA)
+    orc, gpu = make_pair(w, hanging=0, precision=G.FP32)
     ud = gpu.project_ic(W.IC_UNIFORM, [1.0, 0.3, -0.2, 0.0, 1.0])
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
     u0 = _host(ud)
@@ -177,7 +177,7 @@ def test_fp32_sedov_3d_with_limiter_and_regrid():
     G = _G()
     w = W.sedov_c3()
     w.n_cell = 4
-    orc, gpu = make_pair(w, limiter=True, precision=G.FP32_MFMA)
+    orc, gpu = make_pair(w, limiter=True, precision=G.FP32)
     u = orc.project_ic(O.IC_SEDOV, w.ic_params)
     ud = gpu.project_ic(W.IC_SEDOV, w.ic_params)
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")

@@ -40,7 +40,7 @@ def test_vortex_order_fp64_and_fp32(p, Ns, T):
     from paper_2502_12620_amd import dgamr as G
 
     e64 = [_gpu_error(p, N, T, G.FP64) for N in Ns]
-    e32 = [_gpu_error(p, N, T, G.FP32_MFMA) for N in Ns]
+    e32 = [_gpu_error(p, N, T, G.FP32) for N in Ns]
     for errs in (e64, e32):
         order = math.log2(errs[0] / errs[1])
         assert order >= p + 1 - 0.3, (errs, order)

@@ -187,6 +187,31 @@ def test_autotune_keeps_results():
     assert rel_diff(_host(tuned.u), _host(ref.u)).max() <= 1e-13
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fp32_pool_persistent_grid(dim):
+    """FP32 pools (degree 2: the volume integral on the matrix cores, whose
+    per-wave LDS regions alias the face exchange of the previous work item)
+    on a persistent grid of fewer workgroups than items: bitwise equal to one
+    workgroup per item."""
+    G = _G()
+    if dim == 2:
+        members = _members_2d(2)
+        args, shape = (2, 2, 8), (8, 3)
+    else:
+        members = [(_vortex("a3", 3, 2, 4, (2, 2, 1), 2.0, 3.0, (2.0, 2.0), levels=2, refine_tree0=True), 0.1),
+                   (_vortex("b3", 3, 2, 4, (1, 2, 2), 2.5, 2.0, (1.0, 2.0)), 0.15)]
+        args, shape = (3, 2, 4), (4, 3)
+    pools = []
+    for grid in (0, shape[1]):
+        pool = G.Pool(*args, capacity_leaves=64, max_members=8, precision=G.FP32)
+        _admit_all(pool, members, precision=G.FP32)
+        pool.set_shape(shape[0], grid)
+        for _ in range(3):
+            pool.step()
+        pools.append(pool)
+    assert torch.equal(pools[0].u, pools[1].u), "a persistent grid changes the FP32 result"
+
+
 @pytest.mark.parametrize("precision,limiter", [(0, False), (1, False), (0, True)])
 def test_pool_3d_members(precision, limiter):
     G = _G()

@@ -109,7 +109,7 @@ def test_rotated_fill_residual_and_steps(dim, p, N, seed):
 def test_rotated_fp32_residual():
     frames = _frames(3, 5)
     G = _G()
-    orc, gpu = _pair(3, 2, 4, frames, precision=G.FP32_MFMA)
+    orc, gpu = _pair(3, 2, 4, frames, precision=G.FP32)
     prm = [2.0, 1.5, 2.5, 0.5, 0.3, 4.0, 4.0]
     u = orc.project_ic(O.IC_VORTEX, prm)
     ud = _cuda(u)
