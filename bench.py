@@ -118,15 +118,14 @@ def _oracle_leg(O, w, ic, threads, budget_s, limiter=False, min_steps=1):
             "leaves": f.n_leaves, "dofs": dof}
 
 
-def cpu_baseline(w, n_ref_steps: int, budget_s: float, legs: bool = True, full_legs: bool = False):
+def cpu_baseline(w, n_ref_steps: int, budget_s: float, legs: bool = True):
     """The oracle (as it stands) on the host cores: whole SSP-RK3 steps of the
     same workload from the same initial state, at every core the process may
     use.  Returns the rate over at least budget_s seconds of steps, and the
     oracle state after n_ref_steps steps (the reference for the accuracy of
     the GPU results).  With legs: the same workload at one thread, and
-    bounded samples of the 3-D blast workload (all cores; one thread too
-    with full_legs) and of the 64 x 64-root uniform degree-2 forest (all
-    cores and one thread)."""
+    bounded samples of the 3-D blast workload and of the 64 x 64-root
+    uniform degree-2 forest, each at all cores and at one thread."""
     import oracle as O
     from paper_2502_12620_amd import workloads as W
 
@@ -158,15 +157,12 @@ def cpu_baseline(w, n_ref_steps: int, budget_s: float, legs: bool = True, full_l
         out["legs"] = {
             f"{w.name}_1_thread": _oracle_leg(O, w, O.IC_VORTEX, 1, leg_budget),
             f"{c3.name}_{ncores}_threads": _oracle_leg(O, c3, O.IC_SEDOV, ncores, leg_budget, limiter=True),
+            f"{c3.name}_1_thread": _oracle_leg(O, c3, O.IC_SEDOV, 1, leg_budget, limiter=True),
             f"{rs.name}_{ncores}_threads": _oracle_leg(O, rs, O.IC_VORTEX, ncores, leg_budget),
             f"{rs.name}_1_thread": _oracle_leg(O, rs, O.IC_VORTEX, 1, leg_budget),
+            "note": "DOF-stage updates/s of whole steps (at least one) from each workload's initial state; the "
+                    "blast with the limiter on, its initial 176-leaf forest, no regrid in the sample",
         }
-        if full_legs:
-            out["legs"][f"{c3.name}_1_thread"] = _oracle_leg(O, c3, O.IC_SEDOV, 1, leg_budget, limiter=True)
-        out["legs"]["note"] = ("DOF-stage updates/s of whole steps (at least one) from each workload's initial "
-                               "state; the blast with the limiter on, its initial 176-leaf forest, no regrid in "
-                               "the sample" + ("" if full_legs else "; its one-thread step (about 40 s) is timed "
-                                                                    "with --cpu-full only"))
         O.set_threads(ncores)
     return out, ref[0], ref[1], t0
 
@@ -268,7 +264,6 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=12.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-cpu-legs", action="store_true", help="time the oracle on the benchmark workload only")
-    ap.add_argument("--cpu-full", action="store_true", help="also time the oracle's 3-D blast step at one thread")
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-residual run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 512-forest run")
     ap.add_argument("--batched-repeats", type=int, default=10)
@@ -344,7 +339,7 @@ def main():
                                             "per_pool", "batch_achieved_GBs", "batch_hbm_frac")}
     if not args.no_cpu:
         cpu, u_ref, tot_ref, tot0 = cpu_baseline(w, args.warmup + args.steps, args.cpu_budget,
-                                                 legs=not args.no_cpu_legs, full_legs=args.cpu_full)
+                                                 legs=not args.no_cpu_legs)
         out["cpu_baseline"] = cpu
         out["accuracy_vs_oracle"] = {"steps": args.warmup + args.steps,
                                      "fp64": accuracy(r64["u"], r64["totals"], u_ref, tot_ref, tot0)}

@@ -485,13 +485,17 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
 template <int D, int P, typename T = double>
 constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
 // default slab (cells per workgroup) when the caller does not choose one:
-// the whole budget, except 3-D degree <= 1 and 2-D degree 2, where
+// the whole budget, except 3-D degree <= 1 and 2-D degree 1 and 2, where
 // 128-cell slabs let several workgroups share a compute unit and hide each
 // other's barriers (measured on 8^3 blocks at degree 1: 512-cell slabs
 // 671 us, 256: 582 us, 128: 564 us; 16^2 blocks at degree 2: 256-cell
-// slabs 184 us, 128: 171 us)
+// slabs 184 us, 128: 171 us; 128^2 roots of 16^2 cells at degree 1:
+// 256-cell slabs 330 us, 128: 311 us, 64: 323 us)
 template <int D, int P, typename T = double>
-constexpr int stage_default_cells() { return ((D == 3 && P <= 1) || (D == 2 && P == 2)) ? 128 : stage_threads<D, P, T>(); }
+constexpr int stage_default_cells()
+{
+    return ((D == 3 && P <= 1) || (D == 2 && (P == 1 || P == 2))) ? 128 : stage_threads<D, P, T>();
+}
 // waves per SIMD the register budget is cut for, chosen by measurement on
 // large forests: 2-D degree 1 in FP32 fits 128 registers (four waves);
 // 2-D degree 2 in FP64 spills 44 bytes per lane to run two waves per SIMD
