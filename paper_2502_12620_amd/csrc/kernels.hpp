@@ -146,7 +146,7 @@ __device__ __forceinline__ void mortar_lift(const StageArgs &g, const T (&K)[nva
 // Coefficients of the split of a coarse cell for child CH (Eq. 11-12):
 // g = S_CH k, one variable at a time.
 template <int D, int P, int CH, typename T>
-__device__ __forceinline__ void split_coeffs(const T *k, T *gk)
+__host__ __device__ __forceinline__ void split_coeffs(const T *k, T *gk)
 {
     constexpr int NB = Tab<D, P>::NB;
 #pragma unroll
@@ -162,7 +162,7 @@ __device__ __forceinline__ void split_coeffs(const T *k, T *gk)
 }
 
 template <int D, int P, typename T>
-__device__ __forceinline__ void split_any(int child, const T *k, T *gk)
+__host__ __device__ __forceinline__ void split_any(int child, const T *k, T *gk)
 {
     switch (child) {
     case 0: split_coeffs<D, P, 0, T>(k, gk); break;
@@ -307,7 +307,7 @@ __device__ __forceinline__ void far_traces(const StageArgs &g, const T (&K)[NV][
 //    coarser neighbour cell (Eq. 16), the combine of the 2^d finer cells
 //    (Eq. 17), or at an outflow boundary the mirror image K_m (-1)^{m_A}.
 template <int D, int P, int A, int GM, int NV, typename T>
-__device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Tab<D, P>::NB], int leaf, int side,
+__host__ __device__ __forceinline__ void far_poly(const StageArgs &g, const T (&K)[NV][Tab<D, P>::NB], int leaf, int side,
                                          int t, const FaceLink &L, T (&Kf)[NV][Tab<D, P>::NB])
 {
     constexpr int NB = Tab<D, P>::NB;
