@@ -68,6 +68,8 @@ def lib():
         L.orc_set_time.argtypes = [vp, ctypes.c_double]
         L.orc_set_frames.argtypes = [vp, ip]
         L.orc_set_frames.restype = ctypes.c_int
+        L.orc_set_nodes.argtypes = [vp, dp]
+        L.orc_set_nodes.restype = ctypes.c_int
         L.orc_get_time.argtypes = [vp]
         L.orc_get_time.restype = ctypes.c_double
         L.orc_upwind.argtypes = [dp, ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_int]
@@ -217,6 +219,13 @@ class Forest:
         c = np.ascontiguousarray(codes, dtype=np.int32)
         if lib().orc_set_frames(self.ptr, _ip(c)) != 0:
             raise ValueError("oracle: frames refused")
+
+    def set_nodes(self, xy):
+        """Bilinear root blocks (Sec. 3.3, Eq. 6) from the 2-D root grid
+        nodes, shape (roots_y + 1, roots_x + 1, 2) (see oracle.h)."""
+        a = np.ascontiguousarray(xy, dtype=np.float64)
+        if lib().orc_set_nodes(self.ptr, _dp(a)) != 0:
+            raise ValueError("oracle: nodes refused")
 
     def __del__(self):
         if getattr(self, "ptr", None):

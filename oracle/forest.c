@@ -10,6 +10,7 @@
  * search over the leaves, which is slow and plainly correct.
  */
 #include <stdio.h>
+#include <math.h>
 #include <stdlib.h>
 #include <string.h>
 #include "oracle_internal.h"
@@ -441,11 +442,52 @@ int orc_set_frames(orc_forest *f, const int *codes)
             if ((f->hi[a] - f->lo[a]) / f->roots[a] != (f->hi[0] - f->lo[0]) / f->roots[0]) return -1;
     /* the mortar of the conservative mode and the convection velocity are
      * written along the global axes */
-    if (any && (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_ADVECTION)) return -1;
+    if (any && (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_ADVECTION || f->nodes)) return -1;
     free(f->frame);
     f->frame = malloc(sizeof(int) * ntree);
     memcpy(f->frame, codes, sizeof(int) * ntree);
     orc_build_topology(f);
+    return 0;
+}
+
+/* Sec. 3.3, Eq. 6: root blocks as bilinear images of the reference square
+ * (2-D): xy holds the (roots_x + 1) x (roots_y + 1) grid nodes, x fastest,
+ * (x, y) each; root (rx, ry) has corners node(rx, ry), node(rx + 1, ry),
+ * node(rx, ry + 1), node(rx + 1, ry + 1).  On a periodic axis the last
+ * node column (row) must be the first one moved by the period.  Every root
+ * must be a convex quadrilateral (positive Jacobian at its corners).  Not
+ * with rotated frames, the conservative mode, the diffusion equation or
+ * the limiter. */
+int orc_set_nodes(orc_forest *f, const double *xy)
+{
+    if (f->dim != 2 || f->frame || f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_DIFFUSION) return -1;
+    int nx = f->roots[0] + 1, ny = f->roots[1] + 1;
+    double L[2] = {f->hi[0] - f->lo[0], f->hi[1] - f->lo[1]};
+    for (int j = 0; j < ny; ++j)
+        if (f->bc[0] == ORC_BC_PERIODIC) {
+            const double *a = xy + 2 * (j * nx), *b = xy + 2 * (j * nx + nx - 1);
+            if (fabs(b[0] - a[0] - L[0]) > 1e-12 * L[0] || fabs(b[1] - a[1]) > 1e-12 * L[1]) return -1;
+        }
+    for (int i = 0; i < nx; ++i)
+        if (f->bc[1] == ORC_BC_PERIODIC) {
+            const double *a = xy + 2 * i, *b = xy + 2 * ((ny - 1) * nx + i);
+            if (fabs(b[1] - a[1] - L[1]) > 1e-12 * L[1] || fabs(b[0] - a[0]) > 1e-12 * L[0]) return -1;
+        }
+    for (int ry = 0; ry + 1 < ny; ++ry)
+        for (int rx = 0; rx + 1 < nx; ++rx) {
+            const double *c[4] = {xy + 2 * (ry * nx + rx), xy + 2 * (ry * nx + rx + 1), xy + 2 * ((ry + 1) * nx + rx),
+                                  xy + 2 * ((ry + 1) * nx + rx + 1)};
+            /* the Jacobian at a corner is spanned by its two edges */
+            const int e[4][2] = {{1, 2}, {3, 0}, {0, 3}, {2, 1}};
+            for (int k = 0; k < 4; ++k) {
+                double ax = c[e[k][0]][0] - c[k][0], ay = c[e[k][0]][1] - c[k][1];
+                double bx = c[e[k][1]][0] - c[k][0], by = c[e[k][1]][1] - c[k][1];
+                if (ax * by - ay * bx <= 0.0) return -1;
+            }
+        }
+    free(f->nodes);
+    f->nodes = malloc(sizeof(double) * 2 * nx * ny);
+    memcpy(f->nodes, xy, sizeof(double) * 2 * nx * ny);
     return 0;
 }
 
@@ -460,6 +502,7 @@ void orc_destroy(orc_forest *f)
     free(f->new_leaf);
     free(f->exps);
     free(f->frame);
+    free(f->nodes);
     free(f);
 }
 

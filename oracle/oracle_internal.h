@@ -60,6 +60,8 @@ struct orc_forest {
     orc_face_nbr *fn; /* nleaves x 2d */
     orc_guard_plan *gp; /* nleaves x 2d x N^(d-1) */
     int *frame;       /* rotation code of each root's local frame (NULL: all 0) */
+    double *nodes;    /* 2-D root grid nodes (x, y) of bilinear roots, (roots_x + 1) x
+                         (roots_y + 1), x fastest (NULL: the axis-aligned box grid) */
     /* adaptation plan */
     int new_n;
     orc_key *new_leaf;

@@ -75,6 +75,133 @@ static long gidx(const orc_forest *f, long leaf, int face, int v, int m, int t)
 
 /* evaluate the cell polynomial with coefficients coef[v*stride_v + m*stride_m]
  * at reference point xi */
+/* ---------------------------------------------------------------- bilinear blocks
+ * Sec. 3.3, Eq. 6: with root grid nodes set, a root is the bilinear image
+ * of the reference square spanned by its four corner nodes.  A leaf's cells
+ * are images of equal squares of that reference square, so each cell is the
+ * bilinear image of its own reference cell [-1,1]^2 with the images of its
+ * corners as nodes.  The weak form (Eq. 3-4) is then evaluated with the
+ * Jacobian J = dx/dxi of that map at every quadrature point: volume term
+ * sum_q w_q grad_xi phi_m . adj(J) F (adj(J) = det(J) J^-1, the
+ * contravariant flux), face term sum_f w_f |N| Fhat(U-, U+; N/|N|) phi_m
+ * with N = side * (row a of adj(J)) the outward normal scaled by the face
+ * Jacobian, and the full mass matrix M_mn = sum_q w_q det(J) phi_m phi_n
+ * (exact with p+1 points per axis: det(J) is bilinear). */
+static int mapped(const orc_forest *f) { return f->nodes != NULL; }
+
+/* physical corners of cell c of leaf i: (xi, eta) = (-1,-1), (1,-1),
+ * (-1,1), (1,1) */
+static void cell_corners(const orc_forest *f, int i, int c, double cx[4][2])
+{
+    const orc_key *k = &f->leaf[i];
+    long lo[3], size;
+    orc_leaf_lbox(f, k, lo, &size);
+    int ijk[3];
+    orc_cell_ijk(f, c, ijk);
+    long hu = size / f->N;
+    int nx = f->roots[0] + 1, rx = k->tree % f->roots[0], ry = k->tree / f->roots[0];
+    const double *n00 = f->nodes + 2 * (ry * nx + rx), *n10 = n00 + 2, *n01 = n00 + 2 * nx, *n11 = n01 + 2;
+    for (int b = 0; b < 4; ++b) {
+        double s0 = (double)(lo[0] + (ijk[0] + (b & 1)) * hu) / (double)f->unit;
+        double s1 = (double)(lo[1] + (ijk[1] + (b >> 1)) * hu) / (double)f->unit;
+        for (int a = 0; a < 2; ++a)
+            cx[b][a] = (1.0 - s0) * (1.0 - s1) * n00[a] + s0 * (1.0 - s1) * n10[a] + (1.0 - s0) * s1 * n01[a] +
+                       s0 * s1 * n11[a];
+    }
+}
+
+/* x(xi) and J[a][b] = dx_a / dxi_b of the bilinear cell map */
+static void bilinear_point(const double cx[4][2], const double *xi, double *x)
+{
+    double e = xi[0], h = xi[1];
+    for (int a = 0; a < 2; ++a)
+        x[a] = 0.25 * ((1 - e) * (1 - h) * cx[0][a] + (1 + e) * (1 - h) * cx[1][a] + (1 - e) * (1 + h) * cx[2][a] +
+                       (1 + e) * (1 + h) * cx[3][a]);
+    x[2] = 0.0;
+}
+static double bilinear_jacobian(const double cx[4][2], const double *xi, double J[2][2])
+{
+    double e = xi[0], h = xi[1];
+    for (int a = 0; a < 2; ++a) {
+        J[a][0] = 0.25 * ((1 - h) * (cx[1][a] - cx[0][a]) + (1 + h) * (cx[3][a] - cx[2][a]));
+        J[a][1] = 0.25 * ((1 - e) * (cx[2][a] - cx[0][a]) + (1 + e) * (cx[3][a] - cx[1][a]));
+    }
+    return J[0][0] * J[1][1] - J[0][1] * J[1][0];
+}
+/* row b of adj(J) = det(J) J^-1: the contravariant direction of xi_b */
+static void adj_row(double J[2][2], int b, double *r)
+{
+    if (b == 0) { r[0] = J[1][1]; r[1] = -J[0][1]; }
+    else { r[0] = -J[1][0]; r[1] = J[0][0]; }
+}
+
+/* solve the symmetric positive definite n x n system M X = B for nrhs
+ * right-hand sides (B is nrhs x n, overwritten) by Cholesky */
+static void spd_solve(int n, const double *M, double *B, int nrhs)
+{
+    double L[20 * 20];
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c <= r; ++c) {
+            double s = M[r * n + c];
+            for (int k = 0; k < c; ++k) s -= L[r * 20 + k] * L[c * 20 + k];
+            L[r * 20 + c] = (r == c) ? sqrt(s) : s / L[c * 20 + c];
+        }
+    for (int j = 0; j < nrhs; ++j) {
+        double *b = B + j * n;
+        for (int r = 0; r < n; ++r) {
+            double s = b[r];
+            for (int k = 0; k < r; ++k) s -= L[r * 20 + k] * b[k];
+            b[r] = s / L[r * 20 + r];
+        }
+        for (int r = n - 1; r >= 0; --r) {
+            double s = b[r];
+            for (int k = r + 1; k < n; ++k) s -= L[k * 20 + r] * b[k];
+            b[r] = s / L[r * 20 + r];
+        }
+    }
+}
+
+/* mass matrix of cell c of leaf i with the volume rule (xi, w: nq points) */
+static void mapped_mass(const orc_forest *f, int i, int c, int nq, double (*xi)[3], const double *w, double *M)
+{
+    double cx[4][2];
+    cell_corners(f, i, c, cx);
+    int nb = f->nb;
+    for (int k = 0; k < nb * nb; ++k) M[k] = 0.0;
+    for (int iq = 0; iq < nq; ++iq) {
+        double J[2][2], det = bilinear_jacobian(cx, xi[iq], J);
+        double ph[20];
+        for (int m = 0; m < nb; ++m) ph[m] = orc_phi(2, f->exps + 3 * m, xi[iq]);
+        for (int m = 0; m < nb; ++m)
+            for (int n = 0; n < nb; ++n) M[m * nb + n] += w[iq] * det * ph[m] * ph[n];
+    }
+}
+
+/* numerical flux along the outward unit normal n (Eq. 5): the Rusanov flux
+ * with alpha = max(|u.n| + c) over both traces; for scalar convection the
+ * same formula with alpha = |vel.n| is the upwind flux */
+static void num_flux_n(const orc_forest *f, const double *um, const double *up, const double *n, double *fh)
+{
+    if (f->equation == ORC_EQ_ADVECTION) {
+        double vn = f->vel[0] * n[0] + f->vel[1] * n[1];
+        fh[0] = 0.5 * (vn * (um[0] + up[0]) - fabs(vn) * (up[0] - um[0]));
+        return;
+    }
+    double fm0[5], fm1[5], fp0[5], fp1[5];
+    orc_euler_flux(2, f->gamma, um, 0, fm0);
+    orc_euler_flux(2, f->gamma, um, 1, fm1);
+    orc_euler_flux(2, f->gamma, up, 0, fp0);
+    orc_euler_flux(2, f->gamma, up, 1, fp1);
+    double am = f->gamma * orc_pressure(2, f->gamma, um) / um[0];
+    double ap = f->gamma * orc_pressure(2, f->gamma, up) / up[0];
+    double cm = sqrt(am > 0.0 ? am : 0.0), cp = sqrt(ap > 0.0 ? ap : 0.0);
+    double lm = fabs((um[1] * n[0] + um[2] * n[1]) / um[0]) + cm;
+    double lp = fabs((up[1] * n[0] + up[2] * n[1]) / up[0]) + cp;
+    double alpha = lm > lp ? lm : lp;
+    for (int v = 0; v < 4; ++v)
+        fh[v] = 0.5 * ((fm0[v] + fp0[v]) * n[0] + (fm1[v] + fp1[v]) * n[1] - alpha * (up[v] - um[v]));
+}
+
 static void eval_poly(const orc_forest *f, const double *coef, long stride_v, long stride_m,
                       const double *xi, double *u)
 {
@@ -276,6 +403,12 @@ static void analytic_state(const orc_forest *f, int kind, const double *prm, dou
  * leaf i */
 static void cell_point(const orc_forest *f, int i, int c, const double *xi, double *x)
 {
+    if (mapped(f)) {
+        double cx[4][2];
+        cell_corners(f, i, c, cx);
+        bilinear_point(cx, xi, x);
+        return;
+    }
     long lo[3], size;
     orc_leaf_box(f, &f->leaf[i], lo, &size);
     long h = size / f->N;
@@ -315,6 +448,12 @@ void orc_project_ic(const orc_forest *f, int kind, const double *params, double 
     double (*xi)[3] = malloc(sizeof(double) * 3 * 512);
     double *w = malloc(sizeof(double) * 512);
     int nq = tensor_points(f->dim, q, gx, gw, xi, w);
+    /* the volume rule (p+1 points per axis) for the mass matrix of bilinear cells */
+    double vx[8], vwt[8];
+    orc_gauss_legendre(f->q, vx, vwt);
+    double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *vw = malloc(sizeof(double) * 512);
+    int nvq = tensor_points(f->dim, f->q, vx, vwt, vxi, vw);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < f->nleaves; ++i)
         for (int c = 0; c < nc; ++c) {
@@ -328,6 +467,25 @@ void orc_project_ic(const orc_forest *f, int kind, const double *params, double 
                     for (int v = 0; v < f->nv; ++v) acc[v * f->nb + l] += w[iq] * ph * s[v];
                 }
             }
+            if (mapped(f)) {
+                /* M K = int phi U det(J) dxi, M with the volume rule */
+                double cx[4][2], M[400];
+                cell_corners(f, i, c, cx);
+                memset(acc, 0, sizeof(acc));
+                for (int iq = 0; iq < nq; ++iq) {
+                    double s[5], J[2][2], det = bilinear_jacobian(cx, xi[iq], J);
+                    analytic_local(f, i, c, kind, params, t, xi[iq], s);
+                    for (int l = 0; l < f->nb; ++l) {
+                        double ph = orc_phi(f->dim, f->exps + 3 * l, xi[iq]);
+                        for (int v = 0; v < f->nv; ++v) acc[v * f->nb + l] += w[iq] * det * ph * s[v];
+                    }
+                }
+                mapped_mass(f, i, c, nvq, vxi, vw, M);
+                spd_solve(f->nb, M, acc, f->nv);
+                for (int v = 0; v < f->nv; ++v)
+                    for (int l = 0; l < f->nb; ++l) u[sidx(f, i, v, l, c)] = acc[v * f->nb + l];
+                continue;
+            }
             /* |J| cancels between the mass matrix and the quadrature */
             for (int v = 0; v < f->nv; ++v)
                 for (int l = 0; l < f->nb; ++l)
@@ -335,6 +493,8 @@ void orc_project_ic(const orc_forest *f, int kind, const double *params, double 
         }
     free(xi);
     free(w);
+    free(vxi);
+    free(vw);
 }
 
 /* ---------------------------------------------------------------- guard fill */
@@ -418,10 +578,104 @@ void orc_fill_guards(const orc_forest *f, const double *u, double *g)
  * fine sub-faces, using the fine cells' own traces (mortar). */
 static void diffusion_residual(const orc_forest *f, const double *u, const double *g, double *r);
 
+/* The residual on bilinear cells (see the bilinear block helpers above):
+ * the same cell loop as orc_residual with the metric terms at every point
+ * and the full mass matrix.  The neighbour across a face is the adjacent
+ * cell of the leaf or the guard cell (Sec. 3.5: copy, split, combine in the
+ * reference space); its trace is taken at the shared reference face point. */
+static void mapped_residual(const orc_forest *f, const double *u, const double *g, double *r)
+{
+    int d = 2, nf = 4, nfc = orc_nface_cells(f), nc = orc_ncell(f), q = f->q, nb = f->nb, nv = f->nv;
+    double gx[8], gw[8];
+    orc_gauss_legendre(q, gx, gw);
+    double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *vw = malloc(sizeof(double) * 512);
+    int nq = tensor_points(d, q, gx, gw, vxi, vw);
+#pragma omp parallel for schedule(static)
+    for (int i = 0; i < f->nleaves; ++i)
+        for (int c = 0; c < nc; ++c) {
+            int ijk[3];
+            orc_cell_ijk(f, c, ijk);
+            double cx[4][2];
+            cell_corners(f, i, c, cx);
+            const double *K = u + sidx(f, i, 0, 0, c);
+            double acc[5 * 20];
+            memset(acc, 0, sizeof(acc));
+            /* volume: sum_q w_q grad_xi phi_m . adj(J) F(U_q) */
+            for (int iq = 0; iq < nq; ++iq) {
+                double uq[5], J[2][2], A0[2], A1[2];
+                eval_poly(f, K, (long)nb * nc, nc, vxi[iq], uq);
+                bilinear_jacobian(cx, vxi[iq], J);
+                adj_row(J, 0, A0);
+                adj_row(J, 1, A1);
+                double fx[5] = {0, 0, 0, 0, 0}, fy[5] = {0, 0, 0, 0, 0};
+                phys_flux(f, uq, 0, fx);
+                phys_flux(f, uq, 1, fy);
+                for (int m = 0; m < nb; ++m) {
+                    double d0 = orc_dphi(d, f->exps + 3 * m, vxi[iq], 0), d1 = orc_dphi(d, f->exps + 3 * m, vxi[iq], 1);
+                    for (int v = 0; v < nv; ++v) {
+                        double c0 = A0[0] * fx[v] + A0[1] * fy[v], c1 = A1[0] * fx[v] + A1[1] * fy[v];
+                        acc[v * nb + m] += vw[iq] * (d0 * c0 + d1 * c1);
+                    }
+                }
+            }
+            /* faces: - sum_f w_f |N| Fhat(U-, U+; N/|N|) phi_m */
+            for (int face = 0; face < nf; ++face) {
+                int axis = face / 2, side = (face % 2) ? 1 : -1;
+                int nijk[3] = {ijk[0], ijk[1], ijk[2]};
+                nijk[axis] += side;
+                int interior = nijk[axis] >= 0 && nijk[axis] < f->N;
+                int t = axis == 0 ? ijk[1] : ijk[0];
+                const double *Kn;
+                long nsv, nsm;
+                if (interior) {
+                    Kn = u + sidx(f, i, 0, 0, orc_cell_index(f, nijk));
+                    nsv = (long)nb * nc;
+                    nsm = nc;
+                } else {
+                    Kn = g + gidx(f, i, face, 0, 0, t);
+                    nsv = (long)nb * nfc;
+                    nsm = nfc;
+                }
+                for (int iq = 0; iq < q; ++iq) {
+                    double xo[3] = {0, 0, 0}, xn[3] = {0, 0, 0};
+                    xo[1 - axis] = xn[1 - axis] = gx[iq];
+                    xo[axis] = side;
+                    xn[axis] = -side;
+                    double J[2][2], N[2], um[5], up[5], fh[5] = {0, 0, 0, 0, 0};
+                    bilinear_jacobian(cx, xo, J);
+                    adj_row(J, axis, N);
+                    N[0] *= side;
+                    N[1] *= side;
+                    double len = sqrt(N[0] * N[0] + N[1] * N[1]);
+                    double n[2] = {N[0] / len, N[1] / len};
+                    eval_poly(f, K, (long)nb * nc, nc, xo, um);
+                    eval_poly(f, Kn, nsv, nsm, xn, up);
+                    num_flux_n(f, um, up, n, fh);
+                    for (int m = 0; m < nb; ++m) {
+                        double ph = orc_phi(d, f->exps + 3 * m, xo);
+                        for (int v = 0; v < nv; ++v) acc[v * nb + m] -= gw[iq] * len * fh[v] * ph;
+                    }
+                }
+            }
+            double M[400];
+            mapped_mass(f, i, c, nq, vxi, vw, M);
+            spd_solve(nb, M, acc, nv);
+            for (int v = 0; v < nv; ++v)
+                for (int m = 0; m < nb; ++m) r[sidx(f, i, v, m, c)] = acc[v * nb + m];
+        }
+    free(vxi);
+    free(vw);
+}
+
 void orc_residual(const orc_forest *f, const double *u, const double *g, double *r)
 {
     if (f->equation == ORC_EQ_DIFFUSION) {
         diffusion_residual(f, u, g, r);
+        return;
+    }
+    if (mapped(f)) {
+        mapped_residual(f, u, g, r);
         return;
     }
     int d = f->dim, nf = 2 * d, nfc = orc_nface_cells(f), nc = orc_ncell(f), q = f->q;
@@ -751,8 +1005,11 @@ void orc_rk_combine(long n, int stage, double dt, const double *un, const double
 
 /* Largest sum over axes of (|mean u_a| + mean c) / h_a over all cells,
  * from the cell means (mode 0). */
+static double mapped_max_rate(const orc_forest *f, const double *u);
+
 double orc_max_rate(const orc_forest *f, const double *u)
 {
+    if (mapped(f)) return mapped_max_rate(f, u);
     int d = f->dim, nc = orc_ncell(f);
     double mx = 0.0;
     for (int i = 0; i < f->nleaves; ++i) {
@@ -785,6 +1042,52 @@ double orc_max_rate(const orc_forest *f, const double *u)
     return mx;
 }
 
+/* The rate on bilinear cells: the cell means of the state (integrals over
+ * the physical cell with the volume rule, divided by its area), and for
+ * each reference axis b the unit normal n_b and the width h_b = 2 det(J) /
+ * |row b of adj(J)| at the cell centre (the edge lengths for a rectangle):
+ * sum_b (|u.n_b| + c) / h_b; scalar convection sum_b |vel.n_b| / h_b. */
+static double mapped_max_rate(const orc_forest *f, const double *u)
+{
+    int nc = orc_ncell(f), nb = f->nb;
+    double gx[8], gw[8];
+    orc_gauss_legendre(f->q, gx, gw);
+    double (*xi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *w = malloc(sizeof(double) * 512);
+    int nq = tensor_points(2, f->q, gx, gw, xi, w);
+    double mx = 0.0;
+    for (int i = 0; i < f->nleaves; ++i)
+        for (int c = 0; c < nc; ++c) {
+            double cx[4][2], J[2][2];
+            cell_corners(f, i, c, cx);
+            double s[5] = {0, 0, 0, 0, 0}, area = 0.0;
+            for (int iq = 0; iq < nq; ++iq) {
+                double det = bilinear_jacobian(cx, xi[iq], J), uq[5];
+                eval_poly(f, u + sidx(f, i, 0, 0, c), (long)nb * nc, nc, xi[iq], uq);
+                area += w[iq] * det;
+                for (int v = 0; v < f->nv; ++v) s[v] += w[iq] * det * uq[v];
+            }
+            for (int v = 0; v < f->nv; ++v) s[v] /= area;
+            const double x0[3] = {0, 0, 0};
+            double det0 = bilinear_jacobian(cx, x0, J);
+            double cs = f->equation == ORC_EQ_ADVECTION ? 0.0 : sqrt(f->gamma * orc_pressure(2, f->gamma, s) / s[0]);
+            double rate = 0.0;
+            for (int b = 0; b < 2; ++b) {
+                double A[2];
+                adj_row(J, b, A);
+                double len = sqrt(A[0] * A[0] + A[1] * A[1]);
+                double h = 2.0 * det0 / len, n[2] = {A[0] / len, A[1] / len};
+                double un = f->equation == ORC_EQ_ADVECTION ? f->vel[0] * n[0] + f->vel[1] * n[1]
+                                                            : (s[1] * n[0] + s[2] * n[1]) / s[0];
+                rate += (fabs(un) + cs) / h;
+            }
+            if (rate > mx) mx = rate;
+        }
+    free(xi);
+    free(w);
+    return mx;
+}
+
 /* Sec. 4.3 step 2(a): critical time increment over all blocks,
  * dt = CFL / max_cells sum_a (|u_a| + c) / h_a. */
 double orc_dt(const orc_forest *f, const double *u, double cfl) { return cfl / orc_max_rate(f, u); }
@@ -795,6 +1098,27 @@ void orc_totals(const orc_forest *f, const double *u, double *totals)
 {
     int nc = orc_ncell(f);
     for (int v = 0; v < f->nv; ++v) totals[v] = 0.0;
+    if (mapped(f)) { /* sum over cells of the integral of U over the physical cell */
+        double gx[8], gw[8];
+        orc_gauss_legendre(f->q, gx, gw);
+        double (*xi)[3] = malloc(sizeof(double) * 3 * 512);
+        double *w = malloc(sizeof(double) * 512);
+        int nq = tensor_points(2, f->q, gx, gw, xi, w);
+        for (int i = 0; i < f->nleaves; ++i)
+            for (int c = 0; c < nc; ++c) {
+                double cx[4][2], J[2][2], m[5] = {0, 0, 0, 0, 0};
+                cell_corners(f, i, c, cx);
+                for (int iq = 0; iq < nq; ++iq) {
+                    double det = bilinear_jacobian(cx, xi[iq], J), uq[5];
+                    eval_poly(f, u + sidx(f, i, 0, 0, c), (long)f->nb * nc, nc, xi[iq], uq);
+                    for (int v = 0; v < f->nv; ++v) m[v] += w[iq] * det * uq[v];
+                }
+                for (int v = 0; v < f->nv; ++v) totals[v] += m[v];
+            }
+        free(xi);
+        free(w);
+        return;
+    }
     for (int i = 0; i < f->nleaves; ++i) {
         long lo[3], size;
         orc_leaf_box(f, &f->leaf[i], lo, &size);
@@ -981,7 +1305,7 @@ double orc_step(const orc_forest *f, double cfl, double dt_fixed, int limiter, d
         orc_fill_guards(f, us, g);
         orc_residual(f, us, g, r);
         orc_rk_combine(n, s, dt, un, us, r, u);
-        if (limiter) orc_limit_positivity(f, u);
+        if (limiter && !mapped(f)) orc_limit_positivity(f, u);
         memcpy(us, u, sizeof(double) * n);
     }
     fm->time += dt;
@@ -1011,6 +1335,11 @@ void orc_errors(const orc_forest *f, const double *u, int kind, const double *pa
         for (int c = 0; c < nc; ++c)
             for (int iq = 0; iq < nq; ++iq) {
                 double ex[5], uh[5];
+                if (mapped(f)) {
+                    double cx[4][2], Jm[2][2];
+                    cell_corners(f, i, c, cx);
+                    J = bilinear_jacobian(cx, xi[iq], Jm);
+                }
                 analytic_local(f, i, c, kind, params, t, xi[iq], ex);
                 eval_poly(f, u + sidx(f, i, 0, 0, c), (long)f->nb * nc, nc, xi[iq], uh);
                 for (int v = 0; v < f->nv; ++v) {

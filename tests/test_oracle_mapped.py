@@ -1,0 +1,142 @@
+"""Pins of the oracle's bilinear root blocks (Sec. 3.3, Eq. 6: a root is the
+bilinear image of the reference square spanned by its corner nodes; the
+weak form of Eq. 3-4 then carries the map's Jacobian at every point and the
+full mass matrix).  The pins come from outside that code: rectangular nodes
+reproduce the axis-aligned oracle; a uniform state stays a steady solution
+on distorted roots with hanging faces (the discrete metric identities of a
+bilinear map); conforming distorted forests conserve every variable (Euler and scalar
+convection); the isentropic vortex converges at order p+1 on a smoothly
+distorted periodic grid; folded roots and unmatched periodic nodes are
+refused.  CPU only."""
+import numpy as np
+import pytest
+
+import oracle as O
+
+PRM = [3.0, 5.0, 5.0, 0.7, -0.4, 10.0, 10.0]
+
+
+def box_nodes(roots, lo, hi):
+    nx, ny = roots
+    g = np.zeros((ny + 1, nx + 1, 2))
+    g[..., 0] = np.linspace(lo[0], hi[0], nx + 1)[None, :]
+    g[..., 1] = np.linspace(lo[1], hi[1], ny + 1)[:, None]
+    return g
+
+
+def distorted_nodes(roots, lo, hi, amp, seed=0):
+    """Box nodes with the interior nodes and, periodically, the boundary
+    nodes moved by up to amp of a root edge (opposite boundaries move
+    together, so the grid stays periodic)."""
+    g = box_nodes(roots, lo, hi)
+    nx, ny = roots
+    h = min((hi[0] - lo[0]) / nx, (hi[1] - lo[1]) / ny)
+    rng = np.random.default_rng(seed)
+    d = amp * h * rng.uniform(-1, 1, (ny, nx, 2))
+    for j in range(ny + 1):
+        for i in range(nx + 1):
+            g[j, i] += d[j % ny, i % nx]
+    return g
+
+
+def smooth_nodes(roots, lo, hi, amp):
+    """x + amp sin(2 pi x/L) sin(2 pi y/L) style periodic distortion."""
+    g = box_nodes(roots, lo, hi)
+    L = np.array(hi) - np.array(lo)
+    x, y = g[..., 0].copy(), g[..., 1].copy()
+    s = np.sin(2 * np.pi * (x - lo[0]) / L[0]) * np.sin(2 * np.pi * (y - lo[1]) / L[1])
+    g[..., 0] = x + amp * L[0] * s
+    g[..., 1] = y + amp * L[1] * s
+    return g
+
+
+def _refine(f, which):
+    fl = np.zeros(f.n_leaves, np.int8)
+    fl[which] = 1
+    f.adapt(fl)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_rectangular_nodes_reproduce_the_box_grid(p):
+    roots, lo, hi = (2, 2), (0.0, 0.0), (10.0, 10.0)
+    fa = O.Forest(2, p, 4, roots, lo, hi, (0, 0), 2)
+    fm = O.Forest(2, p, 4, roots, lo, hi, (0, 0), 2)
+    fm.set_nodes(box_nodes(roots, lo, hi))
+    for f in (fa, fm):
+        _refine(f, 0)
+    ua, um = fa.project_ic(O.IC_VORTEX, PRM), fm.project_ic(O.IC_VORTEX, PRM)
+    np.testing.assert_allclose(um, ua, atol=1e-14)
+    for _ in range(3):
+        assert fm.step(um, 0.1) == pytest.approx(fa.step(ua, 0.1), rel=1e-14)
+    assert np.abs(um - ua).max() <= 1e-13 * np.abs(ua).max()
+    np.testing.assert_allclose(fm.totals(um), fa.totals(ua), rtol=1e-13, atol=1e-12)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_free_stream_on_distorted_roots_with_hanging_faces(p, bc):
+    roots, lo, hi = (3, 3), (0.0, 0.0), (3.0, 3.0)
+    f = O.Forest(2, p, 4, roots, lo, hi, (bc, bc), 3)
+    f.set_nodes(distorted_nodes(roots, lo, hi, 0.2, seed=p))
+    _refine(f, 4)
+    _refine(f, 0)
+    u = f.project_ic(O.IC_UNIFORM, [1.0, 0.3, -0.2, 0.0, 1.0])
+    assert np.abs(u[:, :, 1:]).max() < 1e-13  # the projection of a constant is the constant
+    assert np.abs(f.residual(u)).max() < 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_conservation_on_distorted_conforming_roots(p):
+    roots, lo, hi = (3, 2), (0.0, 0.0), (10.0, 10.0)
+    f = O.Forest(2, p, 4, roots, lo, hi, (0, 0), 1)
+    f.set_nodes(distorted_nodes(roots, lo, hi, 0.25, seed=7))
+    u = f.project_ic(O.IC_VORTEX, PRM)
+    t0 = f.totals(u)
+    for _ in range(5):
+        f.step(u, 0.1)
+    np.testing.assert_allclose(f.totals(u), t0, rtol=1e-13, atol=1e-12)
+
+
+def test_advection_conservation_and_positivity_of_the_map():
+    roots, lo, hi = (2, 2), (0.0, 0.0), (1.0, 1.0)
+    f = O.Forest(2, 2, 4, roots, lo, hi, (0, 0), 1, equation=O.EQ_ADVECTION, velocity=(1.0, 0.5, 0.0))
+    f.set_nodes(distorted_nodes(roots, lo, hi, 0.2, seed=3))
+    u = f.project_ic(O.IC_COSINE, [1.0, 1.0, 1.0, 1.0])
+    t0 = f.totals(u)
+    for _ in range(5):
+        f.step(u, 0.1)
+    np.testing.assert_allclose(f.totals(u), t0, rtol=1e-13, atol=1e-13)
+    bad = box_nodes(roots, lo, hi)
+    bad[1, 1] = [1.2, 1.2]  # folds the four roots around the centre node
+    g = O.Forest(2, 2, 4, roots, lo, hi, (0, 0), 1)
+    with pytest.raises(ValueError):
+        g.set_nodes(bad)
+    moved = box_nodes(roots, lo, hi)
+    moved[0, 2, 1] += 0.01  # the periodic copy of node (0, 0) no longer matches
+    with pytest.raises(ValueError):
+        g.set_nodes(moved)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_vortex_order_on_a_smoothly_distorted_grid(p):
+    """L2 density error against the exact translated vortex on 4x4 roots of
+    N = 8 and 16 cells, periodic [0, 20]^2 (the periodic kink negligible),
+    nodes moved by a smooth periodic field: observed order >= p + 1 - 0.2,
+    the bar of the box-grid order pins."""
+    lo, hi, roots = (0.0, 0.0), (20.0, 20.0), (4, 4)
+    prm = [5.0, 10.0, 10.0, 1.0, 1.0, 20.0, 20.0]
+    T = 0.5
+    errs = []
+    for N in (8, 16):
+        f = O.Forest(2, p, N, roots, lo, hi, (0, 0), 1)
+        f.set_nodes(smooth_nodes(roots, lo, hi, 0.03))
+        u = f.project_ic(O.IC_VORTEX, prm)
+        h = 20.0 / (4 * N)
+        dt = 0.05 * h
+        n = int(round(T / dt))
+        for _ in range(n):
+            f.step(u, dt=T / n)
+        l1, l2 = f.errors(u, O.IC_VORTEX, prm, T)
+        errs.append(l2[0])
+    order = np.log2(errs[0] / errs[1])
+    assert order >= p + 1 - 0.2, (errs, order)
