@@ -7,6 +7,7 @@
 #include <cstring>
 #include <exception>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "api_internal.hpp"
@@ -122,7 +123,7 @@ dgk::StageShape stage_shape(const dgamr_forest *f)
 // the fused stage of this forest reads guard traces (the 3-D lane kernel)
 bool fused_reads_traces(const dgamr_forest *f)
 {
-    if (f->topo.rotated()) return false;
+    if (f->topo.unfused()) return false;
     return dgk::stage_reads_traces(f->topo.dim(), stage_shape(f), f->topo.desc().limiter == DGAMR_LIMITER_POSITIVITY,
                                    f->topo.desc().precision == DGAMR_FP32,
                                    f->topo.desc().hanging == DGAMR_HANG_CONSERVATIVE, f->topo.advection(),
@@ -159,6 +160,38 @@ int launch_limit(dgamr_forest *f, double *u, hipStream_t s)
     });
 }
 
+// arguments of the bilinear-root kernels
+dgk::MappedArgs mapped_args(const dgamr_forest *f, const double *us, const double *un, const double *guard,
+                            double *out, const double *dt, double a, double b)
+{
+    dgk::MappedArgs m{};
+    m.us = us;
+    m.un = un;
+    m.guard = guard;
+    m.out = out;
+    m.geo = f->d_geo;
+    m.dt = dt;
+    m.rk_a = a;
+    m.rk_b = b;
+    m.gamma = f->topo.desc().gamma;
+    for (int k = 0; k < 3; ++k) m.vel[k] = f->topo.desc().velocity[k];
+    m.ncell_total = long(f->topo.n()) * ncell_of(f);
+    m.N = f->topo.desc().n_cell;
+    return m;
+}
+
+// the degree of a 2-D forest as a compile-time constant
+template <class Fn>
+int dispatch_2d(const dgamr_forest *f, Fn &&fn)
+{
+    switch (f->topo.desc().degree) {
+    case 0: return fn(std::integral_constant<int, 0>{});
+    case 1: return fn(std::integral_constant<int, 1>{});
+    case 2: return fn(std::integral_constant<int, 2>{});
+    default: return fn(std::integral_constant<int, 3>{});
+    }
+}
+
 int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, const Work &w, hipStream_t s)
 {
     int n = f->topo.n();
@@ -166,7 +199,14 @@ int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, cons
     int ncell = ncell_of(f), block = 1;
     while (block < ncell && block < 256) block <<= 1; // power of two for the tree reduction
     const double *vel = f->topo.desc().velocity;
-    if (f->topo.advection())
+    if (f->topo.mapped()) {
+        dgk::MappedArgs a = mapped_args(f, u, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0);
+        const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
+        CHECK(dispatch_2d(f, [&](auto P) -> int {
+            HIP_TRY(dgk::launch_mapped_rate<P>(a, eq, n, block, w.leafmax, s));
+            return DGAMR_OK;
+        }));
+    } else if (f->topo.advection())
         hipLaunchKernelGGL(dgk::k_rate_adv, dim3((n + 255) / 256), dim3(256), 0, s, f->d_geo, n, vel[0], vel[1],
                            vel[2], f->topo.dim(), w.leafmax);
     else if (f->topo.dim() == 2)
@@ -393,6 +433,14 @@ int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, voi
     if (f->topo.diffusion())
         return launch_ipdg(f, u, nullptr, guard, static_cast<double *>(r), nullptr, 0.0, 1.0, f->time, dgk::OUT_RES64,
                            stream);
+    if (f->topo.mapped()) {
+        dgk::MappedArgs a = mapped_args(f, u, nullptr, guard, static_cast<double *>(r), nullptr, 0.0, 1.0);
+        const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
+        return dispatch_2d(f, [&](auto P) -> int {
+            HIP_TRY(dgk::launch_mapped<P>(a, eq, dgk::OUT_RES64, stream));
+            return DGAMR_OK;
+        });
+    }
     dgk::StageArgs a{};
     a.us = u;
     a.guard = guard;
@@ -449,6 +497,22 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
     static const double A[3] = {0.0, 0.75, 1.0 / 3.0}, B[3] = {1.0, 0.25, 2.0 / 3.0};
     const double *us = u;
     double *outs[3] = {w.u1, w.u2, u};
+    if (f->topo.mapped()) {
+        // bilinear roots: the guard fill (reference-space copy, split,
+        // combine), then the residual with the metric terms fused with the
+        // stage update
+        const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
+        for (int s = 0; s < 3; ++s) {
+            CHECK(launch_fill(f, us, w.guard, false, stream));
+            dgk::MappedArgs a = mapped_args(f, us, u, w.guard, outs[s], dt_dev, A[s], B[s]);
+            CHECK(dispatch_2d(f, [&](auto P) -> int {
+                HIP_TRY(dgk::launch_mapped<P>(a, eq, dgk::OUT_RK, stream));
+                return DGAMR_OK;
+            }));
+            us = outs[s];
+        }
+        return DGAMR_OK;
+    }
     if (f->topo.rotated()) {
         // roots of different frames: the guard fill applies the rotation of
         // each guard cell (Sec. 3.5) into the guard buffer, then the residual
@@ -544,6 +608,21 @@ int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes)
     })
 }
 
+int dgamr_set_root_nodes(dgamr_forest *f, const double *xy)
+{
+    GUARD_API({
+        CHECK(check_ptr(f, "forest"));
+        CHECK(check_ptr(xy, "xy"));
+        if (f->topo.desc().precision != DGAMR_FP64)
+            return fail(DGAMR_EUNSUPPORTED, "bilinear roots are built for the FP64 residual");
+        std::string err;
+        int rc = f->topo.set_nodes(xy, err);
+        if (rc != DGAMR_OK) return fail(rc, err);
+        f->version += 1;
+        return upload(f);
+    })
+}
+
 int dgamr_set_time(dgamr_forest *f, double t)
 {
     CHECK(check_ptr(f, "forest"));
@@ -594,7 +673,7 @@ int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, do
         return DGAMR_OK;
     }
     auto *slot = reinterpret_cast<unsigned long long *>(w.scal + 2);
-    if (cfl <= 0.0 || f->topo.rotated()) { // rotated frames: the unfused stages take dt per step
+    if (cfl <= 0.0 || f->topo.unfused()) { // rotated frames, bilinear roots: the unfused stages take dt per step
         for (int s = 0; s < nsteps; ++s) {
             if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
             CHECK(run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream));
@@ -646,7 +725,7 @@ int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *
             for (int st = 0; st < nsteps && rc == DGAMR_OK; ++st) {
                 const int rd = st & 1, wr = rd ^ 1;
                 const bool last = st == nsteps - 1;
-                if (f->topo.rotated()) { // unfused stages: the CFL reduction of every step
+                if (f->topo.unfused()) { // unfused stages: the CFL reduction of every step
                     if (st > 0) rc = launch_dt(f, cfl, u, dt_dev, w, s);
                     if (rc == DGAMR_OK) rc = run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, s);
                     continue;
@@ -683,6 +762,18 @@ int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev,
     if (n == 0) return fail(DGAMR_EINVAL, "empty forest");
     int bp = 1;
     while (bp < block) bp <<= 1; // power of two for the tree reduction
+    if (f->topo.mapped()) {
+        dgk::MappedArgs a = mapped_args(f, u, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0);
+        const bool adv = f->topo.advection();
+        CHECK(dispatch_2d(f, [&](auto P) -> int {
+            HIP_TRY(dgk::launch_mapped_totals<P>(a, adv ? dgk::EQ_ADVECTION : dgk::EQ_EULER, n, bp, w.part, stream));
+            return DGAMR_OK;
+        }));
+        if (adv) hipLaunchKernelGGL(dgk::k_totals_final<1>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
+        else hipLaunchKernelGGL(dgk::k_totals_final<4>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
+        HIP_TRY(hipGetLastError());
+        return DGAMR_OK;
+    }
     if (f->topo.scalar()) {
         if (f->topo.dim() == 2)
             hipLaunchKernelGGL((dgk::k_totals_leaf<2, 1>), dim3(n), dim3(bp), 0, stream, u, f->d_geo,
@@ -708,6 +799,7 @@ int dgamr_limit_positivity(dgamr_forest *f, double *u, hipStream_t stream)
 {
     CHECK(check_ptr(f, "forest"));
     CHECK(check_ptr(u, "u"));
+    if (f->topo.mapped()) return fail(DGAMR_EUNSUPPORTED, "the positivity limiter is not built for bilinear roots");
     return launch_limit(f, u, stream);
 }
 
@@ -760,6 +852,11 @@ int dgamr_project_ic(dgamr_forest *f, int kind, const double *params, double t, 
         hmin[a] = (d.hi[a] - d.lo[a]) / (double(d.roots[a]) * d.n_cell * double(1 << (d.max_level - 1)));
     long total = long(f->topo.n()) * ncell_of(f);
     if (total == 0) return DGAMR_OK;
+    if (f->topo.mapped())
+        return dispatch_2d(f, [&](auto P) -> int {
+            HIP_TRY(dgk::launch_mapped_ic<P>(u, f->d_geo, d.n_cell, total, kind, prm, t, d.gamma, nv_of(f), stream));
+            return DGAMR_OK;
+        });
     return dispatch(f->topo.dim(), d.degree, [&](auto D, auto P) -> int {
         HIP_TRY((dgk::launch_project_ic<D, P>(u, f->d_geo, d.n_cell, total, kind, prm, t, d.gamma, hmin, stream,
                                               nv_of(f))));

@@ -180,14 +180,69 @@ int Forest::set_frames(const int32_t *codes, std::string &err)
                 err = "rotated root frames need equal root edges";
                 return DGAMR_EINVAL;
             }
-        if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.equation == DGAMR_EQ_ADVECTION) {
-            err = "rotated root frames are built for the paper hanging mode, Euler and diffusion";
+        if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.equation == DGAMR_EQ_ADVECTION || mapped()) {
+            err = "rotated root frames are built for box roots, the paper hanging mode, Euler and diffusion";
             return DGAMR_EUNSUPPORTED;
         }
     }
     frame_.assign(codes, codes + ntree);
     rotated_ = any;
     return build_links(err);
+}
+
+int Forest::set_nodes(const double *xy, std::string &err)
+{
+    if (desc_.dim != 2) {
+        err = "bilinear root blocks are built in 2-D";
+        return DGAMR_EUNSUPPORTED;
+    }
+    if (rotated_ || desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.limiter != DGAMR_LIMITER_NONE ||
+        desc_.equation == DGAMR_EQ_DIFFUSION) {
+        err = "bilinear root blocks are built for aligned frames, the paper hanging mode, no limiter, Euler and "
+              "scalar convection";
+        return DGAMR_EUNSUPPORTED;
+    }
+    const int nx = desc_.roots[0] + 1, ny = desc_.roots[1] + 1;
+    const double L[2] = {desc_.hi[0] - desc_.lo[0], desc_.hi[1] - desc_.lo[1]};
+    for (int k = 0; k < 2 * nx * ny; ++k)
+        if (!std::isfinite(xy[k])) {
+            err = "nodes must be finite";
+            return DGAMR_EINVAL;
+        }
+    // on a periodic axis the last node column (row) is the first moved by the period
+    if (desc_.bc[0] == DGAMR_BC_PERIODIC)
+        for (int j = 0; j < ny; ++j) {
+            const double *a = xy + 2 * (j * nx), *b = xy + 2 * (j * nx + nx - 1);
+            if (std::fabs(b[0] - a[0] - L[0]) > 1e-12 * L[0] || std::fabs(b[1] - a[1]) > 1e-12 * L[1]) {
+                err = "periodic x: node column roots_x must be node column 0 moved by the period";
+                return DGAMR_EINVAL;
+            }
+        }
+    if (desc_.bc[1] == DGAMR_BC_PERIODIC)
+        for (int i = 0; i < nx; ++i) {
+            const double *a = xy + 2 * i, *b = xy + 2 * ((ny - 1) * nx + i);
+            if (std::fabs(b[1] - a[1] - L[1]) > 1e-12 * L[1] || std::fabs(b[0] - a[0]) > 1e-12 * L[0]) {
+                err = "periodic y: node row roots_y must be node row 0 moved by the period";
+                return DGAMR_EINVAL;
+            }
+        }
+    // every root a convex quadrilateral: positive Jacobian at its corners
+    for (int ry = 0; ry + 1 < ny; ++ry)
+        for (int rx = 0; rx + 1 < nx; ++rx) {
+            const double *c[4] = {xy + 2 * (ry * nx + rx), xy + 2 * (ry * nx + rx + 1), xy + 2 * ((ry + 1) * nx + rx),
+                                  xy + 2 * ((ry + 1) * nx + rx + 1)};
+            static const int e[4][2] = {{1, 2}, {3, 0}, {0, 3}, {2, 1}};
+            for (int k = 0; k < 4; ++k) {
+                const double ax = c[e[k][0]][0] - c[k][0], ay = c[e[k][0]][1] - c[k][1];
+                const double bx = c[e[k][1]][0] - c[k][0], by = c[e[k][1]][1] - c[k][1];
+                if (ax * by - ay * bx <= 0.0) {
+                    err = "every root must be a convex quadrilateral with its nodes counter-clockwise";
+                    return DGAMR_EINVAL;
+                }
+            }
+        }
+    nodes_.assign(xy, xy + 2 * nx * ny);
+    return DGAMR_OK;
 }
 
 // Position of a leaf-level index (at `span` leaves per root edge) moved
@@ -459,6 +514,20 @@ std::vector<LeafGeo> Forest::geometry() const
         }
         G.level = k.level;
         G.pad = 0;
+        for (int b = 0; b < 4; ++b) G.node[b][0] = G.node[b][1] = 0.0;
+        if (mapped()) {
+            // the leaf's corners: the root's bilinear map at the leaf's
+            // corners in the root's unit square
+            const int nx = desc_.roots[0] + 1;
+            const double *n00 = nodes_.data() + 2 * (r[1] * nx + r[0]), *n10 = n00 + 2, *n01 = n00 + 2 * nx,
+                         *n11 = n01 + 2;
+            for (int b = 0; b < 4; ++b) {
+                const double s0 = double(k.idx[0] + (b & 1)) / span, s1 = double(k.idx[1] + (b >> 1)) / span;
+                for (int a = 0; a < 2; ++a)
+                    G.node[b][a] = (1.0 - s0) * (1.0 - s1) * n00[a] + s0 * (1.0 - s1) * n10[a] +
+                                   (1.0 - s0) * s1 * n01[a] + s0 * s1 * n11[a];
+            }
+        }
         for (int gg = 0; gg < 3; ++gg)
             for (int l = 0; l < 3; ++l) G.q[3 * gg + l] = (signed char)Q[gg][l];
         for (int x = 9; x < 12; ++x) G.q[x] = 0;

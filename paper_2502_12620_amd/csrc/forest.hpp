@@ -45,6 +45,10 @@ struct LeafGeo {
     int level;
     int pad;
     signed char q[12]; // the root's frame Q (q[3 g + l]): global vector = Q local
+    // bilinear roots (Forest::set_nodes): the leaf's physical corners at the
+    // reference corners (-1,-1), (1,-1), (-1,1), (1,1), (x, y) each; zero
+    // otherwise
+    double node[4][2];
 };
 
 // Guard cell across a face between roots of different frames (Sec. 3.5:
@@ -101,6 +105,12 @@ class Forest {
     // rotation codes of the root frames (one per tree), before any refinement
     int set_frames(const int32_t *codes, std::string &err);
     bool rotated() const { return rotated_; }
+    // Sec. 3.3, Eq. 6: 2-D roots as bilinear images of the reference square,
+    // from the (roots_x + 1) x (roots_y + 1) grid nodes (x, y), x fastest
+    int set_nodes(const double *xy, std::string &err);
+    bool mapped() const { return !nodes_.empty(); }
+    // steps run the guard fill, the residual and the stage update unfused
+    bool unfused() const { return rotated_ || mapped(); }
     const std::vector<RotPlan> &plans() const { return plans_; }
     std::vector<LeafGeo> geometry() const;
 
@@ -126,6 +136,7 @@ class Forest {
     std::vector<FaceLink> links_;
     std::vector<int> frame_;      // per tree (empty: all 0)
     bool rotated_ = false;        // some root has a non-zero frame
+    std::vector<double> nodes_;   // bilinear root grid nodes (empty: the box grid)
     std::vector<RotPlan> plans_;  // guard-cell plans of rotated faces
     int frame_of(int tree) const { return frame_.empty() ? 0 : frame_[tree]; }
     bool rot_plans(int i, int face, const FaceLink &L);

@@ -338,6 +338,22 @@ struct IcParams {
     double p[8];
 };
 
+// Bilinear-root stage (2-D, Sec. 3.3 Eq. 6): residual over guard
+// coefficients, optionally fused with the SSP-RK3 stage update
+struct MappedArgs {
+    const double *us;    // stage input (read-only)
+    const double *un;    // RK base state (OUT_RK)
+    const double *guard; // guard coefficients G[leaf][face][var][mode][t]
+    double *out;         // residual (OUT_RES64) or next state (OUT_RK)
+    const LeafGeo *geo;  // node[4][2]: each leaf's corners
+    const double *dt;    // device dt (OUT_RK)
+    double rk_a, rk_b;
+    double gamma;
+    double vel[3];       // convection velocity (EQ_ADVECTION)
+    long ncell_total;
+    int N;
+};
+
 // Diffusion stage (Sec. 5.2): interior-penalty residual, optionally fused
 // with the SSP-RK3 stage update.
 struct IpdgArgs {

@@ -289,6 +289,7 @@ int dgamr_pool_admit(dgamr_pool *p, const dgamr_forest *f, double cfl, int32_t *
         CHECK(check_ptr(slot_first, "slot_first"));
         if (!same_class(p->cls, f->topo.desc())) return fail(DGAMR_EINVAL, "forest is not of the pool's class");
         if (f->topo.rotated()) return fail(DGAMR_EUNSUPPORTED, "pools hold forests whose roots share one frame");
+        if (f->topo.mapped()) return fail(DGAMR_EUNSUPPORTED, "pools hold forests of box roots");
         if (!(cfl > 0.0)) return fail(DGAMR_EINVAL, "cfl must be positive");
         const int64_t n = f->topo.n();
         if (n == 0) return fail(DGAMR_EINVAL, "empty forest");

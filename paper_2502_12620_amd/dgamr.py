@@ -33,7 +33,7 @@ EXPORTS = [
     "dgamr_pool_create", "dgamr_pool_destroy", "dgamr_pool_bytes", "dgamr_pool_admit", "dgamr_pool_release",
     "dgamr_pool_step", "dgamr_pool_dt", "dgamr_pool_stats", "dgamr_pool_set_shape", "dgamr_pool_set_lanes", "dgamr_pool_autotune",
     "dgamr_pools_capture", "dgamr_graph_launch", "dgamr_graph_destroy", "dgamr_run_capture",
-    "dgamr_step_static", "dgamr_set_time", "dgamr_get_time", "dgamr_set_root_frames", "dgamr_math_probe",
+    "dgamr_step_static", "dgamr_set_time", "dgamr_get_time", "dgamr_set_root_frames", "dgamr_set_root_nodes", "dgamr_math_probe",
     "dgamr_last_error",
 ]
 
@@ -81,6 +81,7 @@ def lib():
         L.dgamr_step_static.argtypes = [vp, ctypes.c_double, vp, vp, vp]
         L.dgamr_set_time.argtypes = [vp, ctypes.c_double]
         L.dgamr_set_root_frames.argtypes = [vp, vp]
+        L.dgamr_set_root_nodes.argtypes = [vp, vp]
         L.dgamr_math_probe.argtypes = [ctypes.c_int, vp, vp, ctypes.c_int64, vp]
         L.dgamr_get_time.argtypes = [vp, ctypes.POINTER(ctypes.c_double)]
         L.dgamr_run.argtypes = [vp, ctypes.c_double, ctypes.c_int, vp, vp, vp, vp]
@@ -227,6 +228,14 @@ class Forest:
         if c.numel() != self.desc.roots[0] * self.desc.roots[1] * self.desc.roots[2]:
             raise ValueError("one frame code per root")
         _check(lib().dgamr_set_root_frames(self.h, _ptr(c)))
+
+    def set_root_nodes(self, xy):
+        """Bilinear root blocks from the 2-D root grid nodes, shape
+        (roots_y + 1, roots_x + 1, 2) (dgamr_set_root_nodes)."""
+        a = torch.as_tensor(xy, dtype=torch.float64).contiguous()
+        if a.numel() != 2 * (self.desc.roots[0] + 1) * (self.desc.roots[1] + 1):
+            raise ValueError("(roots_x + 1) * (roots_y + 1) nodes of (x, y)")
+        _check(lib().dgamr_set_root_nodes(self.h, _ptr(a)))
 
     def keys(self):
         k = torch.zeros((self.n_leaves, 5), dtype=torch.int32)
