@@ -151,6 +151,27 @@ def convection_3d(degree: int = 1, n_cell: int = 4) -> Workload:
     return w
 
 
+def convection_2d_distorted(degree: int = 2, n_cell: int = 8) -> Workload:
+    """The convection case of Sec. 5.1 on its second root set, four
+    distorted root blocks.  The paper shows that set only as a figure: here
+    a 2x2 root grid on the periodic unit square whose centre node is moved
+    from (0.5, 0.5) to (0.6, 0.42), the boundary nodes staying on the box,
+    so every root is a convex quadrilateral and the grid stays periodic.
+    Everything else as convection_2d."""
+    w = convection_2d(degree, n_cell)
+    w.name = "f1_convection2d_distorted"
+    w.roots = (2, 2)
+    nodes = np.zeros((3, 3, 2))
+    nodes[..., 0] = np.array([0.0, 0.5, 1.0])[None, :]
+    nodes[..., 1] = np.array([0.0, 0.5, 1.0])[:, None]
+    nodes[1, 1] = (0.6, 0.42)
+    w.nodes = nodes
+    w.initial_refinement = [refine_all]
+    w.min_level = 2
+    w.max_level = 4
+    return w
+
+
 def diffusion_2d(degree: int = 2, n_cell: int = 6) -> Workload:
     """Diffusion (Sec. 5.2): u_t = div grad u on the unit square, one root
     block, Dirichlet data and initial state from exp(-x + y + 2t), 6x6-cell
