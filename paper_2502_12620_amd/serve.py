@@ -133,18 +133,24 @@ class Server:
     def _make_room(self, c: _Class, need: int) -> bool:
         """Give c's pool room for `need` more leaves within the budget: grow
         it (by half again at least, as far as the budget allows), shrinking
-        the other pools to what they use only when that makes the request
-        fit.  Nothing is rebuilt when it would not fit anyway."""
+        other pools to what they use only when that makes the request fit,
+        idle pools first and no more of them than needed.  Nothing is rebuilt
+        when it would not fit anyway."""
         used = c.used()
         free = self.budget - self.allocated(skip=c)
         if free // c.per_leaf < used + need:
             spare = sum((o.capacity - o.used()) * o.per_leaf for o in self.classes.values() if o is not c)
             if (free + spare) // c.per_leaf < used + need:
                 return False
-            for o in self.classes.values():
-                if o is not c and o.capacity > o.used():
-                    self._rebuild(o, o.used())
-            free = self.budget - self.allocated(skip=c)
+            # give back only what is missing: idle pools first (nothing to
+            # move), then the pools with the most spare bytes
+            others = sorted((o for o in self.classes.values() if o is not c and o.capacity > o.used()),
+                            key=lambda o: (len(o.members) > 0, -(o.capacity - o.used()) * o.per_leaf))
+            for o in others:
+                if free // c.per_leaf >= used + need:
+                    break
+                self._rebuild(o, o.used())
+                free = self.budget - self.allocated(skip=c)
         self._rebuild(c, min(max(used + need, math.ceil(1.5 * c.capacity)), free // c.per_leaf))
         return True
 
