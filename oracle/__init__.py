@@ -221,8 +221,9 @@ class Forest:
             raise ValueError("oracle: frames refused")
 
     def set_nodes(self, xy):
-        """Bilinear root blocks (Sec. 3.3, Eq. 6) from the 2-D root grid
-        nodes, shape (roots_y + 1, roots_x + 1, 2) (see oracle.h)."""
+        """Bilinear (3-D: trilinear) root blocks (Sec. 3.3, Eq. 6) from the
+        root grid nodes, shape (roots_y + 1, roots_x + 1, 2) or (roots_z + 1,
+        roots_y + 1, roots_x + 1, 3) (see oracle.h)."""
         a = np.ascontiguousarray(xy, dtype=np.float64)
         if lib().orc_set_nodes(self.ptr, _dp(a)) != 0:
             raise ValueError("oracle: nodes refused")

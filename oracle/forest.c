@@ -450,44 +450,62 @@ int orc_set_frames(orc_forest *f, const int *codes)
     return 0;
 }
 
-/* Sec. 3.3, Eq. 6: root blocks as bilinear images of the reference square
- * (2-D): xy holds the (roots_x + 1) x (roots_y + 1) grid nodes, x fastest,
- * (x, y) each; root (rx, ry) has corners node(rx, ry), node(rx + 1, ry),
- * node(rx, ry + 1), node(rx + 1, ry + 1).  On a periodic axis the last
- * node column (row) must be the first one moved by the period.  Every root
- * must be a convex quadrilateral (positive Jacobian at its corners).  Not
- * with rotated frames, the conservative mode, the diffusion equation or
- * the limiter. */
+/* Sec. 3.3, Eq. 6: root blocks as bilinear (3-D: trilinear) images of the
+ * reference square (cube): xy holds the (roots_x + 1) x (roots_y + 1)
+ * [x (roots_z + 1)] grid nodes, x fastest, d coordinates each; root (rx,
+ * ry[, rz]) has the corner nodes (rx + bx, ry + by[, rz + bz]), b in {0,1}^d.
+ * On a periodic axis the last node layer must be the first one moved by the
+ * period.  Every root must have a positive Jacobian at its corners.  Not
+ * with rotated frames, the conservative mode, the diffusion equation or the
+ * limiter. */
 int orc_set_nodes(orc_forest *f, const double *xy)
 {
-    if (f->dim != 2 || f->frame || f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_DIFFUSION) return -1;
-    int nx = f->roots[0] + 1, ny = f->roots[1] + 1;
-    double L[2] = {f->hi[0] - f->lo[0], f->hi[1] - f->lo[1]};
-    for (int j = 0; j < ny; ++j)
-        if (f->bc[0] == ORC_BC_PERIODIC) {
-            const double *a = xy + 2 * (j * nx), *b = xy + 2 * (j * nx + nx - 1);
-            if (fabs(b[0] - a[0] - L[0]) > 1e-12 * L[0] || fabs(b[1] - a[1]) > 1e-12 * L[1]) return -1;
-        }
-    for (int i = 0; i < nx; ++i)
-        if (f->bc[1] == ORC_BC_PERIODIC) {
-            const double *a = xy + 2 * i, *b = xy + 2 * ((ny - 1) * nx + i);
-            if (fabs(b[1] - a[1] - L[1]) > 1e-12 * L[1] || fabs(b[0] - a[0]) > 1e-12 * L[0]) return -1;
-        }
-    for (int ry = 0; ry + 1 < ny; ++ry)
-        for (int rx = 0; rx + 1 < nx; ++rx) {
-            const double *c[4] = {xy + 2 * (ry * nx + rx), xy + 2 * (ry * nx + rx + 1), xy + 2 * ((ry + 1) * nx + rx),
-                                  xy + 2 * ((ry + 1) * nx + rx + 1)};
-            /* the Jacobian at a corner is spanned by its two edges */
-            const int e[4][2] = {{1, 2}, {3, 0}, {0, 3}, {2, 1}};
-            for (int k = 0; k < 4; ++k) {
-                double ax = c[e[k][0]][0] - c[k][0], ay = c[e[k][0]][1] - c[k][1];
-                double bx = c[e[k][1]][0] - c[k][0], by = c[e[k][1]][1] - c[k][1];
-                if (ax * by - ay * bx <= 0.0) return -1;
+    if (f->frame || f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_DIFFUSION) return -1;
+    int d = f->dim, n[3] = {f->roots[0] + 1, f->roots[1] + 1, d == 3 ? f->roots[2] + 1 : 1};
+    long total = (long)n[0] * n[1] * n[2];
+#define NODE(i, j, k) (xy + (long)d * (((long)(k) * n[1] + (j)) * n[0] + (i)))
+    for (int a = 0; a < d; ++a) {
+        if (f->bc[a] != ORC_BC_PERIODIC) continue;
+        double L = f->hi[a] - f->lo[a];
+        for (long id = 0; id < total; ++id) {
+            int idx[3] = {(int)(id % n[0]), (int)((id / n[0]) % n[1]), (int)(id / ((long)n[0] * n[1]))};
+            if (idx[a] != 0) continue;
+            int last[3] = {idx[0], idx[1], idx[2]};
+            last[a] = n[a] - 1;
+            const double *p0 = NODE(idx[0], idx[1], idx[2]), *p1 = NODE(last[0], last[1], last[2]);
+            for (int b = 0; b < d; ++b) {
+                double want = p0[b] + (b == a ? L : 0.0);
+                if (fabs(p1[b] - want) > 1e-12 * (f->hi[b] - f->lo[b])) return -1;
             }
         }
+    }
+    int nr = f->roots[0] * f->roots[1] * (d == 3 ? f->roots[2] : 1);
+    for (int t = 0; t < nr; ++t) {
+        int r[3] = {t % f->roots[0], (t / f->roots[0]) % f->roots[1], d == 3 ? t / (f->roots[0] * f->roots[1]) : 0};
+        /* the Jacobian at each corner: the d edges leaving it, oriented along
+         * the reference axes */
+        for (int b = 0; b < (1 << d); ++b) {
+            double E[3][3] = {{0}};
+            int c0[3] = {r[0] + (b & 1), r[1] + ((b >> 1) & 1), r[2] + ((b >> 2) & 1)};
+            const double *pc = NODE(c0[0], c0[1], d == 3 ? c0[2] : 0);
+            for (int e = 0; e < d; ++e) {
+                int c1[3] = {c0[0], c0[1], c0[2]};
+                int up = !((b >> e) & 1);
+                c1[e] += up ? 1 : -1;
+                const double *pe = NODE(c1[0], c1[1], d == 3 ? c1[2] : 0);
+                for (int a = 0; a < d; ++a) E[a][e] = (up ? 1.0 : -1.0) * (pe[a] - pc[a]);
+            }
+            double det = d == 2 ? E[0][0] * E[1][1] - E[0][1] * E[1][0]
+                                : E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                                      E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                                      E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+            if (!(det > 0.0)) return -1;
+        }
+    }
+#undef NODE
     free(f->nodes);
-    f->nodes = malloc(sizeof(double) * 2 * nx * ny);
-    memcpy(f->nodes, xy, sizeof(double) * 2 * nx * ny);
+    f->nodes = malloc(sizeof(double) * d * total);
+    memcpy(f->nodes, xy, sizeof(double) * d * total);
     return 0;
 }
 

@@ -94,10 +94,11 @@ void orc_set_diffusion(orc_forest *f, double nu, const double *avec);
 int orc_set_frames(orc_forest *f, const int *codes);
 /* time of the state (Dirichlet data of the diffusion equation); orc_step
  * advances it by dt */
-/* Sec. 3.3, Eq. 6: bilinear root blocks from the 2-D root grid nodes xy
- * ((roots_x + 1) x (roots_y + 1) points (x, y), x fastest).  -1 if not
- * allowed (3-D, frames, conservative mode, diffusion), if a root is not a
- * convex quadrilateral, or if periodic node copies do not match. */
+/* Sec. 3.3, Eq. 6: bilinear (3-D: trilinear) root blocks from the root
+ * grid nodes xy ((roots_x + 1) x (roots_y + 1) [x (roots_z + 1)] points of d
+ * coordinates, x fastest).  -1 if not allowed (frames, conservative mode,
+ * diffusion), if a root has a non-positive Jacobian at a corner, or if
+ * periodic node copies do not match. */
 int orc_set_nodes(orc_forest *f, const double *xy);
 void orc_set_time(orc_forest *f, double t);
 double orc_get_time(const orc_forest *f);

@@ -75,64 +75,97 @@ static long gidx(const orc_forest *f, long leaf, int face, int v, int m, int t)
 
 /* evaluate the cell polynomial with coefficients coef[v*stride_v + m*stride_m]
  * at reference point xi */
-/* ---------------------------------------------------------------- bilinear blocks
- * Sec. 3.3, Eq. 6: with root grid nodes set, a root is the bilinear image
- * of the reference square spanned by its four corner nodes.  A leaf's cells
- * are images of equal squares of that reference square, so each cell is the
- * bilinear image of its own reference cell [-1,1]^2 with the images of its
- * corners as nodes.  The weak form (Eq. 3-4) is then evaluated with the
- * Jacobian J = dx/dxi of that map at every quadrature point: volume term
- * sum_q w_q grad_xi phi_m . adj(J) F (adj(J) = det(J) J^-1, the
- * contravariant flux), face term sum_f w_f |N| Fhat(U-, U+; N/|N|) phi_m
- * with N = side * (row a of adj(J)) the outward normal scaled by the face
- * Jacobian, and the full mass matrix M_mn = sum_q w_q det(J) phi_m phi_n
- * (exact with p+1 points per axis: det(J) is bilinear). */
+/* ---------------------------------------------------------------- bilinear / trilinear blocks
+ * Sec. 3.3, Eq. 6: with root grid nodes set, a root is the bilinear (3-D:
+ * trilinear) image of the reference square (cube) spanned by its corner
+ * nodes.  A leaf's cells are images of equal squares (cubes) of that
+ * reference box, so each cell is the multilinear image of its own reference
+ * cell [-1,1]^d with the images of its corners as nodes.  The weak form
+ * (Eq. 3-4) is then evaluated with the Jacobian J = dx/dxi of that map at
+ * every quadrature point: volume term sum_q w_q grad_xi phi_m . adj(J) F
+ * (adj(J) = det(J) J^-1, the contravariant flux), face term
+ * sum_f w_f |N| Fhat(U-, U+; N/|N|) phi_m with N = side * (row a of adj(J))
+ * the outward normal scaled by the face Jacobian, and the full mass matrix
+ * M_mn = sum_q w_q det(J) phi_m phi_n (exact with p+1 points per axis:
+ * det(J) has degree d-1 per axis). */
 static int mapped(const orc_forest *f) { return f->nodes != NULL; }
 
-/* physical corners of cell c of leaf i: (xi, eta) = (-1,-1), (1,-1),
- * (-1,1), (1,1) */
-static void cell_corners(const orc_forest *f, int i, int c, double cx[4][2])
+/* physical corners of cell c of leaf i; corner k has reference coordinate
+ * -1 or +1 along axis a by bit a of k */
+static void cell_corners(const orc_forest *f, int i, int c, double cx[8][3])
 {
     const orc_key *k = &f->leaf[i];
+    int d = f->dim, nk = 1 << d;
     long lo[3], size;
     orc_leaf_lbox(f, k, lo, &size);
     int ijk[3];
     orc_cell_ijk(f, c, ijk);
     long hu = size / f->N;
-    int nx = f->roots[0] + 1, rx = k->tree % f->roots[0], ry = k->tree / f->roots[0];
-    const double *n00 = f->nodes + 2 * (ry * nx + rx), *n10 = n00 + 2, *n01 = n00 + 2 * nx, *n11 = n01 + 2;
-    for (int b = 0; b < 4; ++b) {
-        double s0 = (double)(lo[0] + (ijk[0] + (b & 1)) * hu) / (double)f->unit;
-        double s1 = (double)(lo[1] + (ijk[1] + (b >> 1)) * hu) / (double)f->unit;
-        for (int a = 0; a < 2; ++a)
-            cx[b][a] = (1.0 - s0) * (1.0 - s1) * n00[a] + s0 * (1.0 - s1) * n10[a] + (1.0 - s0) * s1 * n01[a] +
-                       s0 * s1 * n11[a];
+    int nx = f->roots[0] + 1, ny = f->roots[1] + 1;
+    int r[3] = {k->tree % f->roots[0], (k->tree / f->roots[0]) % f->roots[1], k->tree / (f->roots[0] * f->roots[1])};
+    for (int b = 0; b < nk; ++b) {
+        double s[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) s[a] = (double)(lo[a] + (ijk[a] + ((b >> a) & 1)) * hu) / (double)f->unit;
+        for (int a = 0; a < 3; ++a) cx[b][a] = 0.0;
+        /* the root's multilinear map at s */
+        for (int n = 0; n < nk; ++n) {
+            double wgt = 1.0;
+            int node[3] = {r[0], r[1], r[2]};
+            for (int a = 0; a < d; ++a) {
+                int bit = (n >> a) & 1;
+                wgt *= bit ? s[a] : 1.0 - s[a];
+                node[a] += bit;
+            }
+            const double *xy = f->nodes + d * ((d == 3 ? node[2] * ny : 0) * nx + node[1] * nx + node[0]);
+            for (int a = 0; a < d; ++a) cx[b][a] += wgt * xy[a];
+        }
     }
 }
 
-/* x(xi) and J[a][b] = dx_a / dxi_b of the bilinear cell map */
-static void bilinear_point(const double cx[4][2], const double *xi, double *x)
+/* x(xi) of the multilinear cell map */
+static void map_point(const orc_forest *f, const double cx[8][3], const double *xi, double *x)
 {
-    double e = xi[0], h = xi[1];
-    for (int a = 0; a < 2; ++a)
-        x[a] = 0.25 * ((1 - e) * (1 - h) * cx[0][a] + (1 + e) * (1 - h) * cx[1][a] + (1 - e) * (1 + h) * cx[2][a] +
-                       (1 + e) * (1 + h) * cx[3][a]);
-    x[2] = 0.0;
-}
-static double bilinear_jacobian(const double cx[4][2], const double *xi, double J[2][2])
-{
-    double e = xi[0], h = xi[1];
-    for (int a = 0; a < 2; ++a) {
-        J[a][0] = 0.25 * ((1 - h) * (cx[1][a] - cx[0][a]) + (1 + h) * (cx[3][a] - cx[2][a]));
-        J[a][1] = 0.25 * ((1 - e) * (cx[2][a] - cx[0][a]) + (1 + e) * (cx[3][a] - cx[1][a]));
+    int d = f->dim;
+    for (int a = 0; a < 3; ++a) x[a] = 0.0;
+    for (int b = 0; b < (1 << d); ++b) {
+        double wgt = 1.0;
+        for (int a = 0; a < d; ++a) wgt *= 0.5 * (1.0 + (((b >> a) & 1) ? xi[a] : -xi[a]));
+        for (int a = 0; a < d; ++a) x[a] += wgt * cx[b][a];
     }
-    return J[0][0] * J[1][1] - J[0][1] * J[1][0];
 }
-/* row b of adj(J) = det(J) J^-1: the contravariant direction of xi_b */
-static void adj_row(double J[2][2], int b, double *r)
+
+/* J[a][e] = dx_a / dxi_e of the multilinear cell map; returns det J */
+static double map_jacobian(const orc_forest *f, const double cx[8][3], const double *xi, double J[3][3])
 {
-    if (b == 0) { r[0] = J[1][1]; r[1] = -J[0][1]; }
-    else { r[0] = -J[1][0]; r[1] = J[0][0]; }
+    int d = f->dim;
+    for (int a = 0; a < 3; ++a)
+        for (int e = 0; e < 3; ++e) J[a][e] = 0.0;
+    for (int b = 0; b < (1 << d); ++b)
+        for (int e = 0; e < d; ++e) {
+            double wgt = ((b >> e) & 1) ? 0.5 : -0.5;
+            for (int c = 0; c < d; ++c)
+                if (c != e) wgt *= 0.5 * (1.0 + (((b >> c) & 1) ? xi[c] : -xi[c]));
+            for (int a = 0; a < d; ++a) J[a][e] += wgt * cx[b][a];
+        }
+    if (d == 2) return J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+/* row e of adj(J) = det(J) J^-1: the contravariant direction of xi_e */
+static void adj_row(const orc_forest *f, double J[3][3], int e, double *r)
+{
+    if (f->dim == 2) {
+        if (e == 0) { r[0] = J[1][1]; r[1] = -J[0][1]; }
+        else { r[0] = -J[1][0]; r[1] = J[0][0]; }
+        r[2] = 0.0;
+        return;
+    }
+    /* adj[e][a] = cofactor of J[a][e] */
+    for (int a = 0; a < 3; ++a) {
+        int a1 = (a + 1) % 3, a2 = (a + 2) % 3, e1 = (e + 1) % 3, e2 = (e + 2) % 3;
+        r[a] = J[a1][e1] * J[a2][e2] - J[a1][e2] * J[a2][e1];
+    }
 }
 
 /* solve the symmetric positive definite n x n system M X = B for nrhs
@@ -164,14 +197,14 @@ static void spd_solve(int n, const double *M, double *B, int nrhs)
 /* mass matrix of cell c of leaf i with the volume rule (xi, w: nq points) */
 static void mapped_mass(const orc_forest *f, int i, int c, int nq, double (*xi)[3], const double *w, double *M)
 {
-    double cx[4][2];
+    double cx[8][3];
     cell_corners(f, i, c, cx);
     int nb = f->nb;
     for (int k = 0; k < nb * nb; ++k) M[k] = 0.0;
     for (int iq = 0; iq < nq; ++iq) {
-        double J[2][2], det = bilinear_jacobian(cx, xi[iq], J);
+        double J[3][3], det = map_jacobian(f, cx, xi[iq], J);
         double ph[20];
-        for (int m = 0; m < nb; ++m) ph[m] = orc_phi(2, f->exps + 3 * m, xi[iq]);
+        for (int m = 0; m < nb; ++m) ph[m] = orc_phi(f->dim, f->exps + 3 * m, xi[iq]);
         for (int m = 0; m < nb; ++m)
             for (int n = 0; n < nb; ++n) M[m * nb + n] += w[iq] * det * ph[m] * ph[n];
     }
@@ -182,24 +215,32 @@ static void mapped_mass(const orc_forest *f, int i, int c, int nq, double (*xi)[
  * same formula with alpha = |vel.n| is the upwind flux */
 static void num_flux_n(const orc_forest *f, const double *um, const double *up, const double *n, double *fh)
 {
+    int d = f->dim, nv = f->nv;
     if (f->equation == ORC_EQ_ADVECTION) {
-        double vn = f->vel[0] * n[0] + f->vel[1] * n[1];
+        double vn = 0.0;
+        for (int a = 0; a < d; ++a) vn += f->vel[a] * n[a];
         fh[0] = 0.5 * (vn * (um[0] + up[0]) - fabs(vn) * (up[0] - um[0]));
         return;
     }
-    double fm0[5], fm1[5], fp0[5], fp1[5];
-    orc_euler_flux(2, f->gamma, um, 0, fm0);
-    orc_euler_flux(2, f->gamma, um, 1, fm1);
-    orc_euler_flux(2, f->gamma, up, 0, fp0);
-    orc_euler_flux(2, f->gamma, up, 1, fp1);
-    double am = f->gamma * orc_pressure(2, f->gamma, um) / um[0];
-    double ap = f->gamma * orc_pressure(2, f->gamma, up) / up[0];
+    double fm[5] = {0, 0, 0, 0, 0}, fp[5] = {0, 0, 0, 0, 0};
+    double vm = 0.0, vp = 0.0;
+    for (int a = 0; a < d; ++a) {
+        double fa[5], fb[5];
+        orc_euler_flux(d, f->gamma, um, a, fa);
+        orc_euler_flux(d, f->gamma, up, a, fb);
+        for (int v = 0; v < nv; ++v) {
+            fm[v] += fa[v] * n[a];
+            fp[v] += fb[v] * n[a];
+        }
+        vm += um[1 + a] * n[a];
+        vp += up[1 + a] * n[a];
+    }
+    double am = f->gamma * orc_pressure(d, f->gamma, um) / um[0];
+    double ap = f->gamma * orc_pressure(d, f->gamma, up) / up[0];
     double cm = sqrt(am > 0.0 ? am : 0.0), cp = sqrt(ap > 0.0 ? ap : 0.0);
-    double lm = fabs((um[1] * n[0] + um[2] * n[1]) / um[0]) + cm;
-    double lp = fabs((up[1] * n[0] + up[2] * n[1]) / up[0]) + cp;
+    double lm = fabs(vm / um[0]) + cm, lp = fabs(vp / up[0]) + cp;
     double alpha = lm > lp ? lm : lp;
-    for (int v = 0; v < 4; ++v)
-        fh[v] = 0.5 * ((fm0[v] + fp0[v]) * n[0] + (fm1[v] + fp1[v]) * n[1] - alpha * (up[v] - um[v]));
+    for (int v = 0; v < nv; ++v) fh[v] = 0.5 * ((fm[v] + fp[v]) - alpha * (up[v] - um[v]));
 }
 
 static void eval_poly(const orc_forest *f, const double *coef, long stride_v, long stride_m,
@@ -404,9 +445,9 @@ static void analytic_state(const orc_forest *f, int kind, const double *prm, dou
 static void cell_point(const orc_forest *f, int i, int c, const double *xi, double *x)
 {
     if (mapped(f)) {
-        double cx[4][2];
+        double cx[8][3];
         cell_corners(f, i, c, cx);
-        bilinear_point(cx, xi, x);
+        map_point(f, cx, xi, x);
         return;
     }
     long lo[3], size;
@@ -469,11 +510,11 @@ void orc_project_ic(const orc_forest *f, int kind, const double *params, double 
             }
             if (mapped(f)) {
                 /* M K = int phi U det(J) dxi, M with the volume rule */
-                double cx[4][2], M[400];
+                double cx[8][3], M[400];
                 cell_corners(f, i, c, cx);
                 memset(acc, 0, sizeof(acc));
                 for (int iq = 0; iq < nq; ++iq) {
-                    double s[5], J[2][2], det = bilinear_jacobian(cx, xi[iq], J);
+                    double s[5], J[3][3], det = map_jacobian(f, cx, xi[iq], J);
                     analytic_local(f, i, c, kind, params, t, xi[iq], s);
                     for (int l = 0; l < f->nb; ++l) {
                         double ph = orc_phi(f->dim, f->exps + 3 * l, xi[iq]);
@@ -585,39 +626,42 @@ static void diffusion_residual(const orc_forest *f, const double *u, const doubl
  * reference space); its trace is taken at the shared reference face point. */
 static void mapped_residual(const orc_forest *f, const double *u, const double *g, double *r)
 {
-    int d = 2, nf = 4, nfc = orc_nface_cells(f), nc = orc_ncell(f), q = f->q, nb = f->nb, nv = f->nv;
+    int d = f->dim, nf = 2 * d, nfc = orc_nface_cells(f), nc = orc_ncell(f), q = f->q, nb = f->nb, nv = f->nv;
     double gx[8], gw[8];
     orc_gauss_legendre(q, gx, gw);
     double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
     double *vw = malloc(sizeof(double) * 512);
     int nq = tensor_points(d, q, gx, gw, vxi, vw);
+    double (*fxi)[3] = malloc(sizeof(double) * 3 * 64);
+    double *fw = malloc(sizeof(double) * 64);
+    int nfq = tensor_points(d - 1, q, gx, gw, fxi, fw);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < f->nleaves; ++i)
         for (int c = 0; c < nc; ++c) {
             int ijk[3];
             orc_cell_ijk(f, c, ijk);
-            double cx[4][2];
+            double cx[8][3];
             cell_corners(f, i, c, cx);
             const double *K = u + sidx(f, i, 0, 0, c);
             double acc[5 * 20];
             memset(acc, 0, sizeof(acc));
             /* volume: sum_q w_q grad_xi phi_m . adj(J) F(U_q) */
             for (int iq = 0; iq < nq; ++iq) {
-                double uq[5], J[2][2], A0[2], A1[2];
+                double uq[5], J[3][3], A[3][3];
                 eval_poly(f, K, (long)nb * nc, nc, vxi[iq], uq);
-                bilinear_jacobian(cx, vxi[iq], J);
-                adj_row(J, 0, A0);
-                adj_row(J, 1, A1);
-                double fx[5] = {0, 0, 0, 0, 0}, fy[5] = {0, 0, 0, 0, 0};
-                phys_flux(f, uq, 0, fx);
-                phys_flux(f, uq, 1, fy);
-                for (int m = 0; m < nb; ++m) {
-                    double d0 = orc_dphi(d, f->exps + 3 * m, vxi[iq], 0), d1 = orc_dphi(d, f->exps + 3 * m, vxi[iq], 1);
-                    for (int v = 0; v < nv; ++v) {
-                        double c0 = A0[0] * fx[v] + A0[1] * fy[v], c1 = A1[0] * fx[v] + A1[1] * fy[v];
-                        acc[v * nb + m] += vw[iq] * (d0 * c0 + d1 * c1);
+                map_jacobian(f, cx, vxi[iq], J);
+                for (int e = 0; e < d; ++e) adj_row(f, J, e, A[e]);
+                double F[3][5];
+                for (int a = 0; a < d; ++a) phys_flux(f, uq, a, F[a]);
+                for (int m = 0; m < nb; ++m)
+                    for (int e = 0; e < d; ++e) {
+                        double de = orc_dphi(d, f->exps + 3 * m, vxi[iq], e);
+                        for (int v = 0; v < nv; ++v) {
+                            double ce = 0.0;
+                            for (int a = 0; a < d; ++a) ce += A[e][a] * F[a][v];
+                            acc[v * nb + m] += vw[iq] * de * ce;
+                        }
                     }
-                }
             }
             /* faces: - sum_f w_f |N| Fhat(U-, U+; N/|N|) phi_m */
             for (int face = 0; face < nf; ++face) {
@@ -625,7 +669,12 @@ static void mapped_residual(const orc_forest *f, const double *u, const double *
                 int nijk[3] = {ijk[0], ijk[1], ijk[2]};
                 nijk[axis] += side;
                 int interior = nijk[axis] >= 0 && nijk[axis] < f->N;
-                int t = axis == 0 ? ijk[1] : ijk[0];
+                int t = 0, mul = 1;
+                for (int b = 0; b < d; ++b) {
+                    if (b == axis) continue;
+                    t += ijk[b] * mul;
+                    mul *= f->N;
+                }
                 const double *Kn;
                 long nsv, nsm;
                 if (interior) {
@@ -637,24 +686,31 @@ static void mapped_residual(const orc_forest *f, const double *u, const double *
                     nsv = (long)nb * nfc;
                     nsm = nfc;
                 }
-                for (int iq = 0; iq < q; ++iq) {
+                for (int iq = 0; iq < nfq; ++iq) {
                     double xo[3] = {0, 0, 0}, xn[3] = {0, 0, 0};
-                    xo[1 - axis] = xn[1 - axis] = gx[iq];
+                    int n = 0;
+                    for (int b = 0; b < d; ++b) {
+                        if (b == axis) continue;
+                        xo[b] = xn[b] = fxi[iq][n++];
+                    }
                     xo[axis] = side;
                     xn[axis] = -side;
-                    double J[2][2], N[2], um[5], up[5], fh[5] = {0, 0, 0, 0, 0};
-                    bilinear_jacobian(cx, xo, J);
-                    adj_row(J, axis, N);
-                    N[0] *= side;
-                    N[1] *= side;
-                    double len = sqrt(N[0] * N[0] + N[1] * N[1]);
-                    double n[2] = {N[0] / len, N[1] / len};
+                    double J[3][3], N[3], um[5], up[5], fh[5] = {0, 0, 0, 0, 0};
+                    map_jacobian(f, cx, xo, J);
+                    adj_row(f, J, axis, N);
+                    double len = 0.0;
+                    for (int a = 0; a < d; ++a) {
+                        N[a] *= side;
+                        len += N[a] * N[a];
+                    }
+                    len = sqrt(len);
+                    double nn[3] = {N[0] / len, N[1] / len, N[2] / len};
                     eval_poly(f, K, (long)nb * nc, nc, xo, um);
                     eval_poly(f, Kn, nsv, nsm, xn, up);
-                    num_flux_n(f, um, up, n, fh);
+                    num_flux_n(f, um, up, nn, fh);
                     for (int m = 0; m < nb; ++m) {
                         double ph = orc_phi(d, f->exps + 3 * m, xo);
-                        for (int v = 0; v < nv; ++v) acc[v * nb + m] -= gw[iq] * len * fh[v] * ph;
+                        for (int v = 0; v < nv; ++v) acc[v * nb + m] -= fw[iq] * len * fh[v] * ph;
                     }
                 }
             }
@@ -666,6 +722,8 @@ static void mapped_residual(const orc_forest *f, const double *u, const double *
         }
     free(vxi);
     free(vw);
+    free(fxi);
+    free(fw);
 }
 
 void orc_residual(const orc_forest *f, const double *u, const double *g, double *r)
@@ -1049,36 +1107,38 @@ double orc_max_rate(const orc_forest *f, const double *u)
  * sum_b (|u.n_b| + c) / h_b; scalar convection sum_b |vel.n_b| / h_b. */
 static double mapped_max_rate(const orc_forest *f, const double *u)
 {
-    int nc = orc_ncell(f), nb = f->nb;
+    int d = f->dim, nc = orc_ncell(f), nb = f->nb;
     double gx[8], gw[8];
     orc_gauss_legendre(f->q, gx, gw);
     double (*xi)[3] = malloc(sizeof(double) * 3 * 512);
     double *w = malloc(sizeof(double) * 512);
-    int nq = tensor_points(2, f->q, gx, gw, xi, w);
+    int nq = tensor_points(d, f->q, gx, gw, xi, w);
     double mx = 0.0;
     for (int i = 0; i < f->nleaves; ++i)
         for (int c = 0; c < nc; ++c) {
-            double cx[4][2], J[2][2];
+            double cx[8][3], J[3][3];
             cell_corners(f, i, c, cx);
-            double s[5] = {0, 0, 0, 0, 0}, area = 0.0;
+            double s[5] = {0, 0, 0, 0, 0}, vol = 0.0;
             for (int iq = 0; iq < nq; ++iq) {
-                double det = bilinear_jacobian(cx, xi[iq], J), uq[5];
+                double det = map_jacobian(f, cx, xi[iq], J), uq[5];
                 eval_poly(f, u + sidx(f, i, 0, 0, c), (long)nb * nc, nc, xi[iq], uq);
-                area += w[iq] * det;
+                vol += w[iq] * det;
                 for (int v = 0; v < f->nv; ++v) s[v] += w[iq] * det * uq[v];
             }
-            for (int v = 0; v < f->nv; ++v) s[v] /= area;
+            for (int v = 0; v < f->nv; ++v) s[v] /= vol;
             const double x0[3] = {0, 0, 0};
-            double det0 = bilinear_jacobian(cx, x0, J);
-            double cs = f->equation == ORC_EQ_ADVECTION ? 0.0 : sqrt(f->gamma * orc_pressure(2, f->gamma, s) / s[0]);
+            double det0 = map_jacobian(f, cx, x0, J);
+            double cs = f->equation == ORC_EQ_ADVECTION ? 0.0 : sqrt(f->gamma * orc_pressure(d, f->gamma, s) / s[0]);
             double rate = 0.0;
-            for (int b = 0; b < 2; ++b) {
-                double A[2];
-                adj_row(J, b, A);
-                double len = sqrt(A[0] * A[0] + A[1] * A[1]);
-                double h = 2.0 * det0 / len, n[2] = {A[0] / len, A[1] / len};
-                double un = f->equation == ORC_EQ_ADVECTION ? f->vel[0] * n[0] + f->vel[1] * n[1]
-                                                            : (s[1] * n[0] + s[2] * n[1]) / s[0];
+            for (int b = 0; b < d; ++b) {
+                double A[3];
+                adj_row(f, J, b, A);
+                double len = 0.0;
+                for (int a = 0; a < d; ++a) len += A[a] * A[a];
+                len = sqrt(len);
+                double h = 2.0 * det0 / len, un = 0.0;
+                for (int a = 0; a < d; ++a)
+                    un += (f->equation == ORC_EQ_ADVECTION ? f->vel[a] : s[1 + a] / s[0]) * A[a] / len;
                 rate += (fabs(un) + cs) / h;
             }
             if (rate > mx) mx = rate;
@@ -1103,13 +1163,13 @@ void orc_totals(const orc_forest *f, const double *u, double *totals)
         orc_gauss_legendre(f->q, gx, gw);
         double (*xi)[3] = malloc(sizeof(double) * 3 * 512);
         double *w = malloc(sizeof(double) * 512);
-        int nq = tensor_points(2, f->q, gx, gw, xi, w);
+        int nq = tensor_points(f->dim, f->q, gx, gw, xi, w);
         for (int i = 0; i < f->nleaves; ++i)
             for (int c = 0; c < nc; ++c) {
-                double cx[4][2], J[2][2], m[5] = {0, 0, 0, 0, 0};
+                double cx[8][3], J[3][3], m[5] = {0, 0, 0, 0, 0};
                 cell_corners(f, i, c, cx);
                 for (int iq = 0; iq < nq; ++iq) {
-                    double det = bilinear_jacobian(cx, xi[iq], J), uq[5];
+                    double det = map_jacobian(f, cx, xi[iq], J), uq[5];
                     eval_poly(f, u + sidx(f, i, 0, 0, c), (long)f->nb * nc, nc, xi[iq], uq);
                     for (int v = 0; v < f->nv; ++v) m[v] += w[iq] * det * uq[v];
                 }
@@ -1336,9 +1396,9 @@ void orc_errors(const orc_forest *f, const double *u, int kind, const double *pa
             for (int iq = 0; iq < nq; ++iq) {
                 double ex[5], uh[5];
                 if (mapped(f)) {
-                    double cx[4][2], Jm[2][2];
+                    double cx[8][3], Jm[3][3];
                     cell_corners(f, i, c, cx);
-                    J = bilinear_jacobian(cx, xi[iq], Jm);
+                    J = map_jacobian(f, cx, xi[iq], Jm);
                 }
                 analytic_local(f, i, c, kind, params, t, xi[iq], ex);
                 eval_poly(f, u + sidx(f, i, 0, 0, c), (long)f->nb * nc, nc, xi[iq], uh);

@@ -140,3 +140,77 @@ def test_vortex_order_on_a_smoothly_distorted_grid(p):
         errs.append(l2[0])
     order = np.log2(errs[0] / errs[1])
     assert order >= p + 1 - 0.2, (errs, order)
+
+
+def box_nodes3(roots, lo, hi):
+    nx, ny, nz = roots
+    g = np.zeros((nz + 1, ny + 1, nx + 1, 3))
+    g[..., 0] = np.linspace(lo[0], hi[0], nx + 1)[None, None, :]
+    g[..., 1] = np.linspace(lo[1], hi[1], ny + 1)[None, :, None]
+    g[..., 2] = np.linspace(lo[2], hi[2], nz + 1)[:, None, None]
+    return g
+
+
+def distorted_nodes3(roots, lo, hi, amp, seed=0):
+    """3-D box nodes moved by up to amp of a root edge, periodically."""
+    g = box_nodes3(roots, lo, hi)
+    nx, ny, nz = roots
+    h = min((hi[a] - lo[a]) / roots[a] for a in range(3))
+    rng = np.random.default_rng(seed)
+    d = amp * h * rng.uniform(-1, 1, (nz, ny, nx, 3))
+    for k in range(nz + 1):
+        for j in range(ny + 1):
+            for i in range(nx + 1):
+                g[k, j, i] += d[k % nz, j % ny, i % nx]
+    return g
+
+
+PRM3 = [2.0, 1.3, 2.7, 0.5, 0.3, 4.0, 4.0]  # the periodic seam of the vortex off every Gauss node
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_3d_box_nodes_reproduce_the_box_grid(p):
+    roots, lo, hi = (2, 2, 2), (0.0,) * 3, (4.0,) * 3
+    fa = O.Forest(3, p, 2, roots, lo, hi, (0, 0, 0), 2)
+    fm = O.Forest(3, p, 2, roots, lo, hi, (0, 0, 0), 2)
+    fm.set_nodes(box_nodes3(roots, lo, hi))
+    for f in (fa, fm):
+        _refine(f, 0)
+    ua, um = fa.project_ic(O.IC_VORTEX, PRM3), fm.project_ic(O.IC_VORTEX, PRM3)
+    np.testing.assert_allclose(um, ua, atol=1e-14)
+    for _ in range(2):
+        assert fm.step(um, 0.1) == pytest.approx(fa.step(ua, 0.1), rel=1e-14)
+    assert np.abs(um - ua).max() <= 1e-13 * np.abs(ua).max()
+
+
+@pytest.mark.parametrize("p", [1, 2])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_3d_free_stream_on_distorted_roots_with_hanging_faces(p, bc):
+    roots, lo, hi = (2, 2, 2), (0.0,) * 3, (2.0,) * 3
+    f = O.Forest(3, p, 2, roots, lo, hi, (bc,) * 3, 3)
+    f.set_nodes(distorted_nodes3(roots, lo, hi, 0.15, seed=p + 3 * bc))
+    _refine(f, 0)
+    _refine(f, 1)
+    u = f.project_ic(O.IC_UNIFORM, [1.0, 0.3, -0.2, 0.1, 1.0])
+    assert np.abs(u[:, :, 1:]).max() < 1e-13
+    assert np.abs(f.residual(u)).max() < 1e-11
+
+
+def test_3d_conservation_on_distorted_conforming_roots():
+    roots, lo, hi = (2, 2, 2), (0.0,) * 3, (4.0,) * 3
+    f = O.Forest(3, 1, 2, roots, lo, hi, (0, 0, 0), 1)
+    f.set_nodes(distorted_nodes3(roots, lo, hi, 0.2, seed=5))
+    u = f.project_ic(O.IC_VORTEX, PRM3)
+    t0 = f.totals(u)
+    for _ in range(3):
+        f.step(u, 0.1)
+    np.testing.assert_allclose(f.totals(u), t0, rtol=1e-13, atol=1e-12)
+
+
+def test_3d_folded_root_is_refused():
+    roots, lo, hi = (2, 2, 2), (0.0,) * 3, (2.0,) * 3
+    g = box_nodes3(roots, lo, hi)
+    g[1, 1, 1] = [1.9, 1.9, 1.9]  # the centre node pushed through the far corner
+    f = O.Forest(3, 1, 2, roots, lo, hi, (1, 1, 1), 1)
+    with pytest.raises(ValueError):
+        f.set_nodes(g)
