@@ -128,26 +128,27 @@ int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out);
  * pools do not admit such forests. */
 int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes);
 
-/* Sec. 3.3, Eq. 6: 2-D root blocks as bilinear images of the reference
- * square.  xy (host, (roots[0] + 1) * (roots[1] + 1) points (x, y), x
- * fastest) are the root grid nodes: root (rx, ry) has the corners node(rx,
- * ry), node(rx + 1, ry), node(rx, ry + 1), node(rx + 1, ry + 1).  On a
- * periodic axis the last node column (row) must be the first moved by the
- * period.  Every root must be a convex quadrilateral with its nodes
- * counter-clockwise.  A leaf's cells are the images of equal squares of its
- * root's reference square; the residual carries the map's Jacobian at every
- * quadrature point (the contravariant volume flux, face normals and lengths
- * from the adjugate of the Jacobian) and the cell's full mass matrix.  The
- * guard cells and the inheritance on regrid stay the reference-space
- * operators of Eq. 11-17.  The steps of such a forest run the fill and
- * the residual fused with the stage update as separate launches; the CFL
- * rate takes the cell means over the physical cells and, per reference
- * axis, the face normal and width 2 det(J) / |row of adj(J)| at the cell
- * centre; the totals integrate over the physical cells; the indicator keeps
- * the reference cell means (mode 0).  EUNSUPPORTED in 3-D, with rotated
- * frames, the conservative mode, the limiter, the diffusion equation or
- * FP32; EINVAL for nodes that are not finite, a root that is not convex, or
- * unmatched periodic nodes.  Pools do not admit such forests. */
+/* Sec. 3.3, Eq. 6: root blocks as bilinear (3-D: trilinear) images of the
+ * reference square (cube).  xy (host, (roots[0] + 1) * (roots[1] + 1)
+ * [* (roots[2] + 1)] points of dim coordinates, x fastest) are the root
+ * grid nodes: root (rx, ry[, rz]) has the corner nodes (rx + bx, ry + by[,
+ * rz + bz]), b in {0,1}^dim.  On a periodic axis the last node layer must
+ * be the first one moved by the period.  Every root must have a positive
+ * Jacobian at its corners.  A leaf's cells are the images of equal squares
+ * (cubes) of its root's reference box; the residual carries the map's
+ * Jacobian at every quadrature point (the contravariant volume flux, face
+ * normals and areas from the adjugate of the Jacobian) and the cell's full
+ * mass matrix.  The guard cells and the inheritance on regrid stay the
+ * reference-space operators of Eq. 11-17.  The steps of such a forest run
+ * the fill and the residual fused with the stage update as separate
+ * launches; the CFL rate takes the cell means over the physical cells and,
+ * per reference axis, the face normal and width 2 det(J) / |row of adj(J)|
+ * at the cell centre; the totals integrate over the physical cells; the
+ * indicator keeps the reference cell means (mode 0).  EUNSUPPORTED for 3-D
+ * degree 3, with rotated frames, the conservative mode, the limiter, the
+ * diffusion equation or FP32; EINVAL for nodes that are not finite, a root
+ * with a non-positive corner Jacobian, or unmatched periodic nodes.  Pools
+ * do not admit such forests. */
 int dgamr_set_root_nodes(dgamr_forest *f, const double *xy);
 int dgamr_destroy_forest(dgamr_forest *f);
 

@@ -180,15 +180,26 @@ dgk::MappedArgs mapped_args(const dgamr_forest *f, const double *us, const doubl
     return m;
 }
 
-// the degree of a 2-D forest as a compile-time constant
+// dimension and degree of a mapped forest as compile-time constants (the
+// built cases: 2-D any degree, 3-D degree <= 2)
 template <class Fn>
-int dispatch_2d(const dgamr_forest *f, Fn &&fn)
+int dispatch_mapped(const dgamr_forest *f, Fn &&fn)
 {
-    switch (f->topo.desc().degree) {
-    case 0: return fn(std::integral_constant<int, 0>{});
-    case 1: return fn(std::integral_constant<int, 1>{});
-    case 2: return fn(std::integral_constant<int, 2>{});
-    default: return fn(std::integral_constant<int, 3>{});
+    using std::integral_constant;
+    const int p = f->topo.desc().degree;
+    if (f->topo.dim() == 3) {
+        switch (p) {
+        case 0: return fn(integral_constant<int, 3>{}, integral_constant<int, 0>{});
+        case 1: return fn(integral_constant<int, 3>{}, integral_constant<int, 1>{});
+        case 2: return fn(integral_constant<int, 3>{}, integral_constant<int, 2>{});
+        default: return fail(DGAMR_EUNSUPPORTED, "trilinear root blocks are built for degree <= 2");
+        }
+    }
+    switch (p) {
+    case 0: return fn(integral_constant<int, 2>{}, integral_constant<int, 0>{});
+    case 1: return fn(integral_constant<int, 2>{}, integral_constant<int, 1>{});
+    case 2: return fn(integral_constant<int, 2>{}, integral_constant<int, 2>{});
+    default: return fn(integral_constant<int, 2>{}, integral_constant<int, 3>{});
     }
 }
 
@@ -202,8 +213,8 @@ int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, cons
     if (f->topo.mapped()) {
         dgk::MappedArgs a = mapped_args(f, u, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0);
         const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
-        CHECK(dispatch_2d(f, [&](auto P) -> int {
-            HIP_TRY(dgk::launch_mapped_rate<P>(a, eq, n, block, w.leafmax, s));
+        CHECK(dispatch_mapped(f, [&](auto D, auto P) -> int {
+            HIP_TRY((dgk::launch_mapped_rate<D, P>(a, eq, n, block, w.leafmax, s)));
             return DGAMR_OK;
         }));
     } else if (f->topo.advection())
@@ -436,8 +447,8 @@ int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, voi
     if (f->topo.mapped()) {
         dgk::MappedArgs a = mapped_args(f, u, nullptr, guard, static_cast<double *>(r), nullptr, 0.0, 1.0);
         const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
-        return dispatch_2d(f, [&](auto P) -> int {
-            HIP_TRY(dgk::launch_mapped<P>(a, eq, dgk::OUT_RES64, stream));
+        return dispatch_mapped(f, [&](auto D, auto P) -> int {
+            HIP_TRY((dgk::launch_mapped<D, P>(a, eq, dgk::OUT_RES64, stream)));
             return DGAMR_OK;
         });
     }
@@ -505,8 +516,8 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         for (int s = 0; s < 3; ++s) {
             CHECK(launch_fill(f, us, w.guard, false, stream));
             dgk::MappedArgs a = mapped_args(f, us, u, w.guard, outs[s], dt_dev, A[s], B[s]);
-            CHECK(dispatch_2d(f, [&](auto P) -> int {
-                HIP_TRY(dgk::launch_mapped<P>(a, eq, dgk::OUT_RK, stream));
+            CHECK(dispatch_mapped(f, [&](auto D, auto P) -> int {
+                HIP_TRY((dgk::launch_mapped<D, P>(a, eq, dgk::OUT_RK, stream)));
                 return DGAMR_OK;
             }));
             us = outs[s];
@@ -765,12 +776,14 @@ int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev,
     if (f->topo.mapped()) {
         dgk::MappedArgs a = mapped_args(f, u, nullptr, nullptr, nullptr, nullptr, 0.0, 1.0);
         const bool adv = f->topo.advection();
-        CHECK(dispatch_2d(f, [&](auto P) -> int {
-            HIP_TRY(dgk::launch_mapped_totals<P>(a, adv ? dgk::EQ_ADVECTION : dgk::EQ_EULER, n, bp, w.part, stream));
+        CHECK(dispatch_mapped(f, [&](auto D, auto P) -> int {
+            HIP_TRY((dgk::launch_mapped_totals<D, P>(a, adv ? dgk::EQ_ADVECTION : dgk::EQ_EULER, n, bp, w.part, stream)));
             return DGAMR_OK;
         }));
         if (adv) hipLaunchKernelGGL(dgk::k_totals_final<1>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
-        else hipLaunchKernelGGL(dgk::k_totals_final<4>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
+        else if (f->topo.dim() == 2)
+            hipLaunchKernelGGL(dgk::k_totals_final<4>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
+        else hipLaunchKernelGGL(dgk::k_totals_final<5>, dim3(1), dim3(256), 0, stream, w.part, n, totals_dev);
         HIP_TRY(hipGetLastError());
         return DGAMR_OK;
     }
@@ -853,8 +866,8 @@ int dgamr_project_ic(dgamr_forest *f, int kind, const double *params, double t, 
     long total = long(f->topo.n()) * ncell_of(f);
     if (total == 0) return DGAMR_OK;
     if (f->topo.mapped())
-        return dispatch_2d(f, [&](auto P) -> int {
-            HIP_TRY(dgk::launch_mapped_ic<P>(u, f->d_geo, d.n_cell, total, kind, prm, t, d.gamma, nv_of(f), stream));
+        return dispatch_mapped(f, [&](auto D, auto P) -> int {
+            HIP_TRY((dgk::launch_mapped_ic<D, P>(u, f->d_geo, d.n_cell, total, kind, prm, t, d.gamma, nv_of(f), stream)));
             return DGAMR_OK;
         });
     return dispatch(f->topo.dim(), d.degree, [&](auto D, auto P) -> int {

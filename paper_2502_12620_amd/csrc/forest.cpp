@@ -192,56 +192,70 @@ int Forest::set_frames(const int32_t *codes, std::string &err)
 
 int Forest::set_nodes(const double *xy, std::string &err)
 {
-    if (desc_.dim != 2) {
-        err = "bilinear root blocks are built in 2-D";
+    const int d = desc_.dim;
+    if (d == 3 && desc_.degree > 2) {
+        err = "trilinear root blocks are built for degree <= 2";
         return DGAMR_EUNSUPPORTED;
     }
     if (rotated_ || desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.limiter != DGAMR_LIMITER_NONE ||
         desc_.equation == DGAMR_EQ_DIFFUSION) {
-        err = "bilinear root blocks are built for aligned frames, the paper hanging mode, no limiter, Euler and "
-              "scalar convection";
+        err = "bilinear / trilinear root blocks are built for aligned frames, the paper hanging mode, no limiter, "
+              "Euler and scalar convection";
         return DGAMR_EUNSUPPORTED;
     }
-    const int nx = desc_.roots[0] + 1, ny = desc_.roots[1] + 1;
-    const double L[2] = {desc_.hi[0] - desc_.lo[0], desc_.hi[1] - desc_.lo[1]};
-    for (int k = 0; k < 2 * nx * ny; ++k)
+    const int n[3] = {desc_.roots[0] + 1, desc_.roots[1] + 1, d == 3 ? desc_.roots[2] + 1 : 1};
+    const long total = long(n[0]) * n[1] * n[2];
+    for (long k = 0; k < d * total; ++k)
         if (!std::isfinite(xy[k])) {
             err = "nodes must be finite";
             return DGAMR_EINVAL;
         }
-    // on a periodic axis the last node column (row) is the first moved by the period
-    if (desc_.bc[0] == DGAMR_BC_PERIODIC)
-        for (int j = 0; j < ny; ++j) {
-            const double *a = xy + 2 * (j * nx), *b = xy + 2 * (j * nx + nx - 1);
-            if (std::fabs(b[0] - a[0] - L[0]) > 1e-12 * L[0] || std::fabs(b[1] - a[1]) > 1e-12 * L[1]) {
-                err = "periodic x: node column roots_x must be node column 0 moved by the period";
-                return DGAMR_EINVAL;
-            }
-        }
-    if (desc_.bc[1] == DGAMR_BC_PERIODIC)
-        for (int i = 0; i < nx; ++i) {
-            const double *a = xy + 2 * i, *b = xy + 2 * ((ny - 1) * nx + i);
-            if (std::fabs(b[1] - a[1] - L[1]) > 1e-12 * L[1] || std::fabs(b[0] - a[0]) > 1e-12 * L[0]) {
-                err = "periodic y: node row roots_y must be node row 0 moved by the period";
-                return DGAMR_EINVAL;
-            }
-        }
-    // every root a convex quadrilateral: positive Jacobian at its corners
-    for (int ry = 0; ry + 1 < ny; ++ry)
-        for (int rx = 0; rx + 1 < nx; ++rx) {
-            const double *c[4] = {xy + 2 * (ry * nx + rx), xy + 2 * (ry * nx + rx + 1), xy + 2 * ((ry + 1) * nx + rx),
-                                  xy + 2 * ((ry + 1) * nx + rx + 1)};
-            static const int e[4][2] = {{1, 2}, {3, 0}, {0, 3}, {2, 1}};
-            for (int k = 0; k < 4; ++k) {
-                const double ax = c[e[k][0]][0] - c[k][0], ay = c[e[k][0]][1] - c[k][1];
-                const double bx = c[e[k][1]][0] - c[k][0], by = c[e[k][1]][1] - c[k][1];
-                if (ax * by - ay * bx <= 0.0) {
-                    err = "every root must be a convex quadrilateral with its nodes counter-clockwise";
+    auto node = [&](int i, int j, int k) { return xy + long(d) * ((long(k) * n[1] + j) * n[0] + i); };
+    // on a periodic axis the last node layer is the first moved by the period
+    for (int a = 0; a < d; ++a) {
+        if (desc_.bc[a] != DGAMR_BC_PERIODIC) continue;
+        const double L = desc_.hi[a] - desc_.lo[a];
+        for (long id = 0; id < total; ++id) {
+            int idx[3] = {int(id % n[0]), int((id / n[0]) % n[1]), int(id / (long(n[0]) * n[1]))};
+            if (idx[a] != 0) continue;
+            int last[3] = {idx[0], idx[1], idx[2]};
+            last[a] = n[a] - 1;
+            const double *p0 = node(idx[0], idx[1], idx[2]), *p1 = node(last[0], last[1], last[2]);
+            for (int b = 0; b < d; ++b)
+                if (std::fabs(p1[b] - p0[b] - (b == a ? L : 0.0)) > 1e-12 * (desc_.hi[b] - desc_.lo[b])) {
+                    err = "periodic axis: the last node layer must be the first one moved by the period";
                     return DGAMR_EINVAL;
                 }
+        }
+    }
+    // every root with a positive Jacobian at its corners: the d edges
+    // leaving each corner, oriented along the reference axes
+    const int nr = desc_.roots[0] * desc_.roots[1] * (d == 3 ? desc_.roots[2] : 1);
+    for (int t = 0; t < nr; ++t) {
+        const int r[3] = {t % desc_.roots[0], (t / desc_.roots[0]) % desc_.roots[1],
+                          d == 3 ? t / (desc_.roots[0] * desc_.roots[1]) : 0};
+        for (int b = 0; b < (1 << d); ++b) {
+            double E[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+            const int c0[3] = {r[0] + (b & 1), r[1] + ((b >> 1) & 1), r[2] + ((b >> 2) & 1)};
+            const double *pc = node(c0[0], c0[1], d == 3 ? c0[2] : 0);
+            for (int e = 0; e < d; ++e) {
+                int c1[3] = {c0[0], c0[1], c0[2]};
+                const bool up = !((b >> e) & 1);
+                c1[e] += up ? 1 : -1;
+                const double *pe = node(c1[0], c1[1], d == 3 ? c1[2] : 0);
+                for (int a = 0; a < d; ++a) E[a][e] = (up ? 1.0 : -1.0) * (pe[a] - pc[a]);
+            }
+            const double det = d == 2 ? E[0][0] * E[1][1] - E[0][1] * E[1][0]
+                                      : E[0][0] * (E[1][1] * E[2][2] - E[1][2] * E[2][1]) -
+                                            E[0][1] * (E[1][0] * E[2][2] - E[1][2] * E[2][0]) +
+                                            E[0][2] * (E[1][0] * E[2][1] - E[1][1] * E[2][0]);
+            if (!(det > 0.0)) {
+                err = "every root must have a positive Jacobian at its corners (nodes in the order of the axes)";
+                return DGAMR_EINVAL;
             }
         }
-    nodes_.assign(xy, xy + 2 * nx * ny);
+    }
+    nodes_.assign(xy, xy + d * total);
     return DGAMR_OK;
 }
 
@@ -514,18 +528,25 @@ std::vector<LeafGeo> Forest::geometry() const
         }
         G.level = k.level;
         G.pad = 0;
-        for (int b = 0; b < 4; ++b) G.node[b][0] = G.node[b][1] = 0.0;
+        for (int b = 0; b < 8; ++b) G.node[b][0] = G.node[b][1] = G.node[b][2] = 0.0;
         if (mapped()) {
-            // the leaf's corners: the root's bilinear map at the leaf's
-            // corners in the root's unit square
-            const int nx = desc_.roots[0] + 1;
-            const double *n00 = nodes_.data() + 2 * (r[1] * nx + r[0]), *n10 = n00 + 2, *n01 = n00 + 2 * nx,
-                         *n11 = n01 + 2;
-            for (int b = 0; b < 4; ++b) {
-                const double s0 = double(k.idx[0] + (b & 1)) / span, s1 = double(k.idx[1] + (b >> 1)) / span;
-                for (int a = 0; a < 2; ++a)
-                    G.node[b][a] = (1.0 - s0) * (1.0 - s1) * n00[a] + s0 * (1.0 - s1) * n10[a] +
-                                   (1.0 - s0) * s1 * n01[a] + s0 * s1 * n11[a];
+            // the leaf's corners: the root's multilinear map at the leaf's
+            // corners in the root's unit box
+            const int nx = desc_.roots[0] + 1, ny = desc_.roots[1] + 1;
+            for (int b = 0; b < (1 << d); ++b) {
+                double s[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < d; ++a) s[a] = double(k.idx[a] + ((b >> a) & 1)) / span;
+                for (int nn = 0; nn < (1 << d); ++nn) {
+                    double w = 1.0;
+                    int id[3] = {r[0], r[1], r[2]};
+                    for (int a = 0; a < d; ++a) {
+                        const int bit = (nn >> a) & 1;
+                        w *= bit ? s[a] : 1.0 - s[a];
+                        id[a] += bit;
+                    }
+                    const double *xy = nodes_.data() + long(d) * ((long(d == 3 ? id[2] : 0) * ny + id[1]) * nx + id[0]);
+                    for (int a = 0; a < d; ++a) G.node[b][a] += w * xy[a];
+                }
             }
         }
         for (int gg = 0; gg < 3; ++gg)

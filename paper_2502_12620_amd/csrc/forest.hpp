@@ -45,10 +45,10 @@ struct LeafGeo {
     int level;
     int pad;
     signed char q[12]; // the root's frame Q (q[3 g + l]): global vector = Q local
-    // bilinear roots (Forest::set_nodes): the leaf's physical corners at the
-    // reference corners (-1,-1), (1,-1), (-1,1), (1,1), (x, y) each; zero
-    // otherwise
-    double node[4][2];
+    // bilinear / trilinear roots (Forest::set_nodes): the leaf's physical
+    // corners, corner b at reference coordinate -1 or +1 along axis a by bit
+    // a of b; zero otherwise
+    double node[8][3];
 };
 
 // Guard cell across a face between roots of different frames (Sec. 3.5:
@@ -105,8 +105,8 @@ class Forest {
     // rotation codes of the root frames (one per tree), before any refinement
     int set_frames(const int32_t *codes, std::string &err);
     bool rotated() const { return rotated_; }
-    // Sec. 3.3, Eq. 6: 2-D roots as bilinear images of the reference square,
-    // from the (roots_x + 1) x (roots_y + 1) grid nodes (x, y), x fastest
+    // Sec. 3.3, Eq. 6: roots as bilinear (3-D: trilinear) images of the
+    // reference square (cube), from the root grid nodes, x fastest
     int set_nodes(const double *xy, std::string &err);
     bool mapped() const { return !nodes_.empty(); }
     // steps run the guard fill, the residual and the stage update unfused

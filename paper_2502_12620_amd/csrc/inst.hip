@@ -267,55 +267,58 @@ hipError_t launch_ipdg(const IpdgArgs &a, int om, hipStream_t s)
     return hipGetLastError();
 }
 template hipError_t launch_ipdg<DG_D, DG_P>(const IpdgArgs &, int, hipStream_t);
-#if DG_D == 2
-template <int P>
+#if DG_D == 2 || DG_P <= 2
+template <int D, int P>
 hipError_t launch_mapped(const MappedArgs &a, int eq, int om, hipStream_t s)
 {
     if (a.ncell_total == 0) return hipSuccess;
     const dim3 grid(unsigned((a.ncell_total + 127) / 128)), block(128);
     if (eq == EQ_ADVECTION) {
-        if (om == OUT_RES64) hipLaunchKernelGGL((k_mapped<P, EQ_ADVECTION, OUT_RES64>), grid, block, 0, s, a);
-        else if (om == OUT_RK) hipLaunchKernelGGL((k_mapped<P, EQ_ADVECTION, OUT_RK>), grid, block, 0, s, a);
+        if (om == OUT_RES64) hipLaunchKernelGGL((k_mapped<D, P, EQ_ADVECTION, OUT_RES64>), grid, block, 0, s, a);
+        else if (om == OUT_RK) hipLaunchKernelGGL((k_mapped<D, P, EQ_ADVECTION, OUT_RK>), grid, block, 0, s, a);
         else return hipErrorInvalidValue;
     } else {
-        if (om == OUT_RES64) hipLaunchKernelGGL((k_mapped<P, EQ_EULER, OUT_RES64>), grid, block, 0, s, a);
-        else if (om == OUT_RK) hipLaunchKernelGGL((k_mapped<P, EQ_EULER, OUT_RK>), grid, block, 0, s, a);
+        if (om == OUT_RES64) hipLaunchKernelGGL((k_mapped<D, P, EQ_EULER, OUT_RES64>), grid, block, 0, s, a);
+        else if (om == OUT_RK) hipLaunchKernelGGL((k_mapped<D, P, EQ_EULER, OUT_RK>), grid, block, 0, s, a);
         else return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
-template <int P>
+template <int D, int P>
 hipError_t launch_mapped_rate(const MappedArgs &a, int eq, int nleaves, int block, double *leaf_max, hipStream_t s)
 {
     if (eq == EQ_ADVECTION)
-        hipLaunchKernelGGL((k_mapped_rate<P, EQ_ADVECTION>), dim3(nleaves), dim3(block), 0, s, a, leaf_max);
+        hipLaunchKernelGGL((k_mapped_rate<D, P, EQ_ADVECTION>), dim3(nleaves), dim3(block), 0, s, a, leaf_max);
     else
-        hipLaunchKernelGGL((k_mapped_rate<P, EQ_EULER>), dim3(nleaves), dim3(block), 0, s, a, leaf_max);
+        hipLaunchKernelGGL((k_mapped_rate<D, P, EQ_EULER>), dim3(nleaves), dim3(block), 0, s, a, leaf_max);
     return hipGetLastError();
 }
-template <int P>
+template <int D, int P>
 hipError_t launch_mapped_totals(const MappedArgs &a, int eq, int nleaves, int block, double *part, hipStream_t s)
 {
     if (eq == EQ_ADVECTION)
-        hipLaunchKernelGGL((k_mapped_totals_leaf<P, EQ_ADVECTION>), dim3(nleaves), dim3(block), 0, s, a, part);
+        hipLaunchKernelGGL((k_mapped_totals_leaf<D, P, EQ_ADVECTION>), dim3(nleaves), dim3(block), 0, s, a, part);
     else
-        hipLaunchKernelGGL((k_mapped_totals_leaf<P, EQ_EULER>), dim3(nleaves), dim3(block), 0, s, a, part);
+        hipLaunchKernelGGL((k_mapped_totals_leaf<D, P, EQ_EULER>), dim3(nleaves), dim3(block), 0, s, a, part);
     return hipGetLastError();
 }
-template <int P>
+template <int D, int P>
 hipError_t launch_mapped_ic(double *u, const LeafGeo *geo, int N, long total, int kind, const IcParams &prm,
                             double t, double gamma, int nv, hipStream_t s)
 {
     const dim3 grid(unsigned((total + 127) / 128)), block(128);
-    if (nv == 1) hipLaunchKernelGGL((k_mapped_project_ic<P, 1>), grid, block, 0, s, u, geo, N, total, kind, prm, t, gamma);
-    else hipLaunchKernelGGL((k_mapped_project_ic<P, 4>), grid, block, 0, s, u, geo, N, total, kind, prm, t, gamma);
+    if (nv == 1)
+        hipLaunchKernelGGL((k_mapped_project_ic<D, P, 1>), grid, block, 0, s, u, geo, N, total, kind, prm, t, gamma);
+    else
+        hipLaunchKernelGGL((k_mapped_project_ic<D, P, D + 2>), grid, block, 0, s, u, geo, N, total, kind, prm, t,
+                           gamma);
     return hipGetLastError();
 }
-template hipError_t launch_mapped<DG_P>(const MappedArgs &, int, int, hipStream_t);
-template hipError_t launch_mapped_rate<DG_P>(const MappedArgs &, int, int, int, double *, hipStream_t);
-template hipError_t launch_mapped_totals<DG_P>(const MappedArgs &, int, int, int, double *, hipStream_t);
-template hipError_t launch_mapped_ic<DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double, double,
-                                           int, hipStream_t);
+template hipError_t launch_mapped<DG_D, DG_P>(const MappedArgs &, int, int, hipStream_t);
+template hipError_t launch_mapped_rate<DG_D, DG_P>(const MappedArgs &, int, int, int, double *, hipStream_t);
+template hipError_t launch_mapped_totals<DG_D, DG_P>(const MappedArgs &, int, int, int, double *, hipStream_t);
+template hipError_t launch_mapped_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,
+                                                 double, int, hipStream_t);
 #endif
 #elif DG_PART == 1
 template hipError_t launch_stage_cell<DG_D, DG_P, double, EQ_EULER>(const StageArgs &, int, int, bool,

@@ -1,19 +1,20 @@
-// Bilinear root blocks (Sec. 3.3, Eq. 6), 2-D: a root is the bilinear image
-// of the reference square spanned by its four corner nodes, and every cell
-// of its leaves the bilinear image of the cell's reference square with the
-// images of its corners as nodes.  The weak form (Sec. 2, Eq. 3-4) then
-// carries the map's Jacobian J = dx/dxi at every quadrature point:
+// Bilinear (3-D: trilinear) root blocks (Sec. 3.3, Eq. 6): a root is the
+// multilinear image of the reference square (cube) spanned by its corner
+// nodes, and every cell of its leaves the multilinear image of the cell's
+// reference box with the images of its corners as nodes.  The weak form
+// (Sec. 2, Eq. 3-4) then carries the map's Jacobian J = dx/dxi at every
+// quadrature point:
 //   volume  sum_q w_q grad_xi phi_m . adj(J) F(U_q)   (adj(J) = det(J) J^-1:
 //           the contravariant flux),
 //   faces   - sum_f w_f |N| Fhat(U-, U+; N / |N|) phi_m with N = side * (row
 //           a of adj(J)) on the face xi_a = side (the outward normal scaled
 //           by the face Jacobian),
 // and the residual is M^-1 of that with the full mass matrix M_mn =
-// sum_q w_q det(J_q) phi_m phi_n (exact with p+1 points per axis: det(J) is
-// bilinear), solved per cell by Cholesky.  The neighbour across a block
-// face is the guard cell (coefficients from the fill kernel: copy, split,
-// combine in the reference space, Eq. 15-17); its trace is taken at the
-// shared reference face point.
+// sum_q w_q det(J_q) phi_m phi_n (exact with p+1 points per axis: det(J)
+// has degree d-1 per axis), solved per cell by Cholesky.  The neighbour
+// across a block face is the guard cell (coefficients from the fill kernel:
+// copy, split, combine in the reference space, Eq. 15-17); its trace is
+// taken at the shared reference face point.
 //
 // One thread per cell; these forests step through the fill, this kernel
 // and the stage update as separate launches.
@@ -24,76 +25,149 @@
 
 namespace dgk {
 
-// corners of cell (i, j) of a leaf: the leaf's bilinear map at the cell's
-// corners in the leaf's unit square; (xi, eta) = (-1,-1), (1,-1), (-1,1), (1,1)
-__device__ __forceinline__ void mapped_cell_corners(const LeafGeo &G, int i, int j, int N, double cx[4][2])
+// corners of cell ijk of a leaf: the leaf's multilinear map at the cell's
+// corners in the leaf's unit box; corner b lies at reference coordinate
+// -1 or +1 along axis a by bit a of b
+template <int D>
+__device__ __forceinline__ void mapped_cell_corners(const LeafGeo &G, const int *ijk, int N, double (&cx)[1 << D][3])
 {
     const double inv = 1.0 / N;
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-        const double s0 = (i + (b & 1)) * inv, s1 = (j + (b >> 1)) * inv;
+    for (int b = 0; b < (1 << D); ++b) {
+        double s[3];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-            cx[b][a] = (1.0 - s0) * (1.0 - s1) * G.node[0][a] + s0 * (1.0 - s1) * G.node[1][a] +
-                       (1.0 - s0) * s1 * G.node[2][a] + s0 * s1 * G.node[3][a];
+        for (int a = 0; a < D; ++a) s[a] = (ijk[a] + ((b >> a) & 1)) * inv;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) cx[b][a] = 0.0;
+#pragma unroll
+        for (int n = 0; n < (1 << D); ++n) {
+            double w = 1.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) w *= ((n >> a) & 1) ? s[a] : 1.0 - s[a];
+#pragma unroll
+            for (int a = 0; a < D; ++a) cx[b][a] = fma(w, G.node[n][a], cx[b][a]);
+        }
     }
 }
 
-// J[a][b] = dx_a / dxi_b of the bilinear cell map at (e, h); returns det J
-__device__ __forceinline__ double mapped_jacobian(const double cx[4][2], double e, double h, double J[2][2])
+// J[a][e] = dx_a / dxi_e of the multilinear cell map at xi; returns det J
+template <int D>
+__device__ __forceinline__ double mapped_jacobian(const double (&cx)[1 << D][3], const double *xi, double (&J)[3][3])
 {
 #pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        J[a][0] = 0.25 * ((1.0 - h) * (cx[1][a] - cx[0][a]) + (1.0 + h) * (cx[3][a] - cx[2][a]));
-        J[a][1] = 0.25 * ((1.0 - e) * (cx[2][a] - cx[0][a]) + (1.0 + e) * (cx[3][a] - cx[1][a]));
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int e = 0; e < 3; ++e) J[a][e] = 0.0;
+#pragma unroll
+    for (int b = 0; b < (1 << D); ++b)
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+            double w = ((b >> e) & 1) ? 0.5 : -0.5;
+#pragma unroll
+            for (int c = 0; c < D; ++c)
+                if (c != e) w *= 0.5 * (1.0 + (((b >> c) & 1) ? xi[c] : -xi[c]));
+#pragma unroll
+            for (int a = 0; a < D; ++a) J[a][e] = fma(w, cx[b][a], J[a][e]);
+        }
+    if constexpr (D == 2) return J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) - J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+           J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+// row e of adj(J) = det(J) J^-1: the contravariant direction of xi_e
+template <int D>
+__device__ __forceinline__ void mapped_adj_row(const double (&J)[3][3], int e, double *r)
+{
+    if constexpr (D == 2) {
+        r[0] = e == 0 ? J[1][1] : -J[1][0];
+        r[1] = e == 0 ? -J[0][1] : J[0][0];
+        r[2] = 0.0;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int a1 = (a + 1) % 3, a2 = (a + 2) % 3, e1 = (e + 1) % 3, e2 = (e + 2) % 3;
+            r[a] = J[a1][e1] * J[a2][e2] - J[a1][e2] * J[a2][e1];
+        }
     }
-    return J[0][0] * J[1][1] - J[0][1] * J[1][0];
 }
 
-// physical point of the bilinear cell map at (e, h)
-__device__ __forceinline__ void mapped_point(const double cx[4][2], double e, double h, double *x)
+// physical point of the multilinear cell map at xi
+template <int D>
+__device__ __forceinline__ void mapped_point(const double (&cx)[1 << D][3], const double *xi, double *x)
 {
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
-        x[a] = 0.25 * ((1.0 - e) * (1.0 - h) * cx[0][a] + (1.0 + e) * (1.0 - h) * cx[1][a] +
-                       (1.0 - e) * (1.0 + h) * cx[2][a] + (1.0 + e) * (1.0 + h) * cx[3][a]);
-    x[2] = 0.0;
+    for (int a = 0; a < 3; ++a) x[a] = 0.0;
+#pragma unroll
+    for (int b = 0; b < (1 << D); ++b) {
+        double w = 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) w *= 0.5 * (1.0 + (((b >> a) & 1) ? xi[a] : -xi[a]));
+#pragma unroll
+        for (int a = 0; a < D; ++a) x[a] = fma(w, cx[b][a], x[a]);
+    }
 }
 
-// numerical flux along the outward unit normal (n0, n1) (Eq. 5): Rusanov
-// with alpha = max(|u.n| + c) over both traces; for scalar convection the
-// same formula with alpha = |vel.n| (upwind)
-template <int EQ>
-__device__ __forceinline__ void mapped_flux(const MappedArgs &g, const double *UL, const double *UR, double n0,
-                                            double n1, double *Phi)
+// reference coordinates of volume point q (x fastest)
+template <int D, int P>
+__device__ __forceinline__ void mapped_vpoint(int q, double *xi)
+{
+    constexpr int Q = P + 1;
+    xi[0] = gl_x(Q, q % Q);
+    xi[1] = gl_x(Q, (q / Q) % Q);
+    xi[2] = D == 3 ? gl_x(Q, q / (Q * Q)) : 0.0;
+}
+
+// numerical flux along the outward unit normal n (Eq. 5): Rusanov with
+// alpha = max(|u.n| + c) over both traces; for scalar convection the same
+// formula with alpha = |vel.n| (upwind)
+template <int D, int EQ>
+__device__ __forceinline__ void mapped_flux(const MappedArgs &g, const double *UL, const double *UR, const double *n,
+                                            double *Phi)
 {
     if constexpr (EQ == EQ_ADVECTION) {
-        const double vn = g.vel[0] * n0 + g.vel[1] * n1;
+        double vn = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) vn = fma(g.vel[a], n[a], vn);
         Phi[0] = 0.5 * (vn * (UL[0] + UR[0]) - fabs(vn) * (UR[0] - UL[0]));
     } else {
+        constexpr int NV = D + 2;
         const double gm1 = g.gamma - 1.0;
         const double rl = recip(UL[0]), rr = recip(UR[0]);
-        const double pl = pressure_r<2>(UL, gm1, rl), pr = pressure_r<2>(UR, gm1, rr);
-        const double unl = (UL[1] * n0 + UL[2] * n1) * rl, unr = (UR[1] * n0 + UR[2] * n1) * rr;
+        const double pl = pressure_r<D>(UL, gm1, rl), pr = pressure_r<D>(UR, gm1, rr);
+        double ml = 0.0, mr = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            ml = fma(UL[1 + a], n[a], ml);
+            mr = fma(UR[1 + a], n[a], mr);
+        }
+        const double unl = ml * rl, unr = mr * rr;
         const double al = fabs(unl) + sqrt_nn(g.gamma * pl * rl), ar = fabs(unr) + sqrt_nn(g.gamma * pr * rr);
         const double alpha = al > ar ? al : ar;
-        const double FL[4] = {UL[0] * unl, UL[1] * unl + pl * n0, UL[2] * unl + pl * n1, (UL[3] + pl) * unl};
-        const double FR[4] = {UR[0] * unr, UR[1] * unr + pr * n0, UR[2] * unr + pr * n1, (UR[3] + pr) * unr};
+        double FL[NV], FR[NV];
+        FL[0] = UL[0] * unl;
+        FR[0] = UR[0] * unr;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) Phi[v] = 0.5 * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
+        for (int a = 0; a < D; ++a) {
+            FL[1 + a] = UL[1 + a] * unl + pl * n[a];
+            FR[1 + a] = UR[1 + a] * unr + pr * n[a];
+        }
+        FL[D + 1] = (UL[D + 1] + pl) * unl;
+        FR[D + 1] = (UR[D + 1] + pr) * unr;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) Phi[v] = 0.5 * ((FL[v] + FR[v]) - alpha * (UR[v] - UL[v]));
     }
 }
 
-// physical flux along the x (A = 0) or y (A = 1) axis
-template <int EQ, int A>
+// physical flux along axis A
+template <int D, int EQ, int A>
 __device__ __forceinline__ void mapped_phys_flux(const MappedArgs &g, const double *U, double *F)
 {
     if constexpr (EQ == EQ_ADVECTION) {
         F[0] = g.vel[A] * U[0];
     } else {
         const double rinv = recip(U[0]);
-        const double p = pressure_r<2>(U, g.gamma - 1.0, rinv);
-        euler_flux<2, A, double>(U, U[1 + A] * rinv, p, F);
+        const double p = pressure_r<D>(U, g.gamma - 1.0, rinv);
+        euler_flux<D, A, double>(U, U[1 + A] * rinv, p, F);
     }
 }
 
@@ -130,23 +204,24 @@ __device__ __forceinline__ void mapped_solve(const double (&M)[NB][NB], double (
     }
 }
 
-// mass matrix of a bilinear cell with the volume rule
-template <int P>
-__device__ __forceinline__ void mapped_mass(const double cx[4][2], double (&M)[Tab<2, P>::NB][Tab<2, P>::NB])
+// mass matrix of a multilinear cell with the volume rule
+template <int D, int P>
+__device__ __forceinline__ void mapped_mass(const double (&cx)[1 << D][3], double (&M)[Tab<D, P>::NB][Tab<D, P>::NB])
 {
-    constexpr int NB = Tab<2, P>::NB, NQ = Tab<2, P>::NQ, Q = P + 1;
+    constexpr int NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ;
 #pragma unroll
     for (int m = 0; m < NB; ++m)
 #pragma unroll
         for (int n = 0; n < NB; ++n) M[m][n] = 0.0;
 #pragma unroll 1
     for (int q = 0; q < NQ; ++q) {
-        double J[2][2];
-        const double wd = kDiffTab<2, P>.wv[q] * mapped_jacobian(cx, gl_x(Q, q % Q), gl_x(Q, q / Q), J);
+        double J[3][3], xi[3];
+        mapped_vpoint<D, P>(q, xi);
+        const double wd = kDiffTab<D, P>.wv[q] * mapped_jacobian<D>(cx, xi, J);
 #pragma unroll
         for (int m = 0; m < NB; ++m)
 #pragma unroll
-            for (int n = 0; n <= m; ++n) M[m][n] = fma(wd * kTab<2, P>.phi_v[q][m], kTab<2, P>.phi_v[q][n], M[m][n]);
+            for (int n = 0; n <= m; ++n) M[m][n] = fma(wd * kTab<D, P>.phi_v[q][m], kTab<D, P>.phi_v[q][n], M[m][n]);
     }
 #pragma unroll
     for (int m = 0; m < NB; ++m)
@@ -154,17 +229,19 @@ __device__ __forceinline__ void mapped_mass(const double cx[4][2], double (&M)[T
         for (int n = m + 1; n < NB; ++n) M[m][n] = M[n][m];
 }
 
-template <int P, int EQ, int OM>
+template <int D, int P, int EQ, int OM>
 __global__ __launch_bounds__(128) void k_mapped(MappedArgs g)
 {
-    constexpr int NV = EQ == EQ_ADVECTION ? 1 : 4, NB = Tab<2, P>::NB, NQ = Tab<2, P>::NQ, Q = P + 1;
-    const int N = g.N, ncell = N * N;
+    constexpr int NV = EQ == EQ_ADVECTION ? 1 : D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
+    constexpr int Q = P + 1;
+    const int N = g.N, ncell = D == 2 ? N * N : N * N * N, nfc = D == 2 ? N : N * N;
     const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= g.ncell_total) return;
     const int leaf = int(gid / ncell), c = int(gid % ncell);
-    const int ci = c % N, cj = c / N;
-    double cx[4][2];
-    mapped_cell_corners(g.geo[leaf], ci, cj, N, cx);
+    int ijk[3];
+    cell_ijk(c, N, D, ijk);
+    double cx[1 << D][3];
+    mapped_cell_corners<D>(g.geo[leaf], ijk, N, cx);
     const long sv = long(NB) * ncell;
     const double *K0 = g.us + long(leaf) * NV * sv + c;
     double K[NV][NB], R[NV][NB];
@@ -178,33 +255,39 @@ __global__ __launch_bounds__(128) void k_mapped(MappedArgs g)
     // ---- volume: sum_q w_q grad_xi phi_m . adj(J) F(U_q)
 #pragma unroll 1
     for (int q = 0; q < NQ; ++q) {
-        double J[2][2];
-        mapped_jacobian(cx, gl_x(Q, q % Q), gl_x(Q, q / Q), J);
-        const double a00 = J[1][1], a01 = -J[0][1], a10 = -J[1][0], a11 = J[0][0]; // rows of adj(J)
-        double U[NV], Fx[NV], Fy[NV];
+        double J[3][3], xi[3], A[D][3];
+        mapped_vpoint<D, P>(q, xi);
+        mapped_jacobian<D>(cx, xi, J);
+#pragma unroll
+        for (int e = 0; e < D; ++e) mapped_adj_row<D>(J, e, A[e]);
+        double U[NV], F[D][NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
             double s = 0.0;
 #pragma unroll
-            for (int m = 0; m < NB; ++m) s = fma(kTab<2, P>.phi_v[q][m], K[v][m], s);
+            for (int m = 0; m < NB; ++m) s = fma(kTab<D, P>.phi_v[q][m], K[v][m], s);
             U[v] = s;
         }
-        mapped_phys_flux<EQ, 0>(g, U, Fx);
-        mapped_phys_flux<EQ, 1>(g, U, Fy);
-        const double w = kDiffTab<2, P>.wv[q];
+        static_for<0, D>([&](auto Ai) __attribute__((always_inline)) { mapped_phys_flux<D, EQ, Ai>(g, U, F[Ai]); });
+        const double w = kDiffTab<D, P>.wv[q];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) {
-            const double c0 = w * (a00 * Fx[v] + a01 * Fy[v]), c1 = w * (a10 * Fx[v] + a11 * Fy[v]);
+        for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m)
-                R[v][m] = fma(kDiffTab<2, P>.dphi_v[0][q][m], c0, fma(kDiffTab<2, P>.dphi_v[1][q][m], c1, R[v][m]));
-        }
+            for (int e = 0; e < D; ++e) {
+                double ce = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) ce = fma(A[e][a], F[a][v], ce);
+                ce *= w;
+#pragma unroll
+                for (int m = 0; m < NB; ++m) R[v][m] = fma(kDiffTab<D, P>.dphi_v[e][q][m], ce, R[v][m]);
+            }
     }
     // ---- faces
-    static_for<0, 2>([&](auto Ai) __attribute__((always_inline)) {
+    static_for<0, D>([&](auto Ai) __attribute__((always_inline)) {
         constexpr int A = Ai;
-        const int stride = A == 0 ? 1 : N;
-        const int ia = A == 0 ? ci : cj, t = A == 0 ? cj : ci;
+        constexpr int TA = A == 0 ? 1 : 0, TB = A == 2 ? 1 : 2; // tangential axes, lower first
+        const int stride = A == 0 ? 1 : (A == 1 ? N : N * N);
+        const int ia = ijk[A], t = face_t(ijk, A, N, D);
 #pragma unroll 1
         for (int si = 0; si < 2; ++si) {
             const int s = si ? 1 : -1;
@@ -217,9 +300,9 @@ __global__ __launch_bounds__(128) void k_mapped(MappedArgs g)
                 nsv = sv;
                 nsm = ncell;
             } else {
-                Kn = g.guard + (long(leaf) * 4 + face) * NV * NB * N + t;
-                nsv = long(NB) * N;
-                nsm = N;
+                Kn = g.guard + (long(leaf) * 2 * D + face) * NV * NB * nfc + t;
+                nsv = long(NB) * nfc;
+                nsm = nfc;
             }
             double KN[NV][NB];
 #pragma unroll
@@ -227,38 +310,48 @@ __global__ __launch_bounds__(128) void k_mapped(MappedArgs g)
 #pragma unroll
                 for (int m = 0; m < NB; ++m) KN[v][m] = Kn[v * nsv + m * nsm];
 #pragma unroll 1
-            for (int f = 0; f < Q; ++f) {
-                const double xt = gl_x(Q, f);
-                double J[2][2];
-                if (A == 0) mapped_jacobian(cx, double(s), xt, J);
-                else mapped_jacobian(cx, xt, double(s), J);
-                // outward normal scaled by the face Jacobian: side * row A of adj(J)
-                const double N0 = s * (A == 0 ? J[1][1] : -J[1][0]), N1 = s * (A == 0 ? -J[0][1] : J[0][0]);
-                const double len = sqrt(N0 * N0 + N1 * N1), il = 1.0 / len;
+            for (int f = 0; f < NF; ++f) {
+                double xi[3] = {0.0, 0.0, 0.0};
+                xi[A] = double(s);
+                xi[TA] = gl_x(Q, f % Q);
+                if (D == 3) xi[TB] = gl_x(Q, f / Q);
+                double J[3][3], Nv[3];
+                mapped_jacobian<D>(cx, xi, J);
+                mapped_adj_row<D>(J, A, Nv);
+                double len2 = 0.0;
+#pragma unroll
+                for (int a = 0; a < D; ++a) {
+                    Nv[a] *= s;
+                    len2 = fma(Nv[a], Nv[a], len2);
+                }
+                const double len = sqrt(len2), il = 1.0 / len;
+                double n[3];
+#pragma unroll
+                for (int a = 0; a < D; ++a) n[a] = Nv[a] * il;
                 double UL[NV], UR[NV], Phi[NV];
 #pragma unroll
                 for (int v = 0; v < NV; ++v) {
                     double a = 0.0, b = 0.0;
 #pragma unroll
                     for (int m = 0; m < NB; ++m) {
-                        a = fma(face_phi<2, P, A>(m, f, s), K[v][m], a);
-                        b = fma(face_phi<2, P, A>(m, f, -s), KN[v][m], b);
+                        a = fma(face_phi<D, P, A>(m, f, s), K[v][m], a);
+                        b = fma(face_phi<D, P, A>(m, f, -s), KN[v][m], b);
                     }
                     UL[v] = a;
                     UR[v] = b;
                 }
-                mapped_flux<EQ>(g, UL, UR, N0 * il, N1 * il, Phi);
-                const double w = gl_w(Q, f) * len;
+                mapped_flux<D, EQ>(g, UL, UR, n, Phi);
+                const double w = kDiffTab<D, P>.wf[f] * len;
 #pragma unroll
                 for (int v = 0; v < NV; ++v)
 #pragma unroll
-                    for (int m = 0; m < NB; ++m) R[v][m] = fma(-w * Phi[v], face_phi<2, P, A>(m, f, s), R[v][m]);
+                    for (int m = 0; m < NB; ++m) R[v][m] = fma(-w * Phi[v], face_phi<D, P, A>(m, f, s), R[v][m]);
             }
         }
     });
     // ---- M^-1
     double M[NB][NB];
-    mapped_mass<P>(cx, M);
+    mapped_mass<D, P>(cx, M);
     mapped_solve<NB, NV>(M, R);
     double *o = g.out + long(leaf) * NV * sv + c;
     if constexpr (OM == OUT_RES64) {
@@ -277,51 +370,69 @@ __global__ __launch_bounds__(128) void k_mapped(MappedArgs g)
     }
 }
 
-// CFL rate of the leaves of a bilinear forest (one workgroup per leaf): per
-// cell the means of the state over the physical cell (volume rule), and for
-// each reference axis b the unit normal n_b and the width h_b = 2 det(J) /
-// |row b of adj(J)| at the cell centre (the edge lengths of a rectangle):
-// sum_b (|u.n_b| + c) / h_b (scalar convection: sum_b |vel.n_b| / h_b).
-template <int P, int EQ>
+// the integrals of the state over the physical cell (volume rule) and the
+// cell's volume
+template <int D, int P, int NV>
+__device__ __forceinline__ double mapped_cell_integrals(const double (&cx)[1 << D][3], const double *K0, long sv,
+                                                        int ncell, double *s)
+{
+    constexpr int NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ;
+    double vol = 0.0;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) s[v] = 0.0;
+    for (int q = 0; q < NQ; ++q) {
+        double J[3][3], xi[3];
+        mapped_vpoint<D, P>(q, xi);
+        const double wd = kDiffTab<D, P>.wv[q] * mapped_jacobian<D>(cx, xi, J);
+        vol += wd;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            double u = 0.0;
+#pragma unroll
+            for (int m = 0; m < NB; ++m) u = fma(kTab<D, P>.phi_v[q][m], K0[v * sv + long(m) * ncell], u);
+            s[v] = fma(wd, u, s[v]);
+        }
+    }
+    return vol;
+}
+
+// CFL rate of the leaves of a mapped forest (one workgroup per leaf, a
+// power of two of threads): per cell the means over the physical cell, and
+// for each reference axis b the unit normal n_b and the width h_b =
+// 2 det(J) / |row b of adj(J)| at the cell centre (the edge lengths of a
+// box): sum_b (|u.n_b| + c) / h_b (scalar convection: sum_b |vel.n_b| / h_b).
+template <int D, int P, int EQ>
 __global__ __launch_bounds__(256) void k_mapped_rate(MappedArgs g, double *leaf_max)
 {
-    constexpr int NV = EQ == EQ_ADVECTION ? 1 : 4, NB = Tab<2, P>::NB, NQ = Tab<2, P>::NQ, Q = P + 1;
+    constexpr int NV = EQ == EQ_ADVECTION ? 1 : D + 2, NB = Tab<D, P>::NB;
     __shared__ double red[256];
-    const int leaf = blockIdx.x, N = g.N, ncell = N * N;
+    const int leaf = blockIdx.x, N = g.N, ncell = D == 2 ? N * N : N * N * N;
     const long sv = long(NB) * ncell;
     double mx = 0.0;
     for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-        double cx[4][2], J[2][2];
-        mapped_cell_corners(g.geo[leaf], c % N, c / N, N, cx);
-        const double *K0 = g.us + long(leaf) * NV * sv + c;
-        double s[NV], area = 0.0;
+        int ijk[3];
+        cell_ijk(c, N, D, ijk);
+        double cx[1 << D][3], J[3][3], s[NV];
+        mapped_cell_corners<D>(g.geo[leaf], ijk, N, cx);
+        const double vol = mapped_cell_integrals<D, P, NV>(cx, g.us + long(leaf) * NV * sv + c, sv, ncell, s);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) s[v] = 0.0;
-        for (int q = 0; q < NQ; ++q) {
-            const double wd = kDiffTab<2, P>.wv[q] * mapped_jacobian(cx, gl_x(Q, q % Q), gl_x(Q, q / Q), J);
-            area += wd;
-#pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                double u = 0.0;
-#pragma unroll
-                for (int m = 0; m < NB; ++m) u = fma(kTab<2, P>.phi_v[q][m], K0[v * sv + long(m) * ncell], u);
-                s[v] += wd * u;
-            }
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) s[v] /= area;
-        const double det0 = mapped_jacobian(cx, 0.0, 0.0, J);
+        for (int v = 0; v < NV; ++v) s[v] /= vol;
+        const double x0[3] = {0.0, 0.0, 0.0};
+        const double det0 = mapped_jacobian<D>(cx, x0, J);
         double cs = 0.0;
-        if constexpr (EQ != EQ_ADVECTION) cs = sqrt(g.gamma * pressure_r<2>(s, g.gamma - 1.0, 1.0 / s[0]) / s[0]);
+        if constexpr (EQ != EQ_ADVECTION) cs = sqrt(g.gamma * pressure_r<D>(s, g.gamma - 1.0, 1.0 / s[0]) / s[0]);
         double rate = 0.0;
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            const double A0 = b == 0 ? J[1][1] : -J[1][0], A1 = b == 0 ? -J[0][1] : J[0][0];
-            const double len = sqrt(A0 * A0 + A1 * A1), h = 2.0 * det0 / len;
-            const double n0 = A0 / len, n1 = A1 / len;
-            double un;
-            if constexpr (EQ == EQ_ADVECTION) un = g.vel[0] * n0 + g.vel[1] * n1;
-            else un = (s[1] * n0 + s[2] * n1) / s[0];
+        for (int b = 0; b < D; ++b) {
+            double A[3];
+            mapped_adj_row<D>(J, b, A);
+            double len2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) len2 += A[a] * A[a];
+            const double len = sqrt(len2), h = 2.0 * det0 / len;
+            double un = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) un += (EQ == EQ_ADVECTION ? g.vel[a] : s[1 + a] / s[0]) * (A[a] / len);
             rate += (fabs(un) + cs) / h;
         }
         mx = rate > mx ? rate : mx;
@@ -337,30 +448,24 @@ __global__ __launch_bounds__(256) void k_mapped_rate(MappedArgs g, double *leaf_
 
 // Integrals of the state over the physical cells of a leaf (volume rule),
 // one workgroup per leaf (a power of two of threads): part[leaf * NV + v]
-template <int P, int EQ>
+template <int D, int P, int EQ>
 __global__ __launch_bounds__(256) void k_mapped_totals_leaf(MappedArgs g, double *part)
 {
-    constexpr int NV = EQ == EQ_ADVECTION ? 1 : 4, NB = Tab<2, P>::NB, NQ = Tab<2, P>::NQ, Q = P + 1;
+    constexpr int NV = EQ == EQ_ADVECTION ? 1 : D + 2, NB = Tab<D, P>::NB;
     __shared__ double red[NV][256];
-    const int leaf = blockIdx.x, N = g.N, ncell = N * N;
+    const int leaf = blockIdx.x, N = g.N, ncell = D == 2 ? N * N : N * N * N;
     const long sv = long(NB) * ncell;
     double s[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) s[v] = 0.0;
     for (int c = threadIdx.x; c < ncell; c += blockDim.x) {
-        double cx[4][2], J[2][2];
-        mapped_cell_corners(g.geo[leaf], c % N, c / N, N, cx);
-        const double *K0 = g.us + long(leaf) * NV * sv + c;
-        for (int q = 0; q < NQ; ++q) {
-            const double wd = kDiffTab<2, P>.wv[q] * mapped_jacobian(cx, gl_x(Q, q % Q), gl_x(Q, q / Q), J);
+        int ijk[3];
+        cell_ijk(c, N, D, ijk);
+        double cx[1 << D][3], sc[NV];
+        mapped_cell_corners<D>(g.geo[leaf], ijk, N, cx);
+        mapped_cell_integrals<D, P, NV>(cx, g.us + long(leaf) * NV * sv + c, sv, ncell, sc);
 #pragma unroll
-            for (int v = 0; v < NV; ++v) {
-                double u = 0.0;
-#pragma unroll
-                for (int m = 0; m < NB; ++m) u = fma(kTab<2, P>.phi_v[q][m], K0[v * sv + long(m) * ncell], u);
-                s[v] = fma(wd, u, s[v]);
-            }
-        }
+        for (int v = 0; v < NV; ++v) s[v] += sc[v];
     }
 #pragma unroll
     for (int v = 0; v < NV; ++v) red[v][threadIdx.x] = s[v];
@@ -376,20 +481,22 @@ __global__ __launch_bounds__(256) void k_mapped_totals_leaf(MappedArgs g, double
         for (int v = 0; v < NV; ++v) part[long(leaf) * NV + v] = red[v][0];
 }
 
-// Initial state on bilinear cells: M K = int phi_m U0 det(J) dxi with p+3
+// Initial state on mapped cells: M K = int phi_m U0 det(J) dxi with p+3
 // Gauss points per axis for the right-hand side and the volume rule for M.
-template <int P, int NV>
+template <int D, int P, int NV>
 __global__ __launch_bounds__(128) void k_mapped_project_ic(double *u, const LeafGeo *geo, int N, long ncell_total,
                                                            int kind, IcParams prm, double t, double gamma)
 {
-    constexpr int NB = Tab<2, P>::NB, QI = P + 3, NQI = QI * QI;
-    const int ncell = N * N;
+    constexpr int NB = Tab<D, P>::NB, QI = P + 3, NQI = ipow(QI, D);
+    const int ncell = D == 2 ? N * N : N * N * N;
     const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
     if (gid >= ncell_total) return;
     const long leaf = gid / ncell;
     const int c = int(gid % ncell);
-    double cx[4][2];
-    mapped_cell_corners(geo[leaf], c % N, c / N, N, cx);
+    int ijk[3];
+    cell_ijk(c, N, D, ijk);
+    double cx[1 << D][3];
+    mapped_cell_corners<D>(geo[leaf], ijk, N, cx);
     const double hmin[3] = {0.0, 0.0, 0.0};
     double acc[NV][NB];
 #pragma unroll
@@ -398,22 +505,28 @@ __global__ __launch_bounds__(128) void k_mapped_project_ic(double *u, const Leaf
         for (int m = 0; m < NB; ++m) acc[v][m] = 0.0;
 #pragma unroll 1
     for (int q = 0; q < NQI; ++q) {
-        const int q0 = q % QI, q1 = q / QI;
-        double J[2][2], x[3];
-        const double e = kIcTab<P>.x[q0], h = kIcTab<P>.x[q1];
-        const double wd = kIcTab<P>.w[q0] * kIcTab<P>.w[q1] * mapped_jacobian(cx, e, h, J);
-        mapped_point(cx, e, h, x);
-        double U[4];
-        analytic<2>(kind, prm, t, gamma, x, hmin, U);
+        const int qi[3] = {q % QI, (q / QI) % QI, q / (QI * QI)};
+        double J[3][3], x[3], xi[3] = {0.0, 0.0, 0.0}, w = 1.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+            xi[a] = kIcTab<P>.x[qi[a]];
+            w *= kIcTab<P>.w[qi[a]];
+        }
+        const double wd = w * mapped_jacobian<D>(cx, xi, J);
+        mapped_point<D>(cx, xi, x);
+        double U[D + 2];
+        analytic<D>(kind, prm, t, gamma, x, hmin, U);
 #pragma unroll
         for (int m = 0; m < NB; ++m) {
-            const double ph = wd * kIcTab<P>.leg1[q0][kTab<2, P>.e[m][0]] * kIcTab<P>.leg1[q1][kTab<2, P>.e[m][1]];
+            double ph = wd;
+#pragma unroll
+            for (int a = 0; a < D; ++a) ph *= kIcTab<P>.leg1[qi[a]][kTab<D, P>.e[m][a]];
 #pragma unroll
             for (int v = 0; v < NV; ++v) acc[v][m] = fma(ph, U[v], acc[v][m]);
         }
     }
     double M[NB][NB];
-    mapped_mass<P>(cx, M);
+    mapped_mass<D, P>(cx, M);
     mapped_solve<NB, NV>(M, acc);
     const long sv = long(NB) * ncell, base = leaf * NV * sv + c;
 #pragma unroll

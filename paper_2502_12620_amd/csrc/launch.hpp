@@ -68,17 +68,18 @@ hipError_t launch_fill(const FillArgs &a, int nfc, hipStream_t s, int nv = D + 2
 template <int D, int P>
 hipError_t launch_ipdg(const IpdgArgs &a, int out_mode, hipStream_t s);
 
-// Bilinear roots (2-D): the residual or fused RK stage (out_mode OUT_RES64 /
-// OUT_RK; eq EQ_EULER or EQ_ADVECTION), the CFL rate per leaf, the
-// per-leaf totals (one workgroup of `block` threads per leaf, a power of
-// two), and the initial projection (nv variables).
-template <int P>
+// Bilinear / trilinear roots (2-D any degree, 3-D degree <= 2): the
+// residual or fused RK stage (out_mode OUT_RES64 / OUT_RK; eq EQ_EULER or
+// EQ_ADVECTION), the CFL rate per leaf, the per-leaf totals (one workgroup
+// of `block` threads per leaf, a power of two), and the initial projection
+// (nv variables).
+template <int D, int P>
 hipError_t launch_mapped(const MappedArgs &a, int eq, int out_mode, hipStream_t s);
-template <int P>
+template <int D, int P>
 hipError_t launch_mapped_rate(const MappedArgs &a, int eq, int nleaves, int block, double *leaf_max, hipStream_t s);
-template <int P>
+template <int D, int P>
 hipError_t launch_mapped_totals(const MappedArgs &a, int eq, int nleaves, int block, double *part, hipStream_t s);
-template <int P>
+template <int D, int P>
 hipError_t launch_mapped_ic(double *u, const LeafGeo *geo, int N, long total, int kind, const IcParams &prm,
                             double t, double gamma, int nv, hipStream_t s);
 template <int D, int P>

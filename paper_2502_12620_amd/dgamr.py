@@ -230,11 +230,14 @@ class Forest:
         _check(lib().dgamr_set_root_frames(self.h, _ptr(c)))
 
     def set_root_nodes(self, xy):
-        """Bilinear root blocks from the 2-D root grid nodes, shape
-        (roots_y + 1, roots_x + 1, 2) (dgamr_set_root_nodes)."""
+        """Bilinear (3-D: trilinear) root blocks from the root grid nodes,
+        shape (roots_y + 1, roots_x + 1, 2) or (roots_z + 1, roots_y + 1,
+        roots_x + 1, 3) (dgamr_set_root_nodes)."""
         a = torch.as_tensor(xy, dtype=torch.float64).contiguous()
-        if a.numel() != 2 * (self.desc.roots[0] + 1) * (self.desc.roots[1] + 1):
-            raise ValueError("(roots_x + 1) * (roots_y + 1) nodes of (x, y)")
+        d = self.desc.dim
+        n = (self.desc.roots[0] + 1) * (self.desc.roots[1] + 1) * (self.desc.roots[2] + 1 if d == 3 else 1)
+        if a.numel() != d * n:
+            raise ValueError("one node of dim coordinates per root grid vertex")
         _check(lib().dgamr_set_root_nodes(self.h, _ptr(a)))
 
     def keys(self):

@@ -1,4 +1,4 @@
-"""GPU parity on bilinear root blocks (Sec. 3.3, Eq. 6; 2-D): distorted
+"""GPU parity on bilinear and trilinear root blocks (Sec. 3.3, Eq. 6): distorted
 root grids, periodic and outflow, with hanging faces, against the oracle's
 bilinear blocks element by element: the initial projection (full mass
 matrix), the guard fill (reference-space copy, split, combine), the
@@ -14,8 +14,8 @@ import numpy as np
 import pytest
 
 import oracle as O
-from tests.gpu_helpers import rel_diff
-from tests.test_oracle_mapped import distorted_nodes
+from tests.gpu_helpers import rel_diff, rel_diff_floored
+from tests.test_oracle_mapped import PRM3, box_nodes3, distorted_nodes, distorted_nodes3
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -186,6 +186,69 @@ def test_mapped_refusals():
     with pytest.raises(G.DgamrError) as e:
         f.limit_positivity(u)
     assert e.value.code == G.EUNSUPPORTED
-    g = G.Forest(3, 1, 4, (1, 1, 1), (0.0,) * 3, (1.0,) * 3, (0, 0, 0), 1)
-    with pytest.raises(G.DgamrError):
-        g.set_root_nodes(np.zeros((2, 2, 2)))
+    g = G.Forest(3, 3, 2, (1, 1, 1), (0.0,) * 3, (1.0,) * 3, (0, 0, 0), 1)
+    with pytest.raises(G.DgamrError) as e:
+        g.set_root_nodes(box_nodes3((1, 1, 1), (0.0,) * 3, (1.0,) * 3))
+    assert e.value.code == G.EUNSUPPORTED  # trilinear blocks at degree <= 2
+
+
+CASES3 = [(1, 2), (2, 2), (1, 4)]
+
+
+@pytest.mark.parametrize("p,N", CASES3)
+@pytest.mark.parametrize("bc", [0, 1])
+def test_trilinear_fill_residual_and_steps(p, N, bc):
+    """2x2x2 distorted roots, root 0 refined and then one of its children:
+    the same checks as in 2-D, against the oracle's trilinear blocks."""
+    print(f"trilinear parity p={p} N={N} bc={bc}", flush=True)
+    G = _G()
+    roots, lo, hi = (2, 2, 2), (0.0,) * 3, (4.0,) * 3
+    args = (3, p, N, roots, lo, hi, (bc,) * 3, 3)
+    orc, gpu = O.Forest(*args), G.Forest(*args)
+    nodes = distorted_nodes3(roots, lo, hi, 0.15, seed=p + 10 * N + bc)
+    orc.set_nodes(nodes)
+    gpu.set_root_nodes(nodes)
+    _adapt_both(orc, gpu, 0)
+    _adapt_both(orc, gpu, 1)
+    assert np.array_equal(orc.keys(), gpu.keys())
+    u = orc.project_ic(O.IC_VORTEX, PRM3)
+    ud = gpu.project_ic(G.IC_VORTEX, PRM3)
+    assert rel_diff_floored(_host(ud), u, 1e-3).max() <= TOL
+    rng = np.random.default_rng(p + N + bc)
+    u[:, :, 1:, :] += 0.01 * rng.standard_normal(u[:, :, 1:, :].shape)
+    ud = _cuda(u)
+    gd = gpu.new_guard()
+    gpu.fill_guardcells(ud, gd)
+    g_ref = orc.fill_guards(u)
+    assert np.abs(_host(gd) - g_ref).max() <= 1e-13 * np.abs(g_ref).max()
+    rd = gpu.new_residual()
+    gpu.dg_residual(ud, gd, rd)
+    assert rel_diff_floored(_host(rd), orc.residual(u, g_ref), 1e-3).max() <= TOL_RES
+    work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(2):
+        dref = orc.step(u, 0.1)
+        gpu.step(ud, work, dt, 0.1)
+        assert _host(dt)[0] == pytest.approx(dref, rel=1e-13)
+    assert rel_diff_floored(_host(ud), u, 1e-3).max() <= TOL
+    np.testing.assert_allclose(_host(gpu.conserved_totals(ud, work)), orc.totals(u), rtol=1e-12, atol=1e-12)
+
+
+def test_trilinear_scalar_convection():
+    G = _G()
+    roots, lo, hi = (2, 2, 2), (0.0,) * 3, (1.0,) * 3
+    args = (3, 1, 2, roots, lo, hi, (0, 0, 0), 2)
+    orc = O.Forest(*args, equation=O.EQ_ADVECTION, velocity=(1.0, 0.5, 0.25))
+    gpu = G.Forest(*args, equation=G.EQ_ADVECTION, velocity=(1.0, 0.5, 0.25))
+    nodes = distorted_nodes3(roots, lo, hi, 0.15, seed=4)
+    orc.set_nodes(nodes)
+    gpu.set_root_nodes(nodes)
+    _adapt_both(orc, gpu, 3)
+    prm = [1.0, 1.0, 1.0, 1.0]
+    u = orc.project_ic(O.IC_COSINE, prm)
+    ud = gpu.project_ic(G.IC_COSINE, prm)
+    work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        dref = orc.step(u, 0.1)
+        gpu.step(ud, work, dt, 0.1)
+        assert _host(dt)[0] == pytest.approx(dref, rel=1e-13)
+    assert rel_diff(_host(ud), u).max() <= TOL
