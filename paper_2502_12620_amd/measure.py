@@ -137,8 +137,23 @@ def cmd_copy(args):
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / args.reps
-    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "ms": ms,
-                      "GBs_read_plus_write": 2 * n * 8 / ms / 1e6}), flush=True)
+    out = {"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "ms": ms,
+           "GBs_read_plus_write": 2 * n * 8 / ms / 1e6}
+    if args.triad:
+        # the traffic of an RK stage 2 or 3 (two arrays read, one written)
+        # through torch's elementwise kernel
+        third = torch.empty_like(src)
+        for _ in range(3):
+            torch.add(src, dst, alpha=0.25, out=third)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.reps):
+            torch.add(src, dst, alpha=0.25, out=third)
+        e1.record()
+        torch.cuda.synchronize()
+        tms = e0.elapsed_time(e1) / args.reps
+        out.update({"triad_ms": tms, "triad_GBs": 3 * n * 8 / tms / 1e6})
+    print(json.dumps(out), flush=True)
 
 
 def _pct(xs, q):
@@ -554,6 +569,7 @@ def main(argv=None):
     c = sub.add_parser("copy")
     c.add_argument("--mb", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)
+    c.add_argument("--triad", action="store_true", help="also time a two-read one-write elementwise kernel")
     b = sub.add_parser("batch")
     b.add_argument("--forests", type=int, default=512)
     b.add_argument("--repeats", type=int, default=20)
