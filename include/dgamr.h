@@ -313,7 +313,9 @@ int dgamr_set_tuning(dgamr_forest *f, int knob, long value);
 
 /* Measurement hook: while enabled, every launch of the fused stage kernel
  * inside dgamr_step is bracketed by two HIP events on the caller's stream
- * (not usable under HIP graph capture).  dgamr_profile_read waits for the
+ * (not usable under HIP graph capture); on forests with rotated frames or
+ * non-affine roots, whose stages are several launches, each stage's
+ * launches (fill, residual, update, limiter) are bracketed together.  dgamr_profile_read waits for the
  * recorded events, returns the summed kernel time in milliseconds and the
  * number of launches, and clears the record. */
 int dgamr_profile_enable(dgamr_forest *f, int enable);

@@ -497,6 +497,25 @@ int dgamr_compute_dt(dgamr_forest *f, double cfl, const double *u, double *dt_de
     return launch_dt(f, cfl, u, dt_dev, carve(f, work), stream);
 }
 
+// Measurement hook: events before and after one stage's launches
+int prof_begin(dgamr_forest *f, hipStream_t stream, hipEvent_t &e1)
+{
+    e1 = nullptr;
+    if (!f->prof) return DGAMR_OK;
+    hipEvent_t e0 = nullptr;
+    CHECK(take_event(f, e0));
+    CHECK(take_event(f, e1));
+    f->ev_rec.emplace_back(e0, e1);
+    HIP_TRY(hipEventRecord(e0, stream));
+    return DGAMR_OK;
+}
+
+int prof_end(dgamr_forest *f, hipStream_t stream, hipEvent_t e1)
+{
+    if (e1) HIP_TRY(hipEventRecord(e1, stream));
+    return DGAMR_OK;
+}
+
 // One SSP-RK3 step as three fused stage launches (far side of block faces
 // inline, or from guard traces for the 3-D lane kernel; limiter fused).  rate_in / rate_clear / rate_out select the CFL
 // time step folded into the stages (see StageArgs).
@@ -514,35 +533,40 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
         // stage update
         const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
         for (int s = 0; s < 3; ++s) {
+            hipEvent_t e1;
+            CHECK(prof_begin(f, stream, e1));
             CHECK(launch_fill(f, us, w.guard, false, stream));
             dgk::MappedArgs a = mapped_args(f, us, u, w.guard, outs[s], dt_dev, A[s], B[s]);
             CHECK(dispatch_mapped(f, [&](auto D, auto P) -> int {
                 HIP_TRY((dgk::launch_mapped<D, P>(a, eq, dgk::OUT_RK, stream)));
                 return DGAMR_OK;
             }));
+            CHECK(prof_end(f, stream, e1));
             us = outs[s];
         }
         return DGAMR_OK;
     }
     if (f->topo.rotated()) {
         // roots of different frames: the guard fill applies the rotation of
-        // each guard cell (Sec. 3.5) into the guard buffer, then the residual
-        // over guard coefficients, the stage update and the limiter, unfused
-        const bool r32 = f->topo.desc().precision == DGAMR_FP32;
+        // each guard cell (Sec. 3.5) into the guard buffer; the stage kernel
+        // reads the far side of block faces from there, fused with the stage
+        // update and the limiter (dt from the step's CFL reduction)
         for (int s = 0; s < 3; ++s) {
+            hipEvent_t e1;
+            CHECK(prof_begin(f, stream, e1));
             CHECK(launch_fill(f, us, w.guard, false, stream));
             dgk::StageArgs a{};
             a.us = us;
+            a.un = u;
             a.guard = w.guard;
-            a.out64 = r32 ? nullptr : w.res;
-            a.out32 = r32 ? reinterpret_cast<float *>(w.res) : nullptr;
-            CHECK(launch_stage(f, a, dgk::GUARD_BUFFER, r32 ? dgk::OUT_RES32 : dgk::OUT_RES64, stream));
-            dgk::RkArgs rk{u, us, w.res, outs[s], dt_dev, A[s], B[s], long(state_elems(f)), r32 ? 1 : 0};
-            long blocks = (rk.n + 255) / 256;
-            if (blocks > 65536) blocks = 65536;
-            hipLaunchKernelGGL(dgk::k_rk, dim3(unsigned(blocks)), dim3(256), 0, stream, rk);
-            HIP_TRY(hipGetLastError());
-            if (lim) CHECK(launch_limit(f, outs[s], stream));
+            a.out64 = outs[s];
+            a.dt = dt_dev;
+            a.rk_a = A[s];
+            a.rk_b = B[s];
+            a.cfl = cfl;
+            a.dt_out = dt_dev;
+            CHECK(launch_stage(f, a, dgk::GUARD_BUFFER, dgk::OUT_RK, stream, lim));
+            CHECK(prof_end(f, stream, e1));
             us = outs[s];
         }
         return DGAMR_OK;
@@ -568,15 +592,10 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
             a.guard = w.guard;
             CHECK(launch_fill(f, us, w.guard, true, stream));
         }
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (f->prof) {
-            CHECK(take_event(f, e0));
-            CHECK(take_event(f, e1));
-            f->ev_rec.emplace_back(e0, e1);
-            HIP_TRY(hipEventRecord(e0, stream));
-        }
+        hipEvent_t e1;
+        CHECK(prof_begin(f, stream, e1));
         CHECK(launch_stage(f, a, guard3 ? dgk::GUARD_TRACE : dgk::GUARD_INLINE, dgk::OUT_RK, stream, lim));
-        if (f->prof) HIP_TRY(hipEventRecord(e1, stream));
+        CHECK(prof_end(f, stream, e1));
         us = outs[s];
     }
     return DGAMR_OK;
@@ -684,7 +703,7 @@ int dgamr_run(dgamr_forest *f, double cfl, int nsteps, double *u, void *work, do
         return DGAMR_OK;
     }
     auto *slot = reinterpret_cast<unsigned long long *>(w.scal + 2);
-    if (cfl <= 0.0 || f->topo.unfused()) { // rotated frames, bilinear roots: the unfused stages take dt per step
+    if (cfl <= 0.0 || f->topo.unfused()) { // rotated frames, bilinear roots: dt from a reduction per step
         for (int s = 0; s < nsteps; ++s) {
             if (cfl > 0.0) CHECK(launch_dt(f, cfl, u, dt_dev, w, stream));
             CHECK(run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, stream));
@@ -736,7 +755,7 @@ int dgamr_run_capture(dgamr_forest *f, double cfl, int nsteps, double *u, void *
             for (int st = 0; st < nsteps && rc == DGAMR_OK; ++st) {
                 const int rd = st & 1, wr = rd ^ 1;
                 const bool last = st == nsteps - 1;
-                if (f->topo.unfused()) { // unfused stages: the CFL reduction of every step
+                if (f->topo.unfused()) { // fill + stage kernel per stage: the CFL reduction of every step
                     if (st > 0) rc = launch_dt(f, cfl, u, dt_dev, w, s);
                     if (rc == DGAMR_OK) rc = run_step(f, cfl, u, w, dt_dev, nullptr, nullptr, nullptr, s);
                     continue;

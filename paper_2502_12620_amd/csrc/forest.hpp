@@ -109,7 +109,9 @@ class Forest {
     // reference square (cube), from the root grid nodes, x fastest
     int set_nodes(const double *xy, std::string &err);
     bool mapped() const { return !nodes_.empty(); }
-    // steps run the guard fill, the residual and the stage update unfused
+    // steps run the guard fill before every stage kernel (the far side is
+    // not taken inline) and a CFL reduction per step (none folded into the
+    // stages)
     bool unfused() const { return rotated_ || mapped(); }
     const std::vector<RotPlan> &plans() const { return plans_; }
     std::vector<LeafGeo> geometry() const;

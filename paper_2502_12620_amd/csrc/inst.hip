@@ -50,6 +50,8 @@ hipError_t launch_stage_2v(const StageArgs &a, int gm, int om, hipStream_t s, in
         hipLaunchKernelGGL((k_stage2v<P, GUARD_BUFFER, OUT_RES64>), grid, block, lds, s, a, rows);
     else if (gm == GUARD_INLINE && om == OUT_RK)
         hipLaunchKernelGGL((k_stage2v<P, GUARD_INLINE, OUT_RK>), grid, block, lds, s, a, rows);
+    else if (gm == GUARD_BUFFER && om == OUT_RK) // far side from the (rotated) guard fill
+        hipLaunchKernelGGL((k_stage2v<P, GUARD_BUFFER, OUT_RK>), grid, block, lds, s, a, rows);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -147,6 +149,20 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
         else
             hipLaunchKernelGGL((k_stage<D, P, GMRK, OUT_RK, false, T, EQ_EULER, false, MF>), grid, block, lds, s, a, rows);
         return hipGetLastError();
+    }
+    if (gm == GUARD_BUFFER && om == OUT_RK) {
+        // the fused stage reading the far side from the guard fill (forests
+        // with rotated root frames), one workgroup per item, on the vector
+        // unit
+        if constexpr (MF) {
+            return hipErrorNotSupported;
+        } else {
+            if (lim)
+                hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RK, true, T>), grid_all, block, lds, s, a, rows);
+            else
+                hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RK, false, T>), grid_all, block, lds, s, a, rows);
+            return hipGetLastError();
+        }
     }
     if constexpr (std::is_same<T, float>::value) {
         if (gm == GUARD_BUFFER && om == OUT_RES32) {

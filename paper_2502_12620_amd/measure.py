@@ -60,11 +60,21 @@ def stage_bytes_per_dof(dim: int, n_cell: int, stage=None) -> float:
     return (sum(per) / 3.0 if stage is None else per[stage]) + face
 
 
-def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1, rows=0, mfma=0):
+def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1, rows=0, mfma=0, roots="affine"):
+    """Time w's steps; roots "mapped" moves the root grid nodes smoothly
+    (bilinear / trilinear roots), "rotated" gives every root a seeded
+    frame.  The stage time is that of each stage's launches; the
+    algorithmic bytes are the same for every kind of root."""
     f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma, precision=precision)
     f.set_tuning(G.TUNE_STAGE_VARIANT, variant)
     f.set_tuning(G.TUNE_SLAB_ROWS, rows)
     f.set_tuning(G.TUNE_MFMA, mfma)
+    if roots == "mapped":
+        f.set_root_nodes(W.smooth_root_nodes(w))
+    elif roots == "rotated":
+        f.set_root_frames(W.random_root_frames(w))
+    elif roots != "affine":
+        raise ValueError(f"unknown root kind {roots}")
     u = f.project_ic(G.IC_VORTEX, w.ic_params)
     work = f.new_work()
     dt = torch.zeros(1, dtype=torch.float64, device="cuda")
@@ -87,7 +97,7 @@ def run_workload(w, steps: int, warmup: int = 3, precision=G.FP64, variant=-1, r
     del f, u, work
     torch.cuda.empty_cache()
     fp32 = precision == G.FP32
-    out = {"workload": w.name, "precision": "fp32" if fp32 else "fp64", "variant": variant,
+    out = {"workload": w.name, "roots": roots, "precision": "fp32" if fp32 else "fp64", "variant": variant,
             "rows": rows, "mfma_volume": bool(mfma and fp32 and mfma_volume(w.dim, w.degree)),
             "dim": w.dim, "degree": w.degree, "leaves": n, "dofs": dof,
             "state_MB": dof * 8 / 1e6, "steps": steps, "dof_stage_per_s": dof * 3 * steps / el,
@@ -119,8 +129,9 @@ def cmd_sweep(args):
         for var in variants:
             for rows in [int(r) for r in args.rows.split(",")]:
                 for mf in [int(m) for m in args.mfma.split(",")]:
-                    print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var, rows=rows, mfma=mf)),
-                          flush=True)
+                    for rk in args.roots.split(","):
+                        print(json.dumps(run_workload(w, args.steps, precision=prec, variant=var, rows=rows,
+                                                      mfma=mf, roots=rk)), flush=True)
 
 
 def cmd_copy(args):
@@ -566,6 +577,7 @@ def main(argv=None):
     s.add_argument("--precision", choices=["fp64", "fp32"], default="fp64", help="residual arithmetic")
     s.add_argument("--rows", default="0", help="comma-separated slab heights to time (0: the kernel's own)")
     s.add_argument("--mfma", default="0", help="FP32: comma-separated 1 (volume integral on the matrix cores) / 0")
+    s.add_argument("--roots", default="affine", help="comma-separated root kinds: affine, mapped (bilinear / trilinear), rotated (frames)")
     c = sub.add_parser("copy")
     c.add_argument("--mb", type=int, default=1024)
     c.add_argument("--reps", type=int, default=5)

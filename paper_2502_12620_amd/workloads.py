@@ -211,6 +211,35 @@ def roofline_3d(k: int, degree: int) -> Workload:
                     (PERIODIC, PERIODIC, PERIODIC), 1, IC_VORTEX, [5.0, L / 2, L / 2, 1.0, 1.0, L, L], 10)
 
 
+def smooth_root_nodes(w: Workload, amp: float = 0.1):
+    """Root grid nodes of w's uniform root grid moved by a smooth periodic
+    displacement of amp root widths (each coordinate by amp h sin(2 pi x_b /
+    L_b) over the other axes b), so that every root becomes a bilinear
+    (trilinear) block and a periodic axis stays periodic.  Shape (ry + 1,
+    rx + 1, 2) or (rz + 1, ry + 1, rx + 1, 3)."""
+    d = w.dim
+    r = list(w.roots[:d])
+    axes = [np.linspace(w.lo[a], w.hi[a], r[a] + 1) for a in range(d)]
+    grids = np.meshgrid(*axes[::-1], indexing="ij")[::-1]  # x varies fastest (last index)
+    L = [w.hi[a] - w.lo[a] for a in range(d)]
+    nodes = np.stack(grids, axis=-1)
+    for a in range(d):
+        h = L[a] / r[a]
+        disp = np.ones_like(grids[0])
+        for b in range(d):
+            if b != a:
+                disp = disp * np.sin(2.0 * np.pi * (grids[b] - w.lo[b]) / L[b])
+        nodes[..., a] += amp * h * disp
+    return nodes
+
+
+def random_root_frames(w: Workload, seed: int = 31):
+    """A seeded rotation code per root (4 frames in 2-D, 24 in 3-D)."""
+    rng = np.random.default_rng(seed)
+    n = int(np.prod(w.roots[:w.dim]))
+    return [int(x) for x in rng.integers(0, 4 if w.dim == 2 else 24, n)]
+
+
 def batched_forests(n: int = 512, seed: int = 2502):
     """The batched workload: n independent 2-D vortex forests.  Root count
     R ~ U{4..256} as nx x ny (nx the largest divisor of R not above sqrt R),

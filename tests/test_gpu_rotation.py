@@ -120,12 +120,34 @@ def test_rotated_fp32_residual():
     assert rel_diff_floored(_host(ud), u, 1e-3).max() <= 1e-5
 
 
-def test_rotated_blast_with_limiter():
-    """A pressure jump with the positivity limiter on rotated 3-D roots."""
-    frames = _frames(3, 7)
-    orc, gpu = _pair(3, 2, 4, frames, limiter=True, levels=2)
+@pytest.mark.parametrize("p,N", [(1, 4), (2, 6), (3, 4)])
+@pytest.mark.parametrize("variant", [0, 1])
+def test_rotated_2d_steps_in_both_stage_kernels(p, N, variant):
+    """The fused stage reading the far side from the rotated guard fill, in
+    both 2-D stage kernels (one lane per cell and variable; one thread per
+    cell), on a three-level forest."""
+    G = _G()
+    frames = _frames(2, 3)
+    orc, gpu = _pair(2, p, N, frames)
+    gpu.set_tuning(G.TUNE_STAGE_VARIANT, variant)
+    prm = [3.0, 4.0, 6.0, 0.7, -0.4, 10.0, 10.0]
+    u = orc.project_ic(O.IC_VORTEX, prm)
+    ud = _cuda(u)
+    work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(4):
+        dref = orc.step(u, 0.1)
+        gpu.step(ud, work, dt, 0.1)
+        assert _host(dt)[0] == pytest.approx(dref, rel=1e-13)
+    assert rel_diff_floored(_host(ud), u, 1e-3).max() <= TOL
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rotated_blast_with_limiter(dim):
+    """A pressure jump with the positivity limiter on rotated roots."""
+    frames = _frames(dim, 7)
+    orc, gpu = _pair(dim, 2, 4, frames, limiter=True, levels=2)
     u = orc.project_ic(O.IC_UNIFORM, [1.0, 0.0, 0.0, 0.0, 1e-3])
-    u[0, 4, 0, :] = 1e3 / 0.4  # one leaf at high pressure, the rest near vacuum
+    u[0, dim + 1, 0, :] = 1e3 / 0.4  # one leaf at high pressure, the rest near vacuum
     ud = _cuda(u)
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(3):
