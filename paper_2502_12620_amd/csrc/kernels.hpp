@@ -501,10 +501,12 @@ constexpr int stage_default_cells()
 // 2-D degree 2 in FP64 spills 44 bytes per lane to run two waves per SIMD
 // instead of one (-20% time); 2-D degree 3 in FP32 runs two waves with 212
 // bytes of spills (-18%), while in FP64 (536 bytes) that is slower; 3-D
-// degree 1 in FP32 fits 164 registers (three waves); 3-D degree 2 in FP32
-// runs two waves with 268 bytes of spills (16^3 roots: 3.46 -> 2.17 ms),
-// while three waves (more spills) take 7.0 ms and in FP64 two waves spill
-// 936 bytes (2.69 -> 10.0 ms)
+// degree 1 in FP32 fits 164 registers (three waves; four: 335 -> 550 us on
+// 16^3 roots); 3-D degree 2 in FP32 runs two waves with 268 bytes of
+// spills (16^3 roots: 3.46 -> 2.17 ms), while three waves (more spills)
+// take 7.0 ms and in FP64 two waves spill 936 bytes (2.69 -> 10.0 ms); 2-D
+// degree 2 in FP32 fits 227 registers (two waves; three: 159 -> 263 us on
+// 64^2 roots)
 template <int D, int P, typename T = double>
 constexpr int stage_min_waves()
 {
