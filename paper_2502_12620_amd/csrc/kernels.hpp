@@ -490,11 +490,15 @@ constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
 // other's barriers (measured on 8^3 blocks at degree 1: 512-cell slabs
 // 671 us, 256: 582 us, 128: 564 us; 16^2 blocks at degree 2: 256-cell
 // slabs 184 us, 128: 171 us; 128^2 roots of 16^2 cells at degree 1:
-// 256-cell slabs 330 us, 128: 311 us, 64: 323 us)
+// 256-cell slabs 330 us, 128: 311 us, 64: 323 us; 16^3 roots of 8^3 cells
+// at degree 2 in FP64: 256-cell slabs 2.68 ms, 128: 2.53 ms, while in FP32
+// 2.18 against 2.21 ms)
 template <int D, int P, typename T = double>
 constexpr int stage_default_cells()
 {
-    return ((D == 3 && P <= 1) || (D == 2 && (P == 1 || P == 2))) ? 128 : stage_threads<D, P, T>();
+    return ((D == 3 && P <= 1) || (D == 3 && P == 2 && sizeof(T) == 8) || (D == 2 && (P == 1 || P == 2)))
+               ? 128
+               : stage_threads<D, P, T>();
 }
 // waves per SIMD the register budget is cut for, chosen by measurement on
 // large forests: 2-D degree 1 in FP32 fits 128 registers (four waves);
