@@ -234,7 +234,9 @@ def roofline_sweep(steps: int) -> dict:
     2-D 128 x 128 roots of 16 x 16 cells at degrees 1 and 2, 3-D 16^3 roots of
     8^3 cells at degrees 1 and 2 (FP64), and the 3-D degree-2 forest with the
     FP32 residual, its volume integral on the vector unit and on the matrix
-    cores.  Per case: the
+    cores; the 2-D 64 x 64-root degree-2 forest and the 3-D degree-1 forest
+    also with a rotated frame on every root and with bilinear / trilinear
+    roots.  Per case: the
     average stage-kernel duration (HIP events around every stage launch of
     `steps` eager steps), its algorithmic bytes, the fraction of the HBM
     roof, and the estimated flop rate against the FP64 (or FP32) roof."""
@@ -242,16 +244,25 @@ def roofline_sweep(steps: int) -> dict:
     from paper_2502_12620_amd import workloads as W
     from paper_2502_12620_amd.measure import run_workload
 
-    cases = [(W.roofline_2d(128, 1), G.FP64, 0), (W.roofline_2d(128, 2), G.FP64, 0),
-             (W.roofline_3d(16, 1), G.FP64, 0), (W.roofline_3d(16, 2), G.FP64, 0),
-             (W.roofline_3d(16, 2), G.FP32, 0), (W.roofline_3d(16, 2), G.FP32, 1)]
+    cases = [(W.roofline_2d(128, 1), G.FP64, 0, "affine"), (W.roofline_2d(128, 2), G.FP64, 0, "affine"),
+             (W.roofline_3d(16, 1), G.FP64, 0, "affine"), (W.roofline_3d(16, 2), G.FP64, 0, "affine"),
+             (W.roofline_3d(16, 2), G.FP32, 0, "affine"), (W.roofline_3d(16, 2), G.FP32, 1, "affine")]
+    # rotated frames on every root, and bilinear / trilinear roots (the stage
+    # time spans the guard fill and the stage kernel)
+    cases += [(W.roofline_2d(64, 2), G.FP64, 0, rk) for rk in ("affine", "rotated", "mapped")]
+    cases += [(W.roofline_3d(16, 1), G.FP64, 0, rk) for rk in ("rotated", "mapped")]
     out = {}
-    for w, prec, mf in cases:
-        r = run_workload(w, steps, warmup=2, precision=prec, mfma=mf)
+    for w, prec, mf, rk in cases:
+        r = run_workload(w, steps, warmup=2, precision=prec, mfma=mf, roots=rk)
         key = w.name + ("_fp32" + ("_mfma" if mf else "") if prec == G.FP32 else "_fp64")
-        out[key] = {k: r[k] for k in ("leaves", "dofs", "state_MB", "stage_kernel_us", "algorithmic_bytes_per_dof",
-                                      "achieved_GBs", "hbm_frac", "est_TFLOPs", "fp64_frac", "fp32_frac",
-                                      "mfma_volume", "dof_stage_per_s") if k in r}
+        if rk != "affine" or w.name == "rs_vortex2d_k64_p2":
+            key += "_" + rk
+        # (the flop estimate is that of the affine kernels: left out for
+        # the other root kinds)
+        keep = ("leaves", "dofs", "state_MB", "stage_kernel_us", "algorithmic_bytes_per_dof", "achieved_GBs",
+                "hbm_frac", "mfma_volume", "dof_stage_per_s") + (
+                    ("est_TFLOPs", "fp64_frac", "fp32_frac") if rk == "affine" else ("roots",))
+        out[key] = {k: r[k] for k in keep if k in r}
     return out
 
 
