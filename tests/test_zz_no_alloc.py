@@ -1,8 +1,9 @@
 """The allocation-free step (dgamr_step_static, a static device work area)
 against dgamr_step with a caller-owned work buffer: the same launches, so
 the states and time steps must agree bit for bit, on two calls in a row
-with a smaller forest the second time, and in 3-D where the work area also
-holds the guard traces of the lane kernel."""
+with a smaller forest the second time, in 3-D where the work area also
+holds the guard traces of the lane kernel, and on rotated and bilinear roots
+whose stages fill its guard buffer."""
 import numpy as np
 import pytest
 
@@ -12,16 +13,18 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _forest(G, w):
+def _forest(G, w, setup=None):
     f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
+    if setup is not None:
+        setup(f)
     z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
     for rule in w.initial_refinement:
         z = f.adapt(rule(w, f.keys()), z)
     return f
 
 
-def _compare(G, w, steps):
-    f = _forest(G, w)
+def _compare(G, w, steps, setup=None):
+    f = _forest(G, w, setup)
     print(f"static step: {w.name}, {f.n_leaves} leaves, {steps} steps", flush=True)
     u0 = f.project_ic(G.IC_VORTEX, w.ic_params)
     ua, ub = u0.clone(), u0.clone()
@@ -50,6 +53,23 @@ def test_static_step_in_3d_with_guard_traces():
     w = W.roofline_3d(2, 3)   # degree 3: the lane kernel reads guard traces from the work area
     w.n_cell = 4
     _compare(G, w, 2)
+    _compare(G, W.vortex_c1(), 2)
+
+
+@pytest.mark.parametrize("roots", ["rotated", "mapped"])
+def test_static_step_on_rotated_and_bilinear_roots(roots):
+    """Forests whose stages first fill the guard buffer of the work area:
+    a rotated frame on every root, or bilinear roots; then a plain forest."""
+    from paper_2502_12620_amd import dgamr as G
+
+    w = W.roofline_2d(4, 2)
+    w.n_cell = 8
+    if roots == "rotated":
+        frames = W.random_root_frames(w)
+        _compare(G, w, 2, lambda f: f.set_root_frames(frames))
+    else:
+        nodes = W.smooth_root_nodes(w)
+        _compare(G, w, 2, lambda f: f.set_root_nodes(nodes))
     _compare(G, W.vortex_c1(), 2)
 
 
