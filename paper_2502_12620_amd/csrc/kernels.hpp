@@ -492,11 +492,13 @@ constexpr int stage_threads() { return (D == 3 && P <= 1) ? 512 : 256; }
 // slabs 184 us, 128: 171 us; 128^2 roots of 16^2 cells at degree 1:
 // 256-cell slabs 330 us, 128: 311 us, 64: 323 us; 16^3 roots of 8^3 cells
 // at degree 2 in FP64: 256-cell slabs 2.68 ms, 128: 2.53 ms, while in FP32
-// 2.18 against 2.21 ms)
+// 2.18 against 2.21 ms; 64^2 roots of 16^2 cells at degree 3 in FP64: 256
+// cells 596 us, 128: 508 us, 64: 514 us, while in FP32 801 against 817 us)
 template <int D, int P, typename T = double>
 constexpr int stage_default_cells()
 {
-    return ((D == 3 && P <= 1) || (D == 3 && P == 2 && sizeof(T) == 8) || (D == 2 && (P == 1 || P == 2)))
+    return ((D == 3 && P <= 1) || (D == 3 && P == 2 && sizeof(T) == 8) || (D == 2 && (P == 1 || P == 2)) ||
+            (D == 2 && P == 3 && sizeof(T) == 8))
                ? 128
                : stage_threads<D, P, T>();
 }
