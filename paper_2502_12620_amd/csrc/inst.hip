@@ -124,8 +124,9 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
     const dim3 grid(unsigned(persist ? sh.grid : items)), block(nslab);
     const dim3 grid_all = dim3(unsigned(items));
     // the fused stage takes the far side of block faces inline (copy,
-    // split, combine, mirror of the neighbour cells); the residual entry
-    // point reads guard coefficients
+    // split, combine, mirror of the neighbour cells), or on forests with
+    // rotated root frames from the guard fill; the residual entry point
+    // reads guard coefficients
     if constexpr (EQ == EQ_ADVECTION) {
         // one variable: the far side is always taken inline
         if (gm == GUARD_INLINE && om == OUT_RK) {
