@@ -442,7 +442,7 @@ int orc_set_frames(orc_forest *f, const int *codes)
             if ((f->hi[a] - f->lo[a]) / f->roots[a] != (f->hi[0] - f->lo[0]) / f->roots[0]) return -1;
     /* the mortar of the conservative mode and the convection velocity are
      * written along the global axes */
-    if (any && (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_ADVECTION || f->nodes)) return -1;
+    if (any && (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_ADVECTION)) return -1;
     free(f->frame);
     f->frame = malloc(sizeof(int) * ntree);
     memcpy(f->frame, codes, sizeof(int) * ntree);
@@ -455,12 +455,15 @@ int orc_set_frames(orc_forest *f, const int *codes)
  * [x (roots_z + 1)] grid nodes, x fastest, d coordinates each; root (rx,
  * ry[, rz]) has the corner nodes (rx + bx, ry + by[, rz + bz]), b in {0,1}^d.
  * On a periodic axis the last node layer must be the first one moved by the
- * period.  Every root must have a positive Jacobian at its corners.  Not
- * with rotated frames, the conservative mode, the diffusion equation or the
- * limiter. */
+ * period.  Every root must have a positive Jacobian at its corners.  A
+ * root with a rotated frame takes its local axes along the node grid's axes
+ * as its frame turns them (its corner b is the grid node the frame maps it
+ * to); on such forests the momentum is stored along the global axes, and
+ * the guard fill turns only coordinates.  Not with the conservative mode,
+ * the diffusion equation or the limiter. */
 int orc_set_nodes(orc_forest *f, const double *xy)
 {
-    if (f->frame || f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_DIFFUSION) return -1;
+    if (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_DIFFUSION) return -1;
     int d = f->dim, n[3] = {f->roots[0] + 1, f->roots[1] + 1, d == 3 ? f->roots[2] + 1 : 1};
     long total = (long)n[0] * n[1] * n[2];
 #define NODE(i, j, k) (xy + (long)d * (((long)(k) * n[1] + (j)) * n[0] + (i)))

@@ -96,9 +96,11 @@ int orc_set_frames(orc_forest *f, const int *codes);
  * advances it by dt */
 /* Sec. 3.3, Eq. 6: bilinear (3-D: trilinear) root blocks from the root
  * grid nodes xy ((roots_x + 1) x (roots_y + 1) [x (roots_z + 1)] points of d
- * coordinates, x fastest).  -1 if not allowed (frames, conservative mode,
- * diffusion), if a root has a non-positive Jacobian at a corner, or if
- * periodic node copies do not match. */
+ * coordinates, x fastest).  With rotated frames (either call first) a
+ * root's local axes follow the node grid's axes as its frame turns them,
+ * and the momentum is stored along the global axes.  -1 if not allowed
+ * (conservative mode, diffusion), if a root has a non-positive Jacobian at
+ * a corner, or if periodic node copies do not match. */
 int orc_set_nodes(orc_forest *f, const double *xy);
 void orc_set_time(orc_forest *f, double t);
 double orc_get_time(const orc_forest *f);

@@ -103,9 +103,18 @@ static void cell_corners(const orc_forest *f, int i, int c, double cx[8][3])
     long hu = size / f->N;
     int nx = f->roots[0] + 1, ny = f->roots[1] + 1;
     int r[3] = {k->tree % f->roots[0], (k->tree / f->roots[0]) % f->roots[1], k->tree / (f->roots[0] * f->roots[1])};
+    /* a rotated root's local axis l runs along the node grid's axis a with
+     * Q[a][l] != 0, reversed where Q[a][l] = -1 */
+    int Q[3][3];
+    orc_frame_matrix(f, k->tree, Q);
     for (int b = 0; b < nk; ++b) {
-        double s[3] = {0, 0, 0};
-        for (int a = 0; a < d; ++a) s[a] = (double)(lo[a] + (ijk[a] + ((b >> a) & 1)) * hu) / (double)f->unit;
+        double sl[3] = {0, 0, 0}, s[3] = {0, 0, 0};
+        for (int a = 0; a < d; ++a) sl[a] = (double)(lo[a] + (ijk[a] + ((b >> a) & 1)) * hu) / (double)f->unit;
+        for (int l = 0; l < d; ++l)
+            for (int a = 0; a < d; ++a) {
+                if (Q[a][l] == 1) s[a] = sl[l];
+                if (Q[a][l] == -1) s[a] = 1.0 - sl[l];
+            }
         for (int a = 0; a < 3; ++a) cx[b][a] = 0.0;
         /* the root's multilinear map at s */
         for (int n = 0; n < nk; ++n) {
@@ -289,7 +298,9 @@ static int tensor_points(int dim, int q, const double *gx, const double *gw, dou
  * dst_size).  Each cell's polynomial lives in its root's local frame: a
  * point's reference coordinates in a cell are Q^T times those taken along
  * the global axes of its box, and the source state's momentum is turned
- * into the destination frame, Qd^T Qs m (Qs, Qd null: identity).  src
+ * into the destination frame, Qd^T Qs m (Qs, Qd null: identity; on
+ * bilinear roots the momentum is stored along the global axes and only the
+ * coordinates turn).  src
  * points at coefficient (v=0,m=0) with modes src_stride apart and
  * variables nb*src_stride apart.  Gauss rule with p+1 points per axis on
  * the overlap box (exact: degree <= 2p per axis). */
@@ -325,7 +336,7 @@ void orc_project_overlap(const orc_forest *f, const double *src, long src_stride
         }
         double u[5];
         eval_poly(f, src, (long)f->nb * src_stride, src_stride, xs, u);
-        if (Qs) {
+        if (Qs && !mapped(f)) { /* bilinear roots keep the momentum along the global axes */
             rotate_state(f, Qs, 0, u);
             rotate_state(f, Qd, 1, u);
         }
@@ -467,13 +478,15 @@ static void cell_point(const orc_forest *f, int i, int c, const double *xi, doub
 }
 
 /* the analytic state at the local reference point xi of cell c of leaf i,
- * in the leaf's frame */
+ * in the leaf's frame (on bilinear roots the momentum stays along the
+ * global axes) */
 static void analytic_local(const orc_forest *f, int i, int c, int kind, const double *params, double t,
                            const double *xi, double *u)
 {
     double x[3];
     cell_point(f, i, c, xi, x);
     analytic_state(f, kind, params, t, x, u);
+    if (mapped(f)) return;
     int Q[3][3];
     orc_frame_matrix(f, f->leaf[i].tree, Q);
     rotate_state(f, Q, 1, u);

@@ -7,7 +7,10 @@ on distorted roots with hanging faces (the discrete metric identities of a
 bilinear map); conforming distorted forests conserve every variable (Euler and scalar
 convection); the isentropic vortex converges at order p+1 on a smoothly
 distorted periodic grid; folded roots and unmatched periodic nodes are
-refused.  CPU only."""
+refused.  With rotated root frames: rectangular nodes reproduce the aligned
+box grid once the frames' cell and mode permutation is undone (the momentum
+stays along the global axes), and on distorted roots the choice of frames
+does not change the solution.  CPU only."""
 import numpy as np
 import pytest
 
@@ -214,3 +217,86 @@ def test_3d_folded_root_is_refused():
     f = O.Forest(3, 1, 2, roots, lo, hi, (1, 1, 1), 1)
     with pytest.raises(ValueError):
         f.set_nodes(g)
+
+
+# ---------------------------------------------------------------- rotated frames on bilinear / trilinear roots
+
+from tests.test_oracle_rotation import to_aligned  # noqa: E402
+
+
+def _refine_tree0(f):
+    fl = np.zeros(f.n_leaves, np.int8)
+    fl[0] = 1
+    f.adapt(fl)
+
+
+@pytest.mark.parametrize("frames", [(1, 0, 0, 0), (0, 1, 2, 3), (3, 2, 1, 1)])
+@pytest.mark.parametrize("p", [1, 2])
+def test_rectangular_nodes_with_frames_reproduce_the_aligned_box_grid(frames, p):
+    """Rotated frames and rectangular nodes, root 0 refined (hanging faces on
+    rotated faces): after three steps the state, with the frames' cell and
+    mode permutation undone, equals the aligned box-grid run."""
+    roots, lo, hi = (2, 2), (0.0, 0.0), (10.0, 10.0)
+    fa = O.Forest(2, p, 4, roots, lo, hi, (0, 0), 2)
+    fm = O.Forest(2, p, 4, roots, lo, hi, (0, 0), 2)
+    fm.set_frames(frames)
+    fm.set_nodes(box_nodes(roots, lo, hi))
+    _refine_tree0(fa)
+    _refine_tree0(fm)
+    ua, um = fa.project_ic(O.IC_VORTEX, PRM), fm.project_ic(O.IC_VORTEX, PRM)
+    np.testing.assert_allclose(to_aligned(fm, um, frames, roots, fa, momentum_local=False), ua, atol=1e-13)
+    for _ in range(3):
+        assert fm.step(um, 0.1) == pytest.approx(fa.step(ua, 0.1), rel=1e-13)
+    got = to_aligned(fm, um, frames, roots, fa, momentum_local=False)
+    assert np.abs(got - ua).max() <= 1e-12 * np.abs(ua).max()
+    np.testing.assert_allclose(fm.totals(um), fa.totals(ua), rtol=1e-12, atol=1e-11)
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_frames_do_not_change_the_solution_on_distorted_roots(p):
+    """The same distorted periodic root grid with and without rotated
+    frames, root 0 refined: the same physical solution after three steps."""
+    roots, lo, hi, frames = (2, 2), (0.0, 0.0), (10.0, 10.0), (2, 1, 3, 1)
+    nodes = distorted_nodes(roots, lo, hi, 0.2, seed=11)
+    fa = O.Forest(2, p, 4, roots, lo, hi, (0, 0), 2)
+    fm = O.Forest(2, p, 4, roots, lo, hi, (0, 0), 2)
+    fa.set_nodes(nodes)
+    fm.set_nodes(nodes)
+    fm.set_frames(frames)  # after the nodes: either order
+    _refine_tree0(fa)
+    _refine_tree0(fm)
+    ua, um = fa.project_ic(O.IC_VORTEX, PRM), fm.project_ic(O.IC_VORTEX, PRM)
+    np.testing.assert_allclose(to_aligned(fm, um, frames, roots, fa, momentum_local=False), ua,
+                               atol=1e-12 * np.abs(ua).max())
+    for _ in range(3):
+        assert fm.step(um, 0.1) == pytest.approx(fa.step(ua, 0.1), rel=1e-12)
+    got = to_aligned(fm, um, frames, roots, fa, momentum_local=False)
+    assert np.abs(got - ua).max() <= 1e-11 * np.abs(ua).max()
+
+
+@pytest.mark.parametrize("bc", [0, 1])
+def test_free_stream_on_rotated_distorted_roots_with_hanging_faces(bc):
+    roots, lo, hi = (3, 3), (0.0, 0.0), (3.0, 3.0)
+    f = O.Forest(2, 2, 4, roots, lo, hi, (bc, bc), 3)
+    f.set_frames([1, 0, 3, 2, 1, 0, 0, 2, 3])
+    f.set_nodes(distorted_nodes(roots, lo, hi, 0.2, seed=5))
+    _refine(f, 4)
+    _refine(f, 0)
+    u = f.project_ic(O.IC_UNIFORM, [1.0, 0.3, -0.2, 0.0, 1.0])
+    assert np.abs(f.residual(u)).max() < 1e-11
+
+
+def test_3d_box_nodes_with_frames_reproduce_the_aligned_box_grid():
+    roots, lo, hi, frames = (2, 2, 2), (0.0,) * 3, (4.0,) * 3, (5, 0, 17, 9, 0, 23, 2, 12)
+    fa = O.Forest(3, 1, 2, roots, lo, hi, (0, 0, 0), 2)
+    fm = O.Forest(3, 1, 2, roots, lo, hi, (0, 0, 0), 2)
+    fm.set_frames(frames)
+    fm.set_nodes(box_nodes3(roots, lo, hi))
+    _refine_tree0(fa)
+    _refine_tree0(fm)
+    ua, um = fa.project_ic(O.IC_VORTEX, PRM3), fm.project_ic(O.IC_VORTEX, PRM3)
+    np.testing.assert_allclose(to_aligned(fm, um, frames, roots, fa, momentum_local=False), ua, atol=1e-13)
+    for _ in range(2):
+        assert fm.step(um, 0.1) == pytest.approx(fa.step(ua, 0.1), rel=1e-13)
+    got = to_aligned(fm, um, frames, roots, fa, momentum_local=False)
+    assert np.abs(got - ua).max() <= 1e-12 * np.abs(ua).max()

@@ -34,9 +34,11 @@ def frame_matrix(dim, code):
     return out[code]
 
 
-def to_aligned(f_rot, u_rot, frames, roots, f_al):
+def to_aligned(f_rot, u_rot, frames, roots, f_al, momentum_local=True):
     """The state of the rotated forest expressed in the aligned forest's
-    leaves, cells, modes and momentum components."""
+    leaves, cells, modes and momentum components (momentum_local False:
+    the rotated forest already stores the momentum along the global axes,
+    as on bilinear roots)."""
     d, N, p = f_rot.dim, f_rot.N, f_rot.p
     modes = RM.graded_modes(d, p)
     R = list(roots) + [1] * (3 - d)
@@ -65,7 +67,7 @@ def to_aligned(f_rot, u_rot, frames, roots, f_al):
                     sign *= Q[g, l] ** m[l]
                 gi = modes.index(tuple(mg))
                 vals = u_rot[li, :, mi, cell].copy()
-                if f_rot.nv == d + 2:
+                if f_rot.nv == d + 2 and momentum_local:
                     vals[1:1 + d] = Q @ vals[1:1 + d]
                 out[ai, :, gi, gcell] = sign * vals
     assert not np.isnan(out).any()
