@@ -121,11 +121,15 @@ int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out);
  * neighbour's frame, then turned into the own frame (K_d = R^n S^i K_s,
  * Eq. 15-17): a signed permutation of the modes (exact: total-degree
  * Legendre spaces are closed under signed permutations of the axes) and of
- * the momentum components.  The steps of such a forest run the fill, the
- * residual over the guard buffer and the stage update as separate launches.
- * Requires equal root edges, the unrefined forest (ESTATE otherwise), the
- * paper hanging mode and the Euler or diffusion equation (EUNSUPPORTED);
- * pools do not admit such forests. */
+ * the momentum components.  Each stage of such a forest runs the fill into
+ * the guard buffer, then the stage kernel reading the far side of block
+ * faces from it, fused with the stage update and the limiter.  With
+ * bilinear / trilinear roots (dgamr_set_root_nodes, before or after this
+ * call) a root's local axes follow the node grid's axes as its frame turns
+ * them, the momentum is stored along the global axes, and the fill turns
+ * the modes only.  Requires equal root edges, the unrefined forest (ESTATE
+ * otherwise), the paper hanging mode and the Euler or diffusion equation
+ * (EUNSUPPORTED); pools do not admit such forests. */
 int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes);
 
 /* Sec. 3.3, Eq. 6: root blocks as bilinear (3-D: trilinear) images of the
@@ -144,9 +148,10 @@ int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes);
  * launches; the CFL rate takes the cell means over the physical cells and,
  * per reference axis, the face normal and width 2 det(J) / |row of adj(J)|
  * at the cell centre; the totals integrate over the physical cells; the
- * indicator keeps the reference cell means (mode 0).  EUNSUPPORTED for 3-D
- * degree 3, with rotated frames, the conservative mode, the limiter, the
- * diffusion equation or FP32; EINVAL for nodes that are not finite, a root
+ * indicator keeps the reference cell means (mode 0).  Root frames
+ * (dgamr_set_root_frames) may be set as well.  EUNSUPPORTED for 3-D degree
+ * 3, the conservative mode, the limiter, the diffusion equation or FP32;
+ * EINVAL for nodes that are not finite, a root
  * with a non-positive corner Jacobian, or unmatched periodic nodes.  Pools
  * do not admit such forests. */
 int dgamr_set_root_nodes(dgamr_forest *f, const double *xy);

@@ -94,7 +94,8 @@ int upload(dgamr_forest *f)
 int launch_fill(dgamr_forest *f, const double *u, double *guard, bool traces, hipStream_t s)
 {
     int nf = 2 * f->topo.dim();
-    dgk::FillArgs a{u, guard, f->d_links, f->d_plans, nullptr, f->topo.n() * nf, f->topo.desc().n_cell, traces ? 1 : 0};
+    dgk::FillArgs a{u,       guard, f->d_links, f->d_plans, nullptr, f->topo.n() * nf, f->topo.desc().n_cell,
+                    traces ? 1 : 0, f->topo.mapped() ? 1 : 0};
     if (a.nfaces == 0) return DGAMR_OK;
     return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
         HIP_TRY((dgk::launch_fill<D, P>(a, nfc_of(f), s, nv_of(f))));

@@ -180,8 +180,8 @@ int Forest::set_frames(const int32_t *codes, std::string &err)
                 err = "rotated root frames need equal root edges";
                 return DGAMR_EINVAL;
             }
-        if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.equation == DGAMR_EQ_ADVECTION || mapped()) {
-            err = "rotated root frames are built for box roots, the paper hanging mode, Euler and diffusion";
+        if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.equation == DGAMR_EQ_ADVECTION) {
+            err = "rotated root frames are built for the paper hanging mode, Euler and diffusion";
             return DGAMR_EUNSUPPORTED;
         }
     }
@@ -197,10 +197,10 @@ int Forest::set_nodes(const double *xy, std::string &err)
         err = "trilinear root blocks are built for degree <= 2";
         return DGAMR_EUNSUPPORTED;
     }
-    if (rotated_ || desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.limiter != DGAMR_LIMITER_NONE ||
+    if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.limiter != DGAMR_LIMITER_NONE ||
         desc_.equation == DGAMR_EQ_DIFFUSION) {
-        err = "bilinear / trilinear root blocks are built for aligned frames, the paper hanging mode, no limiter, "
-              "Euler and scalar convection";
+        err = "bilinear / trilinear root blocks are built for the paper hanging mode, no limiter, Euler and "
+              "scalar convection";
         return DGAMR_EUNSUPPORTED;
     }
     const int n[3] = {desc_.roots[0] + 1, desc_.roots[1] + 1, d == 3 ? desc_.roots[2] + 1 : 1};
@@ -531,11 +531,17 @@ std::vector<LeafGeo> Forest::geometry() const
         for (int b = 0; b < 8; ++b) G.node[b][0] = G.node[b][1] = G.node[b][2] = 0.0;
         if (mapped()) {
             // the leaf's corners: the root's multilinear map at the leaf's
-            // corners in the root's unit box
+            // corners in the root's unit box; the corner's local position
+            // turned onto the node grid's axes by the root's frame
             const int nx = desc_.roots[0] + 1, ny = desc_.roots[1] + 1;
             for (int b = 0; b < (1 << d); ++b) {
-                double s[3] = {0.0, 0.0, 0.0};
-                for (int a = 0; a < d; ++a) s[a] = double(k.idx[a] + ((b >> a) & 1)) / span;
+                double sl[3] = {0.0, 0.0, 0.0}, s[3] = {0.0, 0.0, 0.0};
+                for (int a = 0; a < d; ++a) sl[a] = double(k.idx[a] + ((b >> a) & 1)) / span;
+                for (int l = 0; l < d; ++l)
+                    for (int a = 0; a < d; ++a) {
+                        if (Q[a][l] == 1) s[a] = sl[l];
+                        if (Q[a][l] == -1) s[a] = 1.0 - sl[l];
+                    }
                 for (int nn = 0; nn < (1 << d); ++nn) {
                     double w = 1.0;
                     int id[3] = {r[0], r[1], r[2]};

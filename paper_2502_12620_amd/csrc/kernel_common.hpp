@@ -332,6 +332,8 @@ struct FillArgs {
     int N;
     int traces;        // 0: guard coefficients G[leaf][face][var][mode][t];
                        // 1: their traces on the face, G[leaf][face][var][point][t]
+    int global_vectors; // 1: momentum along the global axes (bilinear / trilinear
+                        // roots): across rotated frames only the coordinates turn
 };
 
 struct IcParams {

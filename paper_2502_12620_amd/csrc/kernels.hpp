@@ -980,7 +980,7 @@ __global__ __launch_bounds__(256) void k_fill(FillArgs g)
                 ks[v][idx] = sg * kv[n];
             }
         }
-        if (NV == D + 2) { // momentum into this leaf's frame: m_dst[l] = sum_l' m[l'][l] m_src[l']
+        if (NV == D + 2 && !g.global_vectors) { // momentum into this leaf's frame: m_dst[l] = sum_l' m[l'][l] m_src[l']
 #pragma unroll
             for (int n = 0; n < NB; ++n) {
                 double mv[3] = {0.0, 0.0, 0.0};

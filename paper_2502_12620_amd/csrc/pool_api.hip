@@ -142,7 +142,7 @@ int pool_stage(dgamr_pool *p, int stage, const double *us, const double *un, dou
     if (dgk::stage_reads_traces(p->dim, sh, lim, fp32, a.conservative != 0, false, p->N)) {
         gm = dgk::GUARD_TRACE;
         a.guard = w.guard;
-        dgk::FillArgs fa{us, w.guard, p->d_links, nullptr, p->d_work, p->nwork * 2 * p->dim, p->N, 1};
+        dgk::FillArgs fa{us, w.guard, p->d_links, nullptr, p->d_work, p->nwork * 2 * p->dim, p->N, 1, 0};
         CHECK(dispatch(p->dim, p->degree, [&](auto D, auto P) -> int {
             HIP_TRY((dgk::launch_fill<D, P>(fa, p->nfc, s)));
             return DGAMR_OK;

@@ -252,3 +252,78 @@ def test_trilinear_scalar_convection():
         gpu.step(ud, work, dt, 0.1)
         assert _host(dt)[0] == pytest.approx(dref, rel=1e-13)
     assert rel_diff(_host(ud), u).max() <= TOL
+
+
+# ---------------------------------------------------------------- rotated frames on bilinear / trilinear roots
+
+def _frames(dim, n, seed):
+    rng = np.random.default_rng(seed)
+    return [int(x) for x in rng.integers(0, 4 if dim == 2 else 24, n)]
+
+
+def _rotated_mapped_checks(orc, gpu, prm, steps, seed):
+    G = _G()
+    u = orc.project_ic(O.IC_VORTEX, prm)
+    ud = gpu.project_ic(G.IC_VORTEX, prm)
+    assert rel_diff_floored(_host(ud), u, 1e-3).max() <= TOL
+    rng = np.random.default_rng(seed)
+    u[:, :, 1:, :] += 0.01 * rng.standard_normal(u[:, :, 1:, :].shape)
+    ud = _cuda(u)
+    gd = gpu.new_guard()
+    gpu.fill_guardcells(ud, gd)
+    g_ref = orc.fill_guards(u)
+    assert np.abs(_host(gd) - g_ref).max() <= 1e-13 * np.abs(g_ref).max()
+    rd = gpu.new_residual()
+    gpu.dg_residual(ud, gd, rd)
+    assert rel_diff_floored(_host(rd), orc.residual(u, g_ref), 1e-3).max() <= TOL_RES
+    work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        dref = orc.step(u, 0.1)
+        gpu.step(ud, work, dt, 0.1)
+        assert _host(dt)[0] == pytest.approx(dref, rel=1e-13)
+    assert rel_diff_floored(_host(ud), u, 1e-3).max() <= TOL
+    np.testing.assert_allclose(_host(gpu.conserved_totals(ud, work)), orc.totals(u), rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("p,N", [(1, 4), (2, 4), (3, 4)])
+@pytest.mark.parametrize("bc", [0, 1])
+def test_rotated_frames_on_bilinear_roots(p, N, bc):
+    """Distorted 3x3 roots with seeded frames (set after the nodes), the
+    centre root and one of its children refined: initial projection, fill
+    (the modes turned, the momentum kept along the global axes), residual,
+    steps and totals against the oracle."""
+    print(f"rotated bilinear parity p={p} N={N} bc={bc}", flush=True)
+    G = _G()
+    roots, lo, hi = (3, 3), (0.0, 0.0), (10.0, 10.0)
+    args = (2, p, N, roots, lo, hi, (bc, bc), 3)
+    orc, gpu = O.Forest(*args), G.Forest(*args)
+    nodes = distorted_nodes(roots, lo, hi, 0.2, seed=p + 3 * bc)
+    frames = _frames(2, 9, seed=p + N + bc)
+    orc.set_nodes(nodes)
+    gpu.set_root_nodes(nodes)
+    orc.set_frames(frames)
+    gpu.set_root_frames(frames)
+    _adapt_both(orc, gpu, 4)
+    _adapt_both(orc, gpu, 5)
+    assert np.array_equal(orc.keys(), gpu.keys())
+    _rotated_mapped_checks(orc, gpu, PRM, 3, seed=p + bc)
+
+
+@pytest.mark.parametrize("p,N", [(1, 2), (2, 2)])
+def test_rotated_frames_on_trilinear_roots(p, N):
+    """Distorted 2x2x2 roots with seeded frames (set before the nodes),
+    root 0 refined: the same checks in 3-D."""
+    print(f"rotated trilinear parity p={p} N={N}", flush=True)
+    G = _G()
+    roots, lo, hi = (2, 2, 2), (0.0,) * 3, (4.0,) * 3
+    args = (3, p, N, roots, lo, hi, (0, 0, 0), 2)
+    orc, gpu = O.Forest(*args), G.Forest(*args)
+    frames = _frames(3, 8, seed=40 + p)
+    orc.set_frames(frames)
+    gpu.set_root_frames(frames)
+    nodes = distorted_nodes3(roots, lo, hi, 0.15, seed=p + 7)
+    orc.set_nodes(nodes)
+    gpu.set_root_nodes(nodes)
+    _adapt_both(orc, gpu, 0)
+    assert np.array_equal(orc.keys(), gpu.keys())
+    _rotated_mapped_checks(orc, gpu, PRM3, 2, seed=p)
