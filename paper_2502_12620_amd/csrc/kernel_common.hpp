@@ -245,6 +245,16 @@ __device__ __forceinline__ void atomic_max_bits(unsigned long long *out, double 
     if (__hip_atomic_load(out, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < b) atomicMax(out, b);
 }
 
+// Orders this wave's LDS accesses before and after it: enough in place of a
+// workgroup barrier when every lane that exchanges data through LDS
+// belongs to the same wave (a wave executes its LDS instructions in order)
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Folds the workgroup's maximum of x (non-negative; a NaN wins) into *out
 // with an atomic max on the bit pattern.  A workgroup of whole waves takes
 // the maximum across each wave with lane exchanges and combines one value

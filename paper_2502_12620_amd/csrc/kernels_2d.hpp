@@ -191,6 +191,7 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
     const int i = lc % N, j = j0 + lc / N;
     const int cell = i + N * j;
     const int nslab = rows * N;           // cells in the slab
+    const bool x_in_wave = 64 % (4 * N) == 0; // uniform
     const double isE = v == 3 ? 1.0 : 0.0;
     const double scale[2] = {g.geo[leaf].scale[0], g.geo[leaf].scale[1]};
     const long sv = long(NB) * ncell;
@@ -270,6 +271,12 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
     auto slot = [&](int f, int c) { return (f * nslab + c) * 4 + v; };
     static_for<0, 2>([&](auto Ai) {
         constexpr int A = Ai;
+        // x faces join cells of one row; when whole rows fill whole waves
+        // (4 N divides 64) the x exchange stays inside a wave
+        auto sync_axis = [&]() __attribute__((always_inline)) {
+            if (A == 0 && x_in_wave) wave_lds_sync();
+            else __syncthreads();
+        };
         const double isM = v == 1 + A ? 1.0 : 0.0;
         const int ia = A == 0 ? i : j;
         const int t = A == 0 ? j : i;
@@ -292,7 +299,7 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
         if (mort_m) mortar_lift_v<P, A>(g, K, R, v, -1, A == 0 ? Lxm : Lym, t, sc, isM, isE);
         if (mort_p) mortar_lift_v<P, A>(g, K, R, v, +1, A == 0 ? Lxp : Lyp, t, sc, isM, isE);
         double Tm[NF], Fm[NF], Fp[NF];
-        __syncthreads();
+        sync_axis();
 #pragma unroll
         for (int f = 0; f < NF; ++f) {
             double e, o;
@@ -300,7 +307,7 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
             lds[slot(f, lc)] = e + o;
             Tm[f] = e - o;
         }
-        __syncthreads();
+        sync_axis();
         // - face: left state = the + trace of the polynomial below
         if (mort_m) {
 #pragma unroll
@@ -312,10 +319,10 @@ __global__ __launch_bounds__(512) void k_stage2v(StageArgs g, int rows)
                 Fm[f] = rusanov_v<A>(tl, Tm[f], g.gamma, isM, isE);
             }
         }
-        __syncthreads();
+        sync_axis();
 #pragma unroll
         for (int f = 0; f < NF; ++f) lds[slot(f, lc)] = Fm[f];
-        __syncthreads();
+        sync_axis();
         // + face: computed by the cell above, unless that cell is outside the slab
         if (lds_p) {
 #pragma unroll
