@@ -440,9 +440,8 @@ int orc_set_frames(orc_forest *f, const int *codes)
     if (any)
         for (int a = 1; a < f->dim; ++a)
             if ((f->hi[a] - f->lo[a]) / f->roots[a] != (f->hi[0] - f->lo[0]) / f->roots[0]) return -1;
-    /* the mortar of the conservative mode and the convection velocity are
-     * written along the global axes */
-    if (any && (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_ADVECTION)) return -1;
+    /* the mortar of the conservative mode is written along the global axes */
+    if (any && f->hanging == ORC_HANG_CONSERVATIVE) return -1;
     free(f->frame);
     f->frame = malloc(sizeof(int) * ntree);
     memcpy(f->frame, codes, sizeof(int) * ntree);

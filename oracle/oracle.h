@@ -88,9 +88,9 @@ void orc_set_diffusion(orc_forest *f, double nu, const double *avec);
  * determinant +1 (permutations of the local axes in lexicographic order,
  * then the sign patterns of the local axes, bit l = axis l negative).  The
  * leaf keys, cells, modes and momentum of a root are in its local frame.
- * Requires equal root edges, the paper hanging mode and the Euler or
- * diffusion equation; returns 0, or -1 (nothing changed).  Call before
- * refining. */
+ * The convection velocity is taken along each root's local axes.
+ * Requires equal root edges and the paper hanging mode; returns 0, or -1
+ * (nothing changed).  Call before refining. */
 int orc_set_frames(orc_forest *f, const int *codes);
 /* time of the state (Dirichlet data of the diffusion equation); orc_step
  * advances it by dt */

@@ -370,18 +370,31 @@ static double wrap_half(double d, double period)
 }
 
 /* Physical flux along axis a: Euler (Eq. 2, 23) or scalar convection
- * (Sec. 5.1, F = vel u). */
-static void phys_flux(const orc_forest *f, const double *u, int a, double *fl)
+ * (Sec. 5.1, F = vel u, vel the velocity along the axes a is taken on). */
+static void phys_flux(const orc_forest *f, const double *vel, const double *u, int a, double *fl)
 {
-    if (f->equation == ORC_EQ_ADVECTION) fl[0] = f->vel[a] * u[0];
+    if (f->equation == ORC_EQ_ADVECTION) fl[0] = vel[a] * u[0];
     else orc_euler_flux(f->dim, f->gamma, u, a, fl);
 }
 
 /* Numerical flux for the outward normal side*e_axis (Eq. 5). */
-static void num_flux(const orc_forest *f, const double *um, const double *up, int axis, int side, double *fh)
+static void num_flux(const orc_forest *f, const double *vel, const double *um, const double *up, int axis, int side,
+                     double *fh)
 {
-    if (f->equation == ORC_EQ_ADVECTION) fh[0] = orc_upwind(f->vel, um[0], up[0], axis, side);
+    if (f->equation == ORC_EQ_ADVECTION) fh[0] = orc_upwind(vel, um[0], up[0], axis, side);
     else orc_rusanov(f->dim, f->gamma, um, up, axis, side, fh);
+}
+
+/* the convection velocity along the local axes of leaf i's root,
+ * Q^T vel (Sec. 3.1 frames; the identity on aligned roots) */
+static void local_velocity(const orc_forest *f, int i, double *vl)
+{
+    int Q[3][3];
+    orc_frame_matrix(f, f->leaf[i].tree, Q);
+    for (int l = 0; l < 3; ++l) {
+        vl[l] = 0.0;
+        for (int a = 0; a < f->dim; ++a) vl[l] += Q[a][l] * f->vel[a];
+    }
 }
 
 /* Analytic states used as initial conditions and exact solutions.
@@ -665,7 +678,7 @@ static void mapped_residual(const orc_forest *f, const double *u, const double *
                 map_jacobian(f, cx, vxi[iq], J);
                 for (int e = 0; e < d; ++e) adj_row(f, J, e, A[e]);
                 double F[3][5];
-                for (int a = 0; a < d; ++a) phys_flux(f, uq, a, F[a]);
+                for (int a = 0; a < d; ++a) phys_flux(f, f->vel, uq, a, F[a]);
                 for (int m = 0; m < nb; ++m)
                     for (int e = 0; e < d; ++e) {
                         double de = orc_dphi(d, f->exps + 3 * m, vxi[iq], e);
@@ -794,6 +807,8 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
         long hu = size / f->N;
         double h[3] = {1, 1, 1};
         for (int a = 0; a < d; ++a) h[a] = local_h(f, i, a); /* local axes */
+        double vl[3];
+        local_velocity(f, i, vl);
         double J = 1.0;
         for (int a = 0; a < d; ++a) J *= 0.5 * h[a];
         for (int c = 0; c < nc; ++c) {
@@ -808,7 +823,7 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
                 eval_with(f, K, (long)f->nb * nc, nc, vphi + iq * nb, uq);
                 for (int a = 0; a < d; ++a) {
                     double fl[5] = {0, 0, 0, 0, 0};
-                    phys_flux(f, uq, a, fl);
+                    phys_flux(f, vl, uq, a, fl);
                     for (int m = 0; m < f->nb; ++m) {
                         double dp = vdphi[(iq * d + a) * nb + m] * 2.0 / h[a];
                         for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] += vw[iq] * J * fl[v] * dp;
@@ -861,7 +876,7 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
                             double um[5], up[5], fh[5];
                             eval_poly(f, K, (long)f->nb * nc, nc, xo, um);
                             eval_poly(f, Kf, (long)f->nb * nc, nc, xf, up);
-                            num_flux(f, um, up, axis, side, fh);
+                            num_flux(f, vl, um, up, axis, side, fh);
                             for (int m = 0; m < f->nb; ++m) {
                                 double ph = orc_phi(d, f->exps + 3 * m, xo);
                                 for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] -= fw[iq] * Jff * fh[v] * ph;
@@ -886,7 +901,7 @@ void orc_residual(const orc_forest *f, const double *u, const double *g, double 
                     double um[5], up[5], fh[5];
                     eval_with(f, K, (long)f->nb * nc, nc, po, um);
                     eval_with(f, Kn, nsv, nsm, fnbr + (face * nfq + iq) * nb, up);
-                    num_flux(f, um, up, axis, side, fh);
+                    num_flux(f, vl, um, up, axis, side, fh);
                     for (int m = 0; m < f->nb; ++m) {
                         double ph = po[m];
                         for (int v = 0; v < f->nv; ++v) acc[v * f->nb + m] -= fw[iq] * Jf * fh[v] * ph;
