@@ -127,9 +127,10 @@ int dgamr_create_forest(const dgamr_forest_desc *desc, dgamr_forest **out);
  * bilinear / trilinear roots (dgamr_set_root_nodes, before or after this
  * call) a root's local axes follow the node grid's axes as its frame turns
  * them, the momentum is stored along the global axes, and the fill turns
- * the modes only.  Requires equal root edges, the unrefined forest (ESTATE
- * otherwise), the paper hanging mode and the Euler or diffusion equation
- * (EUNSUPPORTED); pools do not admit such forests. */
+ * the modes only.  Scalar convection takes the velocity along each root's
+ * local axes.  Requires equal root edges, the unrefined forest (ESTATE
+ * otherwise) and the paper hanging mode (EUNSUPPORTED); pools do not admit
+ * such forests. */
 int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes);
 
 /* Sec. 3.3, Eq. 6: root blocks as bilinear (3-D: trilinear) images of the

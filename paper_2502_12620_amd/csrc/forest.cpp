@@ -180,8 +180,8 @@ int Forest::set_frames(const int32_t *codes, std::string &err)
                 err = "rotated root frames need equal root edges";
                 return DGAMR_EINVAL;
             }
-        if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.equation == DGAMR_EQ_ADVECTION) {
-            err = "rotated root frames are built for the paper hanging mode, Euler and diffusion";
+        if (desc_.hanging == DGAMR_HANG_CONSERVATIVE) {
+            err = "rotated root frames are built for the paper hanging mode";
             return DGAMR_EUNSUPPORTED;
         }
     }

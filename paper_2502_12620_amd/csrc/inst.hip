@@ -137,6 +137,10 @@ hipError_t launch_stage_cell(const StageArgs &a, int gm, int om, bool lim, const
             hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RES64, false, T, EQ>), grid_all, block, lds, s, a, rows);
             return hipGetLastError();
         }
+        if (gm == GUARD_BUFFER && om == OUT_RK) { // rotated root frames
+            hipLaunchKernelGGL((k_stage<D, P, GUARD_BUFFER, OUT_RK, false, T, EQ>), grid_all, block, lds, s, a, rows);
+            return hipGetLastError();
+        }
         return hipErrorInvalidValue;
     }
     constexpr int GMRK = GUARD_INLINE; // the fused stage takes the far side inline

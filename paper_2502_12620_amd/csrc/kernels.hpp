@@ -573,6 +573,22 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
 
     // ---- volume integral: sum_q w_q F_a(U_q) (2/h_a) dphi_m/dxi_a / M_m
     const T gamma = T(g.gamma), gm1 = T(g.gamma - 1.0);
+    // scalar convection: the velocity along the leaf's local axes, Q^T vel
+    // (Sec. 3.1 frames; the identity on aligned roots)
+    struct {
+        double vel[3];
+    } gv;
+    if constexpr (EQ == EQ_ADVECTION) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            double s = 0.0;
+#pragma unroll
+            for (int a = 0; a < D; ++a) s += double(g.geo[leaf].q[3 * a + l]) * g.vel[a];
+            gv.vel[l] = s;
+        }
+    } else {
+        gv.vel[0] = gv.vel[1] = gv.vel[2] = 0.0;
+    }
     auto vol_point = [&](auto qv) __attribute__((always_inline)) {
         const int q = qv;
         T U[NV];
@@ -594,7 +610,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
         static_for<0, D>([&](auto Ai) __attribute__((always_inline)) {
             constexpr int A = Ai;
             T F[NV];
-            if constexpr (EQ == EQ_ADVECTION) F[0] = T(g.vel[A]) * U[0];
+            if constexpr (EQ == EQ_ADVECTION) F[0] = T(gv.vel[A]) * U[0];
             else euler_flux<D, A, T>(U, U[1 + A] * rinv, p, F);
 #pragma unroll
             for (int v = 0; v < NV; ++v) F[v] *= scale[A];
@@ -701,7 +717,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                     T TL[NV];
 #pragma unroll
                     for (int v = 0; v < NV; ++v) TL[v] = lds[(v * FCH + fi) * nslab + lc - stride];
-                    num_flux<D, A, EQ, T>(g, TL, Tm[fi], gamma, Fm[fi]);
+                    num_flux<D, A, EQ, T>(gv, TL, Tm[fi], gamma, Fm[fi]);
                 }
             } else if (edge_m) { // slab edge inside the leaf: the layer below
 #pragma unroll
@@ -714,13 +730,13 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         else trace_eo_mem<D, P, T>(g.us + base - stride + v * sv, ncell, A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
-                    num_flux<D, A, EQ, T>(g, TL, Tm[fi], gamma, Fm[fi]);
+                    num_flux<D, A, EQ, T>(gv, TL, Tm[fi], gamma, Fm[fi]);
                 }
             } else if (!mort_m) {
                 T TL[FCH][NV];
                 far_traces<D, P, A, GM, FCH, NV, T>(g, K, leaf, -1, t, Lm, f0, TL);
 #pragma unroll
-                for (int fi = 0; fi < FCH; ++fi) num_flux<D, A, EQ, T>(g, TL[fi], Tm[fi], gamma, Fm[fi]);
+                for (int fi = 0; fi < FCH; ++fi) num_flux<D, A, EQ, T>(gv, TL[fi], Tm[fi], gamma, Fm[fi]);
             } else {
 #pragma unroll
                 for (int fi = 0; fi < FCH; ++fi)
@@ -752,7 +768,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         else trace_eo_mem<D, P, T>(g.us + base + stride + v * sv, ncell, A, f0 + fi, e, o);
                         TR[v] = e - o;
                     }
-                    num_flux<D, A, EQ, T>(g, TL, TR, gamma, Fp[fi]);
+                    num_flux<D, A, EQ, T>(gv, TL, TR, gamma, Fp[fi]);
                 }
             } else if (!mort_p) {
                 T TR[FCH][NV];
@@ -766,7 +782,7 @@ __device__ __forceinline__ void stage_item(const StageArgs &g, int rows, int ite
                         trace_eo<D, P, T>(K[v], A, f0 + fi, e, o);
                         TL[v] = e + o;
                     }
-                    num_flux<D, A, EQ, T>(g, TL, TR[fi], gamma, Fp[fi]);
+                    num_flux<D, A, EQ, T>(gv, TL, TR[fi], gamma, Fp[fi]);
                 }
             } else {
 #pragma unroll

@@ -1,6 +1,7 @@
 """Seeded random forests against the oracle.  Each case draws the
-dimension, degree, block size, root grid, boundary kinds, hanging mode,
-rotated root frames, distorted root nodes and the positivity limiter
+dimension, degree, block size, root grid, boundary kinds, the equation
+(Euler or scalar convection), hanging mode, rotated root frames, distorted
+root nodes and the positivity limiter
 (within what each feature supports), refines twice by random flags, and then
 compares the initial projection and three fused steps (time steps, states,
 conserved totals) with the oracle.  FP64 bar 1e-12 relative per variable.
@@ -31,9 +32,10 @@ def _draw(seed):
     mapped = bool(rng.random() < 0.4)
     frames = bool(rng.random() < 0.4)
     conservative = (not mapped) and (not frames) and bool(rng.random() < 0.3)
-    limiter = (not mapped) and bool(rng.random() < 0.3)
+    advection = bool(rng.random() < 0.25)
+    limiter = (not mapped) and (not advection) and bool(rng.random() < 0.3)
     return dict(dim=dim, p=p, N=N, roots=roots, lo=lo, hi=hi, bc=bc, mapped=mapped, frames=frames,
-                conservative=conservative, limiter=limiter, rng=rng)
+                conservative=conservative, advection=advection, limiter=limiter, rng=rng)
 
 
 @pytest.mark.parametrize("seed", range(48))
@@ -45,9 +47,12 @@ def test_random_forest_matches_the_oracle(seed):
     print(f"random forest {seed}: {c}", flush=True)
     dim, p, N, roots, lo, hi, bc = c["dim"], c["p"], c["N"], c["roots"], c["lo"], c["hi"], c["bc"]
     hang = 1 if c["conservative"] else 0
-    orc = O.Forest(dim, p, N, roots, lo, hi, bc, 3, hanging=hang)
+    vel = (1.0, 0.5, 0.25)
+    kw_o = dict(equation=O.EQ_ADVECTION, velocity=vel) if c["advection"] else {}
+    kw_g = dict(equation=G.EQ_ADVECTION, velocity=vel) if c["advection"] else {}
+    orc = O.Forest(dim, p, N, roots, lo, hi, bc, 3, hanging=hang, **kw_o)
     gpu = G.Forest(dim, p, N, roots, lo, hi, bc, 3, hanging=hang,
-                   limiter=G.LIMITER_POSITIVITY if c["limiter"] else G.LIMITER_NONE)
+                   limiter=G.LIMITER_POSITIVITY if c["limiter"] else G.LIMITER_NONE, **kw_g)
     if c["frames"]:
         codes = [int(x) for x in rng.integers(0, 4 if dim == 2 else 24, int(np.prod(roots)))]
         orc.set_frames(codes)
@@ -63,10 +68,13 @@ def test_random_forest_matches_the_oracle(seed):
         gpu.adapt(flags, torch.zeros(gpu.state_shape(), dtype=torch.float64, device="cuda"))
     assert np.array_equal(orc.keys(), gpu.keys())
     # the vortex centre off every quadrature node (its periodic seam too)
-    L = [hi[a] - lo[a] for a in range(2)]
-    prm = [3.0, 0.4137 * L[0], 0.5821 * L[1], 0.5, 0.3, L[0], L[1]]
-    u = orc.project_ic(O.IC_VORTEX, prm)
-    ud = gpu.project_ic(G.IC_VORTEX, prm)
+    L = [hi[a] - lo[a] for a in range(dim)]
+    if c["advection"]:
+        kind_o, kind_g, prm = O.IC_COSINE, G.IC_COSINE, [1.0] + L
+    else:
+        kind_o, kind_g, prm = O.IC_VORTEX, G.IC_VORTEX, [3.0, 0.4137 * L[0], 0.5821 * L[1], 0.5, 0.3, L[0], L[1]]
+    u = orc.project_ic(kind_o, prm)
+    ud = gpu.project_ic(kind_g, prm)
     assert rel_diff_floored(ud.cpu().numpy(), u, 1e-3).max() <= TOL
     work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
     for _ in range(3):

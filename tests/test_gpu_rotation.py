@@ -40,6 +40,9 @@ def _pair(dim, p, N, frames, levels=3, precision=0, limiter=False, equation=0, b
     if equation == 2:
         kw_o = dict(equation=O.EQ_DIFFUSION, nu=0.8, avec=(-1.0, 0.5, 0.25)[:dim])
         kw_g = dict(equation=G.EQ_DIFFUSION, nu=0.8, exact_a=(-1.0, 0.5, 0.25)[:dim])
+    elif equation == 1:
+        kw_o = dict(equation=O.EQ_ADVECTION, velocity=(1.0, 0.5, 0.25))
+        kw_g = dict(equation=G.EQ_ADVECTION, velocity=(1.0, 0.5, 0.25))
     orc = O.Forest(*args, **kw_o)
     gpu = G.Forest(*args, precision=precision, limiter=G.LIMITER_POSITIVITY if limiter else G.LIMITER_NONE, **kw_g)
     orc.set_frames(frames)
@@ -170,6 +173,28 @@ def test_rotated_diffusion(dim):
         orc.step(u, 0.006)
         gpu.step(ud, work, dt, 0.006)
     assert rel_diff(_host(ud), u).max() <= TOL
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (2, 3), (3, 1), (3, 2)])
+def test_rotated_scalar_convection(dim, p):
+    """Scalar convection on rotated roots (the velocity along each root's
+    local axes), hanging faces across rotated root faces: projection,
+    fused steps with the fill of the rotated guard cells, dt, totals."""
+    G = _G()
+    frames = _frames(dim, 13 + p)
+    orc, gpu = _pair(dim, p, 4 if dim == 2 else 2, frames, equation=1)
+    L = 10.0 if dim == 2 else 4.0
+    prm = [1.0, L, L, L]
+    u = orc.project_ic(O.IC_COSINE, prm)
+    ud = gpu.project_ic(G.IC_COSINE, prm)
+    assert rel_diff(_host(ud), u).max() <= TOL
+    work, dt = gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(4):
+        dref = orc.step(u, 0.2)
+        gpu.step(ud, work, dt, 0.2)
+        assert _host(dt)[0] == pytest.approx(dref, rel=1e-13)
+    assert rel_diff(_host(ud), u).max() <= TOL
+    np.testing.assert_allclose(_host(gpu.conserved_totals(ud, work)), orc.totals(u), rtol=1e-12, atol=1e-12)
 
 
 def test_frames_refused_where_not_defined():
