@@ -348,7 +348,9 @@ def cmd_convection(args):
     block indicator, SSP-RK3 to t_end (last step shortened to land on it),
     DOF-stage/s, and the L2 distance between the solution and the L2
     projection of the exact (translated) solution on the final forest."""
-    if args.distorted:
+    if args.rotated:
+        w = W.convection_2d_rotated(degree=args.degree, n_cell=args.n_cell)
+    elif args.distorted:
         w = W.convection_2d_distorted(degree=args.degree, n_cell=args.n_cell)
     elif args.dim == 2:
         w = W.convection_2d(degree=args.degree, n_cell=args.n_cell)
@@ -359,6 +361,8 @@ def cmd_convection(args):
     nodes = getattr(w, "nodes", None)
     if nodes is not None:
         f.set_root_nodes(nodes)
+    if getattr(w, "frames", None) is not None:
+        f.set_root_frames(w.frames)
     z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
     for rule in w.initial_refinement:
         z = f.adapt(rule(w, f.keys()), z)
@@ -592,6 +596,7 @@ def main(argv=None):
     c2.add_argument("--degree", type=int, default=2)
     c2.add_argument("--n-cell", type=int, default=8)
     c2.add_argument("--distorted", action="store_true", help="2-D, the second root set: four distorted roots")
+    c2.add_argument("--rotated", action="store_true", help="2-D, four square roots with rotated frames")
     df = sub.add_parser("diffusion")
     df.add_argument("--degree", type=int, default=2)
     v = sub.add_parser("serve")

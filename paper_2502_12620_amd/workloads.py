@@ -172,6 +172,20 @@ def convection_2d_distorted(degree: int = 2, n_cell: int = 8) -> Workload:
     return w
 
 
+def convection_2d_rotated(degree: int = 2, n_cell: int = 8) -> Workload:
+    """The convection case of Sec. 5.1 on roots whose local frames are
+    rotated against each other (the paper's third root set, an unstructured
+    mesh shown only as a figure, has rotated roots): a 2x2 grid of square
+    roots on the periodic unit square, each turned by a different number of
+    quarter turns (frames 0, 1, 2, 3), levels 2..4 (the cell sizes of the
+    first set).  Everything else as convection_2d."""
+    w = convection_2d_distorted(degree, n_cell)
+    w.name = "f1_convection2d_rotated"
+    w.frames = [0, 1, 2, 3]
+    del w.nodes
+    return w
+
+
 def diffusion_2d(degree: int = 2, n_cell: int = 6) -> Workload:
     """Diffusion (Sec. 5.2): u_t = div grad u on the unit square, one root
     block, Dirichlet data and initial state from exp(-x + y + 2t), 6x6-cell
