@@ -458,8 +458,8 @@ int orc_set_frames(orc_forest *f, const int *codes)
  * root with a rotated frame takes its local axes along the node grid's axes
  * as its frame turns them (its corner b is the grid node the frame maps it
  * to); on such forests the momentum is stored along the global axes, and
- * the guard fill turns only coordinates.  Not with the conservative mode,
- * the diffusion equation or the limiter. */
+ * the guard fill turns only coordinates.  Not with the conservative mode
+ * or the diffusion equation. */
 int orc_set_nodes(orc_forest *f, const double *xy)
 {
     if (f->hanging == ORC_HANG_CONSERVATIVE || f->equation == ORC_EQ_DIFFUSION) return -1;

@@ -1256,7 +1256,11 @@ static int lobatto_nodes(int L, double *x)
  *      pressure along the segment touches eps, where rounding of order
  *      u becomes sqrt(u) in t; the chord is Lipschitz in the state);
  *      theta2 = min t (1 where p >= eps); all non-mean modes are scaled by
- *      theta2.  Cell means are unchanged. */
+ *      theta2.  Cell means are unchanged.
+ * On bilinear / trilinear roots the mean is the one over the physical cell,
+ * Ubar = int U |J| / int |J| with the volume rule, which differs from the
+ * mode-0 coefficient; each scaling is then U <- Ubar + theta (U - Ubar),
+ * which (phi_0 = 1) also moves mode 0 and keeps the physical mean. */
 void orc_limit_positivity(const orc_forest *f, double *u)
 {
     if (f->equation != ORC_EQ_EULER) return; /* density and pressure only exist for Euler */
@@ -1300,6 +1304,10 @@ void orc_limit_positivity(const orc_forest *f, double *u)
                 ++np;
             }
     double g = f->gamma;
+    /* the volume rule, for the physical mean of bilinear / trilinear cells */
+    double (*vxi)[3] = malloc(sizeof(double) * 3 * 512);
+    double *vw = malloc(sizeof(double) * 512);
+    int nvq = tensor_points(d, q, gx, gw, vxi, vw);
 #pragma omp parallel for schedule(static)
     for (int i = 0; i < f->nleaves; ++i)
         for (int c = 0; c < nc; ++c) {
@@ -1307,6 +1315,17 @@ void orc_limit_positivity(const orc_forest *f, double *u)
             long sv = (long)f->nb * nc, sm = nc;
             double mean[5];
             for (int v = 0; v < nv; ++v) mean[v] = K[v * sv];
+            if (mapped(f)) {
+                double cx[8][3], vol = 0.0, acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+                cell_corners(f, i, c, cx);
+                for (int iq = 0; iq < nvq; ++iq) {
+                    double J[3][3], det = map_jacobian(f, cx, vxi[iq], J), uq[5];
+                    eval_poly(f, K, sv, sm, vxi[iq], uq);
+                    vol += vw[iq] * det;
+                    for (int v = 0; v < nv; ++v) acc[v] += vw[iq] * det * uq[v];
+                }
+                for (int v = 0; v < nv; ++v) mean[v] = acc[v] / vol;
+            }
             double pbar = orc_pressure(d, g, mean);
             double eps = 1e-13;
             if (mean[0] < eps) eps = mean[0];
@@ -1323,8 +1342,10 @@ void orc_limit_positivity(const orc_forest *f, double *u)
                 th1 = (mean[0] - eps) / (mean[0] - rmin);
                 if (th1 > 1.0) th1 = 1.0;
             }
-            if (th1 < 1.0)
+            if (th1 < 1.0) {
                 for (int m = 1; m < f->nb; ++m) K[m * sm] *= th1;
+                if (mapped(f)) K[0] = mean[0] + th1 * (K[0] - mean[0]);
+            }
             /* pressure */
             double th2 = 1.0;
             for (int k = 0; k < npts; ++k) {
@@ -1341,10 +1362,14 @@ void orc_limit_positivity(const orc_forest *f, double *u)
                 if (t < th2) th2 = t;
             }
             if (th2 < 1.0)
-                for (int v = 0; v < nv; ++v)
+                for (int v = 0; v < nv; ++v) {
                     for (int m = 1; m < f->nb; ++m) K[v * sv + m * sm] *= th2;
+                    if (mapped(f)) K[v * sv] = mean[v] + th2 * (K[v * sv] - mean[v]);
+                }
         }
     free(pts);
+    free(vxi);
+    free(vw);
 }
 
 /* Block indicator: ratio of the largest to the smallest density cell mean
@@ -1393,7 +1418,7 @@ double orc_step(const orc_forest *f, double cfl, double dt_fixed, int limiter, d
         orc_fill_guards(f, us, g);
         orc_residual(f, us, g, r);
         orc_rk_combine(n, s, dt, un, us, r, u);
-        if (limiter && !mapped(f)) orc_limit_positivity(f, u);
+        if (limiter) orc_limit_positivity(f, u);
         memcpy(us, u, sizeof(double) * n);
     }
     fm->time += dt;

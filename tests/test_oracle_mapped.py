@@ -300,3 +300,97 @@ def test_3d_box_nodes_with_frames_reproduce_the_aligned_box_grid():
         assert fm.step(um, 0.1) == pytest.approx(fa.step(ua, 0.1), rel=1e-13)
     got = to_aligned(fm, um, frames, roots, fa, momentum_local=False)
     assert np.abs(got - ua).max() <= 1e-12 * np.abs(ua).max()
+
+
+# ------------------------------------------------------------------ positivity limiter
+def _limiter_points(p):
+    """Zhang-Shu points of the 2-D tensor cell (Lobatto along one axis with
+    the fewest points exact for degree p, Gauss along the other) and the
+    volume Gauss points."""
+    from tests import refmath as RM
+
+    L = 2
+    while 2 * L - 3 < p:
+        L += 1
+    lob = {2: [-1.0, 1.0], 3: [-1.0, 0.0, 1.0], 4: [-1.0, -5 ** -0.5, 5 ** -0.5, 1.0]}[L]
+    xg, _ = np.polynomial.legendre.leggauss(p + 1)
+    vol, _ = RM.tensor_gauss(2, p + 1)
+    pts = [tuple(x) for x in vol] + [(a, b) for a in lob for b in xg] + [(b, a) for a in lob for b in xg]
+    return np.array(pts)
+
+
+def _physical_means(u, nodes, p, N):
+    """Cell means over the physical cells of a single unrefined bilinear
+    root, int U |J| / int |J| with a 6-point Gauss rule per axis (the
+    test's own map: X(s) = sum of the corner nodes times the bilinear
+    weights of s in [0,1]^2; cell (i, j) covers s in [i/N,(i+1)/N] x
+    [j/N,(j+1)/N], cell index i + N j)."""
+    from tests import refmath as RM
+
+    modes = RM.graded_modes(2, p)
+    xi, w = RM.tensor_gauss(2, 6)
+    X = nodes  # X[y][x] = node (x, y)
+    out = np.zeros((N * N, u.shape[1]))
+    for c in range(N * N):
+        ci, cj = c % N, c // N
+        s0 = (ci + 0.5 * (xi[:, 0] + 1.0)) / N
+        s1 = (cj + 0.5 * (xi[:, 1] + 1.0)) / N
+        dx_ds0 = (1 - s1)[:, None] * (X[0, 1] - X[0, 0]) + s1[:, None] * (X[1, 1] - X[1, 0])
+        dx_ds1 = (1 - s0)[:, None] * (X[1, 0] - X[0, 0]) + s0[:, None] * (X[1, 1] - X[0, 1])
+        det = dx_ds0[:, 0] * dx_ds1[:, 1] - dx_ds0[:, 1] * dx_ds1[:, 0]
+        assert det.min() > 0
+        vals = RM.eval_cell(u[0, :, :, c], modes, xi)
+        out[c] = (w * det) @ vals / np.sum(w * det)
+    return out
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_limiter_keeps_each_physical_cell_mean_on_a_bilinear_root(p):
+    """On a distorted root the cell mean is the one over the physical cell,
+    not mode 0: the limiter must keep that mean in every cell (a limiter
+    scaling about mode 0 moves it), and leave density and pressure >= eps
+    at the Zhang-Shu points."""
+    from tests import refmath as RM
+
+    N = 4
+    nodes = np.array([[[0.0, 0.0], [1.0, 0.15]], [[0.25, 0.9], [1.4, 1.3]]])
+    f = O.Forest(2, p, N, (1, 1), (0.0, 0.0), (1.0, 1.0), (1, 1), 1)
+    f.set_nodes(nodes)
+    u = f.project_ic(O.IC_UNIFORM, [1.0, 0.0, 0.0, 0.0, 1.0])
+    rng = np.random.default_rng(40 + p)
+    u[0, :, 1:, :] = 0.6 * rng.standard_normal(u[0, :, 1:, :].shape)  # wild higher modes
+    before = u.copy()
+    m0 = _physical_means(u, nodes, p, N)
+    assert m0[:, 0].min() > 0.2
+    assert np.abs(m0 - before[0, :, 0, :].T).max() > 1e-3  # the physical mean is not mode 0
+    f.limit(u)
+    m1 = _physical_means(u, nodes, p, N)
+    np.testing.assert_allclose(m1, m0, rtol=1e-13, atol=1e-13)
+    assert np.abs(u[0, :, 0, :] - before[0, :, 0, :]).max() > 1e-6  # mode 0 moved
+    vals = np.stack([RM.eval_cell(u[0, :, :, c], RM.graded_modes(2, p), _limiter_points(p)) for c in range(N * N)])
+    rho, _, pr = RM.euler_primitives(vals, 2, 1.4)
+    assert rho.min() >= 1e-13 - 1e-14 and pr.min() >= 1e-13 - 1e-14
+
+
+@pytest.mark.parametrize("dim,p", [(2, 1), (2, 2), (3, 1)])
+def test_limited_steps_on_box_nodes_match_the_box_grid(dim, p):
+    """With rectangular nodes the physical mean is mode 0 and the limited
+    steps are the box grid's (Zhang-Shu on tensor cells)."""
+    if dim == 2:
+        roots, lo, hi, nodes = (2, 2), (0.0, 0.0), (4.0, 4.0), box_nodes((2, 2), (0.0, 0.0), (4.0, 4.0))
+    else:
+        roots, lo, hi = (2, 2, 2), (0.0,) * 3, (4.0,) * 3
+        nodes = box_nodes3(roots, lo, hi)
+    fa = O.Forest(dim, p, 4 if dim == 2 else 2, roots, lo, hi, (1,) * dim, 2)
+    fm = O.Forest(dim, p, 4 if dim == 2 else 2, roots, lo, hi, (1,) * dim, 2)
+    fm.set_nodes(nodes)
+    for f in (fa, fm):
+        _refine(f, 0)
+    ua = fa.project_ic(O.IC_UNIFORM, [1.0, 0.0, 0.0, 0.0, 1e-3])
+    ua[0, dim + 1, 0, :] = 1e3 / 0.4
+    um = ua.copy()
+    for _ in range(3):
+        assert fm.step(um, 0.1, limiter=True) == pytest.approx(fa.step(ua, 0.1, limiter=True), rel=1e-13)
+    assert np.abs(um - ua).max() <= 1e-12 * np.abs(ua).max()
+    t = fm.totals(um)
+    np.testing.assert_allclose(t, fa.totals(ua), rtol=1e-12, atol=1e-12 * np.abs(t).max())
