@@ -149,9 +149,11 @@ int dgamr_set_root_frames(dgamr_forest *f, const int32_t *codes);
  * launches; the CFL rate takes the cell means over the physical cells and,
  * per reference axis, the face normal and width 2 det(J) / |row of adj(J)|
  * at the cell centre; the totals integrate over the physical cells; the
- * indicator keeps the reference cell means (mode 0).  Root frames
- * (dgamr_set_root_frames) may be set as well.  EUNSUPPORTED for 3-D degree
- * 3, the conservative mode, the limiter, the diffusion equation or FP32;
+ * indicator keeps the reference cell means (mode 0); the positivity
+ * limiter scales about the mean over the physical cell, int U |J| / int |J|,
+ * and so also moves mode 0.  Root frames (dgamr_set_root_frames) may be set
+ * as well.  EUNSUPPORTED for 3-D degree 3, the conservative mode, the
+ * diffusion equation or FP32;
  * EINVAL for nodes that are not finite, a root
  * with a non-positive corner Jacobian, or unmatched periodic nodes.  Pools
  * do not admit such forests. */
@@ -270,7 +272,9 @@ int dgamr_conserved_totals(dgamr_forest *f, const double *u, double *totals_dev,
                            hipStream_t stream);
 
 /* Positivity-preserving scaling limiter (Zhang-Shu, named in Sec. 5.3.2)
- * applied in place. */
+ * applied in place: each cell scaled about its mean (on bilinear /
+ * trilinear roots, the mean over the physical cell).  EINVAL for scalar
+ * equations. */
 int dgamr_limit_positivity(dgamr_forest *f, double *u, hipStream_t stream);
 
 /* Block indicator per leaf (FP64, device): Euler, max/min density cell mean

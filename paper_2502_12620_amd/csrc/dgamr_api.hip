@@ -150,17 +150,6 @@ int launch_stage(dgamr_forest *f, dgk::StageArgs a, int gm, int om, hipStream_t 
     });
 }
 
-int launch_limit(dgamr_forest *f, double *u, hipStream_t s)
-{
-    if (f->topo.scalar()) return fail(DGAMR_EINVAL, "the positivity limiter is for the Euler equations");
-    long total = long(f->topo.n()) * ncell_of(f);
-    if (total == 0) return DGAMR_OK;
-    return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
-        HIP_TRY((dgk::launch_limit<D, P>(u, f->topo.desc().n_cell, total, f->topo.desc().gamma, s)));
-        return DGAMR_OK;
-    });
-}
-
 // arguments of the bilinear-root kernels
 dgk::MappedArgs mapped_args(const dgamr_forest *f, const double *us, const double *un, const double *guard,
                             double *out, const double *dt, double a, double b)
@@ -202,6 +191,23 @@ int dispatch_mapped(const dgamr_forest *f, Fn &&fn)
     case 2: return fn(integral_constant<int, 2>{}, integral_constant<int, 2>{});
     default: return fn(integral_constant<int, 2>{}, integral_constant<int, 3>{});
     }
+}
+
+int launch_limit(dgamr_forest *f, double *u, hipStream_t s)
+{
+    if (f->topo.scalar()) return fail(DGAMR_EINVAL, "the positivity limiter is for the Euler equations");
+    long total = long(f->topo.n()) * ncell_of(f);
+    if (total == 0) return DGAMR_OK;
+    if (f->topo.mapped())
+        // bilinear / trilinear roots: scaled about the mean over the physical cell
+        return dispatch_mapped(f, [&](auto D, auto P) -> int {
+            HIP_TRY((dgk::launch_mapped_limit<D, P>(u, f->d_geo, f->topo.desc().n_cell, total, f->topo.desc().gamma, s)));
+            return DGAMR_OK;
+        });
+    return dispatch(f->topo.dim(), f->topo.desc().degree, [&](auto D, auto P) -> int {
+        HIP_TRY((dgk::launch_limit<D, P>(u, f->topo.desc().n_cell, total, f->topo.desc().gamma, s)));
+        return DGAMR_OK;
+    });
 }
 
 int launch_dt(dgamr_forest *f, double cfl, const double *u, double *dt_dev, const Work &w, hipStream_t s)
@@ -449,7 +455,7 @@ int dgamr_dg_residual(dgamr_forest *f, const double *u, const double *guard, voi
         dgk::MappedArgs a = mapped_args(f, u, nullptr, guard, static_cast<double *>(r), nullptr, 0.0, 1.0);
         const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
         return dispatch_mapped(f, [&](auto D, auto P) -> int {
-            HIP_TRY((dgk::launch_mapped<D, P>(a, eq, dgk::OUT_RES64, stream)));
+            HIP_TRY((dgk::launch_mapped<D, P>(a, eq, dgk::OUT_RES64, false, stream)));
             return DGAMR_OK;
         });
     }
@@ -531,7 +537,7 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
     if (f->topo.mapped()) {
         // bilinear roots: the guard fill (reference-space copy, split,
         // combine), then the residual with the metric terms fused with the
-        // stage update
+        // stage update (and the limiter about the physical cell mean)
         const int eq = f->topo.advection() ? dgk::EQ_ADVECTION : dgk::EQ_EULER;
         for (int s = 0; s < 3; ++s) {
             hipEvent_t e1;
@@ -539,7 +545,7 @@ int run_step(dgamr_forest *f, double cfl, double *u, const Work &w, double *dt_d
             CHECK(launch_fill(f, us, w.guard, false, stream));
             dgk::MappedArgs a = mapped_args(f, us, u, w.guard, outs[s], dt_dev, A[s], B[s]);
             CHECK(dispatch_mapped(f, [&](auto D, auto P) -> int {
-                HIP_TRY((dgk::launch_mapped<D, P>(a, eq, dgk::OUT_RK, stream)));
+                HIP_TRY((dgk::launch_mapped<D, P>(a, eq, dgk::OUT_RK, lim, stream)));
                 return DGAMR_OK;
             }));
             CHECK(prof_end(f, stream, e1));
@@ -832,7 +838,6 @@ int dgamr_limit_positivity(dgamr_forest *f, double *u, hipStream_t stream)
 {
     CHECK(check_ptr(f, "forest"));
     CHECK(check_ptr(u, "u"));
-    if (f->topo.mapped()) return fail(DGAMR_EUNSUPPORTED, "the positivity limiter is not built for bilinear roots");
     return launch_limit(f, u, stream);
 }
 

@@ -197,10 +197,8 @@ int Forest::set_nodes(const double *xy, std::string &err)
         err = "trilinear root blocks are built for degree <= 2";
         return DGAMR_EUNSUPPORTED;
     }
-    if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.limiter != DGAMR_LIMITER_NONE ||
-        desc_.equation == DGAMR_EQ_DIFFUSION) {
-        err = "bilinear / trilinear root blocks are built for the paper hanging mode, no limiter, Euler and "
-              "scalar convection";
+    if (desc_.hanging == DGAMR_HANG_CONSERVATIVE || desc_.equation == DGAMR_EQ_DIFFUSION) {
+        err = "bilinear / trilinear root blocks are built for the paper hanging mode, Euler and scalar convection";
         return DGAMR_EUNSUPPORTED;
     }
     const int n[3] = {desc_.roots[0] + 1, desc_.roots[1] + 1, d == 3 ? desc_.roots[2] + 1 : 1};

@@ -290,11 +290,14 @@ hipError_t launch_ipdg(const IpdgArgs &a, int om, hipStream_t s)
 template hipError_t launch_ipdg<DG_D, DG_P>(const IpdgArgs &, int, hipStream_t);
 #if DG_D == 2 || DG_P <= 2
 template <int D, int P>
-hipError_t launch_mapped(const MappedArgs &a, int eq, int om, hipStream_t s)
+hipError_t launch_mapped(const MappedArgs &a, int eq, int om, bool lim, hipStream_t s)
 {
     if (a.ncell_total == 0) return hipSuccess;
     const dim3 grid(unsigned((a.ncell_total + 127) / 128)), block(128);
-    if (eq == EQ_ADVECTION) {
+    if (lim) {
+        if (eq != EQ_EULER || om != OUT_RK) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((k_mapped<D, P, EQ_EULER, OUT_RK, true>), grid, block, 0, s, a);
+    } else if (eq == EQ_ADVECTION) {
         if (om == OUT_RES64) hipLaunchKernelGGL((k_mapped<D, P, EQ_ADVECTION, OUT_RES64>), grid, block, 0, s, a);
         else if (om == OUT_RK) hipLaunchKernelGGL((k_mapped<D, P, EQ_ADVECTION, OUT_RK>), grid, block, 0, s, a);
         else return hipErrorInvalidValue;
@@ -303,6 +306,14 @@ hipError_t launch_mapped(const MappedArgs &a, int eq, int om, hipStream_t s)
         else if (om == OUT_RK) hipLaunchKernelGGL((k_mapped<D, P, EQ_EULER, OUT_RK>), grid, block, 0, s, a);
         else return hipErrorInvalidValue;
     }
+    return hipGetLastError();
+}
+template <int D, int P>
+hipError_t launch_mapped_limit(double *u, const LeafGeo *geo, int N, long total, double gamma, hipStream_t s)
+{
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_mapped_limit<D, P>), dim3(unsigned((total + 127) / 128)), dim3(128), 0, s, u, geo, N, total,
+                       gamma);
     return hipGetLastError();
 }
 template <int D, int P>
@@ -335,7 +346,8 @@ hipError_t launch_mapped_ic(double *u, const LeafGeo *geo, int N, long total, in
                            gamma);
     return hipGetLastError();
 }
-template hipError_t launch_mapped<DG_D, DG_P>(const MappedArgs &, int, int, hipStream_t);
+template hipError_t launch_mapped<DG_D, DG_P>(const MappedArgs &, int, int, bool, hipStream_t);
+template hipError_t launch_mapped_limit<DG_D, DG_P>(double *, const LeafGeo *, int, long, double, hipStream_t);
 template hipError_t launch_mapped_rate<DG_D, DG_P>(const MappedArgs &, int, int, int, double *, hipStream_t);
 template hipError_t launch_mapped_totals<DG_D, DG_P>(const MappedArgs &, int, int, int, double *, hipStream_t);
 template hipError_t launch_mapped_ic<DG_D, DG_P>(double *, const LeafGeo *, int, long, int, const IcParams &, double,

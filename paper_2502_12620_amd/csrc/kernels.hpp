@@ -421,15 +421,18 @@ inline constexpr LimiterPoints<D, P> kLimPts{};
 //   t = (p(mean) - eps)/(p(mean) - p(U)) at the points with p(U) < eps
 //   (pressure is concave in the conserved variables where rho > 0, so the
 //   scaled state keeps p >= eps there) scales all non-mean modes.  The cell
-//   mean is never changed.
-template <int D, int P>
-__device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
+//   mean is never changed.  MEAN_GIVEN: the cell mean is given (a bilinear /
+//   trilinear cell, whose full mass matrix makes the mean differ from the
+//   mode-0 coefficient), and the scalings U <- mean + theta (U - mean) move
+//   mode 0 as well.
+template <int D, int P, bool MEAN_GIVEN = false>
+__device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma, const double *given_mean = nullptr)
 {
     constexpr int NV = D + 2, NB = Tab<D, P>::NB, NPT = LimiterPoints<D, P>::NPT;
     const double gm1 = gamma - 1.0;
     double mean[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) mean[v] = K[v][0];
+    for (int v = 0; v < NV; ++v) mean[v] = MEAN_GIVEN ? given_mean[v] : K[v][0];
     const double pbar = pressure<D>(mean, gm1);
     double eps = 1e-13;
     eps = mean[0] < eps ? mean[0] : eps;
@@ -444,9 +447,11 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
     }
     if (rmin < mean[0]) {
         double th1 = (mean[0] - eps) / (mean[0] - rmin);
-        if (th1 < 1.0)
+        if (th1 < 1.0) {
 #pragma unroll
             for (int m = 1; m < NB; ++m) K[0][m] *= th1;
+            if constexpr (MEAN_GIVEN) K[0][0] = mean[0] + th1 * (K[0][0] - mean[0]);
+        }
     }
     double th2 = 1.0;
 #pragma unroll 1
@@ -468,9 +473,11 @@ __device__ __forceinline__ void limit_cell(CellCoef<D, P> &K, double gamma)
     }
     if (th2 < 1.0)
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+        for (int v = 0; v < NV; ++v) {
 #pragma unroll
             for (int m = 1; m < NB; ++m) K[v][m] *= th2;
+            if constexpr (MEAN_GIVEN) K[v][0] = mean[v] + th2 * (K[v][0] - mean[v]);
+        }
 }
 
 // ------------------------------------------------------------------ stage kernel

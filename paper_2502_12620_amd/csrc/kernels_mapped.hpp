@@ -204,6 +204,20 @@ __device__ __forceinline__ void mapped_solve(const double (&M)[NB][NB], double (
     }
 }
 
+// the state's mean over the physical cell from the mass matrix: with
+// phi_0 = 1, M[n][0] = int phi_n det J and M[0][0] is the cell's volume
+template <int NB, int NV>
+__device__ __forceinline__ void mapped_mean(const double (&M)[NB][NB], const double (&K)[NV][NB], double (&mean)[NV])
+{
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+        double s = 0.0;
+#pragma unroll
+        for (int n = 0; n < NB; ++n) s = fma(M[n][0], K[v][n], s);
+        mean[v] = s / M[0][0];
+    }
+}
+
 // mass matrix of a multilinear cell with the volume rule
 template <int D, int P>
 __device__ __forceinline__ void mapped_mass(const double (&cx)[1 << D][3], double (&M)[Tab<D, P>::NB][Tab<D, P>::NB])
@@ -229,7 +243,9 @@ __device__ __forceinline__ void mapped_mass(const double (&cx)[1 << D][3], doubl
         for (int n = m + 1; n < NB; ++n) M[m][n] = M[n][m];
 }
 
-template <int D, int P, int EQ, int OM>
+// LIM: the positivity limiter on the new state, about the cell's mean over
+// the physical cell (Euler, OUT_RK)
+template <int D, int P, int EQ, int OM, bool LIM = false>
 __global__ __launch_bounds__(128) void k_mapped(MappedArgs g)
 {
     constexpr int NV = EQ == EQ_ADVECTION ? 1 : D + 2, NB = Tab<D, P>::NB, NQ = Tab<D, P>::NQ, NF = Tab<D, P>::NF;
@@ -362,12 +378,58 @@ __global__ __launch_bounds__(128) void k_mapped(MappedArgs g)
     } else {
         const double dt = *g.dt, a = g.rk_a, b = g.rk_b;
         const double *U0 = g.un + long(leaf) * NV * sv + c;
+        if constexpr (LIM && EQ == EQ_EULER) {
+            double Kn[NV][NB], mean[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v)
+            for (int v = 0; v < NV; ++v)
 #pragma unroll
-            for (int m = 0; m < NB; ++m)
-                o[v * sv + long(m) * ncell] = a * U0[v * sv + long(m) * ncell] + b * (K[v][m] + dt * R[v][m]);
+                for (int m = 0; m < NB; ++m) Kn[v][m] = a * U0[v * sv + long(m) * ncell] + b * (K[v][m] + dt * R[v][m]);
+            mapped_mean<NB, NV>(M, Kn, mean);
+            limit_cell<D, P, true>(Kn, g.gamma, mean);
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int m = 0; m < NB; ++m) o[v * sv + long(m) * ncell] = Kn[v][m];
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+#pragma unroll
+                for (int m = 0; m < NB; ++m)
+                    o[v * sv + long(m) * ncell] = a * U0[v * sv + long(m) * ncell] + b * (K[v][m] + dt * R[v][m]);
+        }
     }
+}
+
+// the positivity limiter alone on bilinear / trilinear roots: one thread
+// per cell, about the cell's mean over the physical cell
+template <int D, int P>
+__global__ __launch_bounds__(128) void k_mapped_limit(double *u, const LeafGeo *geo, int N, long ncell_total,
+                                                      double gamma)
+{
+    constexpr int NV = D + 2, NB = Tab<D, P>::NB;
+    const int ncell = D == 2 ? N * N : N * N * N;
+    const long gid = long(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (gid >= ncell_total) return;
+    const int leaf = int(gid / ncell), c = int(gid % ncell);
+    int ijk[3];
+    cell_ijk(c, N, D, ijk);
+    double cx[1 << D][3];
+    mapped_cell_corners<D>(geo[leaf], ijk, N, cx);
+    double M[NB][NB];
+    mapped_mass<D, P>(cx, M);
+    const long sv = long(NB) * ncell;
+    double *K0 = u + long(leaf) * NV * sv + c;
+    double K[NV][NB], mean[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NB; ++m) K[v][m] = K0[v * sv + long(m) * ncell];
+    mapped_mean<NB, NV>(M, K, mean);
+    limit_cell<D, P, true>(K, gamma, mean);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+#pragma unroll
+        for (int m = 0; m < NB; ++m) K0[v * sv + long(m) * ncell] = K[v][m];
 }
 
 // the integrals of the state over the physical cell (volume rule) and the

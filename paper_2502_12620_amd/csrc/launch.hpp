@@ -70,11 +70,14 @@ hipError_t launch_ipdg(const IpdgArgs &a, int out_mode, hipStream_t s);
 
 // Bilinear / trilinear roots (2-D any degree, 3-D degree <= 2): the
 // residual or fused RK stage (out_mode OUT_RES64 / OUT_RK; eq EQ_EULER or
-// EQ_ADVECTION), the CFL rate per leaf, the per-leaf totals (one workgroup
-// of `block` threads per leaf, a power of two), and the initial projection
-// (nv variables).
+// EQ_ADVECTION; lim: the positivity limiter fused, Euler OUT_RK only), the
+// positivity limiter alone, the CFL rate per leaf, the per-leaf totals (one
+// workgroup of `block` threads per leaf, a power of two), and the initial
+// projection (nv variables).
 template <int D, int P>
-hipError_t launch_mapped(const MappedArgs &a, int eq, int out_mode, hipStream_t s);
+hipError_t launch_mapped(const MappedArgs &a, int eq, int out_mode, bool lim, hipStream_t s);
+template <int D, int P>
+hipError_t launch_mapped_limit(double *u, const LeafGeo *geo, int N, long ncell_total, double gamma, hipStream_t s);
 template <int D, int P>
 hipError_t launch_mapped_rate(const MappedArgs &a, int eq, int nleaves, int block, double *leaf_max, hipStream_t s);
 template <int D, int P>

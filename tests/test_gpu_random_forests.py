@@ -33,7 +33,7 @@ def _draw(seed):
     frames = bool(rng.random() < 0.4)
     conservative = (not mapped) and (not frames) and bool(rng.random() < 0.3)
     advection = bool(rng.random() < 0.25)
-    limiter = (not mapped) and (not advection) and bool(rng.random() < 0.3)
+    limiter = (not advection) and bool(rng.random() < 0.3)
     return dict(dim=dim, p=p, N=N, roots=roots, lo=lo, hi=hi, bc=bc, mapped=mapped, frames=frames,
                 conservative=conservative, advection=advection, limiter=limiter, rng=rng)
 
