@@ -381,3 +381,12 @@ def test_mapped_limiter_alone_and_fused(dim, p, N):
     np.testing.assert_allclose(_host(gpu.conserved_totals(ud, work)), orc.totals(u), rtol=1e-12,
                                atol=1e-12 * np.abs(orc.totals(u)).max())
     assert gpu.check_state(ud, work) == 0
+    # run (dt per step) and a captured run equal the same limited steps
+    ua, ub = ud.clone(), ud.clone()
+    for _ in range(2):
+        orc.step(u, 0.1, limiter=True)
+    gpu.run(ua, work, dt, 2, 0.1)
+    assert rel_diff_floored(_host(ua), u, 1e-3).max() <= TOL_RES
+    g = gpu.capture_run(ub, gpu.new_work(), torch.zeros(1, dtype=torch.float64, device="cuda"), 2, 0.1)
+    g.launch()
+    assert rel_diff(_host(ub), _host(ua)).max() <= 1e-14

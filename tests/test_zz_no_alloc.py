@@ -13,8 +13,9 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 
-def _forest(G, w, setup=None):
-    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma)
+def _forest(G, w, setup=None, limiter=False):
+    f = G.Forest(w.dim, w.degree, w.n_cell, w.roots, w.lo, w.hi, w.bc, w.max_level, w.gamma,
+                 limiter=G.LIMITER_POSITIVITY if limiter else G.LIMITER_NONE)
     if setup is not None:
         setup(f)
     z = torch.zeros(f.state_shape(), dtype=torch.float64, device="cuda")
@@ -23,8 +24,8 @@ def _forest(G, w, setup=None):
     return f
 
 
-def _compare(G, w, steps, setup=None):
-    f = _forest(G, w, setup)
+def _compare(G, w, steps, setup=None, limiter=False):
+    f = _forest(G, w, setup, limiter)
     print(f"static step: {w.name}, {f.n_leaves} leaves, {steps} steps", flush=True)
     u0 = f.project_ic(G.IC_VORTEX, w.ic_params)
     ua, ub = u0.clone(), u0.clone()
@@ -56,10 +57,11 @@ def test_static_step_in_3d_with_guard_traces():
     _compare(G, W.vortex_c1(), 2)
 
 
-@pytest.mark.parametrize("roots", ["rotated", "mapped"])
+@pytest.mark.parametrize("roots", ["rotated", "mapped", "mapped_limited"])
 def test_static_step_on_rotated_and_bilinear_roots(roots):
     """Forests whose stages first fill the guard buffer of the work area:
-    a rotated frame on every root, or bilinear roots; then a plain forest."""
+    a rotated frame on every root, or bilinear roots (also with the
+    positivity limiter); then a plain forest."""
     from paper_2502_12620_amd import dgamr as G
 
     w = W.roofline_2d(4, 2)
@@ -69,7 +71,7 @@ def test_static_step_on_rotated_and_bilinear_roots(roots):
         _compare(G, w, 2, lambda f: f.set_root_frames(frames))
     else:
         nodes = W.smooth_root_nodes(w)
-        _compare(G, w, 2, lambda f: f.set_root_nodes(nodes))
+        _compare(G, w, 2, lambda f: f.set_root_nodes(nodes), limiter=roots == "mapped_limited")
     _compare(G, W.vortex_c1(), 2)
 
 
