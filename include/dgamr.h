@@ -221,9 +221,11 @@ int dgamr_get_time(const dgamr_forest *f, double *t);
  * guard fill, the residual and the stage update (and the positivity limiter
  * when the forest asks for it).  The far side of every block face is
  * computed inside the stage kernel straight from the neighbours' cells (same
- * values as dgamr_fill_guardcells); only the 3-D lane-per-(cell, variable)
- * kernel reads guard traces that a fill kernel writes into the work buffer
- * before each stage.  Asynchronous; captures into a HIP graph.  Diffusion
+ * values as dgamr_fill_guardcells), except where a fill kernel writes into
+ * the work buffer before each stage: guard traces for the 3-D
+ * lane-per-(cell, variable) kernel, and guard coefficients on forests with
+ * rotated root frames or bilinear / trilinear roots.  Asynchronous;
+ * captures into a HIP graph.  Diffusion
  * forests (cfl > 0 required; dt computed on the host from the forest's
  * finest cells and written to dt_dev): per stage the guard fill of
  * coefficients into the work buffer, then the interior-penalty residual and
