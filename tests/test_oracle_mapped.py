@@ -394,3 +394,58 @@ def test_limited_steps_on_box_nodes_match_the_box_grid(dim, p):
     assert np.abs(um - ua).max() <= 1e-12 * np.abs(ua).max()
     t = fm.totals(um)
     np.testing.assert_allclose(t, fa.totals(ua), rtol=1e-12, atol=1e-12 * np.abs(t).max())
+
+
+def _physical_means3(u, nodes, p, N):
+    """The same on a single unrefined trilinear root: X(s) = sum over the
+    corners b in {0,1}^3 of prod_a (s_a or 1 - s_a) times the node; cell
+    (i, j, k) covers s in [i/N,(i+1)/N] x [j/N,(j+1)/N] x [k/N,(k+1)/N],
+    cell index i + N (j + N k); |J| from the three columns dX/ds_a."""
+    from tests import refmath as RM
+
+    modes = RM.graded_modes(3, p)
+    xi, w = RM.tensor_gauss(3, 5)
+    out = np.zeros((N ** 3, u.shape[1]))
+    for c in range(N ** 3):
+        ijk = (c % N, (c // N) % N, c // (N * N))
+        s = np.stack([(ijk[a] + 0.5 * (xi[:, a] + 1.0)) / N for a in range(3)], axis=-1)
+        J = np.zeros((len(w), 3, 3))
+        for b in range(8):
+            bits = [(b >> a) & 1 for a in range(3)]
+            X = nodes[bits[2], bits[1], bits[0]]
+            fac = [s[:, a] if bits[a] else 1.0 - s[:, a] for a in range(3)]
+            for a in range(3):
+                d = (1.0 if bits[a] else -1.0) * np.prod([fac[e] for e in range(3) if e != a], axis=0)
+                J[:, :, a] += d[:, None] * X[None, :]
+        det = np.linalg.det(J)
+        assert det.min() > 0
+        vals = RM.eval_cell(u[0, :, :, c], modes, xi)
+        out[c] = (w * det) @ vals / np.sum(w * det)
+    return out
+
+
+@pytest.mark.parametrize("p", [1, 2])
+def test_limiter_keeps_each_physical_cell_mean_on_a_trilinear_root(p):
+    """3-D: the limiter keeps every cell's mean over the physical cell of a
+    distorted trilinear root and moves mode 0."""
+    N = 2
+    nodes = np.zeros((2, 2, 2, 3))  # nodes[z][y][x]
+    for k in range(2):
+        for j in range(2):
+            for i in range(2):
+                nodes[k, j, i] = (i, j, k)
+    nodes[1, 1, 1] += (0.3, 0.2, 0.25)
+    nodes[0, 1, 0] += (0.15, -0.1, 0.05)
+    nodes[1, 0, 1] += (-0.1, 0.1, 0.2)
+    f = O.Forest(3, p, N, (1, 1, 1), (0.0,) * 3, (1.0,) * 3, (1, 1, 1), 1)
+    f.set_nodes(nodes)
+    u = f.project_ic(O.IC_UNIFORM, [1.0, 0.0, 0.0, 0.0, 1.0])
+    rng = np.random.default_rng(50 + p)
+    u[0, :, 1:, :] = 0.6 * rng.standard_normal(u[0, :, 1:, :].shape)
+    before = u.copy()
+    m0 = _physical_means3(u, nodes, p, N)
+    assert m0[:, 0].min() > 0.2
+    assert np.abs(m0 - before[0, :, 0, :].T).max() > 1e-3
+    f.limit(u)
+    np.testing.assert_allclose(_physical_means3(u, nodes, p, N), m0, rtol=1e-13, atol=1e-13)
+    assert np.abs(u[0, :, 0, :] - before[0, :, 0, :]).max() > 1e-6
